@@ -1,0 +1,62 @@
+"""Test-only helpers: the exact ISSA used to check the oracle in law."""
+import ctypes as C
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB = None
+
+
+def issa_lib():
+    global _LIB
+    if _LIB is None:
+        so = os.path.join(_HERE, "libissa.so")
+        src = os.path.join(_HERE, "issa.c")
+        if not os.path.exists(so) or os.path.getmtime(so) < os.path.getmtime(src):
+            subprocess.run(["gcc", "-O2", "-fPIC", "-shared", "-o", so + ".tmp", src, "-lm"], check=True)
+            os.replace(so + ".tmp", so)
+        L = C.CDLL(so)
+        P = C.POINTER
+        L.issa_run.argtypes = [C.c_int, C.c_int, C.c_int, P(C.c_int32), P(C.c_double), P(C.c_int32),
+                               P(C.c_int32), P(C.c_int32), P(C.c_int32), P(C.c_double), P(C.c_int32),
+                               C.c_int, P(C.c_double), C.c_uint64, P(C.c_int32)]
+        _LIB = L
+    return _LIB
+
+
+def _p(a, ct):
+    return a.ctypes.data_as(C.POINTER(ct))
+
+
+def issa_run(geo, D, reactions, init, times, seed):
+    """Exact RDME run on the oracle-pinned geometry; returns [n_samples, S, T]."""
+    from workloads import reaction_arrays
+
+    nbr = np.ascontiguousarray(geo["nbr"], np.int32)
+    T = nbr.shape[0]
+    S = len(D)
+    g, w, nav = geo["g"], geo["w"], geo["nav"]
+    drate = np.zeros((S, T, 4))
+    for m in range(S):
+        drate[m] = D[m] * g[:, None] * w
+    drate = np.ascontiguousarray(drate)
+    rn, rid, pn, pid, k = reaction_arrays(reactions)
+    R = len(reactions)
+    c = np.zeros((max(R, 1), T))
+    for r in range(R):
+        if rn[r] == 0:
+            c[r] = k[r] * nav
+        elif rn[r] == 1:
+            c[r] = k[r]
+        else:
+            c[r] = k[r] / nav
+    counts = np.ascontiguousarray(init, np.int32).copy()
+    times = np.ascontiguousarray(times, np.float64)
+    out = np.zeros((len(times), S, T), np.int32)
+    issa_lib().issa_run(T, S, R, _p(nbr, C.c_int32), _p(drate, C.c_double), _p(rn, C.c_int32),
+                        _p(rid, C.c_int32), _p(pn, C.c_int32), _p(pid, C.c_int32), _p(c, C.c_double),
+                        _p(counts, C.c_int32), len(times), _p(times, C.c_double), int(seed),
+                        _p(out, C.c_int32))
+    return out

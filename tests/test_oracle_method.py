@@ -1,0 +1,397 @@
+"""Pins of the oracle's whole step against laws the method must obey.
+
+P1  exact conservation (diffusion only; A+B<->C conserves A+C and B+C)
+P2  diffusion only: binomial thinning + multinomial split moves every molecule
+    independently (leave with probability zeta, Sec. II.A; face f with weight
+    w_f, Sec. II.B), so counts after k periods from a point source are exactly
+    Multinomial(N0, e_i0 P^k) with P_tu = zeta_t w_tu, P_tt = 1 - zeta_t
+P4  mean-square displacement against the exact chain and against 6 D t
+P5  stationary counts are Multinomial(N, V_t / V) (Figs. 2-3 analytic CV)
+P6  A+B<->C: the well-mixed stationary law of the total C
+P7  D -> 0: the surviving total is Binomial(N0, exp(-k t)) at any tau
+P8  occupancy (eq. 2): E[Nbar] = N0 (1 - exp(-k tau)) / (k tau) for A -> 0
+P10 against an exact ISSA on tiny meshes (two-sample KS)
+"""
+import math
+
+import numpy as np
+import pytest
+from scipy import sparse, stats
+
+import workloads as W
+
+from .helpers import issa_run
+
+
+def _chi2_pvalue(obs, exp, min_expected=5.0):
+    o2, e2 = [], []
+    ao = ae = 0.0
+    order = np.argsort(-np.asarray(exp))
+    for i in order:
+        ao += obs[i]
+        ae += exp[i]
+        if ae >= min_expected:
+            o2.append(ao)
+            e2.append(ae)
+            ao = ae = 0.0
+    if ae > 0 and e2:
+        o2[-1] += ao
+        e2[-1] += ae
+    o2, e2 = np.array(o2), np.array(e2)
+    chi2 = float(((o2 - e2) ** 2 / e2).sum())
+    return float(stats.chi2.sf(chi2, len(o2) - 1))
+
+
+def _transition_matrix(geo, D, tau):
+    nbr, w, g = geo["nbr"], geo["w"], geo["g"]
+    T = nbr.shape[0]
+    zeta = np.minimum(1.0, (tau * D) * g)
+    rows, cols, vals = [], [], []
+    for t in range(T):
+        rows.append(t)
+        cols.append(t)
+        vals.append(1.0 - zeta[t])
+        for f in range(4):
+            if nbr[t, f] >= 0:
+                rows.append(t)
+                cols.append(nbr[t, f])
+                vals.append(zeta[t] * w[t, f])
+    return sparse.csr_matrix((vals, (rows, cols)), shape=(T, T))
+
+
+def test_conservation_diffusion_and_reactions(orc):
+    m = W.diffusion_cube()
+    sim = orc.OracleSim.from_model(m)
+    for _ in range(50):
+        sim.step()
+        c = sim.get_counts()
+        assert c.sum() == 1000 and c.min() >= 0
+    m2 = W.abc_lattice(n=6, a=0.1e-6, conc=5e-6, t_end=0.02)
+    sim2 = orc.OracleSim.from_model(m2)
+    c0 = sim2.get_counts()
+    fired = False
+    for _ in range(60):
+        sim2.step()
+        c = sim2.get_counts()
+        assert c.min() >= 0
+        assert c[0].sum() + c[2].sum() == c0[0].sum() + c0[2].sum()
+        assert c[1].sum() + c[2].sum() == c0[1].sum() + c0[2].sum()
+        fired |= c[2].sum() > 0
+    assert fired
+
+
+@pytest.mark.parametrize("N0,tau_scale", [(4, 1.0), (300, 1.0), (40, 0.3)])
+def test_point_source_is_exactly_multinomial(orc, N0, tau_scale):
+    xyz, tets = W.tiny_lattice(2, 0.2e-6, jitter_frac=0.2, seed=3)
+    D = 1e-12
+    T = tets.shape[0]
+    k_steps, runs = 3, 1500
+    agg = np.zeros(T)
+    src = 5
+    for r in range(runs):
+        sim = orc.OracleSim(xyz, tets, [D], [], tau_scale=tau_scale, seed=17, realization=r)
+        init = np.zeros(T, np.int32)
+        init[src] = N0
+        sim.set_counts(0, init)
+        sim.run_steps(k_steps)
+        c = sim.get_counts(0)
+        assert c.sum() == N0
+        agg += c
+    geo = sim.geometry()
+    P = _transition_matrix(geo, D, sim.tau)
+    pi = np.zeros(T)
+    pi[src] = 1.0
+    for _ in range(k_steps):
+        pi = P.T @ pi
+    assert abs(pi.sum() - 1) < 1e-12
+    assert _chi2_pvalue(agg, pi * runs * N0) > 1e-3
+
+
+def test_msd_against_exact_chain_and_6Dt(orc):
+    n, a, D = 16, 0.1e-6, 1e-12
+    xyz, tets = W.kuhn_lattice(n, a)
+    T = tets.shape[0]
+    src = 6 * (8 + n * (8 + n * 8))
+    bc = xyz[tets].mean(axis=1)
+    d2 = ((bc - bc[src]) ** 2).sum(axis=1)
+    N0, seeds, k = 1000, 5, 34
+    tot = 0.0
+    for s in range(seeds):
+        sim = orc.OracleSim(xyz, tets, [D], [], seed=100 + s)
+        init = np.zeros(T, np.int32)
+        init[src] = N0
+        sim.set_counts(0, init)
+        sim.run_steps(k)
+        tot += float((sim.get_counts(0) * d2).sum())
+    msd = tot / (N0 * seeds)
+    geo = sim.geometry()
+    P = _transition_matrix(geo, D, sim.tau)
+    pi = np.zeros(T)
+    pi[src] = 1.0
+    for _ in range(k):
+        pi = P.T @ pi
+    exact = float((pi * d2).sum())
+    se = math.sqrt(float((pi * d2**2).sum()) - exact**2) / math.sqrt(N0 * seeds)
+    assert abs(msd - exact) < 3 * se, (msd, exact, se)
+    # against continuum 6 D t: the finite-volume walk on the Kuhn lattice is
+    # anisotropic (mean of its diffusivity tensor's eigenvalues ~1.034 D), a
+    # property of the mesh discretisation, not of the splitting
+    t = k * sim.tau
+    ratio = exact / (6 * D * t)
+    assert 1.02 < ratio < 1.05, ratio
+    assert abs(msd - 6 * D * t) < 3 * se * (6 * D * t) / exact * 1.0 + abs(exact - 6 * D * t) + 3 * se
+
+
+def test_stationary_counts_and_cv(orc):
+    xyz, tets = W.tiny_lattice(2, 0.2e-6, jitter_frac=0.2, seed=5)
+    T = tets.shape[0]
+    N, runs = 200, 1200
+    samples = np.zeros((runs, T))
+    for r in range(runs):
+        sim = orc.OracleSim(xyz, tets, [1e-12], [], seed=31, realization=r)
+        init = np.zeros(T, np.int32)
+        init[0] = N
+        sim.set_counts(0, init)
+        sim.run_steps(400)
+        samples[r] = sim.get_counts(0)
+    vol = sim.geometry()["vol"]
+    p = vol / vol.sum()
+    assert _chi2_pvalue(samples.sum(axis=0), runs * N * p) > 1e-3
+    cv_obs = samples.std(axis=0, ddof=1) / samples.mean(axis=0)
+    cv_ana = np.sqrt((1 - p) / (N * p))
+    ratio = float((cv_obs / cv_ana).mean())
+    assert abs(ratio - 1.0) < 0.01, ratio      # the paper's own bar (Sec. II.B)
+
+
+def _abc_closed_form(A0, B0, kappa):
+    c = np.arange(0, min(A0, B0) + 1)
+    from scipy.special import gammaln
+
+    lp = c * math.log(kappa) - gammaln(c + 1) - gammaln(A0 - c + 1) - gammaln(B0 - c + 1)
+    lp -= lp.max()
+    p = np.exp(lp)
+    return c, p / p.sum()
+
+
+def test_abc_equilibrium_mean(orc):
+    n, a = 5, 0.2e-6
+    xyz, tets = W.kuhn_lattice(n, a)
+    T = tets.shape[0]
+    V_L = (n * a) ** 3 * 1000
+    kf, kb = 1e6, 10.0
+    A0 = W.count_for(1e-6, (n * a) ** 3)
+    c, p = _abc_closed_form(A0, A0, kf / (W.N_A * V_L * kb))
+    mean_c = float((c * p).sum())
+    runs, burn, keep = 12, 800, 1700
+    means = []
+    rng = np.random.default_rng(8)
+    for r in range(runs):
+        sim = orc.OracleSim(xyz, tets, [1e-12, 1e-12, 0.5e-12], [([0, 1], [2], kf), ([2], [0, 1], kb)],
+                            seed=200 + r)
+        sim.set_counts(0, W.place_by_volume(xyz, tets, A0, rng))
+        sim.set_counts(1, W.place_by_volume(xyz, tets, A0, rng))
+        sim.run_steps(burn)
+        acc = 0.0
+        for _ in range(keep):
+            sim.step()
+            acc += sim.get_counts(2).sum()
+        means.append(acc / keep)
+    means = np.array(means)
+    se = means.std(ddof=1) / math.sqrt(runs)
+    assert abs(means.mean() - mean_c) < 3 * se + 0.005 * mean_c, (means.mean(), mean_c, se)
+
+
+def test_decay_total_is_binomial(orc):
+    xyz, tets = W.tiny_lattice(2, 1e-6, jitter_frac=0.2, seed=7)
+    T = tets.shape[0]
+    N0, kd, t_end, runs = 30, 2.0, 0.5, 2500
+    totals = np.zeros(runs, np.int64)
+    for r in range(runs):
+        sim = orc.OracleSim(xyz, tets, [1e-12], [([0], [], kd)], seed=55, realization=r)
+        init = np.zeros(T, np.int32)
+        init[r % T] = N0
+        sim.set_counts(0, init)
+        sim.run_until(t_end)
+        t, _ = sim.time()
+        assert t == t_end
+        totals[r] = sim.get_counts(0).sum()
+    p = math.exp(-kd * t_end)
+    obs = np.bincount(totals, minlength=N0 + 1)
+    assert _chi2_pvalue(obs, stats.binom.pmf(np.arange(N0 + 1), N0, p) * runs) > 1e-3
+
+
+def test_occupancy_mean(orc):
+    xyz, tets = W.tiny_lattice(1, 0.2e-6)
+    T = tets.shape[0]
+    D = 1e-12
+    sim0 = orc.OracleSim(xyz, tets, [D], [])
+    tau = sim0.tau
+    kd = 1.0 / tau
+    N0, runs = 20, 2500
+    nb = []
+    for r in range(runs):
+        sim = orc.OracleSim(xyz, tets, [D], [([0], [], kd)], seed=9, realization=r)
+        sim.set_counts(0, np.full(T, N0, np.int32))
+        nbar, n = sim.step(record=True)
+        nb.append(nbar[0])
+    nb = np.concatenate(nb)
+    want = N0 * (1 - math.exp(-kd * tau)) / (kd * tau)
+    se = nb.std(ddof=1) / math.sqrt(nb.size)
+    assert abs(nb.mean() - want) < 3 * se, (nb.mean(), want, se)
+    # without reactions the mean occupancy is the count itself, exactly
+    sim = orc.OracleSim(xyz, tets, [D], [])
+    init = np.arange(T, dtype=np.int32) * 7
+    sim.set_counts(0, init)
+    nbar, n = sim.step(record=True)
+    assert (nbar[0] == init).all()
+
+
+def test_occupancy_single_molecule_arithmetic(orc):
+    """One molecule of A -> 0: Nbar = s1/tau if it decays at s1 < tau, else 1."""
+    xyz, tets = W.tiny_lattice(1, 0.2e-6)
+    T = tets.shape[0]
+    D = 1e-12
+    tau = orc.OracleSim(xyz, tets, [D], []).tau
+    kd = 0.7 / tau
+    seen_decay = seen_stay = False
+    for r in range(40):
+        sim = orc.OracleSim(xyz, tets, [D], [([0], [], kd)], seed=4, realization=r)
+        sim.set_counts(0, np.ones(T, np.int32))
+        nbar, _ = sim.step(record=True)
+        for t in range(T):
+            u = orc.uniform(4, r, 0x80000000, t, 0, 0)
+            s1 = -orc.ln(1.0 - u) / kd
+            if s1 < tau:
+                assert nbar[0, t] == (0.0 + 1.0 * (s1 - 0.0) + 0.0 * (tau - s1)) / tau
+                seen_decay = True
+            else:
+                assert nbar[0, t] == 1.0
+                seen_stay = True
+    assert seen_decay and seen_stay
+
+
+def test_run_until_alignment(orc):
+    m = W.diffusion_cube()
+    sim = orc.OracleSim.from_model(m)
+    tau = sim.tau
+    sim.run_until(0.5)
+    t, k = sim.time()
+    assert t == 0.5 and k == math.floor(0.5 / tau) + 1
+    sim.run_until(0.5)                     # nothing left to do
+    assert sim.time() == (0.5, k)
+    sim.run_steps(3)
+    t2, k2 = sim.time()
+    assert k2 == k + 3 and t2 == 0.5 + 3 * tau
+
+
+def test_against_exact_issa_transient(orc):
+    """Diffusion from a point source at t = 20 tau with tau scaled to 0.05."""
+    xyz, tets = W.tiny_lattice(2, 0.2e-6, jitter_frac=0.2, seed=3)
+    T = tets.shape[0]
+    D, N0, runs, k = 1e-12, 20, 2000, 20
+    src = 21
+    os_c, is_c = [], []
+    geo = None
+    for r in range(runs):
+        sim = orc.OracleSim(xyz, tets, [D], [], tau_scale=0.05, seed=71, realization=r)
+        init = np.zeros(T, np.int32)
+        init[src] = N0
+        sim.set_counts(0, init)
+        sim.run_steps(k)
+        os_c.append(sim.get_counts(0))
+        if geo is None:
+            geo = sim.geometry()
+    tend = k * sim.tau
+    for r in range(runs):
+        init = np.zeros((1, T), np.int32)
+        init[0, src] = N0
+        is_c.append(issa_run(geo, [D], [], init, [tend], seed=1000 + r)[0, 0])
+    os_c, is_c = np.array(os_c), np.array(is_c)
+    near = [src] + [int(u) for u in geo["nbr"][src] if u >= 0]
+    for stat in (os_c[:, src], is_c[:, src]), (os_c[:, near].sum(1), is_c[:, near].sum(1)):
+        assert stats.ks_2samp(stat[0], stat[1]).pvalue > 0.01
+    # aggregated occupancy of each tet, two-sample chi-square
+    table = np.vstack([os_c.sum(0), is_c.sum(0)])
+    table = table[:, table.sum(0) > 10]
+    assert stats.chi2_contingency(table)[1] > 0.01
+
+
+def _abc_cell_run(orc, tau_scale, first_order, runs, k, seed, with_issa):
+    xyz, tets = W.tiny_lattice(1, 0.2e-6)
+    T = tets.shape[0]
+    V_L = (0.2e-6) ** 3 * 1000
+    kb = 100.0
+    kappa = 0.1
+    kf = kappa * W.N_A * V_L * kb
+    reactions = [([0, 1], [2], kf), ([2], [0, 1], kb)]
+    D = [1e-12, 1e-12, 0.5e-12]
+    A0 = 20
+    rng = np.random.default_rng(seed)
+    os_t, is_t = [], []
+    geo = None
+    for r in range(runs):
+        sim = orc.OracleSim(xyz, tets, D, reactions, tau_scale=tau_scale, seed=seed, realization=r)
+        sim.set_first_order(first_order)
+        a = W.place_by_volume(xyz, tets, A0, rng)
+        b = W.place_by_volume(xyz, tets, A0, rng)
+        sim.set_counts(0, a)
+        sim.set_counts(1, b)
+        sim.run_steps(k)
+        os_t.append(int(sim.get_counts(2).sum()))
+        if geo is None:
+            geo = sim.geometry()
+        if with_issa:
+            init = np.zeros((3, T), np.int32)
+            init[0], init[1] = a, b
+            is_t.append(int(issa_run(geo, D, reactions, init, [k * sim.tau], seed=5000 + r)[0, 2].sum()))
+    c, p = _abc_closed_form(A0, A0, kappa)
+    return np.array(os_t), np.array(is_t), c, p
+
+
+def test_against_exact_issa_abc_stationary(orc):
+    """A+B<->C in one cubic cell (6 tets), zeta < 1: total C at a late time,
+    operator splitting vs exact ISSA vs the closed-form stationary law."""
+    runs = 2000
+    os_t, is_t, c, p = _abc_cell_run(orc, 0.5, False, runs, 200, 13, True)
+    assert stats.ks_2samp(os_t, is_t).pvalue > 0.01
+    assert _chi2_pvalue(np.bincount(os_t, minlength=len(c))[: len(c)], p * runs) > 1e-3
+    assert _chi2_pvalue(np.bincount(is_t, minlength=len(c))[: len(c)], p * runs) > 1e-3
+
+
+def test_first_order_split_keeps_the_exact_stationary_law(orc):
+    """Without the occupancy correction each period is an exact reaction
+    kernel followed by independent volume-reversible moves, both of which
+    leave the product-Poisson law invariant: exact at any tau with zeta < 1."""
+    runs = 2000
+    os_t, _, c, p = _abc_cell_run(orc, 0.5, True, runs, 200, 21, False)
+    assert _chi2_pvalue(np.bincount(os_t, minlength=len(c))[: len(c)], p * runs) > 1e-3
+
+
+def test_zeta_one_ring_conserves_parity_imbalance(orc):
+    """First-order split at zeta = 1: every A and B leaves its tet every
+    period; the 6 tets of a cell form a ring whose neighbours differ by one
+    transposition of the axis order, so every hop flips the permutation
+    parity.  Reactions create and destroy A and B in pairs of equal parity,
+    hence |A_even - B_even| is invariant: the chain is not ergodic on its
+    conservation slice (why the equilibrium tests above keep zeta < 1).  With
+    the occupancy correction n can fall short of the final count, so this
+    holds for the first-order variant only."""
+    xyz, tets = W.tiny_lattice(1, 0.2e-6)
+    parity = np.array([0, 1, 1, 0, 0, 1])          # permutations in lexicographic order
+    V_L = (0.2e-6) ** 3 * 1000
+    kb = 100.0
+    kf = 0.1 * W.N_A * V_L * kb
+    rng = np.random.default_rng(3)
+    for r in range(20):
+        sim = orc.OracleSim(xyz, tets, [1e-12, 1e-12, 0.5e-12], [([0, 1], [2], kf), ([2], [0, 1], kb)],
+                            seed=3, realization=r)
+        sim.set_first_order(True)
+        sim.set_counts(0, W.place_by_volume(xyz, tets, 20, rng))
+        sim.set_counts(1, W.place_by_volume(xyz, tets, 20, rng))
+        q0 = None
+        for _ in range(60):
+            c = sim.get_counts()
+            q = abs(int(c[0][parity == 0].sum()) - int(c[1][parity == 0].sum()))
+            q0 = q if q0 is None else q0
+            assert q == q0
+            sim.step()

@@ -1,0 +1,245 @@
+"""Seeded synthetic inputs: meshes, species/reaction sets and initial counts.
+
+This module only builds inputs.  It holds none of the method's arithmetic
+(no local rates, weights, period, sampling or stepping); both the GPU library
+and the oracle receive exactly the arrays produced here.
+
+Meshes are Kuhn (Freudenthal) lattices: an n x n x n grid of cubic cells of
+edge ``a``, each cell cut into the 6 tetrahedra that share its main diagonal.
+Numbering (fixed so every consumer sees the same mesh):
+
+* vertex id   = i + (n+1) * (j + (n+1) * k), at (i a, j a, k a)
+* tet id      = 6 * (ci + n * (cj + n * ck)) + p, where p indexes the axis
+  permutations (pi0, pi1, pi2) of (0, 1, 2) in lexicographic order and tet p
+  has the local vertices 0, e_pi0, e_pi0 + e_pi1, (1, 1, 1) of its cell.
+
+The paper's own meshes (its spiny dendrite and its 1060-tet cylinder) are not
+available; these lattices stand in for them (its Fig. 2 cube is 1 um on a
+side, reused here for the small diffusion case).
+"""
+from __future__ import annotations
+
+import dataclasses
+import itertools
+import math
+from typing import List, Optional, Sequence, Tuple
+
+import numpy as np
+
+N_A = 6.02214076e23  # Avogadro constant (SI 2019), for concentration -> count
+
+_PERMS = list(itertools.permutations(range(3)))
+
+
+@dataclasses.dataclass
+class Model:
+    """One simulation request: mesh, species, reactions, initial counts."""
+
+    name: str
+    xyz: np.ndarray                # [n_verts, 3] float64, metres
+    tets: np.ndarray               # [n_tets, 4] int32
+    D: List[float]                 # per species, m^2/s
+    reactions: List[Tuple[List[int], List[int], float]]  # (reactants, products, k SI)
+    init: np.ndarray               # [n_realizations, n_species, n_tets] int32
+    t_end: float
+    seed: int = 1
+    tau_scale: float = 1.0
+    species_names: Optional[List[str]] = None
+
+    @property
+    def n_tets(self) -> int:
+        return int(self.tets.shape[0])
+
+    @property
+    def n_species(self) -> int:
+        return len(self.D)
+
+    @property
+    def n_realizations(self) -> int:
+        return int(self.init.shape[0])
+
+
+def kuhn_lattice(n: int, a: float) -> Tuple[np.ndarray, np.ndarray]:
+    """Vertices and tetrahedra of an n^3-cell Kuhn lattice with cell edge a."""
+    m = n + 1
+    idx = np.arange(m)
+    k, j, i = np.meshgrid(idx, idx, idx, indexing="ij")
+    xyz = np.stack([i.ravel(), j.ravel(), k.ravel()], axis=1).astype(np.float64) * a
+
+    def vid(ci, cj, ck):
+        return ci + m * (cj + m * ck)
+
+    c = np.arange(n)
+    ck, cj, ci = np.meshgrid(c, c, c, indexing="ij")
+    ci, cj, ck = ci.ravel(), cj.ravel(), ck.ravel()
+    tets = np.empty((n * n * n, 6, 4), dtype=np.int64)
+    for p, perm in enumerate(_PERMS):
+        off = np.zeros(3, dtype=np.int64)
+        corners = [off.copy()]
+        for ax in perm:
+            off[ax] += 1
+            corners.append(off.copy())
+        # corners: 0, e_pi0, e_pi0+e_pi1, (1,1,1)
+        for v, cc in enumerate(corners):
+            tets[:, p, v] = vid(ci + cc[0], cj + cc[1], ck + cc[2])
+    return xyz, tets.reshape(-1, 4).astype(np.int32)
+
+
+def jitter(xyz: np.ndarray, n: int, a: float, frac: float, seed: int) -> np.ndarray:
+    """Move every interior vertex by a uniform offset in [-frac a, frac a]^3.
+
+    Boundary vertices stay put, so the box volume is unchanged.  At frac=0.2 no
+    tet can invert (largest height loss 0.69a < smallest Kuhn height 0.707a).
+    """
+    rng = np.random.Generator(np.random.PCG64(seed))
+    out = xyz.copy()
+    lim = n * a
+    eps = 1e-9 * a
+    interior = np.all((xyz > eps) & (xyz < lim - eps), axis=1)
+    delta = rng.uniform(-frac * a, frac * a, size=(int(interior.sum()), 3))
+    out[interior] += delta
+    return out
+
+
+def _tet_volumes(xyz: np.ndarray, tets: np.ndarray) -> np.ndarray:
+    """Tet volumes for placing molecules (input recipe only)."""
+    P = xyz[tets]  # [T,4,3]
+    M = P[:, 1:, :] - P[:, :1, :]
+    return np.abs(np.linalg.det(M)) / 6.0
+
+
+def _barycentres(xyz: np.ndarray, tets: np.ndarray) -> np.ndarray:
+    return xyz[tets].mean(axis=1)
+
+
+def count_for(conc_molar: float, volume_m3: float) -> int:
+    """Molecules for a concentration in a volume, rounded half to even."""
+    return int(round(conc_molar * N_A * volume_m3 * 1000.0))
+
+
+def place_by_volume(xyz, tets, total: int, rng, mask: Optional[np.ndarray] = None) -> np.ndarray:
+    """Scatter ``total`` molecules independently over tets, P(tet) ~ volume."""
+    vol = _tet_volumes(xyz, tets)
+    if mask is not None:
+        vol = np.where(mask, vol, 0.0)
+    p = vol / vol.sum()
+    return rng.multinomial(total, p).astype(np.int32)
+
+
+# ----------------------------------------------------------------------------
+# The workloads
+# ----------------------------------------------------------------------------
+
+def diffusion_cube(seed: int = 1) -> Model:
+    """1 um cube, 5x5x5 cells x 6 (750 tets), one species D=1e-12 m^2/s,
+    1000 molecules in the first tet of the middle cell (2,2,2), 0.5 s."""
+    n, a = 5, 0.2e-6
+    xyz, tets = kuhn_lattice(n, a)
+    init = np.zeros((1, 1, tets.shape[0]), dtype=np.int32)
+    init[0, 0, 6 * (2 + n * (2 + n * 2))] = 1000
+    return Model("diffusion_cube_750", xyz, tets, [1e-12], [], init, 0.5, seed)
+
+
+def _abc_reactions():
+    # A + B -> C at 1e6 /(M s); C -> A + B at 10 /s
+    return [([0, 1], [2], 1e6), ([2], [0, 1], 10.0)]
+
+
+def abc_lattice(n: int = 40, a: float = 0.1e-6, seed: int = 1, n_realizations: int = 1,
+                conc: float = 100e-9, t_end: float = 0.1) -> Model:
+    """A+B<->C on an n^3 x 6 Kuhn lattice: A and B at ``conc`` placed by
+    volume, C empty; D_A = D_B = 1e-12, D_C = 0.5e-12 m^2/s."""
+    xyz, tets = kuhn_lattice(n, a)
+    vol_total = (n * a) ** 3
+    total = count_for(conc, vol_total)
+    rng = np.random.Generator(np.random.PCG64(seed))
+    init = np.zeros((n_realizations, 3, tets.shape[0]), dtype=np.int32)
+    for r in range(n_realizations):
+        init[r, 0] = place_by_volume(xyz, tets, total, rng)
+        init[r, 1] = place_by_volume(xyz, tets, total, rng)
+    return Model(f"abc_{n}cube_{tets.shape[0]}", xyz, tets, [1e-12, 1e-12, 0.5e-12],
+                 _abc_reactions(), init, t_end, seed, species_names=["A", "B", "C"])
+
+
+def abcd_jittered(n: int = 40, a: float = 0.1e-6, seed: int = 1, t_end: float = 0.05) -> Model:
+    """The A+B<->C lattice with interior vertices jittered by +-20% of the cell
+    edge, plus species D (5e-12 m^2/s) decaying D -> 0 at 1/s, initialised at
+    1 uM in the octant x, y, z < n a / 2 (by tet barycentre)."""
+    xyz0, tets = kuhn_lattice(n, a)
+    xyz = jitter(xyz0, n, a, 0.2, seed)
+    rng = np.random.Generator(np.random.PCG64(seed + 1000))
+    vol_total = (n * a) ** 3
+    total = count_for(100e-9, vol_total)
+    init = np.zeros((1, 4, tets.shape[0]), dtype=np.int32)
+    init[0, 0] = place_by_volume(xyz, tets, total, rng)
+    init[0, 1] = place_by_volume(xyz, tets, total, rng)
+    bc = _barycentres(xyz, tets)
+    half = n * a / 2
+    octant = np.all(bc < half, axis=1)
+    vol = _tet_volumes(xyz, tets)
+    total_d = count_for(1e-6, float(vol[octant].sum()))
+    init[0, 3] = place_by_volume(xyz, tets, total_d, rng, mask=octant)
+    reactions = _abc_reactions() + [([3], [], 1.0)]
+    return Model(f"abcd_jitter_{n}cube_{tets.shape[0]}", xyz, tets,
+                 [1e-12, 1e-12, 0.5e-12, 5e-12], reactions, init, t_end, seed,
+                 species_names=["A", "B", "C", "D"])
+
+
+def serving_request(rng: np.random.Generator, a: float = 0.1e-6, t_lo: float = 1e4,
+                    t_hi: float = 1e6, max_species: int = 6) -> Model:
+    """One request of the serving mix: jittered lattice with T log-uniform in
+    [t_lo, t_hi] tets, 1..max_species species with D log-uniform in
+    [1e-13, 1e-11] m^2/s, 0..2S random uni/bimolecular reactions (first order
+    log-U [1, 1e3] /s, second order log-U [1e5, 1e8] /(M s)), each species
+    initialised log-U [10 nM, 1 uM] placed by volume."""
+    T = math.exp(rng.uniform(math.log(t_lo), math.log(t_hi)))
+    n = max(2, int(round((T / 6.0) ** (1.0 / 3.0))))
+    xyz0, tets = kuhn_lattice(n, a)
+    xyz = jitter(xyz0, n, a, 0.2, int(rng.integers(1, 2**31)))
+    S = int(rng.integers(1, max_species + 1))
+    D = [float(math.exp(rng.uniform(math.log(1e-13), math.log(1e-11)))) for _ in range(S)]
+    n_reac = int(rng.integers(0, 2 * S + 1))
+    reactions = []
+    for _ in range(n_reac):
+        if rng.random() < 0.5:
+            r = [int(rng.integers(0, S))]
+            k = float(math.exp(rng.uniform(math.log(1.0), math.log(1e3))))
+        else:
+            r = [int(rng.integers(0, S)), int(rng.integers(0, S))]
+            k = float(math.exp(rng.uniform(math.log(1e5), math.log(1e8))))
+        n_prod = int(rng.integers(0, 3))
+        p = [int(rng.integers(0, S)) for _ in range(n_prod)]
+        reactions.append((r, p, k))
+    vol_total = (n * a) ** 3
+    init = np.zeros((1, S, tets.shape[0]), dtype=np.int32)
+    for s in range(S):
+        c = math.exp(rng.uniform(math.log(10e-9), math.log(1e-6)))
+        init[0, s] = place_by_volume(xyz, tets, count_for(c, vol_total), rng)
+    return Model(f"serve_{n}cube_S{S}_R{n_reac}", xyz, tets, D, reactions, init,
+                 t_end=float("nan"), seed=int(rng.integers(1, 2**31)))
+
+
+def tiny_lattice(n: int = 2, a: float = 0.2e-6, jitter_frac: float = 0.0, seed: int = 3) -> Tuple[np.ndarray, np.ndarray]:
+    """Small meshes for exhaustive tests (n=1: 6 tets, n=2: 48 tets)."""
+    xyz, tets = kuhn_lattice(n, a)
+    if jitter_frac > 0:
+        xyz = jitter(xyz, n, a, jitter_frac, seed)
+    return xyz, tets
+
+
+def reaction_arrays(reactions: Sequence[Tuple[Sequence[int], Sequence[int], float]]):
+    """Flatten (reactants, products, k) triples into the fixed-width arrays the
+    C interfaces take: reac_n[R], reac_ids[R][2], prod_n[R], prod_ids[R][3], k[R]."""
+    R = len(reactions)
+    rn = np.zeros(max(R, 1), dtype=np.int32)
+    rid = np.full((max(R, 1), 2), -1, dtype=np.int32)
+    pn = np.zeros(max(R, 1), dtype=np.int32)
+    pid = np.full((max(R, 1), 3), -1, dtype=np.int32)
+    k = np.zeros(max(R, 1), dtype=np.float64)
+    for i, (re, pr, kk) in enumerate(reactions):
+        rn[i] = len(re)
+        rid[i, : len(re)] = re
+        pn[i] = len(pr)
+        pid[i, : len(pr)] = pr
+        k[i] = kk
+    return rn, rid, pn, pid, k
