@@ -1,0 +1,222 @@
+#!/usr/bin/env python3
+"""Throughput of the operator-split reaction-diffusion step on one MI355X.
+
+Default workload (batched): 256 realizations of the A+B<->C system on the
+40^3 x 6 Kuhn lattice (384,000 tets, 3 species) plus 64 realizations of its
+20^3 x 6 variant (48,000 tets), advanced together by the batching engine
+(hipGraph-captured chunks of periods).  A "step" is one period tau of every
+realization.  Prints one JSON line.
+
+  python bench.py [--steps K] [--warmup W] [--workload batched|plain]
+"""
+import argparse
+import hashlib
+import json
+import os
+import platform
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBPS = 8000.0  # MI355X HBM3E, published
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def kernel_source_hash():
+    h = hashlib.sha256()
+    for f in ("rdos_kernels.hip", "rdos_sampling.h", "rdos_internal.h"):
+        with open(os.path.join(ROOT, "paper_1512_03126_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def traffic_from_profile(workload, steps_key):
+    """HBM bytes per scan launch measured by rocprofv3 counters for this
+    workload, if the kernel sources have not changed since."""
+    path = os.path.join(ROOT, "profiles", f"scan_kernel_{workload}_traffic.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        d = json.load(f)
+    if d.get("kernel_sources") != kernel_source_hash():
+        return None
+    return d.get("bytes_per_launch")
+
+
+def cpu_cores():
+    try:
+        return len(os.sched_getaffinity(0))
+    except Exception:
+        return os.cpu_count() or 1
+
+
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except Exception:
+        pass
+    return platform.processor()
+
+
+def oracle_baseline(model, periods):
+    """The oracle as it stands, single thread, on one realization."""
+    import oracle
+
+    sim = oracle.OracleSim.from_model(model)
+    t0 = time.perf_counter()
+    sim.run_steps(periods)
+    dt = time.perf_counter() - t0
+    return periods * model.n_tets * model.n_species / dt, dt
+
+
+def build_batched():
+    import workloads as W
+
+    big = W.abc_lattice(n=40, a=0.1e-6, seed=1, n_realizations=256)
+    small = W.abc_lattice(n=20, a=0.1e-6, seed=2, n_realizations=64)
+    return [big, small]
+
+
+def make_sims(P, models):
+    sims = []
+    for m in models:
+        s = P.Simulation(m.xyz, m.tets, m.D, m.reactions, seed=m.seed, n_realizations=m.n_realizations,
+                         tau_scale=m.tau_scale)
+        for r in range(m.n_realizations):
+            for q in range(m.n_species):
+                s.set_counts(q, m.init[r, q], realization=r)
+        sims.append(s)
+    return sims
+
+
+def run_engine(P, e, sims, periods):
+    tks = [P.rdos_engine_submit(e, s.h, periods, 1.0) for s in sims]
+    P.rdos_engine_drain(e)
+    for t in tks:
+        P.rdos_engine_release(e, t)
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=338, help="timed periods (338 = 0.1 s of the A+B<->C system)")
+    ap.add_argument("--warmup", type=int, default=96, help="untimed periods first (also tunes launch shapes)")
+    ap.add_argument("--workload", choices=["batched", "plain"], default="batched")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-plain", action="store_true", help="skip the plain one-realization comparison")
+    ap.add_argument("--cpu-periods", type=int, default=338, help="oracle sample length (periods)")
+    args = ap.parse_args()
+
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); realizations and requests shard "
+              "across GPUs without communication, and no multi-GPU path is built.", file=sys.stderr)
+        sys.exit(2)
+
+    import paper_1512_03126_amd as P
+    import workloads as W
+
+    P.lib()
+    K, Wm = args.steps, args.warmup
+    result = {}
+
+    # ---------------- plain: one realization, one launch pair per period
+    plain = None
+    if args.workload == "plain" or not args.no_plain:
+        m2 = W.abc_lattice()
+        (s2,) = make_sims(P, [m2])
+        s2.step(Wm)
+        s2.synchronize()
+        t0 = time.perf_counter()
+        s2.step(K)
+        s2.synchronize()
+        dt = time.perf_counter() - t0
+        plain = dict(value=K * m2.n_tets * m2.n_species / dt, ms_per_step=dt / K * 1e3)
+        log(f"plain A+B<->C 384k tets: {plain['value']:.3e} upd/s, {plain['ms_per_step']:.3f} ms/period")
+        s2.close()
+
+    if args.workload == "plain":
+        value, ms_step = plain["value"], plain["ms_per_step"]
+        workload = "A+B<->C, 40^3x6 Kuhn lattice (384000 tets x 3 species), 1 realization, one launch pair per period"
+        config = {"workload": workload, "tets": 384000, "species": 3, "realizations": 1, "periods": K}
+        roof = None
+    else:
+        log("building the batched workload (256 x 384k-tet + 64 x 48k-tet realizations)")
+        models = build_batched()
+        sims = make_sims(P, models)
+        upd_per_period = sum(m.n_realizations * m.n_tets * m.n_species for m in models)
+        bytes_per_period = 8 * sum(m.n_realizations * m.n_tets * m.n_species for m in models)
+        e = P.rdos_engine_create(0, 0)
+        run_engine(P, e, sims, Wm)
+        t0 = time.perf_counter()
+        run_engine(P, e, sims, K)
+        dt = time.perf_counter() - t0
+        value = K * upd_per_period / dt
+        ms_step = dt / K * 1e3
+        # per-kernel durations: the same periods again, launched directly with
+        # HIP events between the scan and update launches
+        P.rdos_engine_set_profiling(e, True)
+        run_engine(P, e, sims, K)
+        kt = P.rdos_engine_kernel_times(e)
+        P.rdos_engine_set_profiling(e, False)
+        n_scan = kt["scan_launches"]
+        scan_ms = kt["scan_ms"] / max(n_scan, 1)
+        upd_ms = kt["update_ms"] / max(kt["update_launches"], 1)
+        log(f"batched: {value:.3e} upd/s, {ms_step:.3f} ms/period; scan {scan_ms:.3f} ms, update {upd_ms:.3f} ms "
+            f"per launch ({n_scan} launches)")
+        achieved = bytes_per_period / (scan_ms * 1e-3) / 1e9
+        traffic = traffic_from_profile("batched", K)
+        roof = {"bound": "hbm", "kernel": "scan_kernel", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBPS,
+                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBPS, 4),
+                "traffic": traffic,
+                "bytes_per_launch": bytes_per_period, "avg_launch_ms": round(scan_ms, 4),
+                "update_kernel_avg_ms": round(upd_ms, 4),
+                "period_frac": round(bytes_per_period / (ms_step * 1e-3) / 1e9 / HBM_PEAK_GBPS, 4)}
+        try:
+            roof["copy_probe_GBps"] = round(P.rdos_bandwidth_probe(0, 1 << 30, 20), 1)
+        except Exception as ex:  # informational only
+            log(f"bandwidth probe failed: {ex}")
+        st = P.rdos_engine_stats(e)
+        P.rdos_engine_destroy(e)
+        for s in sims:
+            s.close()
+        workload = ("batched A+B<->C: 256 realizations x 40^3x6 Kuhn lattice (384000 tets) + 64 x 20^3x6 "
+                    "(48000 tets), 3 species, one hipGraph-captured launch pair per period")
+        config = {"workload": workload, "tets": [384000, 48000], "realizations": [256, 64], "species": 3,
+                  "periods": K, "tau_s": 2.958758547680654e-4, "updates_per_period": upd_per_period,
+                  "realizations_per_s": round(320.0 / (ms_step * 1e-3 * 338), 3),
+                  "engine_launches": st["launches"]}
+        if plain:
+            config["plain_updates_per_s"] = round(plain["value"], 1)
+            config["plain_ms_per_step"] = round(plain["ms_per_step"], 4)
+            config["batched_over_plain"] = round(value / plain["value"], 2)
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        m2 = W.abc_lattice()
+        v, dt = oracle_baseline(m2, args.cpu_periods)
+        cpu = {"value": round(v, 1), "unit": "tet-species updates/s", "cores": 1, "kind": "oracle",
+               "sample": f"A+B<->C 40^3x6 (384000 tets x 3 species), 1 realization, {args.cpu_periods} periods "
+                         f"({dt:.1f} s, single thread, {cpu_model()}, {cpu_cores()} cores available)"}
+        log(f"cpu oracle: {v:.3e} upd/s over {dt:.1f} s")
+
+    out = {"metric": "tet-species updates/s", "value": round(value, 1), "unit": "tet-species updates/s",
+           "n_gpus": 1, "steps": K, "warmup": Wm, "ms_per_step": round(ms_step, 4), "higher_is_better": True,
+           "scaling": "weak", "vs_baseline": None, "dtype": "i32 counts / f64 probabilities",
+           "data": "synthetic (seeded Kuhn lattices, molecules placed by volume)", "config": config}
+    if roof:
+        out["roofline"] = roof
+    if cpu:
+        out["cpu_baseline"] = cpu
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

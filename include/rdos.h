@@ -1,0 +1,189 @@
+/*
+ * rdos -- operator-split stochastic reaction-diffusion on tetrahedral meshes,
+ * on one AMD Instinct MI355X (gfx950).
+ *
+ * The method is that of Hepburn, Chen & De Schutter, "Accurate
+ * Reaction-Diffusion Operator Splitting on Tetrahedral Meshes for Parallel
+ * Stochastic Molecular Simulations" (arXiv:1512.03126), Algorithm 1: every
+ * period tau each tetrahedron runs an exact SSA of its own reactions while
+ * recording the time-mean population ("occupancy", Sec. II.C, eq. 2); then,
+ * per diffusing species, n = binomial(Nbar, zeta) molecules leave (eq. 3,
+ * zeta = tau d, Sec. II.A) and are split multinomially over the face
+ * neighbours (Sec. II.B).
+ *
+ * Conventions shared by every call
+ *   - Plain C99 ABI: opaque handles, host pointers for inputs/outputs, status
+ *     codes <= 0.  No exception crosses the ABI.  rdos_last_error() returns a
+ *     message for the last failing call on a handle (valid until the next
+ *     call on it).
+ *   - The caller owns every host array it passes; the library copies in and
+ *     out and keeps no caller pointer after a call returns.
+ *   - The library owns all device memory of a simulation from
+ *     rdos_finalize() to rdos_destroy().
+ *   - A handle is not thread-safe: use one handle per host thread.
+ *   - Call order is enforced (RDOS_ESTATE otherwise):
+ *       create -> set_mesh -> add_species / add_reaction -> finalize
+ *              -> set_counts -> step / run_until -> get_counts
+ *     set_counts may also be called before finalize (the counts are staged
+ *     on the host and uploaded by finalize).
+ *   - Random numbers: Philox4x32-10 (Salmon et al., SC'11) with key
+ *     (low 32 bits of seed, high 32 bits of seed XOR realization) and counter
+ *     (draw block, stream, tet, low 32 bits of the period index).  Stream m
+ *     is species m's diffusion draws; stream 0x80000000 the tet's SSA draws.
+ *     Results therefore do not depend on launch shape, batching or order.
+ *   - Units: SI.  Coordinates in metres, D in m^2/s, rate constants in
+ *     M/s (0th order), 1/s (1st order), 1/(M s) (2nd order).
+ */
+#ifndef RDOS_H
+#define RDOS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct rdos_sim rdos_sim;
+typedef struct rdos_engine rdos_engine;
+
+typedef enum {
+    RDOS_OK = 0,
+    RDOS_EINVAL = -1,     /* invalid argument or mesh                         */
+    RDOS_ENOMEM = -2,     /* device or host allocation failed                 */
+    RDOS_EDEVICE = -3,    /* a HIP call failed                                */
+    RDOS_ESTATE = -4,     /* call out of order                                */
+    RDOS_EOVERFLOW = -5,  /* a molecule count left the int32 range            */
+    RDOS_EBUSY = -6       /* the simulation is owned by an engine             */
+} rdos_status;
+
+/* Limits of one simulation. */
+#define RDOS_MAX_SPECIES 8
+#define RDOS_MAX_REACTIONS 16
+
+/* New simulation on HIP device `device` with n_realizations independent
+ * realizations (realization r uses Philox key (seed, r)). */
+rdos_status rdos_create(rdos_sim **out, int device, uint64_t seed, int32_t n_realizations);
+
+/* Tetrahedral mesh (Sec. II.A: subvolumes with up to 4 face neighbours).
+ *   xyz        [n_verts][3] vertex coordinates, metres
+ *   tet_verts  [n_tets][4]  vertex ids; face f of a tet is the triangle
+ *                           opposite its local vertex f
+ * Faces on no other tet are reflecting boundaries.  RDOS_EINVAL for ids out
+ * of range, a face shared by more than two tets (detected at finalize), or
+ * a tet of zero volume (detected at finalize). */
+rdos_status rdos_set_mesh(rdos_sim *s, int32_t n_verts, const double *xyz, int32_t n_tets,
+                          const int32_t *tet_verts);
+
+/* A species with diffusion coefficient D >= 0 (0 = immobile). */
+rdos_status rdos_add_species(rdos_sim *s, double D, int32_t *out_id);
+
+/* A mass-action reaction with 0..2 reactants and 0..3 products (species
+ * ids), rate constant k >= 0.  A reactant listed twice is a homodimer
+ * reaction with k[A]^2 kinetics (propensity k N (N-1) / (N_A V)). */
+rdos_status rdos_add_reaction(rdos_sim *s, int32_t n_reac, const int32_t *reac, int32_t n_prod,
+                              const int32_t *prod, double k, int32_t *out_id);
+
+/* Builds the mesh tables on the device and fixes the period
+ *   tau = tau_scale * min over tets t and diffusing species m of 1/(D_m g_t)
+ * (Algorithm 1, "precompute tau"; the local rate is d = D g with
+ * g = sum_f A_f / (V delta_f), delta_f the distance between barycentres).
+ * tau_scale in (0, 1] shortens tau below the paper's upper limit (Sec. II.A).
+ * Writes tau to *out_tau when non-NULL. */
+rdos_status rdos_finalize(rdos_sim *s, double tau_scale, double *out_tau);
+
+/* Counts of one species in one realization, counts[n_tets] >= 0.  Sets the
+ * state at the current period boundary. */
+rdos_status rdos_set_counts(rdos_sim *s, int32_t realization, int32_t species,
+                            const int32_t *counts);
+
+/* Reads counts[n_tets] at the current period boundary (synchronises).
+ * RDOS_EOVERFLOW if any count overflowed since the last check. */
+rdos_status rdos_get_counts(rdos_sim *s, int32_t realization, int32_t species, int32_t *out);
+
+/* Resume support: the period index keys the random streams, so
+ * get_counts + get_time on one handle and set_counts + set_state on a new
+ * one continue bit-identically.  t is the simulated time of period
+ * step_index; full periods after it end at t + i tau. */
+rdos_status rdos_set_state(rdos_sim *s, int64_t step_index, double t);
+rdos_status rdos_get_time(rdos_sim *s, double *t, int64_t *step_index);
+
+/* n full periods of Algorithm 1 (asynchronous on the simulation's stream). */
+rdos_status rdos_step(rdos_sim *s, int64_t n_steps);
+
+/* Runs to t_end; the last period is shortened to end exactly at t_end
+ * (Algorithm 1, Step 1).  Asynchronous. */
+rdos_status rdos_run_until(rdos_sim *s, double t_end);
+
+/* Waits for all queued work; reports RDOS_EOVERFLOW if raised. */
+rdos_status rdos_synchronize(rdos_sim *s);
+
+/* Use a caller-owned HIP stream (e.g. a PyTorch stream) for all work of
+ * this simulation; NULL returns to the library's own stream. */
+rdos_status rdos_set_stream(rdos_sim *s, void *hip_stream);
+
+/* The mesh tables built by finalize, for inspection:
+ * nbr[n_tets][4] (-1 = boundary), w[n_tets][4] direction weights,
+ * g[n_tets] (1/m^2), nav[n_tets] (N_A times volume in litres).
+ * Any pointer may be NULL. */
+rdos_status rdos_get_geometry(rdos_sim *s, int32_t *nbr, double *w, double *g, double *nav);
+
+/* Sizes: tets, species, reactions, realizations; bytes of device memory the
+ * simulation holds (or will hold once finalized). */
+rdos_status rdos_get_info(rdos_sim *s, int32_t *n_tets, int32_t *n_species, int32_t *n_reactions,
+                          int32_t *n_realizations, size_t *device_bytes);
+
+const char *rdos_last_error(const rdos_sim *s);
+void rdos_destroy(rdos_sim *s);
+
+/* ------------------------------------------------------------------------ */
+/* Batching and serving: many simulations advance together, one launch per   */
+/* period for all of them (hipGraph-captured in chunks of periods).          */
+/* ------------------------------------------------------------------------ */
+
+/* An engine on `device` that admits simulations while their device memory
+ * fits in hbm_budget_bytes (0 = 90% of the free device memory). */
+rdos_status rdos_engine_create(rdos_engine **out, int device, size_t hbm_budget_bytes);
+
+/* Queues n_steps full periods of `sim`.  The simulation may be finalized
+ * already or not (then the engine finalizes it with tau_scale on admission,
+ * uploading the counts staged by set_counts).  The engine owns the handle
+ * until rdos_engine_release(); calls on it meanwhile return RDOS_EBUSY. */
+rdos_status rdos_engine_submit(rdos_engine *e, rdos_sim *sim, int64_t n_steps, double tau_scale,
+                               uint64_t *ticket);
+
+/* Non-blocking: *done = 1 once the ticket's periods have all run;
+ * *latency_s = seconds from submit to completion (valid when done). */
+rdos_status rdos_engine_poll(rdos_engine *e, uint64_t ticket, int *done, double *latency_s);
+
+/* Blocks until every submitted ticket is done. */
+rdos_status rdos_engine_drain(rdos_engine *e);
+
+/* Returns a completed simulation to the caller (its device state is kept;
+ * read it with rdos_get_counts, then rdos_destroy it). */
+rdos_status rdos_engine_release(rdos_engine *e, uint64_t ticket, rdos_sim **sim);
+
+/* Engine counters: periods launched, tet-species updates done, seconds the
+ * device was busy. */
+rdos_status rdos_engine_stats(rdos_engine *e, int64_t *launches, double *updates, double *busy_s);
+
+/* Per-kernel timing: when on, chunks are launched directly (not replayed
+ * from the graph) with HIP events between every scan and update launch;
+ * rdos_engine_kernel_times returns the summed milliseconds and launch counts
+ * since profiling was switched on.  Results do not change. */
+rdos_status rdos_engine_set_profiling(rdos_engine *e, int on);
+rdos_status rdos_engine_kernel_times(rdos_engine *e, double *scan_ms, int64_t *scan_launches,
+                                     double *update_ms, int64_t *update_launches);
+
+/* Measures the device's streaming copy bandwidth (read + write bytes per
+ * second / 1e9) with a 16-byte-per-lane copy kernel over `bytes`, `reps`
+ * times.  The same kernel calibrates hardware byte counters. */
+rdos_status rdos_bandwidth_probe(int device, size_t bytes, int reps, double *gbps);
+
+const char *rdos_engine_last_error(const rdos_engine *e);
+void rdos_engine_destroy(rdos_engine *e);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,596 @@
+// Host side of the rdos C ABI: handles, call-order checks, mesh topology,
+// device set-up and the stepping loop (Algorithm 1, Steps 1 and 4).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <array>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <limits>
+#include <string>
+#include <vector>
+
+#include "rdos_internal.h"
+#include "rdos_sim.h"
+
+using namespace rdos;
+
+namespace rdos {
+
+rdos_status fail(rdos_sim *s, rdos_status code, const char *fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    if (s) s->error = buf;
+    return code;
+}
+
+rdos_status hip_fail(rdos_sim *s, hipError_t e, const char *what)
+{
+    return fail(s, e == hipErrorOutOfMemory ? RDOS_ENOMEM : RDOS_EDEVICE, "%s: %s", what,
+                hipGetErrorString(e));
+}
+
+#define HIP_TRY(sim, expr, what)                         \
+    do {                                                 \
+        hipError_t e__ = (expr);                         \
+        if (e__ != hipSuccess) return hip_fail(sim, e__, what); \
+    } while (0)
+
+int64_t padded_tets(int32_t T) { return ((int64_t)T + 3) & ~(int64_t)3; }
+
+size_t state_bytes(const rdos_sim *s)
+{
+    const int64_t Tp = padded_tets(s->T);
+    const size_t counts = (size_t)s->Rz * s->D.size() * (size_t)Tp * sizeof(int32_t);
+    const size_t tiles = (size_t)s->Rz * (size_t)((s->T + kTetsPerTile - 1) / kTetsPerTile) * sizeof(Tile);
+    const size_t queue = (size_t)s->Rz * (size_t)s->T * sizeof(int32_t);
+    return (size_t)s->T * sizeof(MeshRec) + 3 * counts + tiles + queue + sizeof(DevSim) + 72;
+}
+
+// Face matching: each face is keyed by its sorted vertex triple; two tets with
+// the same key are neighbours across it.  A key seen three times is an error.
+rdos_status build_topology(rdos_sim *s, std::vector<int32_t> &nbr)
+{
+    struct FaceKey {
+        int32_t a, b, c;
+        int32_t slot;  // 4 * tet + face
+    };
+    const int32_t T = s->T;
+    std::vector<FaceKey> keys((size_t)T * 4);
+    for (int32_t t = 0; t < T; ++t) {
+        const int32_t *v = &s->tet_verts[4 * (size_t)t];
+        for (int f = 0; f < 4; ++f) {
+            std::array<int32_t, 3> tri;
+            int q = 0;
+            for (int i = 0; i < 4; ++i)
+                if (i != f) tri[q++] = v[i];
+            std::sort(tri.begin(), tri.end());
+            keys[4 * (size_t)t + f] = {tri[0], tri[1], tri[2], 4 * t + f};
+        }
+    }
+    std::sort(keys.begin(), keys.end(), [](const FaceKey &x, const FaceKey &y) {
+        if (x.a != y.a) return x.a < y.a;
+        if (x.b != y.b) return x.b < y.b;
+        if (x.c != y.c) return x.c < y.c;
+        return x.slot < y.slot;
+    });
+    nbr.assign((size_t)T * 4, -1);
+    const size_t nF = keys.size();
+    for (size_t i = 0; i < nF;) {
+        size_t j = i + 1;
+        while (j < nF && keys[j].a == keys[i].a && keys[j].b == keys[i].b && keys[j].c == keys[i].c) ++j;
+        if (j - i > 2)
+            return fail(s, RDOS_EINVAL, "face (%d,%d,%d) is shared by %zu tetrahedra", keys[i].a, keys[i].b,
+                        keys[i].c, j - i);
+        if (j - i == 2) {
+            const int32_t t0 = keys[i].slot / 4, t1 = keys[i + 1].slot / 4;
+            if (t0 == t1) return fail(s, RDOS_EINVAL, "tetrahedron %d repeats a face", t0);
+            nbr[keys[i].slot] = t1;
+            nbr[keys[i + 1].slot] = t0;
+        }
+        i = j;
+    }
+    return RDOS_OK;
+}
+
+rdos_status upload_desc(rdos_sim *s)
+{
+    HIP_TRY(s, hipMemcpyAsync(s->d_desc, &s->desc, sizeof(DevSim), hipMemcpyHostToDevice, s->stream),
+            "upload simulation descriptor");
+    HIP_TRY(s, hipStreamSynchronize(s->stream), "upload simulation descriptor");
+    return RDOS_OK;
+}
+
+rdos_status fold_inflow(rdos_sim *s)
+{
+    if (!s->dirty) return RDOS_OK;
+    const int64_t n = (int64_t)s->Rz * (int64_t)s->D.size() * padded_tets(s->T);
+    int32_t *pending = s->d_inflow[s->step & 1];
+    HIP_TRY(s, launch_materialize(s->d_cnt, pending, n, s->d_flags, s->stream), "fold arrivals");
+    s->dirty = false;
+    return RDOS_OK;
+}
+
+rdos_status check_flags(rdos_sim *s)
+{
+    int32_t flags = 0;
+    HIP_TRY(s, hipMemcpyAsync(&flags, s->d_flags, sizeof flags, hipMemcpyDeviceToHost, s->stream),
+            "read flags");
+    HIP_TRY(s, hipStreamSynchronize(s->stream), "synchronize");
+    if (flags & 1) return fail(s, RDOS_EOVERFLOW, "a molecule count overflowed int32");
+    if (flags & 2)
+        return fail(s, RDOS_EOVERFLOW, "a tet fired more than %u reactions in one period; shorten tau",
+                    kMaxEventsPerPeriod);
+    return RDOS_OK;
+}
+
+rdos_status enqueue_period(rdos_sim *s, int64_t period, int64_t partial, double tau_last)
+{
+    HIP_TRY(s, launch_step(s->d_desc, s->d_tiles, s->n_tiles, period, partial, tau_last, s->d_queue,
+                           (int32_t)((int64_t)s->Rz * s->T), s->d_qcount, (int32_t)(s->launches & 1), 0,
+                           s->update_grid, s->stream),
+            "launch period");
+    s->launches += 1;
+    s->dirty = true;
+    return RDOS_OK;
+}
+
+double time_of(const rdos_sim *s, int64_t k)
+{
+    return s->anchor_t + (double)(k - s->anchor_step) * s->tau;
+}
+
+void free_device(rdos_sim *s)
+{
+    (void)hipSetDevice(s->device);
+    if (s->stream && s->own_stream) (void)hipStreamSynchronize(s->stream);
+    void *ptrs[] = {s->d_mesh, s->d_cnt, s->d_inflow[0], s->d_inflow[1], s->d_flags, s->d_desc, s->d_tiles,
+                    s->d_queue, s->d_qcount};
+    for (void *p : ptrs)
+        if (p) (void)hipFree(p);
+    s->d_mesh = nullptr;
+    s->d_cnt = s->d_inflow[0] = s->d_inflow[1] = s->d_flags = nullptr;
+    s->d_queue = s->d_qcount = nullptr;
+    s->d_desc = nullptr;
+    s->d_tiles = nullptr;
+    if (s->stream && s->own_stream) (void)hipStreamDestroy(s->stream);
+    s->stream = nullptr;
+}
+
+}  // namespace rdos
+
+// ---------------------------------------------------------------------------
+// C ABI
+// ---------------------------------------------------------------------------
+#define CHECK_HANDLE(s)                                   \
+    do {                                                  \
+        if (!(s)) return RDOS_EINVAL;                     \
+        if ((s)->engine_owned) return fail(s, RDOS_EBUSY, "simulation is owned by an engine"); \
+    } while (0)
+
+extern "C" {
+
+rdos_status rdos_create(rdos_sim **out, int device, uint64_t seed, int32_t n_realizations)
+{
+    if (!out) return RDOS_EINVAL;
+    *out = nullptr;
+    if (n_realizations < 1) return RDOS_EINVAL;
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev) return RDOS_EDEVICE;
+    rdos_sim *s = new (std::nothrow) rdos_sim();
+    if (!s) return RDOS_ENOMEM;
+    s->device = device;
+    s->seed = seed;
+    s->Rz = n_realizations;
+    *out = s;
+    return RDOS_OK;
+}
+
+rdos_status rdos_set_mesh(rdos_sim *s, int32_t n_verts, const double *xyz, int32_t n_tets,
+                          const int32_t *tet_verts)
+{
+    CHECK_HANDLE(s);
+    if (s->state != SimState::Created) return fail(s, RDOS_ESTATE, "set_mesh after the mesh was set");
+    if (n_verts < 4 || n_tets < 1 || !xyz || !tet_verts)
+        return fail(s, RDOS_EINVAL, "mesh needs >= 4 vertices and >= 1 tetrahedron");
+    for (int64_t i = 0; i < 3 * (int64_t)n_verts; ++i)
+        if (!std::isfinite(xyz[i])) return fail(s, RDOS_EINVAL, "vertex coordinate %lld is not finite", (long long)i);
+    for (int64_t i = 0; i < 4 * (int64_t)n_tets; ++i)
+        if (tet_verts[i] < 0 || tet_verts[i] >= n_verts)
+            return fail(s, RDOS_EINVAL, "vertex id %d out of range at %lld", tet_verts[i], (long long)i);
+    s->xyz.assign(xyz, xyz + 3 * (size_t)n_verts);
+    s->tet_verts.assign(tet_verts, tet_verts + 4 * (size_t)n_tets);
+    s->n_verts = n_verts;
+    s->T = n_tets;
+    s->state = SimState::Meshed;
+    return RDOS_OK;
+}
+
+rdos_status rdos_add_species(rdos_sim *s, double D, int32_t *out_id)
+{
+    CHECK_HANDLE(s);
+    if (s->state != SimState::Meshed) return fail(s, RDOS_ESTATE, "add_species needs a mesh and no finalize yet");
+    if (!(D >= 0.0) || !std::isfinite(D)) return fail(s, RDOS_EINVAL, "D must be finite and >= 0");
+    if ((int)s->D.size() >= kMaxSpecies) return fail(s, RDOS_EINVAL, "at most %d species", kMaxSpecies);
+    s->D.push_back(D);
+    if (out_id) *out_id = (int32_t)s->D.size() - 1;
+    return RDOS_OK;
+}
+
+rdos_status rdos_add_reaction(rdos_sim *s, int32_t n_reac, const int32_t *reac, int32_t n_prod,
+                              const int32_t *prod, double k, int32_t *out_id)
+{
+    CHECK_HANDLE(s);
+    if (s->state != SimState::Meshed) return fail(s, RDOS_ESTATE, "add_reaction needs a mesh and no finalize yet");
+    if (n_reac < 0 || n_reac > 2 || n_prod < 0 || n_prod > 3)
+        return fail(s, RDOS_EINVAL, "0..2 reactants and 0..3 products");
+    if ((n_reac && !reac) || (n_prod && !prod)) return fail(s, RDOS_EINVAL, "null species list");
+    if (!(k >= 0.0) || !std::isfinite(k)) return fail(s, RDOS_EINVAL, "rate constant must be finite and >= 0");
+    if ((int)s->rx.size() >= kMaxReactions) return fail(s, RDOS_EINVAL, "at most %d reactions", kMaxReactions);
+    Reaction r;
+    r.rn = n_reac;
+    r.pn = n_prod;
+    for (int i = 0; i < n_reac; ++i) {
+        if (reac[i] < 0 || reac[i] >= (int32_t)s->D.size()) return fail(s, RDOS_EINVAL, "reactant id out of range");
+        r.r[i] = reac[i];
+    }
+    for (int i = 0; i < n_prod; ++i) {
+        if (prod[i] < 0 || prod[i] >= (int32_t)s->D.size()) return fail(s, RDOS_EINVAL, "product id out of range");
+        r.p[i] = prod[i];
+    }
+    r.k = k;
+    s->rx.push_back(r);
+    if (out_id) *out_id = (int32_t)s->rx.size() - 1;
+    return RDOS_OK;
+}
+
+rdos_status rdos_finalize(rdos_sim *s, double tau_scale, double *out_tau)
+{
+    CHECK_HANDLE(s);
+    if (s->state != SimState::Meshed) return fail(s, RDOS_ESTATE, "finalize needs a mesh and must run once");
+    if (s->D.empty()) return fail(s, RDOS_EINVAL, "no species");
+    if (!(tau_scale > 0.0 && tau_scale <= 1.0)) return fail(s, RDOS_EINVAL, "tau_scale must be in (0, 1]");
+    for (const Reaction &r : s->rx)
+        for (int i = 0; i < r.pn; ++i)
+            if (r.p[i] >= (int32_t)s->D.size()) return fail(s, RDOS_EINVAL, "product id out of range");
+    std::vector<int32_t> nbr;
+    rdos_status st = build_topology(s, nbr);
+    if (st != RDOS_OK) return st;
+
+    HIP_TRY(s, hipSetDevice(s->device), "set device");
+    if (!s->stream) {
+        HIP_TRY(s, hipStreamCreateWithFlags(&s->stream, hipStreamNonBlocking), "create stream");
+        s->own_stream = true;
+    }
+    const int32_t T = s->T;
+    const int S = (int)s->D.size();
+    const int64_t Tp = padded_tets(T);
+    const size_t count_bytes = (size_t)s->Rz * S * (size_t)Tp * sizeof(int32_t);
+
+    // temporary set-up buffers
+    double *d_xyz = nullptr, *d_vol = nullptr, *d_bc = nullptr, *d_area = nullptr, *d_D = nullptr;
+    int32_t *d_tv = nullptr, *d_nbr = nullptr;
+    unsigned long long *d_tau = nullptr;
+    auto cleanup = [&]() {
+        void *p[] = {d_xyz, d_vol, d_bc, d_area, d_D, d_tv, d_nbr, d_tau};
+        for (void *q : p)
+            if (q) (void)hipFree(q);
+    };
+#define SETUP_TRY(expr, what)            \
+    do {                                 \
+        hipError_t e__ = (expr);         \
+        if (e__ != hipSuccess) {         \
+            cleanup();                   \
+            free_device(s);              \
+            return hip_fail(s, e__, what); \
+        }                                \
+    } while (0)
+    SETUP_TRY(hipMalloc(&s->d_mesh, (size_t)T * sizeof(MeshRec)), "allocate mesh tables");
+    SETUP_TRY(hipMalloc(&s->d_cnt, count_bytes), "allocate counts");
+    SETUP_TRY(hipMalloc(&s->d_inflow[0], count_bytes), "allocate arrivals");
+    SETUP_TRY(hipMalloc(&s->d_inflow[1], count_bytes), "allocate arrivals");
+    SETUP_TRY(hipMalloc(&s->d_flags, 64), "allocate flags");
+    SETUP_TRY(hipMalloc(&s->d_desc, sizeof(DevSim)), "allocate descriptor");
+    SETUP_TRY(hipMalloc(&s->d_queue, (size_t)s->Rz * (size_t)T * sizeof(int32_t)), "allocate queue");
+    SETUP_TRY(hipMalloc(&s->d_qcount, 2 * sizeof(int32_t)), "allocate queue");
+    SETUP_TRY(hipMemsetAsync(s->d_qcount, 0, 2 * sizeof(int32_t), s->stream), "clear queue");
+    SETUP_TRY(hipMalloc(&d_xyz, s->xyz.size() * sizeof(double)), "allocate set-up");
+    SETUP_TRY(hipMalloc(&d_tv, s->tet_verts.size() * sizeof(int32_t)), "allocate set-up");
+    SETUP_TRY(hipMalloc(&d_nbr, nbr.size() * sizeof(int32_t)), "allocate set-up");
+    SETUP_TRY(hipMalloc(&d_vol, (size_t)T * sizeof(double)), "allocate set-up");
+    SETUP_TRY(hipMalloc(&d_bc, (size_t)T * 3 * sizeof(double)), "allocate set-up");
+    SETUP_TRY(hipMalloc(&d_area, (size_t)T * 4 * sizeof(double)), "allocate set-up");
+    SETUP_TRY(hipMalloc(&d_D, (size_t)S * sizeof(double)), "allocate set-up");
+    SETUP_TRY(hipMalloc(&d_tau, sizeof(unsigned long long) + 8), "allocate set-up");
+    SETUP_TRY(hipMemsetAsync(s->d_cnt, 0, count_bytes, s->stream), "clear counts");
+    SETUP_TRY(hipMemsetAsync(s->d_inflow[0], 0, count_bytes, s->stream), "clear arrivals");
+    SETUP_TRY(hipMemsetAsync(s->d_inflow[1], 0, count_bytes, s->stream), "clear arrivals");
+    SETUP_TRY(hipMemsetAsync(s->d_flags, 0, 64, s->stream), "clear flags");
+    SETUP_TRY(hipMemsetAsync(d_tau, 0xff, sizeof(unsigned long long), s->stream), "clear tau");
+    SETUP_TRY(hipMemcpyAsync(d_xyz, s->xyz.data(), s->xyz.size() * sizeof(double), hipMemcpyHostToDevice, s->stream),
+              "upload vertices");
+    SETUP_TRY(hipMemcpyAsync(d_tv, s->tet_verts.data(), s->tet_verts.size() * sizeof(int32_t), hipMemcpyHostToDevice,
+                             s->stream),
+              "upload tetrahedra");
+    SETUP_TRY(hipMemcpyAsync(d_nbr, nbr.data(), nbr.size() * sizeof(int32_t), hipMemcpyHostToDevice, s->stream),
+              "upload neighbours");
+    SETUP_TRY(hipMemcpyAsync(d_D, s->D.data(), (size_t)S * sizeof(double), hipMemcpyHostToDevice, s->stream),
+              "upload D");
+    SETUP_TRY(launch_geometry(d_xyz, d_tv, d_nbr, T, d_vol, d_bc, d_area, s->d_mesh, s->d_flags + 1, s->stream),
+              "geometry");
+    SETUP_TRY(launch_tau_min(s->d_mesh, T, d_D, S, d_tau, s->stream), "tau");
+    unsigned long long tau_bits = 0;
+    int32_t bad[2] = {0, 0};
+    SETUP_TRY(hipMemcpyAsync(&tau_bits, d_tau, sizeof tau_bits, hipMemcpyDeviceToHost, s->stream), "read tau");
+    SETUP_TRY(hipMemcpyAsync(bad, s->d_flags, sizeof bad, hipMemcpyDeviceToHost, s->stream), "read flags");
+    SETUP_TRY(hipStreamSynchronize(s->stream), "set-up");
+    SETUP_TRY(hipMemsetAsync(s->d_flags, 0, 64, s->stream), "clear flags");
+    cleanup();
+#undef SETUP_TRY
+    if (bad[1]) {
+        free_device(s);
+        return fail(s, RDOS_EINVAL, "degenerate tetrahedron (zero volume)");
+    }
+    if (tau_bits == ~0ull) {
+        free_device(s);
+        return fail(s, RDOS_EINVAL, "no diffusing species on a connected tetrahedron: tau is undefined");
+    }
+    double tmin;
+    std::memcpy(&tmin, &tau_bits, sizeof tmin);
+    s->tau = tau_scale * tmin;
+
+    // kernel-side description
+    DevSim &d = s->desc;
+    std::memset(&d, 0, sizeof d);
+    d.mesh = s->d_mesh;
+    d.cnt = s->d_cnt;
+    d.inflow[0] = s->d_inflow[0];
+    d.inflow[1] = s->d_inflow[1];
+    d.flags = s->d_flags;
+    d.T = T;
+    d.S = S;
+    d.R = (int32_t)s->rx.size();
+    d.Rz = s->Rz;
+    d.key0 = (uint32_t)s->seed;
+    d.key1 = (uint32_t)(s->seed >> 32);
+    d.tau = s->tau;
+    d.step0 = 0;
+    d.step_end = std::numeric_limits<int64_t>::max();
+    for (int m = 0; m < S; ++m) {
+        d.D[m] = s->D[m];
+        if (s->D[m] > 0.0) d.diff_mask |= 1u << m;
+    }
+    for (size_t q = 0; q < s->rx.size(); ++q) {
+        const Reaction &r = s->rx[q];
+        d.rn[q] = r.rn;
+        d.pn[q] = r.pn;
+        d.r0[q] = r.rn > 0 ? r.r[0] : -1;
+        d.r1[q] = r.rn > 1 ? r.r[1] : -1;
+        d.p0[q] = r.pn > 0 ? r.p[0] : -1;
+        d.p1[q] = r.pn > 1 ? r.p[1] : -1;
+        d.p2[q] = r.pn > 2 ? r.p[2] : -1;
+        uint32_t inv = 0;
+        for (int i = 0; i < r.rn; ++i) inv |= 1u << r.r[i];
+        for (int i = 0; i < r.pn; ++i) inv |= 1u << r.p[i];
+        d.involved[q] = inv;
+        d.k[q] = r.k;
+        if (r.rn == 0) d.zeroth = 1;
+    }
+    // work list: one tile per 1024 tets of each realization
+    std::vector<Tile> tiles;
+    for (int32_t r = 0; r < s->Rz; ++r)
+        for (int32_t t0 = 0; t0 < T; t0 += kTetsPerTile)
+            tiles.push_back({0, r, t0, std::min<int32_t>(kTetsPerTile, T - t0)});
+    s->n_tiles = (int32_t)tiles.size();
+    hipError_t e = hipMalloc(&s->d_tiles, tiles.size() * sizeof(Tile));
+    if (e != hipSuccess) {
+        free_device(s);
+        return hip_fail(s, e, "allocate work list");
+    }
+    e = hipMemcpyAsync(s->d_tiles, tiles.data(), tiles.size() * sizeof(Tile), hipMemcpyHostToDevice, s->stream);
+    if (e != hipSuccess) {
+        free_device(s);
+        return hip_fail(s, e, "upload work list");
+    }
+    st = upload_desc(s);
+    if (st != RDOS_OK) {
+        free_device(s);
+        return st;
+    }
+    s->state = SimState::Ready;
+    s->step = 0;
+    s->anchor_step = 0;
+    s->anchor_t = 0.0;
+    s->dirty = false;
+    // counts staged before finalize
+    for (auto &kv : s->staged) {
+        const int32_t r = kv.first / kMaxSpecies, m = kv.first % kMaxSpecies;
+        int32_t *dst = s->d_cnt + ((int64_t)r * S + m) * Tp;
+        HIP_TRY(s, hipMemcpyAsync(dst, kv.second.data(), (size_t)T * sizeof(int32_t), hipMemcpyHostToDevice, s->stream),
+                "upload counts");
+    }
+    HIP_TRY(s, hipStreamSynchronize(s->stream), "upload counts");
+    s->staged.clear();
+    s->xyz.clear();
+    s->xyz.shrink_to_fit();
+    if (out_tau) *out_tau = s->tau;
+    return RDOS_OK;
+}
+
+rdos_status rdos_set_counts(rdos_sim *s, int32_t realization, int32_t species, const int32_t *counts)
+{
+    CHECK_HANDLE(s);
+    if (s->state == SimState::Created) return fail(s, RDOS_ESTATE, "set_counts needs a mesh");
+    if (realization < 0 || realization >= s->Rz || species < 0 || species >= (int32_t)s->D.size() || !counts)
+        return fail(s, RDOS_EINVAL, "realization or species out of range");
+    int64_t total = 0;
+    for (int32_t t = 0; t < s->T; ++t) {
+        if (counts[t] < 0) return fail(s, RDOS_EINVAL, "negative count at tet %d", t);
+        total += counts[t];
+    }
+    if (total > 0x3fffffff) return fail(s, RDOS_EOVERFLOW, "more than 2^30 molecules of one species");
+    if ((int64_t)s->Rz * s->T > 0x7fffffff) return fail(s, RDOS_EINVAL, "realizations x tets exceeds 2^31");
+    if (s->state == SimState::Meshed) {
+        s->staged[realization * kMaxSpecies + species].assign(counts, counts + s->T);
+        return RDOS_OK;
+    }
+    HIP_TRY(s, hipSetDevice(s->device), "set device");
+    rdos_status st = fold_inflow(s);
+    if (st != RDOS_OK) return st;
+    int32_t *dst = s->d_cnt + ((int64_t)realization * (int64_t)s->D.size() + species) * padded_tets(s->T);
+    HIP_TRY(s, hipMemcpyAsync(dst, counts, (size_t)s->T * sizeof(int32_t), hipMemcpyHostToDevice, s->stream),
+            "upload counts");
+    HIP_TRY(s, hipStreamSynchronize(s->stream), "upload counts");
+    return RDOS_OK;
+}
+
+rdos_status rdos_get_counts(rdos_sim *s, int32_t realization, int32_t species, int32_t *out)
+{
+    CHECK_HANDLE(s);
+    if (s->state != SimState::Ready) return fail(s, RDOS_ESTATE, "get_counts before finalize");
+    if (realization < 0 || realization >= s->Rz || species < 0 || species >= (int32_t)s->D.size() || !out)
+        return fail(s, RDOS_EINVAL, "realization or species out of range");
+    HIP_TRY(s, hipSetDevice(s->device), "set device");
+    rdos_status st = fold_inflow(s);
+    if (st != RDOS_OK) return st;
+    const int32_t *src = s->d_cnt + ((int64_t)realization * (int64_t)s->D.size() + species) * padded_tets(s->T);
+    HIP_TRY(s, hipMemcpyAsync(out, src, (size_t)s->T * sizeof(int32_t), hipMemcpyDeviceToHost, s->stream),
+            "download counts");
+    return check_flags(s);
+}
+
+rdos_status rdos_set_state(rdos_sim *s, int64_t step_index, double t)
+{
+    CHECK_HANDLE(s);
+    if (s->state != SimState::Ready) return fail(s, RDOS_ESTATE, "set_state before finalize");
+    if (step_index < 0 || !std::isfinite(t)) return fail(s, RDOS_EINVAL, "bad state");
+    HIP_TRY(s, hipSetDevice(s->device), "set device");
+    rdos_status st = fold_inflow(s);  // pending arrivals belong to the old index's parity
+    if (st != RDOS_OK) return st;
+    HIP_TRY(s, hipStreamSynchronize(s->stream), "set state");
+    s->step = step_index;
+    s->anchor_step = step_index;
+    s->anchor_t = t;
+    return RDOS_OK;
+}
+
+rdos_status rdos_get_time(rdos_sim *s, double *t, int64_t *step_index)
+{
+    if (!s) return RDOS_EINVAL;
+    if (t) *t = time_of(s, s->step);
+    if (step_index) *step_index = s->step;
+    return RDOS_OK;
+}
+
+rdos_status rdos_step(rdos_sim *s, int64_t n_steps)
+{
+    CHECK_HANDLE(s);
+    if (s->state != SimState::Ready) return fail(s, RDOS_ESTATE, "step before finalize");
+    if (n_steps < 0) return fail(s, RDOS_EINVAL, "negative step count");
+    HIP_TRY(s, hipSetDevice(s->device), "set device");
+    for (int64_t i = 0; i < n_steps; ++i) {
+        rdos_status st = enqueue_period(s, s->step, -1, 0.0);
+        if (st != RDOS_OK) return st;
+        s->step += 1;
+    }
+    return RDOS_OK;
+}
+
+rdos_status rdos_run_until(rdos_sim *s, double t_end)
+{
+    CHECK_HANDLE(s);
+    if (s->state != SimState::Ready) return fail(s, RDOS_ESTATE, "run_until before finalize");
+    if (!std::isfinite(t_end)) return fail(s, RDOS_EINVAL, "t_end must be finite");
+    HIP_TRY(s, hipSetDevice(s->device), "set device");
+    for (;;) {
+        const double t = time_of(s, s->step);
+        if (t >= t_end) return RDOS_OK;
+        if (t + s->tau > t_end) {  // Step 1: the last period ends at t_end
+            rdos_status st = enqueue_period(s, s->step, s->step, t_end - t);
+            if (st != RDOS_OK) return st;
+            s->step += 1;
+            s->anchor_step = s->step;
+            s->anchor_t = t_end;
+            return RDOS_OK;
+        }
+        rdos_status st = enqueue_period(s, s->step, -1, 0.0);
+        if (st != RDOS_OK) return st;
+        s->step += 1;
+    }
+}
+
+rdos_status rdos_synchronize(rdos_sim *s)
+{
+    CHECK_HANDLE(s);
+    if (s->state != SimState::Ready) return RDOS_OK;
+    HIP_TRY(s, hipSetDevice(s->device), "set device");
+    return check_flags(s);
+}
+
+rdos_status rdos_set_stream(rdos_sim *s, void *hip_stream)
+{
+    CHECK_HANDLE(s);
+    HIP_TRY(s, hipSetDevice(s->device), "set device");
+    if (s->stream) HIP_TRY(s, hipStreamSynchronize(s->stream), "drain old stream");
+    if (s->stream && s->own_stream) (void)hipStreamDestroy(s->stream);
+    if (hip_stream) {
+        s->stream = (hipStream_t)hip_stream;
+        s->own_stream = false;
+    } else if (s->state == SimState::Ready) {
+        HIP_TRY(s, hipStreamCreateWithFlags(&s->stream, hipStreamNonBlocking), "create stream");
+        s->own_stream = true;
+    } else {
+        s->stream = nullptr;
+        s->own_stream = false;
+    }
+    return RDOS_OK;
+}
+
+rdos_status rdos_get_geometry(rdos_sim *s, int32_t *nbr, double *w, double *g, double *nav)
+{
+    if (!s) return RDOS_EINVAL;
+    if (s->state != SimState::Ready) return fail(s, RDOS_ESTATE, "get_geometry before finalize");
+    HIP_TRY(s, hipSetDevice(s->device), "set device");
+    std::vector<MeshRec> m((size_t)s->T);
+    HIP_TRY(s, hipMemcpyAsync(m.data(), s->d_mesh, m.size() * sizeof(MeshRec), hipMemcpyDeviceToHost, s->stream),
+            "download mesh tables");
+    HIP_TRY(s, hipStreamSynchronize(s->stream), "download mesh tables");
+    for (int32_t t = 0; t < s->T; ++t) {
+        for (int f = 0; f < 4; ++f) {
+            if (nbr) nbr[4 * (size_t)t + f] = m[t].nbr[f];
+            if (w) w[4 * (size_t)t + f] = m[t].w[f];
+        }
+        if (g) g[t] = m[t].g;
+        if (nav) nav[t] = m[t].nav;
+    }
+    return RDOS_OK;
+}
+
+rdos_status rdos_get_info(rdos_sim *s, int32_t *n_tets, int32_t *n_species, int32_t *n_reactions,
+                          int32_t *n_realizations, size_t *device_bytes)
+{
+    if (!s) return RDOS_EINVAL;
+    if (n_tets) *n_tets = s->T;
+    if (n_species) *n_species = (int32_t)s->D.size();
+    if (n_reactions) *n_reactions = (int32_t)s->rx.size();
+    if (n_realizations) *n_realizations = s->Rz;
+    if (device_bytes) *device_bytes = state_bytes(s);
+    return RDOS_OK;
+}
+
+const char *rdos_last_error(const rdos_sim *s) { return s ? s->error.c_str() : "null handle"; }
+
+void rdos_destroy(rdos_sim *s)
+{
+    if (!s) return;
+    free_device(s);
+    delete s;
+}
+
+}  // extern "C"

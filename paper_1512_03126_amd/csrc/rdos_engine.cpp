@@ -1,0 +1,600 @@
+// Batching and serving engine: every admitted simulation ("slot") advances
+// one of its own periods per launch pair, all slots in the same launches.
+// Chunks of periods are captured once into a hipGraph and replayed; the
+// graph is rebuilt only when the set of slots changes.  A worker thread
+// admits queued simulations while their device memory fits the budget and
+// retires slots as soon as their periods are done, so requests that arrive
+// while others run join the next chunk (continuous batching).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <condition_variable>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <deque>
+#include <map>
+#include <mutex>
+#include <string>
+#include <thread>
+#include <vector>
+
+#include "rdos_internal.h"
+#include "rdos_sim.h"
+
+using namespace rdos;
+using Clock = std::chrono::steady_clock;
+
+namespace {
+
+struct Ticket {
+    rdos_sim *sim = nullptr;
+    int64_t n_steps = 0;
+    double tau_scale = 1.0;
+    Clock::time_point submitted;
+    Clock::time_point finished;
+    bool admitted = false;
+    bool done = false;
+    bool failed = false;
+    size_t bytes = 0;
+    int64_t end_step = 0;  // the simulation's period index when done
+    std::string error;
+};
+
+// Launch-shape choices the tuner tries on live work (results do not depend on them).
+struct Shape {
+    int32_t chunk;        // periods per graph replay (even: the queue slots alternate)
+    int32_t update_grid;  // blocks of the update launch
+};
+
+}  // namespace
+
+struct rdos_engine {
+    int device = 0;
+    size_t budget = 0;
+    size_t used = 0;
+    hipStream_t stream = nullptr;
+    std::string error;
+
+    std::mutex mu;
+    std::condition_variable cv_work;  // wakes the worker
+    std::condition_variable cv_done;  // wakes drain()
+    std::thread worker;
+    bool stop = false;
+    bool worker_dead = false;  // the worker left its loop after a device error
+    bool stalled = false;      // nothing runs and the next request does not fit the budget
+
+    uint64_t next_ticket = 1;
+    std::map<uint64_t, Ticket> tickets;
+    std::deque<uint64_t> waiting;  // submitted, not admitted (FIFO)
+    std::vector<uint64_t> slots;   // admitted and running
+
+    // device work list of the current slot set
+    DevSim *d_sims = nullptr;
+    int32_t cap_sims = 0;
+    Tile *d_tiles = nullptr;
+    int64_t cap_tiles = 0;
+    int32_t *d_queue = nullptr;
+    int64_t cap_queue = 0;
+    int32_t *d_qcount = nullptr;
+    int64_t queue_len = 0;  // tets in the current work list (the queue never holds more)
+    int32_t n_tiles = 0;
+    hipGraphExec_t graph = nullptr;
+    Shape graph_shape{0, 0};
+    bool rebuild = true;
+
+    // tuner: candidates tried in turn on each new slot set, best kept
+    std::vector<Shape> candidates;
+    size_t trial = 0;
+    double best_rate = -1.0;
+    Shape best{16, 1024};
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+
+    // tuned shape per work-list signature (tiles, tets)
+    std::map<std::pair<int64_t, int64_t>, Shape> tuned;
+
+    // per-kernel timing: event nodes around every scan and update launch
+    bool profiling = false;
+    std::vector<hipEvent_t> kev;  // 2 * chunk + 1 events of the captured graph
+    double scan_ms = 0.0, update_ms = 0.0;
+    int64_t scan_n = 0, update_n = 0;
+
+    // stats
+    int64_t launches = 0;
+    double updates = 0.0;
+    double busy_s = 0.0;
+};
+
+namespace {
+
+rdos_status efail(rdos_engine *e, rdos_status code, const char *fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    e->error = buf;
+    return code;
+}
+
+#define ENGINE_HIP(e, expr, what)                                                                    \
+    do {                                                                                             \
+        hipError_t err__ = (expr);                                                                   \
+        if (err__ != hipSuccess)                                                                     \
+            return efail(e, err__ == hipErrorOutOfMemory ? RDOS_ENOMEM : RDOS_EDEVICE, "%s: %s", what, \
+                         hipGetErrorString(err__));                                                  \
+    } while (0)
+
+template <typename T>
+rdos_status ensure(rdos_engine *e, T **buf, int64_t *cap, int64_t need, const char *what)
+{
+    if (need <= *cap) return RDOS_OK;
+    if (*buf) (void)hipFree(*buf);
+    *buf = nullptr;
+    const int64_t n = std::max<int64_t>(need, *cap * 2);
+    ENGINE_HIP(e, hipMalloc(buf, (size_t)n * sizeof(T)), what);
+    *cap = n;
+    return RDOS_OK;
+}
+
+// Builds the device work list for the current slots (under the lock).
+rdos_status build_work(rdos_engine *e)
+{
+    std::vector<DevSim> sims;
+    std::vector<Tile> tiles;
+    int64_t queue_need = 0;
+    for (size_t i = 0; i < e->slots.size(); ++i) {
+        Ticket &tk = e->tickets[e->slots[i]];
+        rdos_sim *s = tk.sim;
+        DevSim d = s->desc;
+        d.step0 = s->step;
+        d.step_end = tk.end_step;
+        sims.push_back(d);
+        for (int32_t r = 0; r < s->Rz; ++r)
+            for (int32_t t0 = 0; t0 < s->T; t0 += kTetsPerTile)
+                tiles.push_back({(int32_t)i, r, t0, std::min<int32_t>(kTetsPerTile, s->T - t0)});
+        queue_need += (int64_t)s->Rz * s->T;
+    }
+    int64_t cap_sims = e->cap_sims;
+    rdos_status st = ensure(e, &e->d_sims, &cap_sims, (int64_t)std::max<size_t>(sims.size(), 1), "engine slots");
+    if (st != RDOS_OK) return st;
+    e->cap_sims = (int32_t)cap_sims;
+    st = ensure(e, &e->d_tiles, &e->cap_tiles, (int64_t)std::max<size_t>(tiles.size(), 1), "engine tiles");
+    if (st != RDOS_OK) return st;
+    st = ensure(e, &e->d_queue, &e->cap_queue, std::max<int64_t>(queue_need, 1), "engine queue");
+    if (st != RDOS_OK) return st;
+    if (!sims.empty())
+        ENGINE_HIP(e, hipMemcpyAsync(e->d_sims, sims.data(), sims.size() * sizeof(DevSim), hipMemcpyHostToDevice,
+                                     e->stream),
+                   "upload slots");
+    if (!tiles.empty())
+        ENGINE_HIP(e, hipMemcpyAsync(e->d_tiles, tiles.data(), tiles.size() * sizeof(Tile), hipMemcpyHostToDevice,
+                                     e->stream),
+                   "upload tiles");
+    ENGINE_HIP(e, hipStreamSynchronize(e->stream), "upload work list");
+    e->n_tiles = (int32_t)tiles.size();
+    e->queue_len = queue_need;
+    return RDOS_OK;
+}
+
+// The launches of one chunk: a scan and an update launch per period, then
+// one launch that moves every slot's period index on by the chunk length.
+// With `timed`, events separate every launch (direct launches only: event
+// records are not captured into the graph).
+hipError_t enqueue_chunk(rdos_engine *e, const Shape &sh, bool timed)
+{
+    hipError_t err = hipSuccess;
+    if (timed) err = hipEventRecord(e->kev[0], e->stream);
+    for (int32_t i = 0; i < sh.chunk && err == hipSuccess; ++i) {
+        err = launch_scan(e->d_sims, e->d_tiles, e->n_tiles, i, e->d_queue, (int32_t)e->queue_len, e->d_qcount,
+                          i & 1, 0, e->stream);
+        if (err == hipSuccess && timed) err = hipEventRecord(e->kev[2 * i + 1], e->stream);
+        if (err == hipSuccess)
+            err = launch_update(e->d_sims, e->d_tiles, i, -1, 0.0, e->d_queue, (int32_t)e->queue_len, e->d_qcount,
+                                i & 1, sh.update_grid, e->stream);
+        if (err == hipSuccess && timed) err = hipEventRecord(e->kev[2 * i + 2], e->stream);
+    }
+    if (err == hipSuccess) err = launch_advance(e->d_sims, (int32_t)e->slots.size(), sh.chunk, e->stream);
+    return err;
+}
+
+rdos_status capture(rdos_engine *e, const Shape &sh)
+{
+    if (e->graph) {
+        (void)hipGraphExecDestroy(e->graph);
+        e->graph = nullptr;
+    }
+    hipGraph_t g = nullptr;
+    ENGINE_HIP(e, hipStreamBeginCapture(e->stream, hipStreamCaptureModeThreadLocal), "begin capture");
+    hipError_t err = enqueue_chunk(e, sh, false);
+    hipError_t err2 = hipStreamEndCapture(e->stream, &g);
+    if (err != hipSuccess || err2 != hipSuccess) {
+        if (g) (void)hipGraphDestroy(g);
+        return efail(e, RDOS_EDEVICE, "capture: %s", hipGetErrorString(err != hipSuccess ? err : err2));
+    }
+    err = hipGraphInstantiate(&e->graph, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (err != hipSuccess) return efail(e, RDOS_EDEVICE, "instantiate: %s", hipGetErrorString(err));
+    e->graph_shape = sh;
+    return RDOS_OK;
+}
+
+double slot_updates(const rdos_sim *s) { return (double)s->Rz * (double)s->T * (double)s->D.size(); }
+
+// Admits queued tickets while they fit (called by the worker, lock held for
+// bookkeeping; finalize runs with the lock released).
+void admit(rdos_engine *e, std::unique_lock<std::mutex> &lk)
+{
+    while (!e->waiting.empty()) {
+        const uint64_t id = e->waiting.front();
+        Ticket &tk = e->tickets[id];
+        if (e->used + tk.bytes > e->budget) break;  // FIFO: later requests wait too
+        // queue entries are int32 (tile * kTetsPerTile + offset): keep the work list below 2^31 tets
+        int64_t tiled = 0;
+        for (uint64_t sid : e->slots) {
+            const rdos_sim *q = e->tickets[sid].sim;
+            tiled += (int64_t)q->Rz * ((q->T + kTetsPerTile - 1) / kTetsPerTile) * kTetsPerTile;
+        }
+        tiled += (int64_t)tk.sim->Rz * ((tk.sim->T + kTetsPerTile - 1) / kTetsPerTile) * kTetsPerTile;
+        if (tiled > 0x7fffffff && !e->slots.empty()) break;
+        e->waiting.pop_front();
+        e->used += tk.bytes;
+        rdos_sim *s = tk.sim;
+        bool ok = true;
+        std::string err;
+        if (s->state != SimState::Ready) {
+            lk.unlock();
+            s->engine_owned = false;
+            const rdos_status st = rdos_finalize(s, tk.tau_scale, nullptr);
+            s->engine_owned = true;
+            lk.lock();
+            if (st != RDOS_OK) {
+                ok = false;
+                err = s->error;
+            }
+        }
+        if (ok) {
+            // pending arrivals of direct stepping belong to this index's parity, which the
+            // engine keeps; nothing to fold
+            tk.end_step = s->step + tk.n_steps;
+            if (tk.n_steps == 0) {
+                tk.done = true;
+                tk.finished = Clock::now();
+                e->cv_done.notify_all();
+            } else {
+                tk.admitted = true;
+                e->slots.push_back(id);
+                e->rebuild = true;
+            }
+        } else {
+            tk.failed = tk.done = true;
+            tk.error = err;
+            tk.finished = Clock::now();
+            e->used -= tk.bytes;
+            e->cv_done.notify_all();
+        }
+    }
+}
+
+void worker_main(rdos_engine *e)
+{
+    (void)hipSetDevice(e->device);
+    std::unique_lock<std::mutex> lk(e->mu);
+    while (!e->stop) {
+        admit(e, lk);
+        if (e->slots.empty()) {
+            // idle, or blocked by simulations that finished but were not released yet
+            e->stalled = !e->waiting.empty();
+            if (e->stalled) e->cv_done.notify_all();
+            e->cv_work.wait(lk);
+            continue;
+        }
+        e->stalled = false;
+        if (e->rebuild) {
+            if (build_work(e) != RDOS_OK) break;
+            auto hit = e->tuned.find({e->n_tiles, e->queue_len});
+            if (hit != e->tuned.end()) {
+                e->best = hit->second;
+                e->trial = e->candidates.size();
+            } else {
+                e->trial = 0;
+                e->best_rate = -1.0;
+            }
+            e->rebuild = false;
+            if (e->graph) {
+                (void)hipGraphExecDestroy(e->graph);
+                e->graph = nullptr;
+            }
+        }
+        // the tuner tries each candidate once per slot set, then keeps the best
+        Shape sh = e->trial < e->candidates.size() ? e->candidates[e->trial] : e->best;
+        const bool timed = e->profiling;
+        if (timed) {
+            bool ok = true;
+            while (ok && (int32_t)e->kev.size() < 2 * sh.chunk + 1) {
+                hipEvent_t ev;
+                ok = hipEventCreate(&ev) == hipSuccess;
+                if (ok) e->kev.push_back(ev);
+            }
+            if (!ok) {
+                e->error = "create profiling events";
+                break;
+            }
+        } else if (!e->graph || sh.chunk != e->graph_shape.chunk || sh.update_grid != e->graph_shape.update_grid) {
+            if (capture(e, sh) != RDOS_OK) break;
+        }
+        double work = 0.0;
+        for (uint64_t id : e->slots) {
+            Ticket &tk = e->tickets[id];
+            const int64_t left = tk.end_step - tk.sim->step;
+            work += slot_updates(tk.sim) * (double)std::min<int64_t>(left, sh.chunk);
+        }
+        lk.unlock();
+        hipError_t err = hipEventRecord(e->ev0, e->stream);
+        if (err == hipSuccess) err = timed ? enqueue_chunk(e, sh, true) : hipGraphLaunch(e->graph, e->stream);
+        if (err == hipSuccess) err = hipEventRecord(e->ev1, e->stream);
+        if (err == hipSuccess) err = hipEventSynchronize(e->ev1);
+        float ms = 0.f;
+        if (err == hipSuccess) err = hipEventElapsedTime(&ms, e->ev0, e->ev1);
+        lk.lock();
+        if (err != hipSuccess) {
+            e->error = std::string("chunk: ") + hipGetErrorString(err);
+            for (uint64_t id : e->slots) {
+                Ticket &tk = e->tickets[id];
+                tk.failed = tk.done = true;
+                tk.error = e->error;
+                tk.finished = Clock::now();
+            }
+            e->slots.clear();
+            e->cv_done.notify_all();
+            break;
+        }
+        if (timed) {
+            for (int32_t i = 0; i < sh.chunk; ++i) {
+                float a = 0.f, b = 0.f;
+                if (hipEventElapsedTime(&a, e->kev[2 * i], e->kev[2 * i + 1]) == hipSuccess &&
+                    hipEventElapsedTime(&b, e->kev[2 * i + 1], e->kev[2 * i + 2]) == hipSuccess) {
+                    e->scan_ms += a;
+                    e->update_ms += b;
+                    ++e->scan_n;
+                    ++e->update_n;
+                }
+            }
+        }
+        const double rate = ms > 0.f ? work / (double)ms : 0.0;
+        if (e->trial < e->candidates.size()) {
+            if (rate > e->best_rate) {
+                e->best_rate = rate;
+                e->best = sh;
+            }
+            ++e->trial;
+            if (e->trial == e->candidates.size()) e->tuned[{e->n_tiles, e->queue_len}] = e->best;
+        }
+        e->launches += sh.chunk;
+        e->updates += work;
+        e->busy_s += ms * 1e-3;
+        // progress and retirement
+        const auto now = Clock::now();
+        std::vector<uint64_t> keep;
+        for (uint64_t id : e->slots) {
+            Ticket &tk = e->tickets[id];
+            rdos_sim *s = tk.sim;
+            s->step = std::min<int64_t>(s->step + sh.chunk, tk.end_step);
+            s->dirty = true;
+            if (s->step >= tk.end_step) {
+                tk.done = true;
+                tk.finished = now;
+                e->rebuild = true;
+            } else {
+                keep.push_back(id);
+            }
+        }
+        if (keep.size() != e->slots.size()) e->cv_done.notify_all();
+        e->slots.swap(keep);
+    }
+    e->worker_dead = !e->stop;
+    e->cv_done.notify_all();
+}
+
+}  // namespace
+
+extern "C" {
+
+rdos_status rdos_engine_create(rdos_engine **out, int device, size_t hbm_budget_bytes)
+{
+    if (!out) return RDOS_EINVAL;
+    *out = nullptr;
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev) return RDOS_EDEVICE;
+    if (hipSetDevice(device) != hipSuccess) return RDOS_EDEVICE;
+    rdos_engine *e = new (std::nothrow) rdos_engine();
+    if (!e) return RDOS_ENOMEM;
+    e->device = device;
+    size_t free_b = 0, total_b = 0;
+    if (hipMemGetInfo(&free_b, &total_b) != hipSuccess) {
+        delete e;
+        return RDOS_EDEVICE;
+    }
+    e->budget = hbm_budget_bytes ? hbm_budget_bytes : (size_t)(0.9 * (double)free_b);
+    if (hipStreamCreateWithFlags(&e->stream, hipStreamNonBlocking) != hipSuccess ||
+        hipEventCreate(&e->ev0) != hipSuccess || hipEventCreate(&e->ev1) != hipSuccess ||
+        hipMalloc(&e->d_qcount, 2 * sizeof(int32_t)) != hipSuccess ||
+        hipMemsetAsync(e->d_qcount, 0, 2 * sizeof(int32_t), e->stream) != hipSuccess ||
+        hipStreamSynchronize(e->stream) != hipSuccess) {
+        delete e;
+        return RDOS_EDEVICE;
+    }
+    e->candidates = {{16, 1024}, {16, 2048}, {16, 4096}, {32, 2048}};
+    e->worker = std::thread(worker_main, e);
+    *out = e;
+    return RDOS_OK;
+}
+
+rdos_status rdos_engine_submit(rdos_engine *e, rdos_sim *sim, int64_t n_steps, double tau_scale, uint64_t *ticket)
+{
+    if (!e || !sim || n_steps < 0) return RDOS_EINVAL;
+    if (sim->engine_owned) return efail(e, RDOS_EBUSY, "simulation already owned by an engine");
+    if (sim->state == SimState::Created) return efail(e, RDOS_ESTATE, "simulation has no mesh");
+    if (sim->D.empty()) return efail(e, RDOS_ESTATE, "simulation has no species");
+    if (sim->state == SimState::Ready && sim->device != e->device)
+        return efail(e, RDOS_EINVAL, "simulation lives on another device");
+    if (!(tau_scale > 0.0 && tau_scale <= 1.0)) return efail(e, RDOS_EINVAL, "tau_scale must be in (0, 1]");
+    const size_t bytes = state_bytes(sim);
+    if ((int64_t)sim->Rz * ((sim->T + kTetsPerTile - 1) / kTetsPerTile) * kTetsPerTile > 0x7fffffff)
+        return efail(e, RDOS_EINVAL, "realizations x tets exceeds 2^31");
+    std::lock_guard<std::mutex> g(e->mu);
+    if (bytes > e->budget) return efail(e, RDOS_ENOMEM, "simulation needs %zu bytes, budget is %zu", bytes, e->budget);
+    sim->engine_owned = true;
+    sim->device = e->device;
+    const uint64_t id = e->next_ticket++;
+    Ticket &tk = e->tickets[id];
+    tk.sim = sim;
+    tk.n_steps = n_steps;
+    tk.tau_scale = tau_scale;
+    tk.bytes = bytes;
+    tk.submitted = Clock::now();
+    e->waiting.push_back(id);
+    if (ticket) *ticket = id;
+    e->cv_work.notify_all();
+    return RDOS_OK;
+}
+
+rdos_status rdos_engine_poll(rdos_engine *e, uint64_t ticket, int *done, double *latency_s)
+{
+    if (!e) return RDOS_EINVAL;
+    std::lock_guard<std::mutex> g(e->mu);
+    auto it = e->tickets.find(ticket);
+    if (it == e->tickets.end()) return efail(e, RDOS_EINVAL, "unknown ticket %llu", (unsigned long long)ticket);
+    const Ticket &tk = it->second;
+    if (done) *done = tk.done ? 1 : 0;
+    if (latency_s)
+        *latency_s = tk.done ? std::chrono::duration<double>(tk.finished - tk.submitted).count() : 0.0;
+    if (tk.failed) return efail(e, RDOS_EDEVICE, "ticket failed: %s", tk.error.c_str());
+    return RDOS_OK;
+}
+
+rdos_status rdos_engine_drain(rdos_engine *e)
+{
+    if (!e) return RDOS_EINVAL;
+    std::unique_lock<std::mutex> lk(e->mu);
+    e->cv_done.wait(lk, [&] {
+        return (e->waiting.empty() && e->slots.empty()) || e->worker_dead || e->stalled;
+    });
+    for (auto &kv : e->tickets)
+        if (kv.second.failed) return efail(e, RDOS_EDEVICE, "a ticket failed: %s", kv.second.error.c_str());
+    if (e->worker_dead) return efail(e, RDOS_EDEVICE, "engine stopped: %s", e->error.c_str());
+    if (e->stalled)
+        return efail(e, RDOS_ENOMEM, "queued simulations do not fit the budget until finished ones are released");
+    return RDOS_OK;
+}
+
+rdos_status rdos_engine_release(rdos_engine *e, uint64_t ticket, rdos_sim **sim)
+{
+    if (!e || !sim) return RDOS_EINVAL;
+    std::lock_guard<std::mutex> g(e->mu);
+    auto it = e->tickets.find(ticket);
+    if (it == e->tickets.end()) return efail(e, RDOS_EINVAL, "unknown ticket %llu", (unsigned long long)ticket);
+    if (!it->second.done) return efail(e, RDOS_EBUSY, "ticket %llu is still running", (unsigned long long)ticket);
+    rdos_sim *s = it->second.sim;
+    s->engine_owned = false;
+    e->used -= it->second.bytes;
+    *sim = s;
+    e->tickets.erase(it);
+    e->cv_work.notify_all();
+    return RDOS_OK;
+}
+
+rdos_status rdos_engine_stats(rdos_engine *e, int64_t *launches, double *updates, double *busy_s)
+{
+    if (!e) return RDOS_EINVAL;
+    std::lock_guard<std::mutex> g(e->mu);
+    if (launches) *launches = e->launches;
+    if (updates) *updates = e->updates;
+    if (busy_s) *busy_s = e->busy_s;
+    return RDOS_OK;
+}
+
+rdos_status rdos_engine_set_profiling(rdos_engine *e, int on)
+{
+    if (!e) return RDOS_EINVAL;
+    std::lock_guard<std::mutex> g(e->mu);
+    e->profiling = on != 0;
+    e->scan_ms = e->update_ms = 0.0;
+    e->scan_n = e->update_n = 0;
+    return RDOS_OK;
+}
+
+rdos_status rdos_engine_kernel_times(rdos_engine *e, double *scan_ms, int64_t *scan_launches, double *update_ms,
+                                     int64_t *update_launches)
+{
+    if (!e) return RDOS_EINVAL;
+    std::lock_guard<std::mutex> g(e->mu);
+    if (scan_ms) *scan_ms = e->scan_ms;
+    if (scan_launches) *scan_launches = e->scan_n;
+    if (update_ms) *update_ms = e->update_ms;
+    if (update_launches) *update_launches = e->update_n;
+    return RDOS_OK;
+}
+
+rdos_status rdos_bandwidth_probe(int device, size_t bytes, int reps, double *gbps)
+{
+    if (!gbps || reps < 1 || bytes < 16) return RDOS_EINVAL;
+    if (hipSetDevice(device) != hipSuccess) return RDOS_EDEVICE;
+    void *a = nullptr, *b = nullptr;
+    hipStream_t st = nullptr;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    rdos_status rc = RDOS_OK;
+    float ms = 0.f;
+    if (hipMalloc(&a, bytes) != hipSuccess || hipMalloc(&b, bytes) != hipSuccess) {
+        rc = RDOS_ENOMEM;
+    } else if (hipStreamCreateWithFlags(&st, hipStreamNonBlocking) != hipSuccess || hipEventCreate(&e0) != hipSuccess ||
+               hipEventCreate(&e1) != hipSuccess || hipMemsetAsync(a, 1, bytes, st) != hipSuccess ||
+               launch_copy(a, b, bytes, st) != hipSuccess || hipEventRecord(e0, st) != hipSuccess) {
+        rc = RDOS_EDEVICE;
+    } else {
+        for (int i = 0; i < reps && rc == RDOS_OK; ++i)
+            if (launch_copy((i & 1) ? b : a, (i & 1) ? a : b, bytes, st) != hipSuccess) rc = RDOS_EDEVICE;
+        if (rc == RDOS_OK && (hipEventRecord(e1, st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+                              hipEventElapsedTime(&ms, e0, e1) != hipSuccess))
+            rc = RDOS_EDEVICE;
+    }
+    if (rc == RDOS_OK) *gbps = 2.0 * (double)(bytes / 16 * 16) * reps / ((double)ms * 1e-3) / 1e9;
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    if (st) (void)hipStreamDestroy(st);
+    if (a) (void)hipFree(a);
+    if (b) (void)hipFree(b);
+    return rc;
+}
+
+const char *rdos_engine_last_error(const rdos_engine *e) { return e ? e->error.c_str() : "null engine"; }
+
+void rdos_engine_destroy(rdos_engine *e)
+{
+    if (!e) return;
+    {
+        std::lock_guard<std::mutex> g(e->mu);
+        e->stop = true;
+    }
+    e->cv_work.notify_all();
+    if (e->worker.joinable()) e->worker.join();
+    (void)hipSetDevice(e->device);
+    (void)hipStreamSynchronize(e->stream);
+    for (auto &kv : e->tickets) {  // simulations never released are destroyed with the engine
+        kv.second.sim->engine_owned = false;
+        rdos_destroy(kv.second.sim);
+    }
+    if (e->graph) (void)hipGraphExecDestroy(e->graph);
+    void *p[] = {e->d_sims, e->d_tiles, e->d_queue, e->d_qcount};
+    for (void *q : p)
+        if (q) (void)hipFree(q);
+    for (hipEvent_t ev : e->kev) (void)hipEventDestroy(ev);
+    if (e->ev0) (void)hipEventDestroy(e->ev0);
+    if (e->ev1) (void)hipEventDestroy(e->ev1);
+    if (e->stream) (void)hipStreamDestroy(e->stream);
+    delete e;
+}
+
+}  // extern "C"

@@ -1,0 +1,88 @@
+// Shared host/device definitions of the rdos library (not part of the ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "../../include/rdos.h"
+
+namespace rdos {
+
+constexpr int kMaxSpecies = RDOS_MAX_SPECIES;
+constexpr int kMaxReactions = RDOS_MAX_REACTIONS;
+constexpr uint32_t kSsaStream = 0x80000000u;   // Philox stream id of the SSA draws
+constexpr int kSplitOneByOne = 10;             // Sec. II.B: n below this moves one by one
+constexpr double kAvogadro = 6.02214076e23;    // 1/mol (SI 2019)
+constexpr uint32_t kMaxEventsPerPeriod = 1u << 24;  // SSA events of one tet in one period
+
+// One tetrahedron's tables: one 64-byte line, read only when the tet holds
+// molecules (or has a 0th-order reaction).
+struct alignas(64) MeshRec {
+    int32_t nbr[4];   // neighbour across face f (opposite local vertex f), -1 = boundary
+    double w[4];      // direction weights, sum 1 over interior faces
+    double g;         // sum_f A_f / (V delta_f), 1/m^2; local rate d = D g
+    double nav;       // N_A * volume in litres
+};
+static_assert(sizeof(MeshRec) == 64, "MeshRec must be one cache line");
+
+// One simulation as the step kernel sees it (device memory).
+struct alignas(16) DevSim {
+    const MeshRec *mesh;       // [T]
+    int32_t *cnt;              // [Rz][S][T] counts after the last period's outflow
+    int32_t *inflow[2];        // [Rz][S][T] arrivals; period k reads inflow[k & 1]
+    int32_t *flags;            // bit 0: count overflow; bit 1: SSA event cap reached
+    int32_t T, S, R, Rz;
+    uint32_t key0, key1;       // Philox key words before the realization is mixed in
+    double tau;                // full period
+    int64_t step0;             // period index of launch iteration 0
+    int64_t step_end;          // periods >= step_end are not run
+    double D[kMaxSpecies];
+    uint32_t diff_mask;        // species with D > 0
+    uint32_t zeroth;           // 1 if some reaction has no reactant (every tet active)
+    // reactions
+    int32_t rn[kMaxReactions], r0[kMaxReactions], r1[kMaxReactions];
+    int32_t pn[kMaxReactions], p0[kMaxReactions], p1[kMaxReactions], p2[kMaxReactions];
+    uint32_t involved[kMaxReactions];   // bit m: species m is a reactant or a product
+    double k[kMaxReactions];
+};
+
+// A block's unit of work: up to kTetsPerTile consecutive tets of one
+// realization of one simulation.
+struct Tile {
+    int32_t sim;
+    int32_t realization;
+    int32_t tet0;
+    int32_t ntet;
+};
+
+constexpr int kBlock = 256;        // threads per block (4 wavefronts)
+constexpr int kTetsPerLane = 4;    // one 16-byte load per species and lane
+constexpr int kTetsPerTile = kBlock * kTetsPerLane;
+
+// Kernel launchers (rdos_kernels.hip).
+hipError_t launch_geometry(const double *xyz, const int32_t *tet_verts, const int32_t *nbr,
+                           int32_t T, double *scratch_vol, double *scratch_bc,
+                           double *scratch_area, MeshRec *mesh, int32_t *bad_volume,
+                           hipStream_t st);
+hipError_t launch_tau_min(const MeshRec *mesh, int32_t T, const double *D, int32_t S,
+                          unsigned long long *out_bits, hipStream_t st);
+// One period for every tile: period index = sims[i].step0 + iter; the period
+// whose index equals `partial` lasts tau_last instead of tau.  queue holds
+// qcap >= (tets of the work list) int32 entries; qcount[2] alternates between
+// launches (qsel = 0, 1, 0, ...), both zero before the first.
+hipError_t launch_step(const DevSim *sims, const Tile *tiles, int32_t n_tiles, int64_t iter,
+                       int64_t partial, double tau_last, int32_t *queue, int32_t qcap,
+                       int32_t *qcount, int32_t qsel, int32_t scan_grid, int32_t update_grid,
+                       hipStream_t st);
+hipError_t launch_scan(const DevSim *sims, const Tile *tiles, int32_t n_tiles, int64_t iter, int32_t *queue,
+                       int32_t qcap, int32_t *qcount, int32_t qsel, int32_t scan_grid, hipStream_t st);
+hipError_t launch_update(const DevSim *sims, const Tile *tiles, int64_t iter, int64_t partial, double tau_last,
+                         const int32_t *queue, int32_t qcap, int32_t *qcount, int32_t qsel, int32_t update_grid,
+                         hipStream_t st);
+hipError_t launch_advance(DevSim *sims, int32_t n_sims, int64_t by, hipStream_t st);
+hipError_t launch_copy(const void *src, void *dst, size_t bytes, hipStream_t st);
+hipError_t launch_materialize(int32_t *cnt, int32_t *inflow, int64_t n, int32_t *flags,
+                              hipStream_t st);
+
+}  // namespace rdos

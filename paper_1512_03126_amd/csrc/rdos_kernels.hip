@@ -1,0 +1,481 @@
+// gfx950 kernels of the operator-split reaction-diffusion step.
+//
+// Layout in HBM (one simulation, Rz realizations, S species, T tets, rows
+// padded to Tp = T rounded up to a multiple of 4 so that a lane can read four
+// consecutive tets with one 16-byte load):
+//   cnt[r][s][Tp]        int32  counts left in each tet after the last outflow
+//   inflow[2][r][s][Tp]  int32  molecules that arrived; period k consumes
+//                               inflow[k & 1] and fills inflow[(k + 1) & 1]
+//   mesh[T]              64 B   neighbours, weights, g, N_A V (one line)
+// The state at a period boundary is cnt + inflow[k & 1].
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "rdos_internal.h"
+#include "rdos_sampling.h"
+
+#pragma clang fp contract(off)
+
+namespace rdos {
+
+// ---------------------------------------------------------------------------
+// Set-up (Sec. II.A): volumes, face areas, barycentres, then per face
+// r_f = A_f / (V delta_f), g = sum_f r_f, w_f = r_f / g.
+// ---------------------------------------------------------------------------
+struct V3 {
+    double x, y, z;
+};
+__device__ __forceinline__ V3 vsub(V3 a, V3 b) { return {a.x - b.x, a.y - b.y, a.z - b.z}; }
+__device__ __forceinline__ V3 vcross(V3 a, V3 b)
+{
+    return {a.y * b.z - a.z * b.y, a.z * b.x - a.x * b.z, a.x * b.y - a.y * b.x};
+}
+__device__ __forceinline__ double vdot(V3 a, V3 b) { return (a.x * b.x + a.y * b.y) + a.z * b.z; }
+__device__ __forceinline__ double vnorm(V3 a) { return sqrt((a.x * a.x + a.y * a.y) + a.z * a.z); }
+
+__global__ __launch_bounds__(256) void geometry_pass1(const double *__restrict__ xyz,
+                                                      const int32_t *__restrict__ tet_verts, int32_t T,
+                                                      double *__restrict__ vol, double *__restrict__ bc,
+                                                      double *__restrict__ area, MeshRec *__restrict__ mesh,
+                                                      int32_t *__restrict__ bad)
+{
+    const int32_t t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= T) return;
+    V3 P[4];
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+        const int64_t id = tet_verts[4 * (int64_t)t + v];
+        P[v] = {xyz[3 * id], xyz[3 * id + 1], xyz[3 * id + 2]};
+    }
+    const double V = fabs(vdot(vcross(vsub(P[1], P[0]), vsub(P[2], P[0])), vsub(P[3], P[0]))) / 6.0;
+    if (!(V > 0.0)) atomicOr(bad, 1);
+    vol[t] = V;
+    mesh[t].nav = kAvogadro * (V * 1000.0);
+    bc[3 * (int64_t)t + 0] = ((P[0].x + P[1].x) + (P[2].x + P[3].x)) * 0.25;
+    bc[3 * (int64_t)t + 1] = ((P[0].y + P[1].y) + (P[2].y + P[3].y)) * 0.25;
+    bc[3 * (int64_t)t + 2] = ((P[0].z + P[1].z) + (P[2].z + P[3].z)) * 0.25;
+#pragma unroll
+    for (int f = 0; f < 4; ++f) {
+        // the face opposite vertex f, its vertices in increasing local order
+        const V3 a = P[f == 0 ? 1 : 0];
+        const V3 b = P[f <= 1 ? 2 : 1];
+        const V3 c = P[f <= 2 ? 3 : 2];
+        area[4 * (int64_t)t + f] = 0.5 * vnorm(vcross(vsub(b, a), vsub(c, a)));
+    }
+}
+
+__global__ __launch_bounds__(256) void geometry_pass2(const int32_t *__restrict__ nbr, int32_t T,
+                                                      const double *__restrict__ vol,
+                                                      const double *__restrict__ bc,
+                                                      const double *__restrict__ area,
+                                                      MeshRec *__restrict__ mesh)
+{
+    const int32_t t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= T) return;
+    const V3 me = {bc[3 * (int64_t)t], bc[3 * (int64_t)t + 1], bc[3 * (int64_t)t + 2]};
+    const double V = vol[t];
+    double r[4];
+    int32_t nb[4];
+#pragma unroll
+    for (int f = 0; f < 4; ++f) {
+        nb[f] = nbr[4 * (int64_t)t + f];
+        if (nb[f] < 0) {
+            r[f] = 0.0;
+        } else {
+            const int64_t u = nb[f];
+            const V3 other = {bc[3 * u], bc[3 * u + 1], bc[3 * u + 2]};
+            const double delta = vnorm(vsub(other, me));
+            r[f] = area[4 * (int64_t)t + f] / (V * delta);
+        }
+    }
+    const double g = ((r[0] + r[1]) + r[2]) + r[3];
+    MeshRec &m = mesh[t];
+#pragma unroll
+    for (int f = 0; f < 4; ++f) {
+        m.nbr[f] = nb[f];
+        m.w[f] = g > 0.0 ? r[f] / g : 0.0;
+    }
+    m.g = g;
+}
+
+hipError_t launch_geometry(const double *xyz, const int32_t *tet_verts, const int32_t *nbr, int32_t T,
+                           double *scratch_vol, double *scratch_bc, double *scratch_area, MeshRec *mesh,
+                           int32_t *bad_volume, hipStream_t st)
+{
+    const int grid = (T + 255) / 256;
+    geometry_pass1<<<grid, 256, 0, st>>>(xyz, tet_verts, T, scratch_vol, scratch_bc, scratch_area, mesh,
+                                         bad_volume);
+    geometry_pass2<<<grid, 256, 0, st>>>(nbr, T, scratch_vol, scratch_bc, scratch_area, mesh);
+    return hipGetLastError();
+}
+
+// tau upper limit: min over tets and diffusing species of 1/(D g).  Positive
+// doubles order like their bit patterns, so an integer atomic min is exact.
+__global__ __launch_bounds__(256) void tau_min_kernel(const MeshRec *__restrict__ mesh, int32_t T,
+                                                      const double *__restrict__ D, int32_t S,
+                                                      unsigned long long *__restrict__ out)
+{
+    __shared__ unsigned long long best[256];
+    const int32_t t = blockIdx.x * blockDim.x + threadIdx.x;
+    unsigned long long mine = ~0ull;
+    if (t < T) {
+        const double g = mesh[t].g;
+        if (g > 0.0) {
+            for (int s = 0; s < S; ++s) {
+                if (!(D[s] > 0.0)) continue;
+                const unsigned long long bits = (unsigned long long)__double_as_longlong(1.0 / (D[s] * g));
+                mine = bits < mine ? bits : mine;
+            }
+        }
+    }
+    best[threadIdx.x] = mine;
+    __syncthreads();
+    for (int off = 128; off > 0; off >>= 1) {
+        if (threadIdx.x < off && best[threadIdx.x + off] < best[threadIdx.x])
+            best[threadIdx.x] = best[threadIdx.x + off];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0 && best[0] != ~0ull) atomicMin(out, best[0]);
+}
+
+hipError_t launch_tau_min(const MeshRec *mesh, int32_t T, const double *D, int32_t S,
+                          unsigned long long *out_bits, hipStream_t st)
+{
+    tau_min_kernel<<<(T + 255) / 256, 256, 0, st>>>(mesh, T, D, S, out_bits);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// The period update of one tet (Algorithm 1, Steps 2-3).
+// ---------------------------------------------------------------------------
+// Per-lane working state lives in LDS slots with a stride of kBlock between
+// species, so species can be indexed at run time without private memory.
+struct LaneState {
+    int32_t *N;     // counts during the period
+    double *occ;    // occupancy integral since the start of the period
+    double *last;   // time of the last change
+    __device__ __forceinline__ int32_t &n(int s) const { return N[s * kBlock]; }
+};
+
+// propensity a_r = c_r h_r of reaction q with the tet's counts (mass action)
+__device__ __forceinline__ double propensity(const DevSim &sm, int q, const LaneState &ls, double nav)
+{
+    const int order = sm.rn[q];
+    double h;
+    if (order == 0) {
+        h = 1.0;
+    } else {
+        const int32_t na = ls.n(sm.r0[q]);
+        if (order == 1) {
+            h = (double)na;
+        } else if (sm.r0[q] == sm.r1[q]) {
+            h = (double)na * (double)(na - 1);
+        } else {
+            h = (double)na * (double)ls.n(sm.r1[q]);
+        }
+    }
+    if (h == 0.0) return 0.0;  // c_r * 0 == 0 for every finite c_r
+    const double c = order == 0 ? sm.k[q] * nav : (order == 1 ? sm.k[q] : sm.k[q] / nav);
+    return c * h;
+}
+
+__device__ __forceinline__ void update_tet(const DevSim &sm, int32_t t, int64_t period, double tau_k,
+                                           uint32_t key1, int32_t *__restrict__ cnt,
+                                           int32_t *__restrict__ in_cur, int32_t *__restrict__ in_nxt,
+                                           int64_t Tp, const LaneState &ls)
+{
+    const int S = sm.S;
+    const int R = sm.R;
+    const uint32_t period32 = (uint32_t)period;
+    int32_t N_base[kMaxSpecies];
+#pragma unroll
+    for (int s = 0; s < kMaxSpecies; ++s) {
+        N_base[s] = 0;
+        if (s < S) {
+            const int32_t c = cnt[s * Tp + t];
+            const int32_t f = in_cur[s * Tp + t];
+            if (f != 0) in_cur[s * Tp + t] = 0;
+            const int64_t sum = (int64_t)c + (int64_t)f;
+            if (sum > 0x7fffffff) atomicOr(sm.flags, 1);
+            N_base[s] = c;
+            ls.n(s) = (int32_t)sum;
+        }
+    }
+    const MeshRec &mr = sm.mesh[t];
+    const double nav = mr.nav;
+
+    // Step 2: Gillespie direct method over [0, tau_k); the first event at or
+    // past tau_k is discarded.  Step 2.1: on each event the occupancy
+    // integral of every reactant and product is brought up to the event time.
+    // occ[s] / last[s] are meaningful only once bit s of `touched` is set;
+    // before that they stand for 0 (no stores for tets without events).
+    uint32_t touched = 0;
+    if (R > 0) {
+        Stream ssa(sm.key0, key1, kSsaStream, (uint32_t)t, period32);
+        double now = 0.0;
+        for (uint32_t events = 0;; ++events) {
+            if (events >= kMaxEventsPerPeriod) {  // runaway rates: stop and report, never hang
+                atomicOr(sm.flags, 2);
+                break;
+            }
+            double a0 = 0.0;
+            for (int q = 0; q < R; ++q) a0 = a0 + propensity(sm, q, ls, nav);
+            if (!(a0 > 0.0)) break;
+            const double dt = -log_basic(1.0 - ssa.uniform()) / a0;
+            if (now + dt >= tau_k) break;
+            now = now + dt;
+            const double x = ssa.uniform() * a0;
+            int chosen = -1;
+            double cum = 0.0;
+            for (int q = 0; q < R; ++q) {
+                cum = cum + propensity(sm, q, ls, nav);
+                if (x < cum) {
+                    chosen = q;
+                    break;
+                }
+            }
+            if (chosen < 0) {  // x rounded up to a0: the last reaction able to fire
+                for (int q = R - 1; q >= 0; --q)
+                    if (propensity(sm, q, ls, nav) > 0.0) {
+                        chosen = q;
+                        break;
+                    }
+            }
+            const uint32_t inv = sm.involved[chosen];
+            const int rn = sm.rn[chosen], pn = sm.pn[chosen];
+            const int a = rn > 0 ? sm.r0[chosen] : -1, b = rn > 1 ? sm.r1[chosen] : -1;
+            const int c0 = pn > 0 ? sm.p0[chosen] : -1, c1 = pn > 1 ? sm.p1[chosen] : -1;
+            const int c2 = pn > 2 ? sm.p2[chosen] : -1;
+            for (int s = 0; s < S; ++s) {
+                if (!((inv >> s) & 1u)) continue;
+                const bool seen = (touched >> s) & 1u;
+                const double o = seen ? ls.occ[s * kBlock] : 0.0;
+                const double l = seen ? ls.last[s * kBlock] : 0.0;
+                int32_t &ns = ls.n(s);
+                ls.occ[s * kBlock] = o + (double)ns * (now - l);
+                ls.last[s * kBlock] = now;
+                ns += (int)(s == c0) + (int)(s == c1) + (int)(s == c2) - (int)(s == a) - (int)(s == b);
+                if (ns > 0x3fffffff) atomicOr(sm.flags, 1);
+            }
+            touched |= inv;
+        }
+    }
+
+    // Step 3, per diffusing species: mean occupancy (eq. 2), stochastic
+    // rounding to an integer population, n = binomial(Nbar, zeta) (eq. 3)
+    // limited to the molecules present, then the multinomial split.
+    int32_t nb[4];
+    double w[4];
+    bool have_faces = false;
+    double g = 0.0;
+    for (int s = 0; s < S; ++s) {
+        if (!((sm.diff_mask >> s) & 1u)) continue;
+        const int32_t Ns = ls.n(s);
+        if (Ns == 0) continue;  // n = min(binomial(.), 0) = 0: no outflow
+        const bool hit = (touched >> s) & 1u;
+        const double nbar = hit ? (ls.occ[s * kBlock] + (double)Ns * (tau_k - ls.last[s * kBlock])) / tau_k
+                                : (double)Ns;
+        Stream rng(sm.key0, key1, (uint32_t)s, (uint32_t)t, period32);
+        int64_t ni = (int64_t)floor(nbar);
+        const double frac = nbar - (double)ni;
+        if (frac > 0.0 && rng.uniform() < frac) ni += 1;
+        if (!have_faces) {
+            const int4 n4 = *reinterpret_cast<const int4 *>(mr.nbr);
+            nb[0] = n4.x;
+            nb[1] = n4.y;
+            nb[2] = n4.z;
+            nb[3] = n4.w;
+#pragma unroll
+            for (int f = 0; f < 4; ++f) w[f] = mr.w[f];
+            g = mr.g;
+            have_faces = true;
+        }
+        double zeta = (tau_k * sm.D[s]) * g;
+        if (zeta > 1.0) zeta = 1.0;
+        int64_t n = binomial(ni, zeta, rng);
+        if (n > Ns) n = Ns;
+        if (n == 0) continue;
+        int64_t out[4];
+        split_over_faces(n, nb, w, rng, out);
+#pragma unroll
+        for (int f = 0; f < 4; ++f)
+            if (out[f] > 0) atomicAdd(&in_nxt[s * Tp + nb[f]], (int32_t)out[f]);
+        ls.n(s) = Ns - (int32_t)n;
+    }
+
+#pragma unroll
+    for (int s = 0; s < kMaxSpecies; ++s)
+        if (s < S && ls.n(s) != N_base[s]) cnt[s * Tp + t] = ls.n(s);
+}
+
+// Each period is two launches.
+//  scan:   every lane reads four consecutive tets of every species (16-byte
+//          loads of cnt and inflow) and the block appends the tets holding
+//          any molecule (all tets if a reaction has no reactant) to a queue;
+//  update: the queued tets run Steps 2-3 with every lane busy.
+// The queue length lives in qcount[qsel]; the update launch clears
+// qcount[qsel ^ 1] for the next scan, so consecutive launches alternate qsel.
+__global__ __launch_bounds__(kBlock) void scan_kernel(const DevSim *__restrict__ sims,
+                                                      const Tile *__restrict__ tiles, int32_t n_tiles,
+                                                      int64_t iter, int32_t *__restrict__ queue,
+                                                      int32_t *__restrict__ qcount, int32_t qsel,
+                                                      int32_t qcap)
+{
+    __shared__ int32_t n_active;
+    __shared__ int32_t block_base;
+    for (int32_t ti = blockIdx.x; ti < n_tiles; ti += gridDim.x) {
+        const Tile tile = tiles[ti];
+        const DevSim &sm = sims[tile.sim];
+        const int64_t period = sm.step0 + iter;
+        if (period >= sm.step_end) continue;  // uniform over the block
+        const int64_t Tp = ((int64_t)sm.T + 3) & ~(int64_t)3;
+        const int64_t base = (int64_t)tile.realization * sm.S * Tp;
+        const int32_t *cnt = sm.cnt + base;
+        const int32_t *in_cur = sm.inflow[period & 1] + base;
+
+        if (threadIdx.x == 0) n_active = 0;
+        __syncthreads();
+        const int32_t off = threadIdx.x * kTetsPerLane;
+        uint32_t bits = 0;
+        if (off < tile.ntet) {
+            const int64_t t4 = tile.tet0 + off;
+            for (int s = 0; s < sm.S; ++s) {
+                const int4 c = *reinterpret_cast<const int4 *>(cnt + s * Tp + t4);
+                const int4 f = *reinterpret_cast<const int4 *>(in_cur + s * Tp + t4);
+                bits |= (uint32_t)((c.x | f.x) != 0) | ((uint32_t)((c.y | f.y) != 0) << 1) |
+                        ((uint32_t)((c.z | f.z) != 0) << 2) | ((uint32_t)((c.w | f.w) != 0) << 3);
+            }
+            if (sm.zeroth) bits = 0xFu;
+            const int32_t valid = tile.ntet - off;  // tets of this lane inside the tile
+            if (valid < 4) bits &= (1u << valid) - 1u;
+        }
+        int pos = 0;
+        if (bits) pos = atomicAdd(&n_active, __popc(bits));
+        __syncthreads();
+        if (threadIdx.x == 0) block_base = n_active ? atomicAdd(&qcount[qsel], n_active) : 0;
+        __syncthreads();
+        if (bits && block_base + pos + __popc(bits) <= qcap) {  // qcap bounds every write
+            int32_t *dst = queue + block_base + pos;
+            int q = 0;
+#pragma unroll
+            for (int b = 0; b < 4; ++b)
+                if ((bits >> b) & 1u) dst[q++] = ti * kTetsPerTile + off + b;
+        }
+        __syncthreads();
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void update_kernel(const DevSim *__restrict__ sims,
+                                                        const Tile *__restrict__ tiles,
+                                                        const int32_t *__restrict__ queue,
+                                                        int32_t *__restrict__ qcount, int32_t qsel,
+                                                        int32_t qcap, int64_t iter, int64_t partial,
+                                                        double tau_last)
+{
+    __shared__ double occ[kMaxSpecies * kBlock];
+    __shared__ double last[kMaxSpecies * kBlock];
+    __shared__ int32_t counts[kMaxSpecies * kBlock];
+    const LaneState ls{counts + threadIdx.x, occ + threadIdx.x, last + threadIdx.x};
+    if (blockIdx.x == 0 && threadIdx.x == 0) qcount[qsel ^ 1] = 0;
+    const int32_t n = min(qcount[qsel], qcap);
+    for (int32_t i = blockIdx.x * kBlock + threadIdx.x; i < n; i += gridDim.x * kBlock) {
+        const int32_t entry = queue[i];
+        const Tile tile = tiles[entry / kTetsPerTile];
+        const DevSim &sm = sims[tile.sim];
+        const int64_t period = sm.step0 + iter;
+        const double tau_k = period == partial ? tau_last : sm.tau;
+        const int64_t Tp = ((int64_t)sm.T + 3) & ~(int64_t)3;
+        const int64_t base = (int64_t)tile.realization * sm.S * Tp;
+        update_tet(sm, tile.tet0 + entry % kTetsPerTile, period, tau_k, sm.key1 ^ (uint32_t)tile.realization,
+                   sm.cnt + base, sm.inflow[period & 1] + base, sm.inflow[(period + 1) & 1] + base, Tp, ls);
+    }
+}
+
+hipError_t launch_scan(const DevSim *sims, const Tile *tiles, int32_t n_tiles, int64_t iter, int32_t *queue,
+                       int32_t qcap, int32_t *qcount, int32_t qsel, int32_t scan_grid, hipStream_t st)
+{
+    if (n_tiles <= 0) return hipSuccess;
+    const int32_t g = scan_grid > 0 ? (scan_grid < n_tiles ? scan_grid : n_tiles) : n_tiles;
+    scan_kernel<<<g, kBlock, 0, st>>>(sims, tiles, n_tiles, iter, queue, qcount, qsel, qcap);
+    return hipGetLastError();
+}
+
+hipError_t launch_update(const DevSim *sims, const Tile *tiles, int64_t iter, int64_t partial, double tau_last,
+                         const int32_t *queue, int32_t qcap, int32_t *qcount, int32_t qsel, int32_t update_grid,
+                         hipStream_t st)
+{
+    update_kernel<<<update_grid > 0 ? update_grid : 1024, kBlock, 0, st>>>(sims, tiles, queue, qcount, qsel, qcap,
+                                                                         iter, partial, tau_last);
+    return hipGetLastError();
+}
+
+hipError_t launch_step(const DevSim *sims, const Tile *tiles, int32_t n_tiles, int64_t iter, int64_t partial,
+                       double tau_last, int32_t *queue, int32_t qcap, int32_t *qcount, int32_t qsel,
+                       int32_t scan_grid, int32_t update_grid, hipStream_t st)
+{
+    if (n_tiles <= 0) return hipSuccess;
+    hipError_t e = launch_scan(sims, tiles, n_tiles, iter, queue, qcap, qcount, qsel, scan_grid, st);
+    if (e != hipSuccess) return e;
+    return launch_update(sims, tiles, iter, partial, tau_last, queue, qcap, qcount, qsel, update_grid, st);
+}
+
+// Streaming copy used to measure the device's achievable HBM bandwidth (and
+// to calibrate byte counters): 16-byte loads and stores, grid-stride.
+__global__ __launch_bounds__(256) void bandwidth_copy_kernel(const int4 *__restrict__ src, int4 *__restrict__ dst,
+                                                            int64_t n)
+{
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        dst[i] = src[i];
+}
+
+hipError_t launch_copy(const void *src, void *dst, size_t bytes, hipStream_t st)
+{
+    const int64_t n = (int64_t)(bytes / sizeof(int4));
+    if (n <= 0) return hipSuccess;
+    int64_t blocks = (n + 255) / 256;
+    if (blocks > 8192) blocks = 8192;
+    bandwidth_copy_kernel<<<(int)blocks, 256, 0, st>>>((const int4 *)src, (int4 *)dst, n);
+    return hipGetLastError();
+}
+
+// After a chunk of periods: every simulation's period index moves on.
+__global__ void advance_kernel(DevSim *sims, int32_t n_sims, int64_t by)
+{
+    const int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n_sims) sims[i].step0 += by;
+}
+
+hipError_t launch_advance(DevSim *sims, int32_t n_sims, int64_t by, hipStream_t st)
+{
+    if (n_sims <= 0) return hipSuccess;
+    advance_kernel<<<(n_sims + 63) / 64, 64, 0, st>>>(sims, n_sims, by);
+    return hipGetLastError();
+}
+
+// Folds the pending arrivals into the counts: cnt += inflow; inflow = 0.
+__global__ __launch_bounds__(256) void materialize_kernel(int32_t *__restrict__ cnt,
+                                                          int32_t *__restrict__ inflow, int64_t n,
+                                                          int32_t *__restrict__ flags)
+{
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        const int32_t f = inflow[i];
+        if (f != 0) {
+            const int64_t sum = (int64_t)cnt[i] + f;
+            if (sum > 0x7fffffff) atomicOr(flags, 1);
+            cnt[i] = (int32_t)sum;
+            inflow[i] = 0;
+        }
+    }
+}
+
+hipError_t launch_materialize(int32_t *cnt, int32_t *inflow, int64_t n, int32_t *flags, hipStream_t st)
+{
+    if (n <= 0) return hipSuccess;
+    int64_t blocks = (n + 255) / 256;
+    if (blocks > 65536) blocks = 65536;
+    materialize_kernel<<<(int)blocks, 256, 0, st>>>(cnt, inflow, n, flags);
+    return hipGetLastError();
+}
+
+}  // namespace rdos

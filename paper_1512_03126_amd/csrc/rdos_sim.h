@@ -1,0 +1,75 @@
+// Host-side state of one simulation handle.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <map>
+#include <string>
+#include <vector>
+
+#include "rdos_internal.h"
+
+namespace rdos {
+
+enum class SimState { Created, Meshed, Ready };
+
+struct Reaction {
+    int32_t rn = 0, pn = 0;
+    int32_t r[2] = {-1, -1};
+    int32_t p[3] = {-1, -1, -1};
+    double k = 0.0;
+};
+
+}  // namespace rdos
+
+struct rdos_sim {
+    int device = 0;
+    uint64_t seed = 0;
+    int32_t Rz = 1;
+    rdos::SimState state = rdos::SimState::Created;
+    std::string error;
+    bool engine_owned = false;
+
+    // model (host copy)
+    int32_t n_verts = 0, T = 0;
+    std::vector<double> xyz;
+    std::vector<int32_t> tet_verts;
+    std::vector<double> D;
+    std::vector<rdos::Reaction> rx;
+    std::map<int32_t, std::vector<int32_t>> staged;  // (r * kMaxSpecies + s) -> counts before finalize
+
+    // time: time(k) = anchor_t + (k - anchor_step) * tau
+    double tau = 0.0;
+    int64_t step = 0;
+    int64_t anchor_step = 0;
+    double anchor_t = 0.0;
+    bool dirty = false;  // arrivals pending in inflow[step & 1]
+
+    // device
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    rdos::MeshRec *d_mesh = nullptr;
+    int32_t *d_cnt = nullptr;
+    int32_t *d_inflow[2] = {nullptr, nullptr};
+    int32_t *d_flags = nullptr;
+    rdos::DevSim *d_desc = nullptr;
+    rdos::Tile *d_tiles = nullptr;
+    int32_t n_tiles = 0;
+    int32_t *d_queue = nullptr;   // occupied tets of one period, one int32 per tet of the work list
+    int32_t *d_qcount = nullptr;  // [2] queue lengths, alternating between launches
+    int64_t launches = 0;         // periods launched on this handle (selects the queue length slot)
+    int32_t update_grid = 1024;   // blocks of the update launch
+    rdos::DevSim desc{};
+};
+
+namespace rdos {
+rdos_status fail(rdos_sim *s, rdos_status code, const char *fmt, ...);
+rdos_status hip_fail(rdos_sim *s, hipError_t e, const char *what);
+int64_t padded_tets(int32_t T);
+size_t state_bytes(const rdos_sim *s);
+rdos_status fold_inflow(rdos_sim *s);
+rdos_status check_flags(rdos_sim *s);
+double time_of(const rdos_sim *s, int64_t k);
+rdos_status rdos_finalize_internal(rdos_sim *s, double tau_scale);
+}  // namespace rdos

@@ -1,0 +1,370 @@
+"""GPU path against the oracle, bit for bit (integer counts: tolerance 0).
+
+Both sides receive the same seeded inputs (workloads) and draw from the same
+Philox streams; every test compares whole count arrays.  Tests print the case
+they are about to run so that a failing GPU step is named in the log.
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def note(msg):
+    print(f"[gpu-case] {msg}", flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def P():
+    import paper_1512_03126_amd as P
+
+    P.lib()
+    return P
+
+
+def make_pair(P, orc, xyz, tets, D, reactions, init, seed=1, tau_scale=1.0):
+    """init: [Rz][S][T]"""
+    init = np.asarray(init, np.int32)
+    Rz = init.shape[0]
+    g = P.Simulation(xyz, tets, D, reactions, seed=seed, n_realizations=Rz, tau_scale=tau_scale)
+    os_ = []
+    for r in range(Rz):
+        o = orc.OracleSim(xyz, tets, D, reactions, tau_scale=tau_scale, seed=seed, realization=r)
+        for s in range(len(D)):
+            o.set_counts(s, init[r, s])
+            g.set_counts(s, init[r, s], realization=r)
+        os_.append(o)
+    assert g.tau == os_[0].tau
+    return g, os_
+
+
+def assert_same(g, os_, where=""):
+    for r, o in enumerate(os_):
+        got = g.get_counts(None, realization=r)
+        want = o.get_counts()
+        if not np.array_equal(got, want):
+            diff = np.argwhere(got != want)
+            raise AssertionError(f"{where}: realization {r}: {len(diff)} counts differ, first at "
+                                 f"(species, tet) {tuple(diff[0])}: gpu {got[tuple(diff[0])]} oracle "
+                                 f"{want[tuple(diff[0])]}")
+
+
+RICH_D = [1e-12, 1e-12, 0.5e-12, 0.0, 2e-12]
+RICH_REACTIONS = [
+    ([0, 1], [2], 3e8),        # A + B -> C
+    ([2], [0, 1], 400.0),      # C -> A + B
+    ([0, 0], [3], 5e7),        # 2A -> E   (homodimer)
+    ([3], [0, 0], 80.0),       # E -> 2A   (E immobile)
+    ([], [4], 2e-5),           # 0 -> F    (0th order, every tet active)
+    ([4], [], 150.0),          # F -> 0
+    ([1, 4], [1, 1, 4], 1e8),  # B + F -> 2B + F (three products)
+]
+
+
+def rich_init(T, Rz, seed, hi=25):
+    rng = np.random.default_rng(seed)
+    init = rng.integers(0, hi, size=(Rz, len(RICH_D), T)).astype(np.int32)
+    init[:, 4] = 0
+    return init
+
+
+# ---------------------------------------------------------------------------
+def test_geometry_and_tau_bit_exact(P, orc):
+    cases = [("kuhn n=3", W.kuhn_lattice(3, 0.1e-6)),
+             ("jittered n=4", (W.jitter(W.kuhn_lattice(4, 0.1e-6)[0], 4, 0.1e-6, 0.2, 2), W.kuhn_lattice(4, 0.1e-6)[1])),
+             ("jittered n=40", (W.abcd_jittered().xyz, W.abcd_jittered().tets))]
+    for name, (xyz, tets) in cases:
+        note(f"geometry {name} T={tets.shape[0]}")
+        for D, ts in [([1e-12, 0.5e-12], 1.0), ([3e-12, 0.0], 0.37)]:
+            g = P.Simulation(xyz, tets, D, [], tau_scale=ts)
+            o = orc.OracleSim(xyz, tets, D, [], tau_scale=ts)
+            assert g.tau == o.tau, name
+            gg, og = g.geometry(), o.geometry()
+            np.testing.assert_array_equal(gg["nbr"], og["nbr"])
+            for key in ("w", "g", "nav"):
+                assert np.array_equal(gg[key].view(np.uint64), og[key].view(np.uint64)), (name, key)
+            g.close()
+
+
+@pytest.mark.parametrize("n,jit,Rz,seed", [(1, 0.0, 3, 1), (2, 0.2, 2, 7), (3, 0.2, 1, 11)])
+def test_rich_chemistry_every_period(P, orc, n, jit, Rz, seed):
+    xyz, tets = W.tiny_lattice(n, 0.2e-6, jitter_frac=jit, seed=seed)
+    T = tets.shape[0]
+    note(f"rich chemistry n={n} T={T} Rz={Rz} seed={seed}")
+    g, os_ = make_pair(P, orc, xyz, tets, RICH_D, RICH_REACTIONS, rich_init(T, Rz, seed), seed=seed)
+    for k in range(40):
+        g.step(1)
+        for o in os_:
+            o.step()
+        assert_same(g, os_, f"period {k}")
+    g.close()
+
+
+def test_diffusion_cube_run_until(P, orc):
+    m = W.diffusion_cube()
+    note("diffusion cube 750 tets, run_until 0.5 s")
+    g, os_ = make_pair(P, orc, m.xyz, m.tets, m.D, m.reactions, m.init, seed=m.seed)
+    for t_end in (0.01, 0.1, 0.25, m.t_end):
+        g.run_until(t_end)
+        os_[0].run_until(t_end)
+        assert g.time() == os_[0].time()
+        assert_same(g, os_, f"t={t_end}")
+    g.close()
+    # one call: 422 full periods and one shortened to end at 0.5 s (Step 1)
+    g, os_ = make_pair(P, orc, m.xyz, m.tets, m.D, m.reactions, m.init, seed=m.seed)
+    g.run_until(m.t_end)
+    os_[0].run_until(m.t_end)
+    assert g.time() == (m.t_end, 423)
+    assert_same(g, os_, "single run_until")
+    g.close()
+
+
+def test_abc_lattice_full_size(P, orc):
+    m = W.abc_lattice()
+    note(f"A+B<->C 40^3x6 T={m.n_tets}, 0.1 s")
+    g, os_ = make_pair(P, orc, m.xyz, m.tets, m.D, m.reactions, m.init, seed=m.seed)
+    g.run_until(0.02)
+    os_[0].run_until(0.02)
+    assert_same(g, os_, "t=0.02")
+    g.run_until(m.t_end)
+    os_[0].run_until(m.t_end)
+    assert_same(g, os_, f"t={m.t_end}")
+    c = g.get_counts()
+    assert c[0].sum() + c[2].sum() == m.init[0, 0].sum()
+    g.close()
+
+
+def test_abcd_jittered_full_size_truncated(P, orc):
+    m = W.abcd_jittered()
+    note(f"A+B<->C + D decay, jittered 40^3x6 T={m.n_tets}, 60 periods")
+    g, os_ = make_pair(P, orc, m.xyz, m.tets, m.D, m.reactions, m.init, seed=m.seed)
+    for _ in range(3):
+        g.step(20)
+        os_[0].run_steps(20)
+        assert_same(g, os_, "jittered")
+    g.close()
+
+
+def test_dense_counts_exercise_btrd(P, orc):
+    xyz, tets = W.tiny_lattice(2, 0.2e-6, jitter_frac=0.2, seed=5)
+    T = tets.shape[0]
+    note(f"dense counts T={T}")
+    rng = np.random.default_rng(3)
+    init = np.zeros((2, 2, T), np.int32)
+    init[:, 0] = rng.integers(0, 200000, size=(2, T))
+    init[:, 1] = rng.integers(0, 40, size=(2, T))
+    reactions = [([0], [1], 3000.0), ([1], [0], 1.0)]
+    g, os_ = make_pair(P, orc, xyz, tets, [1e-12, 1e-12], reactions, init, seed=9, tau_scale=0.37)
+    for k in range(6):
+        g.step(1)
+        for o in os_:
+            o.step()
+        assert_same(g, os_, f"dense period {k}")
+    g.close()
+
+
+@pytest.mark.parametrize("n", [6, 11])
+def test_ragged_multi_tile_meshes(P, orc, n):
+    xyz, tets = W.kuhn_lattice(n, 0.1e-6)
+    T = tets.shape[0]
+    note(f"ragged tiles T={T}")
+    rng = np.random.default_rng(n)
+    init = np.zeros((2, 2, T), np.int32)
+    init[:, 0] = (rng.random((2, T)) < 0.3) * rng.integers(1, 40, size=(2, T))
+    init[:, 1] = (rng.random((2, T)) < 0.05) * rng.integers(1, 4, size=(2, T))
+    g, os_ = make_pair(P, orc, xyz, tets, [1e-12, 0.3e-12], [([0, 1], [1, 1], 1e9)], init, seed=n)
+    for _ in range(4):
+        g.step(5)
+        for o in os_:
+            o.run_steps(5)
+        assert_same(g, os_, f"n={n}")
+    g.close()
+
+
+def test_zeroth_order_and_empty_start(P, orc):
+    xyz, tets = W.kuhn_lattice(3, 0.1e-6)
+    T = tets.shape[0]
+    note("0th-order production from empty")
+    init = np.zeros((1, 1, T), np.int32)
+    g, os_ = make_pair(P, orc, xyz, tets, [1e-12], [([], [0], 1e-4), ([0], [], 10.0)], init, seed=4)
+    for k in range(10):
+        g.step(1)
+        os_[0].step()
+        assert_same(g, os_, f"period {k}")
+    assert g.get_counts(0).sum() > 0
+    g.close()
+    note("empty state stays empty")
+    g2, os2 = make_pair(P, orc, xyz, tets, [1e-12, 1e-12], [([0, 1], [], 1e6)], np.zeros((1, 2, T), np.int32))
+    g2.step(7)
+    assert g2.get_counts().sum() == 0
+    g2.close()
+
+
+def test_resume_is_bit_identical(P, orc):
+    xyz, tets = W.tiny_lattice(2, 0.2e-6, jitter_frac=0.2, seed=8)
+    T = tets.shape[0]
+    note("resume")
+    init = rich_init(T, 1, 21)
+    g, os_ = make_pair(P, orc, xyz, tets, RICH_D, RICH_REACTIONS, init, seed=21)
+    g.step(13)
+    mid = g.get_counts()
+    t_mid, k_mid = g.time()
+    g.step(11)
+    end = g.get_counts()
+    h = P.Simulation(xyz, tets, RICH_D, RICH_REACTIONS, seed=21)
+    for s in range(len(RICH_D)):
+        h.set_counts(s, mid[s])
+    h.set_state(k_mid, t_mid)
+    h.step(11)
+    np.testing.assert_array_equal(h.get_counts(), end)
+    os_[0].run_steps(24)
+    assert_same(g, os_, "continuous")
+    g.close()
+    h.close()
+
+
+def test_counts_can_be_reset_between_periods(P, orc):
+    xyz, tets = W.kuhn_lattice(2, 0.1e-6)
+    T = tets.shape[0]
+    note("set_counts between periods")
+    init = np.zeros((1, 1, T), np.int32)
+    init[0, 0, 3] = 50
+    g, os_ = make_pair(P, orc, xyz, tets, [1e-12], [], init, seed=2)
+    g.step(3)
+    os_[0].run_steps(3)
+    new = np.arange(T, dtype=np.int32) % 5
+    g.set_counts(0, new)
+    os_[0].set_counts(0, new)
+    g.step(4)
+    os_[0].run_steps(4)
+    assert_same(g, os_, "after reset")
+    g.close()
+
+
+def test_torch_stream(P, orc):
+    import torch
+
+    xyz, tets = W.kuhn_lattice(2, 0.1e-6)
+    T = tets.shape[0]
+    note("torch stream")
+    init = np.zeros((1, 1, T), np.int32)
+    init[0, 0, 0] = 300
+    g, os_ = make_pair(P, orc, xyz, tets, [1e-12], [], init, seed=6)
+    st = torch.cuda.Stream()
+    g.set_stream(st)
+    g.step(9)
+    g.synchronize()
+    os_[0].run_steps(9)
+    assert_same(g, os_, "torch stream")
+    g.set_stream(None)
+    g.step(2)
+    os_[0].run_steps(2)
+    assert_same(g, os_, "own stream again")
+    g.close()
+
+
+def test_invalid_inputs(P):
+    note("invalid inputs")
+    xyz, tets = W.kuhn_lattice(1, 0.1e-6)
+    h = P.rdos_create(0, 1, 1)
+    with pytest.raises(P.RdosError) as ei:
+        P.rdos_set_counts(h, 0, 0, np.zeros(6, np.int32))
+    assert ei.value.status == -4
+    P.rdos_set_mesh(h, xyz, tets)
+    with pytest.raises(P.RdosError):
+        P.rdos_add_reaction(h, [0], [], 1.0)      # no species yet
+    P.rdos_add_species(h, 1e-12)
+    with pytest.raises(P.RdosError):
+        P.rdos_set_counts(h, 0, 0, -np.ones(6, np.int32))
+    with pytest.raises(P.RdosError):
+        P.rdos_finalize(h, 1.5)
+    P.rdos_destroy(h)
+    bad = tets.copy()
+    bad[0, 3] = bad[0, 2]
+    with pytest.raises(P.RdosError, match="repeats a face"):
+        P.Simulation(xyz, bad, [1e-12], [])
+    flat = tets.copy()
+    flat[0] = [0, 1, 2, 3]                    # four corners of the z = 0 face: zero volume
+    with pytest.raises(P.RdosError, match="degenerate"):
+        P.Simulation(xyz, flat, [1e-12], [])
+    with pytest.raises(P.RdosError, match="shared"):
+        P.Simulation(xyz, np.concatenate([tets, tets[:1]]), [1e-12], [])
+    with pytest.raises(P.RdosError, match="tau"):
+        P.Simulation(xyz, tets, [0.0], [])
+
+
+# ---------------------------------------------------------------------------
+# Batching / serving engine
+# ---------------------------------------------------------------------------
+def test_engine_batched_equals_alone_and_oracle(P, orc):
+    note("engine: three simulations in one batch")
+    specs = []
+    xyz1, tets1 = W.tiny_lattice(2, 0.2e-6, jitter_frac=0.2, seed=3)
+    specs.append((xyz1, tets1, RICH_D, RICH_REACTIONS, rich_init(tets1.shape[0], 2, 5), 5, 37))
+    m = W.diffusion_cube()
+    specs.append((m.xyz, m.tets, m.D, [], m.init, 1, 50))
+    xyz3, tets3 = W.kuhn_lattice(6, 0.1e-6)
+    init3 = np.zeros((3, 2, tets3.shape[0]), np.int32)
+    init3[:, 0, ::7] = 3
+    init3[:, 1, ::11] = 2
+    specs.append((xyz3, tets3, [1e-12, 0.3e-12], [([0, 1], [1, 1], 1e9)], init3, 8, 22))
+    e = P.rdos_engine_create(0, 0)
+    tickets = []
+    for xyz, tets, D, rx, init, seed, n in specs:
+        s = P.Simulation(xyz, tets, D, rx, seed=seed, n_realizations=init.shape[0], tau_scale=None)
+        for r in range(init.shape[0]):
+            for q in range(len(D)):
+                s.set_counts(q, init[r, q], realization=r)
+        tickets.append((P.rdos_engine_submit(e, s.h, n, 1.0), s))
+    P.rdos_engine_drain(e)
+    for (t, s), (xyz, tets, D, rx, init, seed, n) in zip(tickets, specs):
+        done, lat = P.rdos_engine_poll(e, t)
+        assert done and lat > 0
+        P.rdos_engine_release(e, t)
+        assert s.time()[1] == n
+        for r in range(init.shape[0]):
+            o = orc.OracleSim(xyz, tets, D, rx, seed=seed, realization=r)
+            for q in range(len(D)):
+                o.set_counts(q, init[r, q])
+            o.run_steps(n)
+            np.testing.assert_array_equal(s.get_counts(None, realization=r), o.get_counts())
+        s.close()
+    stats = P.rdos_engine_stats(e)
+    assert stats["launches"] >= 50 and stats["updates"] > 0
+    P.rdos_engine_destroy(e)
+
+
+def test_engine_budget_admits_in_turn(P, orc):
+    note("engine: budget admits one simulation at a time")
+    xyz, tets = W.kuhn_lattice(4, 0.1e-6)
+    T = tets.shape[0]
+    sims = []
+    for i in range(3):
+        s = P.Simulation(xyz, tets, [1e-12], [], seed=40 + i, tau_scale=None)
+        init = np.zeros(T, np.int32)
+        init[i * 10] = 500
+        s.set_counts(0, init)
+        sims.append((s, init))
+    need = sims[0][0].info()["device_bytes"]
+    e = P.rdos_engine_create(0, int(need * 1.5))
+    tks = [P.rdos_engine_submit(e, s.h, 12 + 2 * i, 1.0) for i, (s, _) in enumerate(sims)]
+    # only one fits at a time: release each as it finishes
+    for i, t in enumerate(tks):
+        while True:
+            done, _ = P.rdos_engine_poll(e, t)
+            if done:
+                break
+        P.rdos_engine_release(e, t)
+        s, init = sims[i]
+        o = orc.OracleSim(xyz, tets, [1e-12], [], seed=40 + i)
+        o.set_counts(0, init)
+        o.run_steps(12 + 2 * i)
+        np.testing.assert_array_equal(s.get_counts(0), o.get_counts(0))
+        s.close()
+    P.rdos_engine_destroy(e)

@@ -117,13 +117,19 @@ def count_for(conc_molar: float, volume_m3: float) -> int:
     return int(round(conc_molar * N_A * volume_m3 * 1000.0))
 
 
-def place_by_volume(xyz, tets, total: int, rng, mask: Optional[np.ndarray] = None) -> np.ndarray:
-    """Scatter ``total`` molecules independently over tets, P(tet) ~ volume."""
-    vol = _tet_volumes(xyz, tets)
+def place_by_volume(xyz, tets, total: int, rng, mask: Optional[np.ndarray] = None,
+                    vol: Optional[np.ndarray] = None) -> np.ndarray:
+    """Scatter ``total`` molecules independently over tets, P(tet) ~ volume
+    (inverse CDF of the volume prefix sum, one uniform per molecule)."""
+    if vol is None:
+        vol = _tet_volumes(xyz, tets)
     if mask is not None:
         vol = np.where(mask, vol, 0.0)
-    p = vol / vol.sum()
-    return rng.multinomial(total, p).astype(np.int32)
+    cdf = np.cumsum(vol)
+    u = rng.random(int(total)) * cdf[-1]
+    idx = np.searchsorted(cdf, u, side="right")
+    idx = np.minimum(idx, len(vol) - 1)
+    return np.bincount(idx, minlength=len(vol)).astype(np.int32)
 
 
 # ----------------------------------------------------------------------------
@@ -154,9 +160,10 @@ def abc_lattice(n: int = 40, a: float = 0.1e-6, seed: int = 1, n_realizations: i
     total = count_for(conc, vol_total)
     rng = np.random.Generator(np.random.PCG64(seed))
     init = np.zeros((n_realizations, 3, tets.shape[0]), dtype=np.int32)
+    vol = _tet_volumes(xyz, tets)
     for r in range(n_realizations):
-        init[r, 0] = place_by_volume(xyz, tets, total, rng)
-        init[r, 1] = place_by_volume(xyz, tets, total, rng)
+        init[r, 0] = place_by_volume(xyz, tets, total, rng, vol=vol)
+        init[r, 1] = place_by_volume(xyz, tets, total, rng, vol=vol)
     return Model(f"abc_{n}cube_{tets.shape[0]}", xyz, tets, [1e-12, 1e-12, 0.5e-12],
                  _abc_reactions(), init, t_end, seed, species_names=["A", "B", "C"])
 
