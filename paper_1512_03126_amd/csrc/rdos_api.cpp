@@ -44,13 +44,42 @@ rdos_status hip_fail(rdos_sim *s, hipError_t e, const char *what)
 
 int64_t padded_tets(int32_t T) { return ((int64_t)T + 3) & ~(int64_t)3; }
 
+size_t queue_bytes(int64_t n_tiles, int32_t n_species)
+{
+    int32_t nseg, seg_cap;
+    queue_shape(n_tiles, &nseg, &seg_cap);
+    return (size_t)nseg * seg_cap * (1 + (size_t)n_species) * sizeof(int32_t) + 2 * (size_t)nseg * sizeof(int32_t);
+}
+
+hipError_t alloc_queue(QueueView *q, int64_t n_tiles, int32_t n_species)
+{
+    queue_shape(n_tiles, &q->nseg, &q->seg_cap);
+    q->species = std::max(n_species, 1);
+    const size_t cap = (size_t)q->nseg * q->seg_cap;
+    hipError_t e = hipMalloc(&q->tet, cap * sizeof(int32_t));
+    if (e == hipSuccess) e = hipMalloc(&q->counts, cap * (size_t)std::max(n_species, 1) * sizeof(int32_t));
+    if (e == hipSuccess) e = hipMalloc(&q->len, 2 * (size_t)q->nseg * sizeof(int32_t));
+    if (e == hipSuccess) e = hipMemset(q->len, 0, 2 * (size_t)q->nseg * sizeof(int32_t));
+    return e;
+}
+
+void free_queue(QueueView *q)
+{
+    if (q->tet) (void)hipFree(q->tet);
+    if (q->counts) (void)hipFree(q->counts);
+    if (q->len) (void)hipFree(q->len);
+    *q = QueueView{};
+}
+
+static int64_t tiles_of(const rdos_sim *s) { return (int64_t)s->Rz * ((s->T + kTetsPerTile - 1) / kTetsPerTile); }
+
 size_t state_bytes(const rdos_sim *s)
 {
     const int64_t Tp = padded_tets(s->T);
     const size_t counts = (size_t)s->Rz * s->D.size() * (size_t)Tp * sizeof(int32_t);
-    const size_t tiles = (size_t)s->Rz * (size_t)((s->T + kTetsPerTile - 1) / kTetsPerTile) * sizeof(Tile);
-    const size_t queue = (size_t)s->Rz * (size_t)s->T * sizeof(int32_t);
-    return (size_t)s->T * sizeof(MeshRec) + 3 * counts + tiles + queue + sizeof(DevSim) + 72;
+    const size_t tiles = (size_t)tiles_of(s) * sizeof(Tile);
+    return (size_t)s->T * sizeof(MeshRec) + 3 * counts + tiles + queue_bytes(tiles_of(s), (int32_t)s->D.size()) +
+           sizeof(DevSim) + 64;
 }
 
 // Face matching: each face is keyed by its sorted vertex triple; two tets with
@@ -124,6 +153,7 @@ rdos_status check_flags(rdos_sim *s)
             "read flags");
     HIP_TRY(s, hipStreamSynchronize(s->stream), "synchronize");
     if (flags & 1) return fail(s, RDOS_EOVERFLOW, "a molecule count overflowed int32");
+    if (flags & 4) return fail(s, RDOS_EDEVICE, "occupied-tet queue overflowed (internal error)");
     if (flags & 2)
         return fail(s, RDOS_EOVERFLOW, "a tet fired more than %u reactions in one period; shorten tau",
                     kMaxEventsPerPeriod);
@@ -132,9 +162,8 @@ rdos_status check_flags(rdos_sim *s)
 
 rdos_status enqueue_period(rdos_sim *s, int64_t period, int64_t partial, double tau_last)
 {
-    HIP_TRY(s, launch_step(s->d_desc, s->d_tiles, s->n_tiles, period, partial, tau_last, s->d_queue,
-                           (int32_t)((int64_t)s->Rz * s->T), s->d_qcount, (int32_t)(s->launches & 1), 0,
-                           s->update_grid, s->stream),
+    HIP_TRY(s, launch_step(s->d_desc, s->d_tiles, s->n_tiles, period, partial, tau_last, s->queue,
+                           (int32_t)(s->launches & 1), 0, s->update_bps, s->stream),
             "launch period");
     s->launches += 1;
     s->dirty = true;
@@ -150,13 +179,12 @@ void free_device(rdos_sim *s)
 {
     (void)hipSetDevice(s->device);
     if (s->stream && s->own_stream) (void)hipStreamSynchronize(s->stream);
-    void *ptrs[] = {s->d_mesh, s->d_cnt, s->d_inflow[0], s->d_inflow[1], s->d_flags, s->d_desc, s->d_tiles,
-                    s->d_queue, s->d_qcount};
+    void *ptrs[] = {s->d_mesh, s->d_cnt, s->d_inflow[0], s->d_inflow[1], s->d_flags, s->d_desc, s->d_tiles};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
+    free_queue(&s->queue);
     s->d_mesh = nullptr;
     s->d_cnt = s->d_inflow[0] = s->d_inflow[1] = s->d_flags = nullptr;
-    s->d_queue = s->d_qcount = nullptr;
     s->d_desc = nullptr;
     s->d_tiles = nullptr;
     if (s->stream && s->own_stream) (void)hipStreamDestroy(s->stream);
@@ -297,9 +325,7 @@ rdos_status rdos_finalize(rdos_sim *s, double tau_scale, double *out_tau)
     SETUP_TRY(hipMalloc(&s->d_inflow[1], count_bytes), "allocate arrivals");
     SETUP_TRY(hipMalloc(&s->d_flags, 64), "allocate flags");
     SETUP_TRY(hipMalloc(&s->d_desc, sizeof(DevSim)), "allocate descriptor");
-    SETUP_TRY(hipMalloc(&s->d_queue, (size_t)s->Rz * (size_t)T * sizeof(int32_t)), "allocate queue");
-    SETUP_TRY(hipMalloc(&s->d_qcount, 2 * sizeof(int32_t)), "allocate queue");
-    SETUP_TRY(hipMemsetAsync(s->d_qcount, 0, 2 * sizeof(int32_t), s->stream), "clear queue");
+    SETUP_TRY(alloc_queue(&s->queue, tiles_of(s), S), "allocate queue");
     SETUP_TRY(hipMalloc(&d_xyz, s->xyz.size() * sizeof(double)), "allocate set-up");
     SETUP_TRY(hipMalloc(&d_tv, s->tet_verts.size() * sizeof(int32_t)), "allocate set-up");
     SETUP_TRY(hipMalloc(&d_nbr, nbr.size() * sizeof(int32_t)), "allocate set-up");

@@ -44,8 +44,13 @@ struct Ticket {
 
 // Launch-shape choices the tuner tries on live work (results do not depend on them).
 struct Shape {
-    int32_t chunk;        // periods per graph replay (even: the queue slots alternate)
-    int32_t update_grid;  // blocks of the update launch
+    int32_t chunk;      // periods per graph replay (even: the queue length halves alternate)
+    int32_t scan_grid;  // blocks of the scan launch (0: one per tile)
+    int32_t update_bps; // update blocks per queue segment
+    bool operator==(const Shape &o) const
+    {
+        return chunk == o.chunk && scan_grid == o.scan_grid && update_bps == o.update_bps;
+    }
 };
 
 }  // namespace
@@ -75,20 +80,19 @@ struct rdos_engine {
     int32_t cap_sims = 0;
     Tile *d_tiles = nullptr;
     int64_t cap_tiles = 0;
-    int32_t *d_queue = nullptr;
-    int64_t cap_queue = 0;
-    int32_t *d_qcount = nullptr;
-    int64_t queue_len = 0;  // tets in the current work list (the queue never holds more)
+    QueueView queue{};
+    int64_t queue_tiles = 0;    // tiles the allocated queue can hold
+    int32_t queue_species = 0;  // species rows the allocated queue can hold
     int32_t n_tiles = 0;
     hipGraphExec_t graph = nullptr;
-    Shape graph_shape{0, 0};
+    Shape graph_shape{0, 0, 0};
     bool rebuild = true;
 
     // tuner: candidates tried in turn on each new slot set, best kept
     std::vector<Shape> candidates;
     size_t trial = 0;
     double best_rate = -1.0;
-    Shape best{16, 1024};
+    Shape best{16, 0, 4};
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
 
     // tuned shape per work-list signature (tiles, tets)
@@ -144,7 +148,7 @@ rdos_status build_work(rdos_engine *e)
 {
     std::vector<DevSim> sims;
     std::vector<Tile> tiles;
-    int64_t queue_need = 0;
+    int32_t max_species = 1;
     for (size_t i = 0; i < e->slots.size(); ++i) {
         Ticket &tk = e->tickets[e->slots[i]];
         rdos_sim *s = tk.sim;
@@ -155,7 +159,7 @@ rdos_status build_work(rdos_engine *e)
         for (int32_t r = 0; r < s->Rz; ++r)
             for (int32_t t0 = 0; t0 < s->T; t0 += kTetsPerTile)
                 tiles.push_back({(int32_t)i, r, t0, std::min<int32_t>(kTetsPerTile, s->T - t0)});
-        queue_need += (int64_t)s->Rz * s->T;
+        max_species = std::max(max_species, (int32_t)s->D.size());
     }
     int64_t cap_sims = e->cap_sims;
     rdos_status st = ensure(e, &e->d_sims, &cap_sims, (int64_t)std::max<size_t>(sims.size(), 1), "engine slots");
@@ -163,8 +167,18 @@ rdos_status build_work(rdos_engine *e)
     e->cap_sims = (int32_t)cap_sims;
     st = ensure(e, &e->d_tiles, &e->cap_tiles, (int64_t)std::max<size_t>(tiles.size(), 1), "engine tiles");
     if (st != RDOS_OK) return st;
-    st = ensure(e, &e->d_queue, &e->cap_queue, std::max<int64_t>(queue_need, 1), "engine queue");
-    if (st != RDOS_OK) return st;
+    // the queue's segment geometry follows the tile count, so it is rebuilt whenever that changes
+    const int64_t nt = (int64_t)std::max<size_t>(tiles.size(), 1);
+    if (nt != e->queue_tiles || max_species > e->queue_species) {
+        free_queue(&e->queue);
+        e->queue_tiles = e->queue_species = 0;
+        ENGINE_HIP(e, alloc_queue(&e->queue, nt, max_species), "engine queue");
+        e->queue_tiles = nt;
+        e->queue_species = max_species;
+    } else {
+        ENGINE_HIP(e, hipMemsetAsync(e->queue.len, 0, 2 * (size_t)e->queue.nseg * sizeof(int32_t), e->stream),
+                   "clear queue");
+    }
     if (!sims.empty())
         ENGINE_HIP(e, hipMemcpyAsync(e->d_sims, sims.data(), sims.size() * sizeof(DevSim), hipMemcpyHostToDevice,
                                      e->stream),
@@ -175,7 +189,6 @@ rdos_status build_work(rdos_engine *e)
                    "upload tiles");
     ENGINE_HIP(e, hipStreamSynchronize(e->stream), "upload work list");
     e->n_tiles = (int32_t)tiles.size();
-    e->queue_len = queue_need;
     return RDOS_OK;
 }
 
@@ -188,12 +201,10 @@ hipError_t enqueue_chunk(rdos_engine *e, const Shape &sh, bool timed)
     hipError_t err = hipSuccess;
     if (timed) err = hipEventRecord(e->kev[0], e->stream);
     for (int32_t i = 0; i < sh.chunk && err == hipSuccess; ++i) {
-        err = launch_scan(e->d_sims, e->d_tiles, e->n_tiles, i, e->d_queue, (int32_t)e->queue_len, e->d_qcount,
-                          i & 1, 0, e->stream);
+        err = launch_scan(e->d_sims, e->d_tiles, e->n_tiles, i, e->queue, i & 1, sh.scan_grid, e->stream);
         if (err == hipSuccess && timed) err = hipEventRecord(e->kev[2 * i + 1], e->stream);
         if (err == hipSuccess)
-            err = launch_update(e->d_sims, e->d_tiles, i, -1, 0.0, e->d_queue, (int32_t)e->queue_len, e->d_qcount,
-                                i & 1, sh.update_grid, e->stream);
+            err = launch_update(e->d_sims, e->d_tiles, i, -1, 0.0, e->queue, i & 1, sh.update_bps, e->stream);
         if (err == hipSuccess && timed) err = hipEventRecord(e->kev[2 * i + 2], e->stream);
     }
     if (err == hipSuccess) err = launch_advance(e->d_sims, (int32_t)e->slots.size(), sh.chunk, e->stream);
@@ -294,7 +305,7 @@ void worker_main(rdos_engine *e)
         e->stalled = false;
         if (e->rebuild) {
             if (build_work(e) != RDOS_OK) break;
-            auto hit = e->tuned.find({e->n_tiles, e->queue_len});
+            auto hit = e->tuned.find({e->n_tiles, e->queue_tiles});
             if (hit != e->tuned.end()) {
                 e->best = hit->second;
                 e->trial = e->candidates.size();
@@ -322,7 +333,7 @@ void worker_main(rdos_engine *e)
                 e->error = "create profiling events";
                 break;
             }
-        } else if (!e->graph || sh.chunk != e->graph_shape.chunk || sh.update_grid != e->graph_shape.update_grid) {
+        } else if (!e->graph || !(sh == e->graph_shape)) {
             if (capture(e, sh) != RDOS_OK) break;
         }
         double work = 0.0;
@@ -370,7 +381,7 @@ void worker_main(rdos_engine *e)
                 e->best = sh;
             }
             ++e->trial;
-            if (e->trial == e->candidates.size()) e->tuned[{e->n_tiles, e->queue_len}] = e->best;
+            if (e->trial == e->candidates.size()) e->tuned[{e->n_tiles, (int64_t)e->queue_species}] = e->best;
         }
         e->launches += sh.chunk;
         e->updates += work;
@@ -420,13 +431,11 @@ rdos_status rdos_engine_create(rdos_engine **out, int device, size_t hbm_budget_
     e->budget = hbm_budget_bytes ? hbm_budget_bytes : (size_t)(0.9 * (double)free_b);
     if (hipStreamCreateWithFlags(&e->stream, hipStreamNonBlocking) != hipSuccess ||
         hipEventCreate(&e->ev0) != hipSuccess || hipEventCreate(&e->ev1) != hipSuccess ||
-        hipMalloc(&e->d_qcount, 2 * sizeof(int32_t)) != hipSuccess ||
-        hipMemsetAsync(e->d_qcount, 0, 2 * sizeof(int32_t), e->stream) != hipSuccess ||
         hipStreamSynchronize(e->stream) != hipSuccess) {
         delete e;
         return RDOS_EDEVICE;
     }
-    e->candidates = {{16, 1024}, {16, 2048}, {16, 4096}, {32, 2048}};
+    e->candidates = {{16, 0, 4}, {16, 0, 8}, {16, 2048, 4}, {16, 4096, 8}, {32, 0, 8}};
     e->worker = std::thread(worker_main, e);
     *out = e;
     return RDOS_OK;
@@ -587,9 +596,10 @@ void rdos_engine_destroy(rdos_engine *e)
         rdos_destroy(kv.second.sim);
     }
     if (e->graph) (void)hipGraphExecDestroy(e->graph);
-    void *p[] = {e->d_sims, e->d_tiles, e->d_queue, e->d_qcount};
+    void *p[] = {e->d_sims, e->d_tiles};
     for (void *q : p)
         if (q) (void)hipFree(q);
+    free_queue(&e->queue);
     for (hipEvent_t ev : e->kev) (void)hipEventDestroy(ev);
     if (e->ev0) (void)hipEventDestroy(e->ev0);
     if (e->ev1) (void)hipEventDestroy(e->ev1);

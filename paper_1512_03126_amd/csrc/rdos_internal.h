@@ -31,7 +31,7 @@ struct alignas(16) DevSim {
     const MeshRec *mesh;       // [T]
     int32_t *cnt;              // [Rz][S][T] counts after the last period's outflow
     int32_t *inflow[2];        // [Rz][S][T] arrivals; period k reads inflow[k & 1]
-    int32_t *flags;            // bit 0: count overflow; bit 1: SSA event cap reached
+    int32_t *flags;            // bit 0: count overflow; bit 1: SSA event cap; bit 2: queue overflow
     int32_t T, S, R, Rz;
     uint32_t key0, key1;       // Philox key words before the realization is mixed in
     double tau;                // full period
@@ -67,19 +67,35 @@ hipError_t launch_geometry(const double *xyz, const int32_t *tet_verts, const in
                            hipStream_t st);
 hipError_t launch_tau_min(const MeshRec *mesh, int32_t T, const double *D, int32_t S,
                           unsigned long long *out_bits, hipStream_t st);
+// Occupied-tet queue of one launch pair (device memory, see the scan kernel).
+struct QueueView {
+    int32_t *tet;     // [nseg * seg_cap] tile * kTetsPerTile + offset
+    int32_t *counts;  // [species][nseg * seg_cap] counts at the start of the period
+    int32_t *len;     // [2][nseg] segment lengths, both halves zero before the first launch
+    int32_t nseg;     // 1..kMaxSegments
+    int32_t seg_cap;  // entries per segment
+    int32_t species;  // rows of counts: the largest species count of the work list
+};
+constexpr int kMaxSegments = 256;
+
+// Queue geometry for a work list of n_tiles tiles.
+inline void queue_shape(int64_t n_tiles, int32_t *nseg, int32_t *seg_cap)
+{
+    const int64_t ns = n_tiles < kMaxSegments ? (n_tiles > 0 ? n_tiles : 1) : kMaxSegments;
+    *nseg = (int32_t)ns;
+    *seg_cap = (int32_t)(((n_tiles + ns - 1) / ns) * kTetsPerTile);
+}
+
 // One period for every tile: period index = sims[i].step0 + iter; the period
-// whose index equals `partial` lasts tau_last instead of tau.  queue holds
-// qcap >= (tets of the work list) int32 entries; qcount[2] alternates between
-// launches (qsel = 0, 1, 0, ...), both zero before the first.
-hipError_t launch_step(const DevSim *sims, const Tile *tiles, int32_t n_tiles, int64_t iter,
-                       int64_t partial, double tau_last, int32_t *queue, int32_t qcap,
-                       int32_t *qcount, int32_t qsel, int32_t scan_grid, int32_t update_grid,
-                       hipStream_t st);
-hipError_t launch_scan(const DevSim *sims, const Tile *tiles, int32_t n_tiles, int64_t iter, int32_t *queue,
-                       int32_t qcap, int32_t *qcount, int32_t qsel, int32_t scan_grid, hipStream_t st);
+// whose index equals `partial` lasts tau_last instead of tau.  Consecutive
+// launches on one queue alternate qsel = 0, 1, 0, ...
+hipError_t launch_scan(const DevSim *sims, const Tile *tiles, int32_t n_tiles, int64_t iter, const QueueView &q,
+                       int32_t qsel, int32_t scan_grid, hipStream_t st);
 hipError_t launch_update(const DevSim *sims, const Tile *tiles, int64_t iter, int64_t partial, double tau_last,
-                         const int32_t *queue, int32_t qcap, int32_t *qcount, int32_t qsel, int32_t update_grid,
-                         hipStream_t st);
+                         const QueueView &q, int32_t qsel, int32_t blocks_per_segment, hipStream_t st);
+hipError_t launch_step(const DevSim *sims, const Tile *tiles, int32_t n_tiles, int64_t iter, int64_t partial,
+                       double tau_last, const QueueView &q, int32_t qsel, int32_t scan_grid,
+                       int32_t blocks_per_segment, hipStream_t st);
 hipError_t launch_advance(DevSim *sims, int32_t n_sims, int64_t by, hipStream_t st);
 hipError_t launch_copy(const void *src, void *dst, size_t bytes, hipStream_t st);
 hipError_t launch_materialize(int32_t *cnt, int32_t *inflow, int64_t n, int32_t *flags,

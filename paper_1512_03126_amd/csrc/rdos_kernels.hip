@@ -182,33 +182,18 @@ __device__ __forceinline__ double propensity(const DevSim &sm, int q, const Lane
 
 __device__ __forceinline__ void update_tet(const DevSim &sm, int32_t t, int64_t period, double tau_k,
                                            uint32_t key1, int32_t *__restrict__ cnt,
-                                           int32_t *__restrict__ in_cur, int32_t *__restrict__ in_nxt,
-                                           int64_t Tp, const LaneState &ls)
+                                           int32_t *__restrict__ in_nxt, int64_t Tp, const LaneState &ls)
 {
     const int S = sm.S;
     const int R = sm.R;
     const uint32_t period32 = (uint32_t)period;
-    int32_t N_base[kMaxSpecies];
-#pragma unroll
-    for (int s = 0; s < kMaxSpecies; ++s) {
-        N_base[s] = 0;
-        if (s < S) {
-            const int32_t c = cnt[s * Tp + t];
-            const int32_t f = in_cur[s * Tp + t];
-            if (f != 0) in_cur[s * Tp + t] = 0;
-            const int64_t sum = (int64_t)c + (int64_t)f;
-            if (sum > 0x7fffffff) atomicOr(sm.flags, 1);
-            N_base[s] = c;
-            ls.n(s) = (int32_t)sum;
-        }
-    }
     const MeshRec &mr = sm.mesh[t];
     const double nav = mr.nav;
 
     // Step 2: Gillespie direct method over [0, tau_k); the first event at or
     // past tau_k is discarded.  Step 2.1: on each event the occupancy
     // integral of every reactant and product is brought up to the event time.
-    // occ[s] / last[s] are meaningful only once bit s of `touched` is set;
+    // occ/last of species s are meaningful once bit s of `touched` is set;
     // before that they stand for 0 (no stores for tets without events).
     uint32_t touched = 0;
     if (R > 0) {
@@ -270,171 +255,235 @@ __device__ __forceinline__ void update_tet(const DevSim &sm, int32_t t, int64_t 
     bool have_faces = false;
     double g = 0.0;
     for (int s = 0; s < S; ++s) {
-        if (!((sm.diff_mask >> s) & 1u)) continue;
         const int32_t Ns = ls.n(s);
-        if (Ns == 0) continue;  // n = min(binomial(.), 0) = 0: no outflow
-        const bool hit = (touched >> s) & 1u;
-        const double nbar = hit ? (ls.occ[s * kBlock] + (double)Ns * (tau_k - ls.last[s * kBlock])) / tau_k
-                                : (double)Ns;
-        Stream rng(sm.key0, key1, (uint32_t)s, (uint32_t)t, period32);
-        int64_t ni = (int64_t)floor(nbar);
-        const double frac = nbar - (double)ni;
-        if (frac > 0.0 && rng.uniform() < frac) ni += 1;
-        if (!have_faces) {
-            const int4 n4 = *reinterpret_cast<const int4 *>(mr.nbr);
-            nb[0] = n4.x;
-            nb[1] = n4.y;
-            nb[2] = n4.z;
-            nb[3] = n4.w;
+        if (((sm.diff_mask >> s) & 1u) && Ns > 0) {  // Ns == 0: n = min(binomial(.), 0) = 0
+            const bool hit = (touched >> s) & 1u;
+            const double nbar = hit ? (ls.occ[s * kBlock] + (double)Ns * (tau_k - ls.last[s * kBlock])) / tau_k
+                                    : (double)Ns;
+            Stream rng(sm.key0, key1, (uint32_t)s, (uint32_t)t, period32);
+            int64_t ni = (int64_t)floor(nbar);
+            const double frac = nbar - (double)ni;
+            if (frac > 0.0 && rng.uniform() < frac) ni += 1;
+            if (!have_faces) {
+                const int4 n4 = *reinterpret_cast<const int4 *>(mr.nbr);
+                nb[0] = n4.x;
+                nb[1] = n4.y;
+                nb[2] = n4.z;
+                nb[3] = n4.w;
 #pragma unroll
-            for (int f = 0; f < 4; ++f) w[f] = mr.w[f];
-            g = mr.g;
-            have_faces = true;
+                for (int f = 0; f < 4; ++f) w[f] = mr.w[f];
+                g = mr.g;
+                have_faces = true;
+            }
+            double zeta = (tau_k * sm.D[s]) * g;
+            if (zeta > 1.0) zeta = 1.0;
+            int64_t n = binomial(ni, zeta, rng);
+            if (n > Ns) n = Ns;
+            if (n > 0) {
+                int64_t out[4];
+                split_over_faces(n, nb, w, rng, out);
+#pragma unroll
+                for (int f = 0; f < 4; ++f)
+                    if (out[f] > 0) atomicAdd(&in_nxt[s * Tp + nb[f]], (int32_t)out[f]);
+                ls.n(s) = Ns - (int32_t)n;
+            }
         }
-        double zeta = (tau_k * sm.D[s]) * g;
-        if (zeta > 1.0) zeta = 1.0;
-        int64_t n = binomial(ni, zeta, rng);
-        if (n > Ns) n = Ns;
-        if (n == 0) continue;
-        int64_t out[4];
-        split_over_faces(n, nb, w, rng, out);
-#pragma unroll
-        for (int f = 0; f < 4; ++f)
-            if (out[f] > 0) atomicAdd(&in_nxt[s * Tp + nb[f]], (int32_t)out[f]);
-        ls.n(s) = Ns - (int32_t)n;
+        cnt[s * Tp + t] = ls.n(s);
     }
-
-#pragma unroll
-    for (int s = 0; s < kMaxSpecies; ++s)
-        if (s < S && ls.n(s) != N_base[s]) cnt[s * Tp + t] = ls.n(s);
 }
 
 // Each period is two launches.
 //  scan:   every lane reads four consecutive tets of every species (16-byte
-//          loads of cnt and inflow) and the block appends the tets holding
-//          any molecule (all tets if a reaction has no reactant) to a queue;
+//          loads of cnt and inflow).  Each wavefront compacts its tets that
+//          hold any molecule (all tets if a reaction has no reactant) with
+//          ballots, reserves room with one atomic on its queue segment and
+//          writes the tet and its counts (cnt + arrivals) to the queue; the
+//          arrivals it consumed are cleared.
 //  update: the queued tets run Steps 2-3 with every lane busy.
-// The queue length lives in qcount[qsel]; the update launch clears
-// qcount[qsel ^ 1] for the next scan, so consecutive launches alternate qsel.
+// The queue has nseg segments of seg_cap entries (tiles ti with
+// ti % nseg == k fill segment k, so seg_cap = tets of those tiles suffices);
+// entry i of segment k is qtet[k * seg_cap + i] with counts
+// qcnt[s * qcap + k * seg_cap + i].  Segment lengths live in
+// qcount[qsel * nseg + k]; the update launch clears the other half for the
+// next scan, so consecutive launches alternate qsel.
+struct Queue {
+    int32_t *tet;     // [qcap]
+    int32_t *counts;  // [max species][qcap]
+    int32_t *len;     // [2][nseg]
+    int32_t nseg;
+    int32_t seg_cap;
+    int64_t qcap;     // nseg * seg_cap
+};
+
+template <int MAXS>
 __global__ __launch_bounds__(kBlock) void scan_kernel(const DevSim *__restrict__ sims,
                                                       const Tile *__restrict__ tiles, int32_t n_tiles,
-                                                      int64_t iter, int32_t *__restrict__ queue,
-                                                      int32_t *__restrict__ qcount, int32_t qsel,
-                                                      int32_t qcap)
+                                                      int64_t iter, Queue q, int32_t qsel)
 {
-    __shared__ int32_t n_active;
-    __shared__ int32_t block_base;
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+    const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
     for (int32_t ti = blockIdx.x; ti < n_tiles; ti += gridDim.x) {
         const Tile tile = tiles[ti];
         const DevSim &sm = sims[tile.sim];
         const int64_t period = sm.step0 + iter;
         if (period >= sm.step_end) continue;  // uniform over the block
+        const int32_t wave_off = wave * 64 * kTetsPerLane;
+        if (wave_off >= tile.ntet) continue;  // uniform over the wavefront
+        const int S = sm.S;
         const int64_t Tp = ((int64_t)sm.T + 3) & ~(int64_t)3;
-        const int64_t base = (int64_t)tile.realization * sm.S * Tp;
+        const int64_t base = (int64_t)tile.realization * S * Tp;
         const int32_t *cnt = sm.cnt + base;
-        const int32_t *in_cur = sm.inflow[period & 1] + base;
-
-        if (threadIdx.x == 0) n_active = 0;
-        __syncthreads();
-        const int32_t off = threadIdx.x * kTetsPerLane;
-        uint32_t bits = 0;
-        if (off < tile.ntet) {
-            const int64_t t4 = tile.tet0 + off;
-            for (int s = 0; s < sm.S; ++s) {
-                const int4 c = *reinterpret_cast<const int4 *>(cnt + s * Tp + t4);
-                const int4 f = *reinterpret_cast<const int4 *>(in_cur + s * Tp + t4);
-                bits |= (uint32_t)((c.x | f.x) != 0) | ((uint32_t)((c.y | f.y) != 0) << 1) |
-                        ((uint32_t)((c.z | f.z) != 0) << 2) | ((uint32_t)((c.w | f.w) != 0) << 3);
-            }
-            if (sm.zeroth) bits = 0xFu;
-            const int32_t valid = tile.ntet - off;  // tets of this lane inside the tile
-            if (valid < 4) bits &= (1u << valid) - 1u;
-        }
-        int pos = 0;
-        if (bits) pos = atomicAdd(&n_active, __popc(bits));
-        __syncthreads();
-        if (threadIdx.x == 0) block_base = n_active ? atomicAdd(&qcount[qsel], n_active) : 0;
-        __syncthreads();
-        if (bits && block_base + pos + __popc(bits) <= qcap) {  // qcap bounds every write
-            int32_t *dst = queue + block_base + pos;
-            int q = 0;
+        int32_t *in_cur = sm.inflow[period & 1] + base;
+        const int32_t off = wave_off + lane * kTetsPerLane;
+        const int64_t t4 = tile.tet0 + off;
+        const bool mine = off < tile.ntet;
+        int4 c[MAXS], f[MAXS];
 #pragma unroll
-            for (int b = 0; b < 4; ++b)
-                if ((bits >> b) & 1u) dst[q++] = ti * kTetsPerTile + off + b;
+        for (int s = 0; s < MAXS; ++s) {
+            c[s] = make_int4(0, 0, 0, 0);
+            f[s] = make_int4(0, 0, 0, 0);
+            if (s < S && mine) {
+                c[s] = *reinterpret_cast<const int4 *>(cnt + s * Tp + t4);
+                f[s] = *reinterpret_cast<const int4 *>(in_cur + s * Tp + t4);
+            }
         }
-        __syncthreads();
+        uint32_t bits = 0;
+#pragma unroll
+        for (int s = 0; s < MAXS; ++s)
+            bits |= (uint32_t)((c[s].x | f[s].x) != 0) | ((uint32_t)((c[s].y | f[s].y) != 0) << 1) |
+                    ((uint32_t)((c[s].z | f[s].z) != 0) << 2) | ((uint32_t)((c[s].w | f[s].w) != 0) << 3);
+        if (sm.zeroth) bits = 0xFu;
+        if (!mine) bits = 0;
+        const int32_t valid = tile.ntet - off;  // tets of this lane inside the tile
+        if (valid < 4) bits &= (1u << (valid > 0 ? valid : 0)) - 1u;
+        // positions: bit plane b of all lanes after bit planes < b
+        uint64_t plane[4];
+        int32_t before[4];
+        int32_t total = 0;
+#pragma unroll
+        for (int b = 0; b < 4; ++b) {
+            plane[b] = __ballot((bits >> b) & 1u);
+            before[b] = total;
+            total += __popcll(plane[b]);
+        }
+        if (total == 0) continue;  // uniform over the wavefront
+        const int32_t seg = ti % q.nseg;
+        int32_t slot = 0;
+        if (lane == 0) slot = atomicAdd(&q.len[qsel * q.nseg + seg], total);
+        slot = __shfl(slot, 0);
+        if (slot + total > q.seg_cap) {  // cannot happen when len starts at 0; never write past
+            if (lane == 0) atomicOr(sm.flags, 4);
+            continue;
+        }
+        const int64_t seg_base = (int64_t)seg * q.seg_cap + slot;
+#pragma unroll
+        for (int b = 0; b < 4; ++b) {
+            if (!((bits >> b) & 1u)) continue;
+            const int64_t idx = seg_base + before[b] + __popcll(plane[b] & below);
+            q.tet[idx] = ti * kTetsPerTile + off + b;
+#pragma unroll
+            for (int s = 0; s < MAXS; ++s) {
+                if (s >= S) break;
+                const int32_t cv = b == 0 ? c[s].x : b == 1 ? c[s].y : b == 2 ? c[s].z : c[s].w;
+                const int32_t fv = b == 0 ? f[s].x : b == 1 ? f[s].y : b == 2 ? f[s].z : f[s].w;
+                const int64_t sum = (int64_t)cv + (int64_t)fv;
+                if (sum > 0x7fffffff) atomicOr(sm.flags, 1);
+                q.counts[s * q.qcap + idx] = (int32_t)sum;
+                if (fv != 0) in_cur[s * Tp + t4 + b] = 0;
+            }
+        }
     }
 }
 
 __global__ __launch_bounds__(kBlock) void update_kernel(const DevSim *__restrict__ sims,
-                                                        const Tile *__restrict__ tiles,
-                                                        const int32_t *__restrict__ queue,
-                                                        int32_t *__restrict__ qcount, int32_t qsel,
-                                                        int32_t qcap, int64_t iter, int64_t partial,
-                                                        double tau_last)
+                                                        const Tile *__restrict__ tiles, Queue q, int32_t qsel,
+                                                        int64_t iter, int64_t partial, double tau_last)
 {
     __shared__ double occ[kMaxSpecies * kBlock];
     __shared__ double last[kMaxSpecies * kBlock];
     __shared__ int32_t counts[kMaxSpecies * kBlock];
     const LaneState ls{counts + threadIdx.x, occ + threadIdx.x, last + threadIdx.x};
-    if (blockIdx.x == 0 && threadIdx.x == 0) qcount[qsel ^ 1] = 0;
-    const int32_t n = min(qcount[qsel], qcap);
-    for (int32_t i = blockIdx.x * kBlock + threadIdx.x; i < n; i += gridDim.x * kBlock) {
-        const int32_t entry = queue[i];
+    if (blockIdx.x == 0 && threadIdx.x < q.nseg) q.len[(qsel ^ 1) * q.nseg + threadIdx.x] = 0;
+    const int32_t seg = blockIdx.x % q.nseg;
+    const int32_t per_seg = max(1, (int32_t)(gridDim.x / q.nseg));  // blocks sharing a segment
+    const int32_t part = blockIdx.x / q.nseg;
+    if (part >= per_seg) return;
+    const int32_t n = min(q.len[qsel * q.nseg + seg], q.seg_cap);
+    for (int32_t i = part * kBlock + threadIdx.x; i < n; i += per_seg * kBlock) {
+        const int64_t idx = (int64_t)seg * q.seg_cap + i;
+        const int32_t entry = q.tet[idx];
         const Tile tile = tiles[entry / kTetsPerTile];
         const DevSim &sm = sims[tile.sim];
         const int64_t period = sm.step0 + iter;
         const double tau_k = period == partial ? tau_last : sm.tau;
         const int64_t Tp = ((int64_t)sm.T + 3) & ~(int64_t)3;
         const int64_t base = (int64_t)tile.realization * sm.S * Tp;
+        for (int s = 0; s < sm.S; ++s) ls.n(s) = q.counts[s * q.qcap + idx];
         update_tet(sm, tile.tet0 + entry % kTetsPerTile, period, tau_k, sm.key1 ^ (uint32_t)tile.realization,
-                   sm.cnt + base, sm.inflow[period & 1] + base, sm.inflow[(period + 1) & 1] + base, Tp, ls);
+                   sm.cnt + base, sm.inflow[(period + 1) & 1] + base, Tp, ls);
     }
 }
 
-hipError_t launch_scan(const DevSim *sims, const Tile *tiles, int32_t n_tiles, int64_t iter, int32_t *queue,
-                       int32_t qcap, int32_t *qcount, int32_t qsel, int32_t scan_grid, hipStream_t st)
+hipError_t launch_scan(const DevSim *sims, const Tile *tiles, int32_t n_tiles, int64_t iter, const QueueView &qv,
+                       int32_t qsel, int32_t scan_grid, hipStream_t st)
 {
     if (n_tiles <= 0) return hipSuccess;
     const int32_t g = scan_grid > 0 ? (scan_grid < n_tiles ? scan_grid : n_tiles) : n_tiles;
-    scan_kernel<<<g, kBlock, 0, st>>>(sims, tiles, n_tiles, iter, queue, qcount, qsel, qcap);
+    const Queue q{qv.tet, qv.counts, qv.len, qv.nseg, qv.seg_cap, (int64_t)qv.nseg * qv.seg_cap};
+    // register arrays sized for the largest species count of the work list
+    if (qv.species <= 2)
+        scan_kernel<2><<<g, kBlock, 0, st>>>(sims, tiles, n_tiles, iter, q, qsel);
+    else if (qv.species <= 4)
+        scan_kernel<4><<<g, kBlock, 0, st>>>(sims, tiles, n_tiles, iter, q, qsel);
+    else
+        scan_kernel<kMaxSpecies><<<g, kBlock, 0, st>>>(sims, tiles, n_tiles, iter, q, qsel);
     return hipGetLastError();
 }
 
 hipError_t launch_update(const DevSim *sims, const Tile *tiles, int64_t iter, int64_t partial, double tau_last,
-                         const int32_t *queue, int32_t qcap, int32_t *qcount, int32_t qsel, int32_t update_grid,
-                         hipStream_t st)
+                         const QueueView &qv, int32_t qsel, int32_t blocks_per_segment, hipStream_t st)
 {
-    update_kernel<<<update_grid > 0 ? update_grid : 1024, kBlock, 0, st>>>(sims, tiles, queue, qcount, qsel, qcap,
-                                                                         iter, partial, tau_last);
+    const Queue q{qv.tet, qv.counts, qv.len, qv.nseg, qv.seg_cap, (int64_t)qv.nseg * qv.seg_cap};
+    const int32_t bps = blocks_per_segment > 0 ? blocks_per_segment : 4;
+    update_kernel<<<qv.nseg * bps, kBlock, 0, st>>>(sims, tiles, q, qsel, iter, partial, tau_last);
     return hipGetLastError();
 }
 
 hipError_t launch_step(const DevSim *sims, const Tile *tiles, int32_t n_tiles, int64_t iter, int64_t partial,
-                       double tau_last, int32_t *queue, int32_t qcap, int32_t *qcount, int32_t qsel,
-                       int32_t scan_grid, int32_t update_grid, hipStream_t st)
+                       double tau_last, const QueueView &qv, int32_t qsel, int32_t scan_grid,
+                       int32_t blocks_per_segment, hipStream_t st)
 {
     if (n_tiles <= 0) return hipSuccess;
-    hipError_t e = launch_scan(sims, tiles, n_tiles, iter, queue, qcap, qcount, qsel, scan_grid, st);
+    hipError_t e = launch_scan(sims, tiles, n_tiles, iter, qv, qsel, scan_grid, st);
     if (e != hipSuccess) return e;
-    return launch_update(sims, tiles, iter, partial, tau_last, queue, qcap, qcount, qsel, update_grid, st);
+    return launch_update(sims, tiles, iter, partial, tau_last, qv, qsel, blocks_per_segment, st);
 }
 
 // Streaming copy used to measure the device's achievable HBM bandwidth (and
-// to calibrate byte counters): 16-byte loads and stores, grid-stride.
+// to calibrate byte counters): four independent 16-byte loads per lane in
+// flight, then four stores, grid-stride.
 __global__ __launch_bounds__(256) void bandwidth_copy_kernel(const int4 *__restrict__ src, int4 *__restrict__ dst,
                                                             int64_t n)
 {
-    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
-        dst[i] = src[i];
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    for (; i + 3 * stride < n; i += 4 * stride) {
+        const int4 a = src[i], b = src[i + stride], c = src[i + 2 * stride], d = src[i + 3 * stride];
+        dst[i] = a;
+        dst[i + stride] = b;
+        dst[i + 2 * stride] = c;
+        dst[i + 3 * stride] = d;
+    }
+    for (; i < n; i += stride) dst[i] = src[i];
 }
 
 hipError_t launch_copy(const void *src, void *dst, size_t bytes, hipStream_t st)
 {
     const int64_t n = (int64_t)(bytes / sizeof(int4));
     if (n <= 0) return hipSuccess;
-    int64_t blocks = (n + 255) / 256;
-    if (blocks > 8192) blocks = 8192;
+    int64_t blocks = (n + 1023) / 1024;
+    if (blocks > 16384) blocks = 16384;
     bandwidth_copy_kernel<<<(int)blocks, 256, 0, st>>>((const int4 *)src, (int4 *)dst, n);
     return hipGetLastError();
 }

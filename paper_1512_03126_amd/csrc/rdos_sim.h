@@ -56,10 +56,9 @@ struct rdos_sim {
     rdos::DevSim *d_desc = nullptr;
     rdos::Tile *d_tiles = nullptr;
     int32_t n_tiles = 0;
-    int32_t *d_queue = nullptr;   // occupied tets of one period, one int32 per tet of the work list
-    int32_t *d_qcount = nullptr;  // [2] queue lengths, alternating between launches
-    int64_t launches = 0;         // periods launched on this handle (selects the queue length slot)
-    int32_t update_grid = 1024;   // blocks of the update launch
+    rdos::QueueView queue{};      // occupied tets of one period (tet ids + counts + segment lengths)
+    int64_t launches = 0;         // periods launched on this handle (selects the queue length half)
+    int32_t update_bps = 4;       // update blocks per queue segment
     rdos::DevSim desc{};
 };
 
@@ -68,6 +67,9 @@ rdos_status fail(rdos_sim *s, rdos_status code, const char *fmt, ...);
 rdos_status hip_fail(rdos_sim *s, hipError_t e, const char *what);
 int64_t padded_tets(int32_t T);
 size_t state_bytes(const rdos_sim *s);
+size_t queue_bytes(int64_t n_tiles, int32_t n_species);
+hipError_t alloc_queue(rdos::QueueView *q, int64_t n_tiles, int32_t n_species);
+void free_queue(rdos::QueueView *q);
 rdos_status fold_inflow(rdos_sim *s);
 rdos_status check_flags(rdos_sim *s);
 double time_of(const rdos_sim *s, int64_t k);
