@@ -184,6 +184,8 @@ def main():
         except Exception as ex:  # informational only
             log(f"bandwidth probe failed: {ex}")
         st = P.rdos_engine_stats(e)
+        shape = P.rdos_engine_launch_shape(e)
+        log(f"tuned launch shape: {shape}")
         P.rdos_engine_destroy(e)
         for s in sims:
             s.close()
@@ -192,7 +194,7 @@ def main():
         config = {"workload": workload, "tets": [384000, 48000], "realizations": [256, 64], "species": 3,
                   "periods": K, "tau_s": 2.958758547680654e-4, "updates_per_period": upd_per_period,
                   "realizations_per_s": round(320.0 / (ms_step * 1e-3 * 338), 3),
-                  "engine_launches": st["launches"]}
+                  "engine_launches": st["launches"], "launch_shape": shape}
         if plain:
             config["plain_updates_per_s"] = round(plain["value"], 1)
             config["plain_ms_per_step"] = round(plain["ms_per_step"], 4)

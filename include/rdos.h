@@ -175,6 +175,12 @@ rdos_status rdos_engine_set_profiling(rdos_engine *e, int on);
 rdos_status rdos_engine_kernel_times(rdos_engine *e, double *scan_ms, int64_t *scan_launches,
                                      double *update_ms, int64_t *update_launches);
 
+/* The launch shape the tuner settled on for the current work list: periods
+ * per graph replay, scan blocks (0 = one per tile), update blocks per queue
+ * segment.  Results never depend on it. */
+rdos_status rdos_engine_launch_shape(rdos_engine *e, int32_t *chunk, int32_t *scan_grid,
+                                     int32_t *update_bps);
+
 /* Measures the device's streaming copy bandwidth (read + write bytes per
  * second / 1e9) with a 16-byte-per-lane copy kernel over `bytes`, `reps`
  * times.  The same kernel calibrates hardware byte counters. */

@@ -59,6 +59,7 @@ _SIGS = [
     ("rdos_engine_drain", C.c_int, [C.c_void_p]),
     ("rdos_engine_release", C.c_int, [C.c_void_p, C.c_uint64, _P(C.c_void_p)]),
     ("rdos_engine_stats", C.c_int, [C.c_void_p, _P(C.c_int64), _P(C.c_double), _P(C.c_double)]),
+    ("rdos_engine_launch_shape", C.c_int, [C.c_void_p, _P(C.c_int32), _P(C.c_int32), _P(C.c_int32)]),
     ("rdos_engine_set_profiling", C.c_int, [C.c_void_p, C.c_int]),
     ("rdos_engine_kernel_times", C.c_int, [C.c_void_p, _P(C.c_double), _P(C.c_int64), _P(C.c_double),
                                            _P(C.c_int64)]),
@@ -254,6 +255,12 @@ def rdos_engine_stats(engine):
     b = C.c_double()
     _check(lib().rdos_engine_stats(engine, C.byref(n), C.byref(u), C.byref(b)), engine, True)
     return dict(launches=n.value, updates=u.value, busy_s=b.value)
+
+
+def rdos_engine_launch_shape(engine):
+    a, b, c = C.c_int32(), C.c_int32(), C.c_int32()
+    _check(lib().rdos_engine_launch_shape(engine, C.byref(a), C.byref(b), C.byref(c)), engine, True)
+    return dict(chunk=a.value, scan_grid=b.value, update_blocks_per_segment=c.value)
 
 
 def rdos_engine_set_profiling(engine, on: bool):

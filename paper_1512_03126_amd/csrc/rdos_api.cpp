@@ -48,7 +48,8 @@ size_t queue_bytes(int64_t n_tiles, int32_t n_species)
 {
     int32_t nseg, seg_cap;
     queue_shape(n_tiles, &nseg, &seg_cap);
-    return (size_t)nseg * seg_cap * (1 + (size_t)n_species) * sizeof(int32_t) + 2 * (size_t)nseg * sizeof(int32_t);
+    return (size_t)nseg * seg_cap * (1 + (size_t)n_species) * sizeof(int32_t) +
+           2 * (size_t)nseg * kLenStride * sizeof(int32_t);
 }
 
 hipError_t alloc_queue(QueueView *q, int64_t n_tiles, int32_t n_species)
@@ -58,8 +59,9 @@ hipError_t alloc_queue(QueueView *q, int64_t n_tiles, int32_t n_species)
     const size_t cap = (size_t)q->nseg * q->seg_cap;
     hipError_t e = hipMalloc(&q->tet, cap * sizeof(int32_t));
     if (e == hipSuccess) e = hipMalloc(&q->counts, cap * (size_t)std::max(n_species, 1) * sizeof(int32_t));
-    if (e == hipSuccess) e = hipMalloc(&q->len, 2 * (size_t)q->nseg * sizeof(int32_t));
-    if (e == hipSuccess) e = hipMemset(q->len, 0, 2 * (size_t)q->nseg * sizeof(int32_t));
+    const size_t len_bytes = 2 * (size_t)q->nseg * kLenStride * sizeof(int32_t);
+    if (e == hipSuccess) e = hipMalloc(&q->len, len_bytes);
+    if (e == hipSuccess) e = hipMemset(q->len, 0, len_bytes);
     return e;
 }
 
@@ -78,7 +80,7 @@ size_t state_bytes(const rdos_sim *s)
     const int64_t Tp = padded_tets(s->T);
     const size_t counts = (size_t)s->Rz * s->D.size() * (size_t)Tp * sizeof(int32_t);
     const size_t tiles = (size_t)tiles_of(s) * sizeof(Tile);
-    return (size_t)s->T * sizeof(MeshRec) + 3 * counts + tiles + queue_bytes(tiles_of(s), (int32_t)s->D.size()) +
+    return (size_t)s->T * sizeof(MeshRec) + 2 * counts + tiles + queue_bytes(tiles_of(s), (int32_t)s->D.size()) +
            sizeof(DevSim) + 64;
 }
 
@@ -136,14 +138,15 @@ rdos_status upload_desc(rdos_sim *s)
     return RDOS_OK;
 }
 
-rdos_status fold_inflow(rdos_sim *s)
+// The kernels read the state of period k from buf[k & 1]; the descriptor's
+// buf[] follows the handle's buffers, which swap when set_state changes the
+// parity of the period index (the other buffer is all zero between periods).
+rdos_status match_parity(rdos_sim *s)
 {
-    if (!s->dirty) return RDOS_OK;
-    const int64_t n = (int64_t)s->Rz * (int64_t)s->D.size() * padded_tets(s->T);
-    int32_t *pending = s->d_inflow[s->step & 1];
-    HIP_TRY(s, launch_materialize(s->d_cnt, pending, n, s->d_flags, s->stream), "fold arrivals");
-    s->dirty = false;
-    return RDOS_OK;
+    if (s->desc.buf[0] == s->d_buf[0] && s->desc.buf[1] == s->d_buf[1]) return RDOS_OK;
+    s->desc.buf[0] = s->d_buf[0];
+    s->desc.buf[1] = s->d_buf[1];
+    return upload_desc(s);
 }
 
 rdos_status check_flags(rdos_sim *s)
@@ -166,7 +169,6 @@ rdos_status enqueue_period(rdos_sim *s, int64_t period, int64_t partial, double 
                            (int32_t)(s->launches & 1), 0, s->update_bps, s->stream),
             "launch period");
     s->launches += 1;
-    s->dirty = true;
     return RDOS_OK;
 }
 
@@ -179,12 +181,12 @@ void free_device(rdos_sim *s)
 {
     (void)hipSetDevice(s->device);
     if (s->stream && s->own_stream) (void)hipStreamSynchronize(s->stream);
-    void *ptrs[] = {s->d_mesh, s->d_cnt, s->d_inflow[0], s->d_inflow[1], s->d_flags, s->d_desc, s->d_tiles};
+    void *ptrs[] = {s->d_mesh, s->d_buf[0], s->d_buf[1], s->d_flags, s->d_desc, s->d_tiles};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
     free_queue(&s->queue);
     s->d_mesh = nullptr;
-    s->d_cnt = s->d_inflow[0] = s->d_inflow[1] = s->d_flags = nullptr;
+    s->d_buf[0] = s->d_buf[1] = s->d_flags = nullptr;
     s->d_desc = nullptr;
     s->d_tiles = nullptr;
     if (s->stream && s->own_stream) (void)hipStreamDestroy(s->stream);
@@ -320,9 +322,8 @@ rdos_status rdos_finalize(rdos_sim *s, double tau_scale, double *out_tau)
         }                                \
     } while (0)
     SETUP_TRY(hipMalloc(&s->d_mesh, (size_t)T * sizeof(MeshRec)), "allocate mesh tables");
-    SETUP_TRY(hipMalloc(&s->d_cnt, count_bytes), "allocate counts");
-    SETUP_TRY(hipMalloc(&s->d_inflow[0], count_bytes), "allocate arrivals");
-    SETUP_TRY(hipMalloc(&s->d_inflow[1], count_bytes), "allocate arrivals");
+    SETUP_TRY(hipMalloc(&s->d_buf[0], count_bytes), "allocate counts");
+    SETUP_TRY(hipMalloc(&s->d_buf[1], count_bytes), "allocate counts");
     SETUP_TRY(hipMalloc(&s->d_flags, 64), "allocate flags");
     SETUP_TRY(hipMalloc(&s->d_desc, sizeof(DevSim)), "allocate descriptor");
     SETUP_TRY(alloc_queue(&s->queue, tiles_of(s), S), "allocate queue");
@@ -334,9 +335,8 @@ rdos_status rdos_finalize(rdos_sim *s, double tau_scale, double *out_tau)
     SETUP_TRY(hipMalloc(&d_area, (size_t)T * 4 * sizeof(double)), "allocate set-up");
     SETUP_TRY(hipMalloc(&d_D, (size_t)S * sizeof(double)), "allocate set-up");
     SETUP_TRY(hipMalloc(&d_tau, sizeof(unsigned long long) + 8), "allocate set-up");
-    SETUP_TRY(hipMemsetAsync(s->d_cnt, 0, count_bytes, s->stream), "clear counts");
-    SETUP_TRY(hipMemsetAsync(s->d_inflow[0], 0, count_bytes, s->stream), "clear arrivals");
-    SETUP_TRY(hipMemsetAsync(s->d_inflow[1], 0, count_bytes, s->stream), "clear arrivals");
+    SETUP_TRY(hipMemsetAsync(s->d_buf[0], 0, count_bytes, s->stream), "clear counts");
+    SETUP_TRY(hipMemsetAsync(s->d_buf[1], 0, count_bytes, s->stream), "clear counts");
     SETUP_TRY(hipMemsetAsync(s->d_flags, 0, 64, s->stream), "clear flags");
     SETUP_TRY(hipMemsetAsync(d_tau, 0xff, sizeof(unsigned long long), s->stream), "clear tau");
     SETUP_TRY(hipMemcpyAsync(d_xyz, s->xyz.data(), s->xyz.size() * sizeof(double), hipMemcpyHostToDevice, s->stream),
@@ -375,9 +375,8 @@ rdos_status rdos_finalize(rdos_sim *s, double tau_scale, double *out_tau)
     DevSim &d = s->desc;
     std::memset(&d, 0, sizeof d);
     d.mesh = s->d_mesh;
-    d.cnt = s->d_cnt;
-    d.inflow[0] = s->d_inflow[0];
-    d.inflow[1] = s->d_inflow[1];
+    d.buf[0] = s->d_buf[0];
+    d.buf[1] = s->d_buf[1];
     d.flags = s->d_flags;
     d.T = T;
     d.S = S;
@@ -433,11 +432,10 @@ rdos_status rdos_finalize(rdos_sim *s, double tau_scale, double *out_tau)
     s->step = 0;
     s->anchor_step = 0;
     s->anchor_t = 0.0;
-    s->dirty = false;
     // counts staged before finalize
     for (auto &kv : s->staged) {
         const int32_t r = kv.first / kMaxSpecies, m = kv.first % kMaxSpecies;
-        int32_t *dst = s->d_cnt + ((int64_t)r * S + m) * Tp;
+        int32_t *dst = s->d_buf[0] + ((int64_t)r * S + m) * Tp;
         HIP_TRY(s, hipMemcpyAsync(dst, kv.second.data(), (size_t)T * sizeof(int32_t), hipMemcpyHostToDevice, s->stream),
                 "upload counts");
     }
@@ -467,9 +465,7 @@ rdos_status rdos_set_counts(rdos_sim *s, int32_t realization, int32_t species, c
         return RDOS_OK;
     }
     HIP_TRY(s, hipSetDevice(s->device), "set device");
-    rdos_status st = fold_inflow(s);
-    if (st != RDOS_OK) return st;
-    int32_t *dst = s->d_cnt + ((int64_t)realization * (int64_t)s->D.size() + species) * padded_tets(s->T);
+    int32_t *dst = s->d_buf[s->step & 1] + ((int64_t)realization * (int64_t)s->D.size() + species) * padded_tets(s->T);
     HIP_TRY(s, hipMemcpyAsync(dst, counts, (size_t)s->T * sizeof(int32_t), hipMemcpyHostToDevice, s->stream),
             "upload counts");
     HIP_TRY(s, hipStreamSynchronize(s->stream), "upload counts");
@@ -483,9 +479,8 @@ rdos_status rdos_get_counts(rdos_sim *s, int32_t realization, int32_t species, i
     if (realization < 0 || realization >= s->Rz || species < 0 || species >= (int32_t)s->D.size() || !out)
         return fail(s, RDOS_EINVAL, "realization or species out of range");
     HIP_TRY(s, hipSetDevice(s->device), "set device");
-    rdos_status st = fold_inflow(s);
-    if (st != RDOS_OK) return st;
-    const int32_t *src = s->d_cnt + ((int64_t)realization * (int64_t)s->D.size() + species) * padded_tets(s->T);
+    const int32_t *src =
+        s->d_buf[s->step & 1] + ((int64_t)realization * (int64_t)s->D.size() + species) * padded_tets(s->T);
     HIP_TRY(s, hipMemcpyAsync(out, src, (size_t)s->T * sizeof(int32_t), hipMemcpyDeviceToHost, s->stream),
             "download counts");
     return check_flags(s);
@@ -497,13 +492,12 @@ rdos_status rdos_set_state(rdos_sim *s, int64_t step_index, double t)
     if (s->state != SimState::Ready) return fail(s, RDOS_ESTATE, "set_state before finalize");
     if (step_index < 0 || !std::isfinite(t)) return fail(s, RDOS_EINVAL, "bad state");
     HIP_TRY(s, hipSetDevice(s->device), "set device");
-    rdos_status st = fold_inflow(s);  // pending arrivals belong to the old index's parity
-    if (st != RDOS_OK) return st;
     HIP_TRY(s, hipStreamSynchronize(s->stream), "set state");
+    if ((step_index & 1) != (s->step & 1)) std::swap(s->d_buf[0], s->d_buf[1]);  // the state moves with k & 1
     s->step = step_index;
     s->anchor_step = step_index;
     s->anchor_t = t;
-    return RDOS_OK;
+    return match_parity(s);
 }
 
 rdos_status rdos_get_time(rdos_sim *s, double *t, int64_t *step_index)

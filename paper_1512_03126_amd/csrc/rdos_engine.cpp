@@ -176,7 +176,8 @@ rdos_status build_work(rdos_engine *e)
         e->queue_tiles = nt;
         e->queue_species = max_species;
     } else {
-        ENGINE_HIP(e, hipMemsetAsync(e->queue.len, 0, 2 * (size_t)e->queue.nseg * sizeof(int32_t), e->stream),
+        ENGINE_HIP(e, hipMemsetAsync(e->queue.len, 0, 2 * (size_t)e->queue.nseg * kLenStride * sizeof(int32_t),
+                                     e->stream),
                    "clear queue");
     }
     if (!sims.empty())
@@ -267,8 +268,6 @@ void admit(rdos_engine *e, std::unique_lock<std::mutex> &lk)
             }
         }
         if (ok) {
-            // pending arrivals of direct stepping belong to this index's parity, which the
-            // engine keeps; nothing to fold
             tk.end_step = s->step + tk.n_steps;
             if (tk.n_steps == 0) {
                 tk.done = true;
@@ -393,7 +392,6 @@ void worker_main(rdos_engine *e)
             Ticket &tk = e->tickets[id];
             rdos_sim *s = tk.sim;
             s->step = std::min<int64_t>(s->step + sh.chunk, tk.end_step);
-            s->dirty = true;
             if (s->step >= tk.end_step) {
                 tk.done = true;
                 tk.finished = now;
@@ -435,7 +433,7 @@ rdos_status rdos_engine_create(rdos_engine **out, int device, size_t hbm_budget_
         delete e;
         return RDOS_EDEVICE;
     }
-    e->candidates = {{16, 0, 4}, {16, 0, 8}, {16, 2048, 4}, {16, 4096, 8}, {32, 0, 8}};
+    e->candidates = {{16, 0, 4}, {16, 0, 8}, {16, 8192, 4}, {16, 2048, 8}, {32, 0, 8}};
     e->worker = std::thread(worker_main, e);
     *out = e;
     return RDOS_OK;
@@ -522,6 +520,16 @@ rdos_status rdos_engine_stats(rdos_engine *e, int64_t *launches, double *updates
     if (launches) *launches = e->launches;
     if (updates) *updates = e->updates;
     if (busy_s) *busy_s = e->busy_s;
+    return RDOS_OK;
+}
+
+rdos_status rdos_engine_launch_shape(rdos_engine *e, int32_t *chunk, int32_t *scan_grid, int32_t *update_bps)
+{
+    if (!e) return RDOS_EINVAL;
+    std::lock_guard<std::mutex> g(e->mu);
+    if (chunk) *chunk = e->best.chunk;
+    if (scan_grid) *scan_grid = e->best.scan_grid;
+    if (update_bps) *update_bps = e->best.update_bps;
     return RDOS_OK;
 }
 

@@ -29,8 +29,7 @@ static_assert(sizeof(MeshRec) == 64, "MeshRec must be one cache line");
 // One simulation as the step kernel sees it (device memory).
 struct alignas(16) DevSim {
     const MeshRec *mesh;       // [T]
-    int32_t *cnt;              // [Rz][S][T] counts after the last period's outflow
-    int32_t *inflow[2];        // [Rz][S][T] arrivals; period k reads inflow[k & 1]
+    int32_t *buf[2];           // [Rz][S][Tp] counts; period k reads buf[k & 1] and fills buf[(k + 1) & 1]
     int32_t *flags;            // bit 0: count overflow; bit 1: SSA event cap; bit 2: queue overflow
     int32_t T, S, R, Rz;
     uint32_t key0, key1;       // Philox key words before the realization is mixed in
@@ -71,12 +70,14 @@ hipError_t launch_tau_min(const MeshRec *mesh, int32_t T, const double *D, int32
 struct QueueView {
     int32_t *tet;     // [nseg * seg_cap] tile * kTetsPerTile + offset
     int32_t *counts;  // [species][nseg * seg_cap] counts at the start of the period
-    int32_t *len;     // [2][nseg] segment lengths, both halves zero before the first launch
+    int32_t *len;     // [2][nseg] segment lengths, one per kLenStride ints (own cache line);
+                      // both halves zero before the first launch
     int32_t nseg;     // 1..kMaxSegments
     int32_t seg_cap;  // entries per segment
     int32_t species;  // rows of counts: the largest species count of the work list
 };
 constexpr int kMaxSegments = 256;
+constexpr int kLenStride = 32;  // 128 bytes between segment lengths: no two share a line
 
 // Queue geometry for a work list of n_tiles tiles.
 inline void queue_shape(int64_t n_tiles, int32_t *nseg, int32_t *seg_cap)
@@ -98,7 +99,6 @@ hipError_t launch_step(const DevSim *sims, const Tile *tiles, int32_t n_tiles, i
                        int32_t blocks_per_segment, hipStream_t st);
 hipError_t launch_advance(DevSim *sims, int32_t n_sims, int64_t by, hipStream_t st);
 hipError_t launch_copy(const void *src, void *dst, size_t bytes, hipStream_t st);
-hipError_t launch_materialize(int32_t *cnt, int32_t *inflow, int64_t n, int32_t *flags,
-                              hipStream_t st);
+
 
 }  // namespace rdos

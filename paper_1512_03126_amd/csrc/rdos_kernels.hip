@@ -3,11 +3,11 @@
 // Layout in HBM (one simulation, Rz realizations, S species, T tets, rows
 // padded to Tp = T rounded up to a multiple of 4 so that a lane can read four
 // consecutive tets with one 16-byte load):
-//   cnt[r][s][Tp]        int32  counts left in each tet after the last outflow
-//   inflow[2][r][s][Tp]  int32  molecules that arrived; period k consumes
-//                               inflow[k & 1] and fills inflow[(k + 1) & 1]
-//   mesh[T]              64 B   neighbours, weights, g, N_A V (one line)
-// The state at a period boundary is cnt + inflow[k & 1].
+//   buf[2][r][s][Tp]  int32  molecule counts, double-buffered: the state at the
+//                            start of period k is buf[k & 1]; buf[(k + 1) & 1]
+//                            is all zero then and receives, by integer
+//                            atomics, every molecule that stays or arrives
+//   mesh[T]           64 B   neighbours, weights, g, N_A V (one line)
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
@@ -18,6 +18,8 @@
 #pragma clang fp contract(off)
 
 namespace rdos {
+
+typedef int32_t v4i __attribute__((ext_vector_type(4)));
 
 // ---------------------------------------------------------------------------
 // Set-up (Sec. II.A): volumes, face areas, barycentres, then per face
@@ -181,8 +183,8 @@ __device__ __forceinline__ double propensity(const DevSim &sm, int q, const Lane
 }
 
 __device__ __forceinline__ void update_tet(const DevSim &sm, int32_t t, int64_t period, double tau_k,
-                                           uint32_t key1, int32_t *__restrict__ cnt,
-                                           int32_t *__restrict__ in_nxt, int64_t Tp, const LaneState &ls)
+                                           uint32_t key1, int32_t *__restrict__ nxt, int64_t Tp,
+                                           const LaneState &ls)
 {
     const int S = sm.S;
     const int R = sm.R;
@@ -284,22 +286,23 @@ __device__ __forceinline__ void update_tet(const DevSim &sm, int32_t t, int64_t 
                 split_over_faces(n, nb, w, rng, out);
 #pragma unroll
                 for (int f = 0; f < 4; ++f)
-                    if (out[f] > 0) atomicAdd(&in_nxt[s * Tp + nb[f]], (int32_t)out[f]);
+                    if (out[f] > 0) atomicAdd(&nxt[s * Tp + nb[f]], (int32_t)out[f]);
                 ls.n(s) = Ns - (int32_t)n;
             }
         }
-        cnt[s * Tp + t] = ls.n(s);
+        if (ls.n(s) > 0) atomicAdd(&nxt[s * Tp + t], ls.n(s));  // the molecules that stay
     }
 }
 
 // Each period is two launches.
-//  scan:   every lane reads four consecutive tets of every species (16-byte
-//          loads of cnt and inflow).  Each wavefront compacts its tets that
-//          hold any molecule (all tets if a reaction has no reactant) with
-//          ballots, reserves room with one atomic on its queue segment and
-//          writes the tet and its counts (cnt + arrivals) to the queue; the
-//          arrivals it consumed are cleared.
-//  update: the queued tets run Steps 2-3 with every lane busy.
+//  scan:   every lane reads four consecutive tets of every species (one
+//          16-byte non-temporal load per species).  Each wavefront compacts
+//          its tets that hold any molecule (all tets if a reaction has no
+//          reactant) with ballots, reserves room with one atomic on its queue
+//          segment, writes the tet and its counts to the queue and clears
+//          those counts, so the buffer is all zero by the time it is refilled.
+//  update: the queued tets run Steps 2-3 with every lane busy and add what
+//          stays and what leaves into the other buffer.
 // The queue has nseg segments of seg_cap entries (tiles ti with
 // ti % nseg == k fill segment k, so seg_cap = tets of those tiles suffices);
 // entry i of segment k is qtet[k * seg_cap + i] with counts
@@ -333,26 +336,22 @@ __global__ __launch_bounds__(kBlock) void scan_kernel(const DevSim *__restrict__
         const int S = sm.S;
         const int64_t Tp = ((int64_t)sm.T + 3) & ~(int64_t)3;
         const int64_t base = (int64_t)tile.realization * S * Tp;
-        const int32_t *cnt = sm.cnt + base;
-        int32_t *in_cur = sm.inflow[period & 1] + base;
+        int32_t *cur = sm.buf[period & 1] + base;
         const int32_t off = wave_off + lane * kTetsPerLane;
         const int64_t t4 = tile.tet0 + off;
         const bool mine = off < tile.ntet;
-        int4 c[MAXS], f[MAXS];
+        v4i c[MAXS];
 #pragma unroll
         for (int s = 0; s < MAXS; ++s) {
-            c[s] = make_int4(0, 0, 0, 0);
-            f[s] = make_int4(0, 0, 0, 0);
-            if (s < S && mine) {
-                c[s] = *reinterpret_cast<const int4 *>(cnt + s * Tp + t4);
-                f[s] = *reinterpret_cast<const int4 *>(in_cur + s * Tp + t4);
-            }
+            c[s] = v4i{0, 0, 0, 0};
+            if (s < S && mine)  // streamed once: non-temporal
+                c[s] = __builtin_nontemporal_load(reinterpret_cast<const v4i *>(cur + s * Tp + t4));
         }
         uint32_t bits = 0;
 #pragma unroll
         for (int s = 0; s < MAXS; ++s)
-            bits |= (uint32_t)((c[s].x | f[s].x) != 0) | ((uint32_t)((c[s].y | f[s].y) != 0) << 1) |
-                    ((uint32_t)((c[s].z | f[s].z) != 0) << 2) | ((uint32_t)((c[s].w | f[s].w) != 0) << 3);
+            bits |= (uint32_t)(c[s].x != 0) | ((uint32_t)(c[s].y != 0) << 1) | ((uint32_t)(c[s].z != 0) << 2) |
+                    ((uint32_t)(c[s].w != 0) << 3);
         if (sm.zeroth) bits = 0xFu;
         if (!mine) bits = 0;
         const int32_t valid = tile.ntet - off;  // tets of this lane inside the tile
@@ -370,7 +369,7 @@ __global__ __launch_bounds__(kBlock) void scan_kernel(const DevSim *__restrict__
         if (total == 0) continue;  // uniform over the wavefront
         const int32_t seg = ti % q.nseg;
         int32_t slot = 0;
-        if (lane == 0) slot = atomicAdd(&q.len[qsel * q.nseg + seg], total);
+        if (lane == 0) slot = atomicAdd(&q.len[(qsel * q.nseg + seg) * kLenStride], total);
         slot = __shfl(slot, 0);
         if (slot + total > q.seg_cap) {  // cannot happen when len starts at 0; never write past
             if (lane == 0) atomicOr(sm.flags, 4);
@@ -386,13 +385,16 @@ __global__ __launch_bounds__(kBlock) void scan_kernel(const DevSim *__restrict__
             for (int s = 0; s < MAXS; ++s) {
                 if (s >= S) break;
                 const int32_t cv = b == 0 ? c[s].x : b == 1 ? c[s].y : b == 2 ? c[s].z : c[s].w;
-                const int32_t fv = b == 0 ? f[s].x : b == 1 ? f[s].y : b == 2 ? f[s].z : f[s].w;
-                const int64_t sum = (int64_t)cv + (int64_t)fv;
-                if (sum > 0x7fffffff) atomicOr(sm.flags, 1);
-                q.counts[s * q.qcap + idx] = (int32_t)sum;
-                if (fv != 0) in_cur[s * Tp + t4 + b] = 0;
+                if (cv < 0) atomicOr(sm.flags, 1);  // wrapped by an overflowing atomic add
+                q.counts[s * q.qcap + idx] = cv;
             }
         }
+        // the queued molecules now live in the queue: clear their slots so
+        // this buffer is all zero when it is next filled
+#pragma unroll
+        for (int s = 0; s < MAXS; ++s)
+            if (s < S && (c[s].x | c[s].y | c[s].z | c[s].w) != 0)
+                *reinterpret_cast<v4i *>(cur + s * Tp + t4) = v4i{0, 0, 0, 0};
     }
 }
 
@@ -404,12 +406,12 @@ __global__ __launch_bounds__(kBlock) void update_kernel(const DevSim *__restrict
     __shared__ double last[kMaxSpecies * kBlock];
     __shared__ int32_t counts[kMaxSpecies * kBlock];
     const LaneState ls{counts + threadIdx.x, occ + threadIdx.x, last + threadIdx.x};
-    if (blockIdx.x == 0 && threadIdx.x < q.nseg) q.len[(qsel ^ 1) * q.nseg + threadIdx.x] = 0;
+    if (blockIdx.x == 0 && threadIdx.x < q.nseg) q.len[((qsel ^ 1) * q.nseg + threadIdx.x) * kLenStride] = 0;
     const int32_t seg = blockIdx.x % q.nseg;
     const int32_t per_seg = max(1, (int32_t)(gridDim.x / q.nseg));  // blocks sharing a segment
     const int32_t part = blockIdx.x / q.nseg;
     if (part >= per_seg) return;
-    const int32_t n = min(q.len[qsel * q.nseg + seg], q.seg_cap);
+    const int32_t n = min(q.len[(qsel * q.nseg + seg) * kLenStride], q.seg_cap);
     for (int32_t i = part * kBlock + threadIdx.x; i < n; i += per_seg * kBlock) {
         const int64_t idx = (int64_t)seg * q.seg_cap + i;
         const int32_t entry = q.tet[idx];
@@ -421,7 +423,7 @@ __global__ __launch_bounds__(kBlock) void update_kernel(const DevSim *__restrict
         const int64_t base = (int64_t)tile.realization * sm.S * Tp;
         for (int s = 0; s < sm.S; ++s) ls.n(s) = q.counts[s * q.qcap + idx];
         update_tet(sm, tile.tet0 + entry % kTetsPerTile, period, tau_k, sm.key1 ^ (uint32_t)tile.realization,
-                   sm.cnt + base, sm.inflow[(period + 1) & 1] + base, Tp, ls);
+                   sm.buf[(period + 1) & 1] + base, Tp, ls);
     }
 }
 
@@ -499,31 +501,6 @@ hipError_t launch_advance(DevSim *sims, int32_t n_sims, int64_t by, hipStream_t 
 {
     if (n_sims <= 0) return hipSuccess;
     advance_kernel<<<(n_sims + 63) / 64, 64, 0, st>>>(sims, n_sims, by);
-    return hipGetLastError();
-}
-
-// Folds the pending arrivals into the counts: cnt += inflow; inflow = 0.
-__global__ __launch_bounds__(256) void materialize_kernel(int32_t *__restrict__ cnt,
-                                                          int32_t *__restrict__ inflow, int64_t n,
-                                                          int32_t *__restrict__ flags)
-{
-    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
-        const int32_t f = inflow[i];
-        if (f != 0) {
-            const int64_t sum = (int64_t)cnt[i] + f;
-            if (sum > 0x7fffffff) atomicOr(flags, 1);
-            cnt[i] = (int32_t)sum;
-            inflow[i] = 0;
-        }
-    }
-}
-
-hipError_t launch_materialize(int32_t *cnt, int32_t *inflow, int64_t n, int32_t *flags, hipStream_t st)
-{
-    if (n <= 0) return hipSuccess;
-    int64_t blocks = (n + 255) / 256;
-    if (blocks > 65536) blocks = 65536;
-    materialize_kernel<<<(int)blocks, 256, 0, st>>>(cnt, inflow, n, flags);
     return hipGetLastError();
 }
 

@@ -44,14 +44,12 @@ struct rdos_sim {
     int64_t step = 0;
     int64_t anchor_step = 0;
     double anchor_t = 0.0;
-    bool dirty = false;  // arrivals pending in inflow[step & 1]
 
     // device
     hipStream_t stream = nullptr;
     bool own_stream = false;
     rdos::MeshRec *d_mesh = nullptr;
-    int32_t *d_cnt = nullptr;
-    int32_t *d_inflow[2] = {nullptr, nullptr};
+    int32_t *d_buf[2] = {nullptr, nullptr};  // counts; the state of period k is d_buf[k & 1]
     int32_t *d_flags = nullptr;
     rdos::DevSim *d_desc = nullptr;
     rdos::Tile *d_tiles = nullptr;
@@ -70,7 +68,7 @@ size_t state_bytes(const rdos_sim *s);
 size_t queue_bytes(int64_t n_tiles, int32_t n_species);
 hipError_t alloc_queue(rdos::QueueView *q, int64_t n_tiles, int32_t n_species);
 void free_queue(rdos::QueueView *q);
-rdos_status fold_inflow(rdos_sim *s);
+rdos_status match_parity(rdos_sim *s);
 rdos_status check_flags(rdos_sim *s);
 double time_of(const rdos_sim *s, int64_t k);
 rdos_status rdos_finalize_internal(rdos_sim *s, double tau_scale);
