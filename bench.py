@@ -104,12 +104,101 @@ def run_engine(P, e, sims, periods):
         P.rdos_engine_release(e, t)
 
 
+def run_serving(P, args):
+    """Poisson arrivals of independent requests (jittered lattices of 1e4-1e6
+    tets, 1-6 species, random reactions), each asking for a fixed number of
+    periods; admission by HBM budget, continuous batching on the device."""
+    import numpy as np
+
+    import workloads as W
+
+    rng = np.random.default_rng(args.seed)
+    arrivals = []
+    t = 0.0
+    while True:
+        t += rng.exponential(1.0 / args.rate)
+        if t > args.duration:
+            break
+        arrivals.append(t)
+    log(f"serving: {len(arrivals)} requests over {args.duration:.0f} s (rate {args.rate}/s), "
+        f"{args.request_steps} periods each, budget {args.budget_gb} GB")
+    e = P.rdos_engine_create(0, int(args.budget_gb * (1 << 30)))
+    pending = {}  # ticket -> (sim, scheduled arrival, updates)
+    lat, total_updates, tets = [], 0.0, []
+    t0 = time.perf_counter()
+    last_done = t0
+
+    def collect(block=False):
+        nonlocal total_updates, last_done
+        for tk in list(pending):
+            done, _ = P.rdos_engine_poll(e, tk)
+            if done:
+                sim, sched, upd = pending.pop(tk)
+                now = time.perf_counter()
+                P.rdos_engine_release(e, tk)
+                sim.close()
+                lat.append(now - (t0 + sched))
+                total_updates += upd
+                last_done = now
+
+    # requests are generated ahead of their arrival by a small thread pool
+    # (request i draws from its own seeded stream, so the mix is deterministic)
+    from concurrent.futures import ThreadPoolExecutor
+
+    pool = ThreadPoolExecutor(max_workers=6)
+    window = {}
+
+    def ahead(i):
+        for j in range(i, min(i + 48, len(arrivals))):
+            if j not in window:
+                window[j] = pool.submit(W.serving_request, np.random.default_rng([args.seed, j]))
+
+    for i, sched in enumerate(arrivals):
+        ahead(i)
+        m = window.pop(i).result()
+        while time.perf_counter() - t0 < sched:
+            collect()
+            time.sleep(0.0005)
+        sim = P.Simulation(m.xyz, m.tets, m.D, m.reactions, seed=m.seed, tau_scale=None)
+        for q in range(m.n_species):
+            sim.set_counts(q, m.init[0, q])
+        tk = P.rdos_engine_submit(e, sim.h, args.request_steps, 1.0)
+        pending[tk] = (sim, sched, float(args.request_steps) * m.n_tets * m.n_species)
+        tets.append(m.n_tets)
+        if (i + 1) % 200 == 0:
+            log(f"  submitted {i + 1}, done {len(lat)}, in flight {len(pending)}")
+    last_log = time.perf_counter()
+    while pending:
+        collect()
+        time.sleep(0.0005)
+        if time.perf_counter() - last_log > 5.0:
+            last_log = time.perf_counter()
+            log(f"  draining: done {len(lat)}, in flight {len(pending)}")
+    pool.shutdown()
+    wall = last_done - t0
+    st = P.rdos_engine_stats(e)
+    P.rdos_engine_destroy(e)
+    lat_ms = np.sort(np.array(lat) * 1e3)
+    res = {"value": total_updates / wall, "wall_s": wall, "requests": len(lat),
+           "p50_ms": float(np.percentile(lat_ms, 50)), "p99_ms": float(np.percentile(lat_ms, 99)),
+           "mean_tets": float(np.mean(tets)), "device_busy_s": st["busy_s"],
+           "device_updates_per_busy_s": st["updates"] / max(st["busy_s"], 1e-9)}
+    log(f"serving: {res['value']:.3e} upd/s aggregate, p50 {res['p50_ms']:.1f} ms, p99 {res['p99_ms']:.1f} ms, "
+        f"{res['requests']} requests, mean {res['mean_tets']:.0f} tets")
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=338, help="timed periods (338 = 0.1 s of the A+B<->C system)")
     ap.add_argument("--warmup", type=int, default=96, help="untimed periods first (also tunes launch shapes)")
-    ap.add_argument("--workload", choices=["batched", "plain"], default="batched")
+    ap.add_argument("--workload", choices=["batched", "plain", "serving"], default="batched")
+    ap.add_argument("--rate", type=float, default=20.0, help="serving: mean arrivals per second")
+    ap.add_argument("--duration", type=float, default=60.0, help="serving: seconds of arrivals")
+    ap.add_argument("--request-steps", type=int, default=1000, help="serving: periods per request")
+    ap.add_argument("--budget-gb", type=float, default=8.0, help="serving: HBM budget of the engine")
+    ap.add_argument("--seed", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-plain", action="store_true", help="skip the plain one-realization comparison")
     ap.add_argument("--cpu-periods", type=int, default=338, help="oracle sample length (periods)")
@@ -126,6 +215,19 @@ def main():
     P.lib()
     K, Wm = args.steps, args.warmup
     result = {}
+
+    if args.workload == "serving":
+        res = run_serving(P, args)
+        out = {"metric": "tet-species updates/s (served, aggregate)", "value": round(res["value"], 1),
+               "unit": "tet-species updates/s", "n_gpus": 1, "steps": args.request_steps, "warmup": 0,
+               "ms_per_step": None, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+               "dtype": "i32 counts / f64 probabilities", "data": "synthetic (seeded jittered lattices)",
+               "config": {"workload": f"serving: Poisson {args.rate}/s for {args.duration} s, jittered Kuhn "
+                                      f"lattices 1e4-1e6 tets, 1-6 species, {args.request_steps} periods each",
+                          **{k: (round(v, 3) if isinstance(v, float) else v) for k, v in res.items()
+                             if k != "value"}}}
+        print(json.dumps(out), flush=True)
+        return
 
     # ---------------- plain: one realization, one launch pair per period
     plain = None

@@ -9,6 +9,9 @@
 #include <cstdio>
 #include <cstring>
 #include <limits>
+#include <map>
+#include <memory>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -49,19 +52,42 @@ size_t queue_bytes(int64_t n_tiles, int32_t n_species)
     int32_t nseg, seg_cap;
     queue_shape(n_tiles, &nseg, &seg_cap);
     return (size_t)nseg * seg_cap * (1 + (size_t)n_species) * sizeof(int32_t) +
-           2 * (size_t)nseg * kLenStride * sizeof(int32_t);
+           2 * (size_t)kMaxSegments * kLenStride * sizeof(int32_t) + sizeof(WorkHeader);
 }
 
-hipError_t alloc_queue(QueueView *q, int64_t n_tiles, int32_t n_species)
+// Room for a work list of up to capacity_tiles tiles and n_species count rows.
+hipError_t alloc_queue(QueueView *q, int64_t capacity_tiles, int32_t n_species, hipStream_t st)
 {
-    queue_shape(n_tiles, &q->nseg, &q->seg_cap);
+    *q = QueueView{};
+    queue_shape(capacity_tiles, &q->nseg, &q->seg_cap);
+    q->qcap = (int64_t)q->nseg * q->seg_cap;
     q->species = std::max(n_species, 1);
-    const size_t cap = (size_t)q->nseg * q->seg_cap;
-    hipError_t e = hipMalloc(&q->tet, cap * sizeof(int32_t));
-    if (e == hipSuccess) e = hipMalloc(&q->counts, cap * (size_t)std::max(n_species, 1) * sizeof(int32_t));
-    const size_t len_bytes = 2 * (size_t)q->nseg * kLenStride * sizeof(int32_t);
+    hipError_t e = hipMalloc(&q->tet, (size_t)q->qcap * sizeof(int32_t));
+    if (e == hipSuccess) e = hipMalloc(&q->counts, (size_t)q->qcap * q->species * sizeof(int32_t));
+    const size_t len_bytes = 2 * (size_t)kMaxSegments * kLenStride * sizeof(int32_t);
     if (e == hipSuccess) e = hipMalloc(&q->len, len_bytes);
-    if (e == hipSuccess) e = hipMemset(q->len, 0, len_bytes);
+    if (e == hipSuccess) e = hipMalloc(&q->hdr, sizeof(WorkHeader));
+    if (e == hipSuccess) e = hipMemsetAsync(q->len, 0, len_bytes, st);
+    return e;
+}
+
+// Points the queue at a work list of n_tiles tiles (<= its capacity) and
+// n_sims descriptors; the kernels read these sizes from q->hdr.
+hipError_t set_queue_work(QueueView *q, int64_t n_tiles, int32_t n_sims, hipStream_t st)
+{
+    int32_t nseg, seg_cap;
+    queue_shape(n_tiles, &nseg, &seg_cap);
+    if ((int64_t)nseg * seg_cap > q->qcap) return hipErrorInvalidValue;
+    q->nseg = nseg;
+    q->seg_cap = seg_cap;
+    WorkHeader h{};
+    h.n_tiles = (int32_t)n_tiles;
+    h.n_sims = n_sims;
+    h.nseg = nseg;
+    h.seg_cap = seg_cap;
+    h.qcap = q->qcap;
+    hipError_t e = hipMemcpyAsync(q->hdr, &h, sizeof h, hipMemcpyHostToDevice, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);  // h lives on this stack frame
     return e;
 }
 
@@ -70,6 +96,7 @@ void free_queue(QueueView *q)
     if (q->tet) (void)hipFree(q->tet);
     if (q->counts) (void)hipFree(q->counts);
     if (q->len) (void)hipFree(q->len);
+    if (q->hdr) (void)hipFree(q->hdr);
     *q = QueueView{};
 }
 
@@ -84,9 +111,76 @@ size_t state_bytes(const rdos_sim *s)
            sizeof(DevSim) + 64;
 }
 
+// Face-matching results are cached by mesh connectivity (the tet_verts
+// array): requests that share a lattice but move its vertices reuse them.
+struct TopologyCache {
+    struct Entry {
+        std::vector<int32_t> tet_verts;
+        std::shared_ptr<const std::vector<int32_t>> nbr;
+        uint64_t last_use = 0;
+    };
+    std::mutex mu;
+    std::multimap<uint64_t, Entry> entries;  // by hash of tet_verts
+    size_t bytes = 0;
+    uint64_t clock = 0;
+    static constexpr size_t kMaxBytes = size_t(1) << 30;
+};
+
+static TopologyCache &topology_cache()
+{
+    static TopologyCache c;
+    return c;
+}
+
+static uint64_t hash_tets(const std::vector<int32_t> &tv)
+{
+    uint64_t h = 1469598103934665603ull;  // FNV-1a over the bytes
+    const unsigned char *p = reinterpret_cast<const unsigned char *>(tv.data());
+    for (size_t i = 0, n = tv.size() * sizeof(int32_t); i < n; ++i) h = (h ^ p[i]) * 1099511628211ull;
+    return h ^ tv.size();
+}
+
+rdos_status build_topology_uncached(rdos_sim *s, std::vector<int32_t> &nbr);
+
+rdos_status build_topology(rdos_sim *s, std::vector<int32_t> &nbr)
+{
+    TopologyCache &c = topology_cache();
+    const uint64_t h = hash_tets(s->tet_verts);
+    {
+        std::lock_guard<std::mutex> g(c.mu);
+        auto range = c.entries.equal_range(h);
+        for (auto it = range.first; it != range.second; ++it)
+            if (it->second.tet_verts == s->tet_verts) {
+                it->second.last_use = ++c.clock;
+                nbr = *it->second.nbr;
+                return RDOS_OK;
+            }
+    }
+    rdos_status st = build_topology_uncached(s, nbr);
+    if (st != RDOS_OK) return st;
+    std::lock_guard<std::mutex> g(c.mu);
+    const size_t add = (s->tet_verts.size() + nbr.size()) * sizeof(int32_t);
+    while (!c.entries.empty() && c.bytes + add > TopologyCache::kMaxBytes) {  // evict least recently used
+        auto old = c.entries.begin();
+        for (auto it = c.entries.begin(); it != c.entries.end(); ++it)
+            if (it->second.last_use < old->second.last_use) old = it;
+        c.bytes -= (old->second.tet_verts.size() + old->second.nbr->size()) * sizeof(int32_t);
+        c.entries.erase(old);
+    }
+    if (add <= TopologyCache::kMaxBytes) {
+        TopologyCache::Entry en;
+        en.tet_verts = s->tet_verts;
+        en.nbr = std::make_shared<const std::vector<int32_t>>(nbr);
+        en.last_use = ++c.clock;
+        c.entries.emplace(h, std::move(en));
+        c.bytes += add;
+    }
+    return RDOS_OK;
+}
+
 // Face matching: each face is keyed by its sorted vertex triple; two tets with
 // the same key are neighbours across it.  A key seen three times is an error.
-rdos_status build_topology(rdos_sim *s, std::vector<int32_t> &nbr)
+rdos_status build_topology_uncached(rdos_sim *s, std::vector<int32_t> &nbr)
 {
     struct FaceKey {
         int32_t a, b, c;
@@ -165,8 +259,8 @@ rdos_status check_flags(rdos_sim *s)
 
 rdos_status enqueue_period(rdos_sim *s, int64_t period, int64_t partial, double tau_last)
 {
-    HIP_TRY(s, launch_step(s->d_desc, s->d_tiles, s->n_tiles, period, partial, tau_last, s->queue,
-                           (int32_t)(s->launches & 1), 0, s->update_bps, s->stream),
+    HIP_TRY(s, launch_step(s->d_desc, s->d_tiles, period, partial, tau_last, s->queue, (int32_t)(s->launches & 1),
+                           s->n_tiles, s->update_bps, s->stream),
             "launch period");
     s->launches += 1;
     return RDOS_OK;
@@ -180,7 +274,8 @@ double time_of(const rdos_sim *s, int64_t k)
 void free_device(rdos_sim *s)
 {
     (void)hipSetDevice(s->device);
-    if (s->stream && s->own_stream) (void)hipStreamSynchronize(s->stream);
+    if (s->stream) (void)hipStreamSynchronize(s->stream);
+    std::lock_guard<std::mutex> g(device_api_mutex());
     void *ptrs[] = {s->d_mesh, s->d_buf[0], s->d_buf[1], s->d_flags, s->d_desc, s->d_tiles};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
@@ -307,26 +402,32 @@ rdos_status rdos_finalize(rdos_sim *s, double tau_scale, double *out_tau)
     double *d_xyz = nullptr, *d_vol = nullptr, *d_bc = nullptr, *d_area = nullptr, *d_D = nullptr;
     int32_t *d_tv = nullptr, *d_nbr = nullptr;
     unsigned long long *d_tau = nullptr;
+    std::unique_lock<std::mutex> alloc_lock(device_api_mutex(), std::defer_lock);
     auto cleanup = [&]() {
+        if (s->stream) (void)hipStreamSynchronize(s->stream);
+        std::unique_lock<std::mutex> g(device_api_mutex(), std::defer_lock);
+        if (!alloc_lock.owns_lock()) g.lock();
         void *p[] = {d_xyz, d_vol, d_bc, d_area, d_D, d_tv, d_nbr, d_tau};
         for (void *q : p)
             if (q) (void)hipFree(q);
     };
-#define SETUP_TRY(expr, what)            \
-    do {                                 \
-        hipError_t e__ = (expr);         \
-        if (e__ != hipSuccess) {         \
-            cleanup();                   \
-            free_device(s);              \
-            return hip_fail(s, e__, what); \
-        }                                \
+#define SETUP_TRY(expr, what)                               \
+    do {                                                    \
+        hipError_t e__ = (expr);                            \
+        if (e__ != hipSuccess) {                            \
+            if (alloc_lock.owns_lock()) alloc_lock.unlock(); \
+            cleanup();                                      \
+            free_device(s);                                 \
+            return hip_fail(s, e__, what);                  \
+        }                                                   \
     } while (0)
+    alloc_lock.lock();
     SETUP_TRY(hipMalloc(&s->d_mesh, (size_t)T * sizeof(MeshRec)), "allocate mesh tables");
     SETUP_TRY(hipMalloc(&s->d_buf[0], count_bytes), "allocate counts");
     SETUP_TRY(hipMalloc(&s->d_buf[1], count_bytes), "allocate counts");
     SETUP_TRY(hipMalloc(&s->d_flags, 64), "allocate flags");
     SETUP_TRY(hipMalloc(&s->d_desc, sizeof(DevSim)), "allocate descriptor");
-    SETUP_TRY(alloc_queue(&s->queue, tiles_of(s), S), "allocate queue");
+    SETUP_TRY(alloc_queue(&s->queue, tiles_of(s), S, s->stream), "allocate queue");
     SETUP_TRY(hipMalloc(&d_xyz, s->xyz.size() * sizeof(double)), "allocate set-up");
     SETUP_TRY(hipMalloc(&d_tv, s->tet_verts.size() * sizeof(int32_t)), "allocate set-up");
     SETUP_TRY(hipMalloc(&d_nbr, nbr.size() * sizeof(int32_t)), "allocate set-up");
@@ -335,6 +436,7 @@ rdos_status rdos_finalize(rdos_sim *s, double tau_scale, double *out_tau)
     SETUP_TRY(hipMalloc(&d_area, (size_t)T * 4 * sizeof(double)), "allocate set-up");
     SETUP_TRY(hipMalloc(&d_D, (size_t)S * sizeof(double)), "allocate set-up");
     SETUP_TRY(hipMalloc(&d_tau, sizeof(unsigned long long) + 8), "allocate set-up");
+    alloc_lock.unlock();
     SETUP_TRY(hipMemsetAsync(s->d_buf[0], 0, count_bytes, s->stream), "clear counts");
     SETUP_TRY(hipMemsetAsync(s->d_buf[1], 0, count_bytes, s->stream), "clear counts");
     SETUP_TRY(hipMemsetAsync(s->d_flags, 0, 64, s->stream), "clear flags");
@@ -413,7 +515,11 @@ rdos_status rdos_finalize(rdos_sim *s, double tau_scale, double *out_tau)
         for (int32_t t0 = 0; t0 < T; t0 += kTetsPerTile)
             tiles.push_back({0, r, t0, std::min<int32_t>(kTetsPerTile, T - t0)});
     s->n_tiles = (int32_t)tiles.size();
-    hipError_t e = hipMalloc(&s->d_tiles, tiles.size() * sizeof(Tile));
+    hipError_t e;
+    {
+        std::lock_guard<std::mutex> g(device_api_mutex());
+        e = hipMalloc(&s->d_tiles, tiles.size() * sizeof(Tile));
+    }
     if (e != hipSuccess) {
         free_device(s);
         return hip_fail(s, e, "allocate work list");
@@ -422,6 +528,11 @@ rdos_status rdos_finalize(rdos_sim *s, double tau_scale, double *out_tau)
     if (e != hipSuccess) {
         free_device(s);
         return hip_fail(s, e, "upload work list");
+    }
+    e = set_queue_work(&s->queue, s->n_tiles, 1, s->stream);
+    if (e != hipSuccess) {
+        free_device(s);
+        return hip_fail(s, e, "queue header");
     }
     st = upload_desc(s);
     if (st != RDOS_OK) {

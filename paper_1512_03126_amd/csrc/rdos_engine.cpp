@@ -1,14 +1,18 @@
 // Batching and serving engine: every admitted simulation ("slot") advances
 // one of its own periods per launch pair, all slots in the same launches.
-// Chunks of periods are captured once into a hipGraph and replayed; the
-// graph is rebuilt only when the set of slots changes.  A worker thread
-// admits queued simulations while their device memory fits the budget and
-// retires slots as soon as their periods are done, so requests that arrive
-// while others run join the next chunk (continuous batching).
+// Chunks of periods are captured into a hipGraph and replayed.  The kernels
+// read the work-list sizes from a small device header, so the graph survives
+// changes of the slot set: admitting or retiring a simulation only rewrites
+// descriptors, tiles and the header; a new capture is needed only when a
+// buffer has to grow or the tuner picks another launch shape.  An admission
+// thread admits queued simulations while their device memory fits the budget
+// (finalizing them on their own streams), and the worker adds them to the
+// work list at its next chunk (continuous batching).
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
 #include <chrono>
+#include <cmath>
 #include <condition_variable>
 #include <cstdarg>
 #include <cstdio>
@@ -44,9 +48,9 @@ struct Ticket {
 
 // Launch-shape choices the tuner tries on live work (results do not depend on them).
 struct Shape {
-    int32_t chunk;      // periods per graph replay (even: the queue length halves alternate)
-    int32_t scan_grid;  // blocks of the scan launch (0: one per tile)
-    int32_t update_bps; // update blocks per queue segment
+    int32_t chunk;       // periods per graph replay (even: the queue length halves alternate)
+    int32_t scan_grid;   // blocks of the scan launch (grid-stride over the tiles)
+    int32_t update_bps;  // update blocks per queue segment
     bool operator==(const Shape &o) const
     {
         return chunk == o.chunk && scan_grid == o.scan_grid && update_bps == o.update_bps;
@@ -63,9 +67,12 @@ struct rdos_engine {
     std::string error;
 
     std::mutex mu;
-    std::condition_variable cv_work;  // wakes the worker
-    std::condition_variable cv_done;  // wakes drain()
+    std::condition_variable cv_work;   // wakes the worker
+    std::condition_variable cv_admit;  // wakes the admission thread
+    std::condition_variable cv_done;   // wakes drain()
     std::thread worker;
+    std::thread admitter;  // finalizes admitted simulations while the worker keeps launching
+    int admitting = 0;     // tickets being finalized right now
     bool stop = false;
     bool worker_dead = false;  // the worker left its loop after a device error
     bool stalled = false;      // nothing runs and the next request does not fit the budget
@@ -73,34 +80,34 @@ struct rdos_engine {
     uint64_t next_ticket = 1;
     std::map<uint64_t, Ticket> tickets;
     std::deque<uint64_t> waiting;  // submitted, not admitted (FIFO)
-    std::vector<uint64_t> slots;   // admitted and running
+    std::vector<uint64_t> ready;   // admitted and finalized, joining at the next chunk
+    std::vector<uint64_t> slots;   // running
 
-    // device work list of the current slot set
+    // device work list of the current slot set (buffers only grow)
     DevSim *d_sims = nullptr;
-    int32_t cap_sims = 0;
+    int64_t cap_sims = 0;
     Tile *d_tiles = nullptr;
     int64_t cap_tiles = 0;
     QueueView queue{};
-    int64_t queue_tiles = 0;    // tiles the allocated queue can hold
-    int32_t queue_species = 0;  // species rows the allocated queue can hold
     int32_t n_tiles = 0;
+    int32_t max_species = 1;
     hipGraphExec_t graph = nullptr;
     Shape graph_shape{0, 0, 0};
-    bool rebuild = true;
+    bool graph_stale = true;  // a buffer the graph names was reallocated
+    bool rebuild = true;      // the slot set changed
 
-    // tuner: candidates tried in turn on each new slot set, best kept
+    // tuner: candidates tried once per work-list size bucket, best kept
     std::vector<Shape> candidates;
+    std::map<std::pair<int, int>, Shape> tuned;
+    std::pair<int, int> bucket{-1, -1};
     size_t trial = 0;
     double best_rate = -1.0;
-    Shape best{16, 0, 4};
+    Shape best{16, 2048, 8};
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
 
-    // tuned shape per work-list signature (tiles, tets)
-    std::map<std::pair<int64_t, int64_t>, Shape> tuned;
-
-    // per-kernel timing: event nodes around every scan and update launch
+    // per-kernel timing: chunks launched directly with events between launches
     bool profiling = false;
-    std::vector<hipEvent_t> kev;  // 2 * chunk + 1 events of the captured graph
+    std::vector<hipEvent_t> kev;
     double scan_ms = 0.0, update_ms = 0.0;
     int64_t scan_n = 0, update_n = 0;
 
@@ -131,19 +138,27 @@ rdos_status efail(rdos_engine *e, rdos_status code, const char *fmt, ...)
                          hipGetErrorString(err__));                                                  \
     } while (0)
 
+// Grows a device array to hold `need` elements (x1.5 headroom); a move
+// makes the captured graph stale.
 template <typename T>
 rdos_status ensure(rdos_engine *e, T **buf, int64_t *cap, int64_t need, const char *what)
 {
     if (need <= *cap) return RDOS_OK;
+    ENGINE_HIP(e, hipStreamSynchronize(e->stream), what);
+    std::lock_guard<std::mutex> g(device_api_mutex());
     if (*buf) (void)hipFree(*buf);
     *buf = nullptr;
-    const int64_t n = std::max<int64_t>(need, *cap * 2);
+    *cap = 0;
+    const int64_t n = std::max<int64_t>(need, need + need / 2);
     ENGINE_HIP(e, hipMalloc(buf, (size_t)n * sizeof(T)), what);
     *cap = n;
+    e->graph_stale = true;
     return RDOS_OK;
 }
 
-// Builds the device work list for the current slots (under the lock).
+int species_bound(int s) { return s <= 2 ? 2 : (s <= 4 ? 4 : kMaxSpecies); }
+
+// Rewrites the device work list for the current slots (lock held).
 rdos_status build_work(rdos_engine *e)
 {
     std::vector<DevSim> sims;
@@ -161,24 +176,22 @@ rdos_status build_work(rdos_engine *e)
                 tiles.push_back({(int32_t)i, r, t0, std::min<int32_t>(kTetsPerTile, s->T - t0)});
         max_species = std::max(max_species, (int32_t)s->D.size());
     }
-    int64_t cap_sims = e->cap_sims;
-    rdos_status st = ensure(e, &e->d_sims, &cap_sims, (int64_t)std::max<size_t>(sims.size(), 1), "engine slots");
+    rdos_status st = ensure(e, &e->d_sims, &e->cap_sims, (int64_t)std::max<size_t>(sims.size(), 1), "engine slots");
     if (st != RDOS_OK) return st;
-    e->cap_sims = (int32_t)cap_sims;
     st = ensure(e, &e->d_tiles, &e->cap_tiles, (int64_t)std::max<size_t>(tiles.size(), 1), "engine tiles");
     if (st != RDOS_OK) return st;
-    // the queue's segment geometry follows the tile count, so it is rebuilt whenever that changes
     const int64_t nt = (int64_t)std::max<size_t>(tiles.size(), 1);
-    if (nt != e->queue_tiles || max_species > e->queue_species) {
-        free_queue(&e->queue);
-        e->queue_tiles = e->queue_species = 0;
-        ENGINE_HIP(e, alloc_queue(&e->queue, nt, max_species), "engine queue");
-        e->queue_tiles = nt;
-        e->queue_species = max_species;
-    } else {
-        ENGINE_HIP(e, hipMemsetAsync(e->queue.len, 0, 2 * (size_t)e->queue.nseg * kLenStride * sizeof(int32_t),
-                                     e->stream),
-                   "clear queue");
+    int32_t nseg, seg_cap;
+    queue_shape(nt, &nseg, &seg_cap);
+    if ((int64_t)nseg * seg_cap > e->queue.qcap || species_bound(max_species) > e->queue.species) {
+        ENGINE_HIP(e, hipStreamSynchronize(e->stream), "drain before reallocating the queue");
+        {
+            std::lock_guard<std::mutex> g(device_api_mutex());
+            free_queue(&e->queue);
+            ENGINE_HIP(e, alloc_queue(&e->queue, nt + nt / 2, species_bound(max_species), e->stream),
+                       "engine queue");
+        }
+        e->graph_stale = true;
     }
     if (!sims.empty())
         ENGINE_HIP(e, hipMemcpyAsync(e->d_sims, sims.data(), sims.size() * sizeof(DevSim), hipMemcpyHostToDevice,
@@ -188,8 +201,10 @@ rdos_status build_work(rdos_engine *e)
         ENGINE_HIP(e, hipMemcpyAsync(e->d_tiles, tiles.data(), tiles.size() * sizeof(Tile), hipMemcpyHostToDevice,
                                      e->stream),
                    "upload tiles");
-    ENGINE_HIP(e, hipStreamSynchronize(e->stream), "upload work list");
+    ENGINE_HIP(e, set_queue_work(&e->queue, (int64_t)tiles.size(), (int32_t)sims.size(), e->stream),
+               "work header");
     e->n_tiles = (int32_t)tiles.size();
+    e->max_species = max_species;
     return RDOS_OK;
 }
 
@@ -202,18 +217,19 @@ hipError_t enqueue_chunk(rdos_engine *e, const Shape &sh, bool timed)
     hipError_t err = hipSuccess;
     if (timed) err = hipEventRecord(e->kev[0], e->stream);
     for (int32_t i = 0; i < sh.chunk && err == hipSuccess; ++i) {
-        err = launch_scan(e->d_sims, e->d_tiles, e->n_tiles, i, e->queue, i & 1, sh.scan_grid, e->stream);
+        err = launch_scan(e->d_sims, e->d_tiles, i, e->queue, i & 1, sh.scan_grid, e->stream);
         if (err == hipSuccess && timed) err = hipEventRecord(e->kev[2 * i + 1], e->stream);
         if (err == hipSuccess)
             err = launch_update(e->d_sims, e->d_tiles, i, -1, 0.0, e->queue, i & 1, sh.update_bps, e->stream);
         if (err == hipSuccess && timed) err = hipEventRecord(e->kev[2 * i + 2], e->stream);
     }
-    if (err == hipSuccess) err = launch_advance(e->d_sims, (int32_t)e->slots.size(), sh.chunk, e->stream);
+    if (err == hipSuccess) err = launch_advance(e->d_sims, e->queue.hdr, sh.chunk, e->stream);
     return err;
 }
 
 rdos_status capture(rdos_engine *e, const Shape &sh)
 {
+    std::lock_guard<std::mutex> lock(device_api_mutex());
     if (e->graph) {
         (void)hipGraphExecDestroy(e->graph);
         e->graph = nullptr;
@@ -230,62 +246,93 @@ rdos_status capture(rdos_engine *e, const Shape &sh)
     (void)hipGraphDestroy(g);
     if (err != hipSuccess) return efail(e, RDOS_EDEVICE, "instantiate: %s", hipGetErrorString(err));
     e->graph_shape = sh;
+    e->graph_stale = false;
     return RDOS_OK;
 }
 
 double slot_updates(const rdos_sim *s) { return (double)s->Rz * (double)s->T * (double)s->D.size(); }
 
-// Admits queued tickets while they fit (called by the worker, lock held for
-// bookkeeping; finalize runs with the lock released).
-void admit(rdos_engine *e, std::unique_lock<std::mutex> &lk)
+int64_t tiled_tets(const rdos_sim *q)
 {
-    while (!e->waiting.empty()) {
-        const uint64_t id = e->waiting.front();
-        Ticket &tk = e->tickets[id];
-        if (e->used + tk.bytes > e->budget) break;  // FIFO: later requests wait too
-        // queue entries are int32 (tile * kTetsPerTile + offset): keep the work list below 2^31 tets
-        int64_t tiled = 0;
-        for (uint64_t sid : e->slots) {
-            const rdos_sim *q = e->tickets[sid].sim;
-            tiled += (int64_t)q->Rz * ((q->T + kTetsPerTile - 1) / kTetsPerTile) * kTetsPerTile;
-        }
-        tiled += (int64_t)tk.sim->Rz * ((tk.sim->T + kTetsPerTile - 1) / kTetsPerTile) * kTetsPerTile;
-        if (tiled > 0x7fffffff && !e->slots.empty()) break;
-        e->waiting.pop_front();
-        e->used += tk.bytes;
-        rdos_sim *s = tk.sim;
-        bool ok = true;
-        std::string err;
-        if (s->state != SimState::Ready) {
-            lk.unlock();
-            s->engine_owned = false;
-            const rdos_status st = rdos_finalize(s, tk.tau_scale, nullptr);
-            s->engine_owned = true;
-            lk.lock();
-            if (st != RDOS_OK) {
-                ok = false;
-                err = s->error;
+    return (int64_t)q->Rz * ((q->T + kTetsPerTile - 1) / kTetsPerTile) * kTetsPerTile;
+}
+
+// Admission thread: takes waiting tickets in FIFO order while their device
+// memory fits the budget, finalizes those that are not finalized yet (with
+// the lock released, on the simulation's own stream) and hands them to the
+// worker, which adds them to the work list at its next chunk.
+void admitter_main(rdos_engine *e)
+{
+    (void)hipSetDevice(e->device);
+    std::unique_lock<std::mutex> lk(e->mu);
+    while (!e->stop) {
+        bool progressed = false;
+        if (!e->waiting.empty()) {
+            const uint64_t id = e->waiting.front();
+            Ticket &tk = e->tickets[id];
+            // queue entries are int32 (tile * kTetsPerTile + offset): keep the work list below 2^31 tets
+            int64_t tiled = tiled_tets(tk.sim);
+            for (uint64_t sid : e->slots) tiled += tiled_tets(e->tickets[sid].sim);
+            for (uint64_t sid : e->ready) tiled += tiled_tets(e->tickets[sid].sim);
+            const bool fits = e->used + tk.bytes <= e->budget &&
+                              (tiled <= 0x7fffffff || (e->slots.empty() && e->ready.empty()));
+            if (fits) {
+                e->waiting.pop_front();
+                e->used += tk.bytes;
+                ++e->admitting;
+                rdos_sim *s = tk.sim;
+                const double tau_scale = tk.tau_scale;
+                rdos_status st = RDOS_OK;
+                std::string err;
+                if (s->state != SimState::Ready) {
+                    lk.unlock();
+                    s->engine_owned = false;
+                    st = rdos_finalize(s, tau_scale, nullptr);
+                    if (st != RDOS_OK) err = s->error;
+                    s->engine_owned = true;
+                    lk.lock();
+                }
+                --e->admitting;
+                Ticket &t2 = e->tickets[id];
+                if (st == RDOS_OK) {
+                    t2.end_step = s->step + t2.n_steps;
+                    t2.admitted = true;
+                    if (t2.n_steps == 0) {
+                        t2.done = true;
+                        t2.finished = Clock::now();
+                        e->cv_done.notify_all();
+                    } else {
+                        e->ready.push_back(id);
+                        e->cv_work.notify_all();
+                    }
+                } else {
+                    t2.failed = t2.done = true;
+                    t2.error = err;
+                    t2.finished = Clock::now();
+                    e->used -= t2.bytes;
+                    e->cv_done.notify_all();
+                }
+                progressed = true;
             }
         }
-        if (ok) {
-            tk.end_step = s->step + tk.n_steps;
-            if (tk.n_steps == 0) {
-                tk.done = true;
-                tk.finished = Clock::now();
-                e->cv_done.notify_all();
-            } else {
-                tk.admitted = true;
-                e->slots.push_back(id);
-                e->rebuild = true;
-            }
-        } else {
-            tk.failed = tk.done = true;
-            tk.error = err;
-            tk.finished = Clock::now();
-            e->used -= tk.bytes;
-            e->cv_done.notify_all();
-        }
+        // nothing runs or waits to join and the next request does not fit: only a release can help
+        e->stalled = !progressed && !e->waiting.empty() && e->slots.empty() && e->ready.empty() &&
+                     e->admitting == 0;
+        if (e->stalled) e->cv_done.notify_all();
+        if (!progressed) e->cv_admit.wait(lk);
     }
+}
+
+void fail_slots(rdos_engine *e)
+{
+    for (uint64_t id : e->slots) {
+        Ticket &tk = e->tickets[id];
+        tk.failed = tk.done = true;
+        tk.error = e->error;
+        tk.finished = Clock::now();
+    }
+    e->slots.clear();
+    e->cv_done.notify_all();
 }
 
 void worker_main(rdos_engine *e)
@@ -293,33 +340,37 @@ void worker_main(rdos_engine *e)
     (void)hipSetDevice(e->device);
     std::unique_lock<std::mutex> lk(e->mu);
     while (!e->stop) {
-        admit(e, lk);
+        if (!e->ready.empty()) {  // continuous batching: newly admitted simulations join here
+            for (uint64_t id : e->ready) e->slots.push_back(id);
+            e->ready.clear();
+            e->rebuild = true;
+        }
         if (e->slots.empty()) {
-            // idle, or blocked by simulations that finished but were not released yet
-            e->stalled = !e->waiting.empty();
-            if (e->stalled) e->cv_done.notify_all();
             e->cv_work.wait(lk);
             continue;
         }
-        e->stalled = false;
         if (e->rebuild) {
-            if (build_work(e) != RDOS_OK) break;
-            auto hit = e->tuned.find({e->n_tiles, e->queue_tiles});
-            if (hit != e->tuned.end()) {
-                e->best = hit->second;
-                e->trial = e->candidates.size();
-            } else {
-                e->trial = 0;
-                e->best_rate = -1.0;
+            if (build_work(e) != RDOS_OK) {
+                fail_slots(e);
+                break;
             }
             e->rebuild = false;
-            if (e->graph) {
-                (void)hipGraphExecDestroy(e->graph);
-                e->graph = nullptr;
+            const std::pair<int, int> b{(int)std::ilogb((double)std::max(e->n_tiles, 1)),
+                                        species_bound(e->max_species)};
+            if (b != e->bucket) {
+                e->bucket = b;
+                auto hit = e->tuned.find(b);
+                if (hit != e->tuned.end()) {
+                    e->best = hit->second;
+                    e->trial = e->candidates.size();
+                } else {
+                    e->trial = 0;
+                    e->best_rate = -1.0;
+                }
             }
         }
-        // the tuner tries each candidate once per slot set, then keeps the best
-        Shape sh = e->trial < e->candidates.size() ? e->candidates[e->trial] : e->best;
+        // the tuner tries each candidate once per size bucket, then keeps the best
+        const Shape sh = e->trial < e->candidates.size() ? e->candidates[e->trial] : e->best;
         const bool timed = e->profiling;
         if (timed) {
             bool ok = true;
@@ -330,10 +381,14 @@ void worker_main(rdos_engine *e)
             }
             if (!ok) {
                 e->error = "create profiling events";
+                fail_slots(e);
                 break;
             }
-        } else if (!e->graph || !(sh == e->graph_shape)) {
-            if (capture(e, sh) != RDOS_OK) break;
+        } else if (!e->graph || e->graph_stale || !(sh == e->graph_shape)) {
+            if (capture(e, sh) != RDOS_OK) {
+                fail_slots(e);
+                break;
+            }
         }
         double work = 0.0;
         for (uint64_t id : e->slots) {
@@ -351,14 +406,7 @@ void worker_main(rdos_engine *e)
         lk.lock();
         if (err != hipSuccess) {
             e->error = std::string("chunk: ") + hipGetErrorString(err);
-            for (uint64_t id : e->slots) {
-                Ticket &tk = e->tickets[id];
-                tk.failed = tk.done = true;
-                tk.error = e->error;
-                tk.finished = Clock::now();
-            }
-            e->slots.clear();
-            e->cv_done.notify_all();
+            fail_slots(e);
             break;
         }
         if (timed) {
@@ -380,7 +428,7 @@ void worker_main(rdos_engine *e)
                 e->best = sh;
             }
             ++e->trial;
-            if (e->trial == e->candidates.size()) e->tuned[{e->n_tiles, (int64_t)e->queue_species}] = e->best;
+            if (e->trial == e->candidates.size()) e->tuned[e->bucket] = e->best;
         }
         e->launches += sh.chunk;
         e->updates += work;
@@ -400,7 +448,10 @@ void worker_main(rdos_engine *e)
                 keep.push_back(id);
             }
         }
-        if (keep.size() != e->slots.size()) e->cv_done.notify_all();
+        if (keep.size() != e->slots.size()) {
+            e->cv_done.notify_all();
+            e->cv_admit.notify_all();  // lets the admission thread re-check whether it is stalled
+        }
         e->slots.swap(keep);
     }
     e->worker_dead = !e->stop;
@@ -433,8 +484,9 @@ rdos_status rdos_engine_create(rdos_engine **out, int device, size_t hbm_budget_
         delete e;
         return RDOS_EDEVICE;
     }
-    e->candidates = {{16, 0, 4}, {16, 0, 8}, {16, 8192, 4}, {16, 2048, 8}, {32, 0, 8}};
+    e->candidates = {{16, 2048, 8}, {16, 4096, 4}, {16, 8192, 8}, {16, 1024, 4}, {32, 2048, 8}};
     e->worker = std::thread(worker_main, e);
+    e->admitter = std::thread(admitter_main, e);
     *out = e;
     return RDOS_OK;
 }
@@ -464,7 +516,7 @@ rdos_status rdos_engine_submit(rdos_engine *e, rdos_sim *sim, int64_t n_steps, d
     tk.submitted = Clock::now();
     e->waiting.push_back(id);
     if (ticket) *ticket = id;
-    e->cv_work.notify_all();
+    e->cv_admit.notify_all();
     return RDOS_OK;
 }
 
@@ -487,7 +539,8 @@ rdos_status rdos_engine_drain(rdos_engine *e)
     if (!e) return RDOS_EINVAL;
     std::unique_lock<std::mutex> lk(e->mu);
     e->cv_done.wait(lk, [&] {
-        return (e->waiting.empty() && e->slots.empty()) || e->worker_dead || e->stalled;
+        return (e->waiting.empty() && e->ready.empty() && e->slots.empty() && e->admitting == 0) ||
+               e->worker_dead || e->stalled;
     });
     for (auto &kv : e->tickets)
         if (kv.second.failed) return efail(e, RDOS_EDEVICE, "a ticket failed: %s", kv.second.error.c_str());
@@ -509,7 +562,8 @@ rdos_status rdos_engine_release(rdos_engine *e, uint64_t ticket, rdos_sim **sim)
     e->used -= it->second.bytes;
     *sim = s;
     e->tickets.erase(it);
-    e->cv_work.notify_all();
+    e->stalled = false;  // budget was freed: the admission thread re-checks
+    e->cv_admit.notify_all();
     return RDOS_OK;
 }
 
@@ -596,7 +650,9 @@ void rdos_engine_destroy(rdos_engine *e)
         e->stop = true;
     }
     e->cv_work.notify_all();
+    e->cv_admit.notify_all();
     if (e->worker.joinable()) e->worker.join();
+    if (e->admitter.joinable()) e->admitter.join();
     (void)hipSetDevice(e->device);
     (void)hipStreamSynchronize(e->stream);
     for (auto &kv : e->tickets) {  // simulations never released are destroyed with the engine

@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <mutex>
 
 #include "../../include/rdos.h"
 
@@ -59,6 +60,14 @@ constexpr int kBlock = 256;        // threads per block (4 wavefronts)
 constexpr int kTetsPerLane = 4;    // one 16-byte load per species and lane
 constexpr int kTetsPerTile = kBlock * kTetsPerLane;
 
+// Held while a graph is captured and around device allocations and frees
+// made by other threads, so neither can interfere with a capture.
+inline std::mutex &device_api_mutex()
+{
+    static std::mutex m;
+    return m;
+}
+
 // Kernel launchers (rdos_kernels.hip).
 hipError_t launch_geometry(const double *xyz, const int32_t *tet_verts, const int32_t *nbr,
                            int32_t T, double *scratch_vol, double *scratch_bc,
@@ -66,20 +75,33 @@ hipError_t launch_geometry(const double *xyz, const int32_t *tet_verts, const in
                            hipStream_t st);
 hipError_t launch_tau_min(const MeshRec *mesh, int32_t T, const double *D, int32_t S,
                           unsigned long long *out_bits, hipStream_t st);
+// Work-list sizes and queue geometry, read by the kernels from device memory
+// so that a captured graph stays valid when the work list changes.
+struct alignas(16) WorkHeader {
+    int32_t n_tiles;   // tiles in the work list
+    int32_t n_sims;    // simulation descriptors
+    int32_t nseg;      // queue segments in use, 1..kMaxSegments
+    int32_t seg_cap;   // entries per segment
+    int64_t qcap;      // stride between the count rows of the queue (allocated entries)
+};
+
 // Occupied-tet queue of one launch pair (device memory, see the scan kernel).
 struct QueueView {
-    int32_t *tet;     // [nseg * seg_cap] tile * kTetsPerTile + offset
-    int32_t *counts;  // [species][nseg * seg_cap] counts at the start of the period
-    int32_t *len;     // [2][nseg] segment lengths, one per kLenStride ints (own cache line);
-                      // both halves zero before the first launch
-    int32_t nseg;     // 1..kMaxSegments
-    int32_t seg_cap;  // entries per segment
-    int32_t species;  // rows of counts: the largest species count of the work list
+    int32_t *tet;       // [qcap] tile * kTetsPerTile + offset
+    int32_t *counts;    // [species][qcap] counts at the start of the period
+    int32_t *len;       // [2][kMaxSegments] segment lengths, one per kLenStride ints (own cache
+                        // line); both halves zero before the first launch
+    WorkHeader *hdr;    // device copy of the sizes below
+    int32_t nseg;       // host copies
+    int32_t seg_cap;
+    int64_t qcap;       // allocated entries per count row
+    int32_t species;    // allocated count rows
 };
 constexpr int kMaxSegments = 256;
 constexpr int kLenStride = 32;  // 128 bytes between segment lengths: no two share a line
 
-// Queue geometry for a work list of n_tiles tiles.
+// Queue geometry for a work list of n_tiles tiles: tiles ti with
+// ti % nseg == k fill segment k.
 inline void queue_shape(int64_t n_tiles, int32_t *nseg, int32_t *seg_cap)
 {
     const int64_t ns = n_tiles < kMaxSegments ? (n_tiles > 0 ? n_tiles : 1) : kMaxSegments;
@@ -90,14 +112,15 @@ inline void queue_shape(int64_t n_tiles, int32_t *nseg, int32_t *seg_cap)
 // One period for every tile: period index = sims[i].step0 + iter; the period
 // whose index equals `partial` lasts tau_last instead of tau.  Consecutive
 // launches on one queue alternate qsel = 0, 1, 0, ...
-hipError_t launch_scan(const DevSim *sims, const Tile *tiles, int32_t n_tiles, int64_t iter, const QueueView &q,
-                       int32_t qsel, int32_t scan_grid, hipStream_t st);
+// scan_grid blocks stride over the tiles named in q.hdr (> 0 required).
+hipError_t launch_scan(const DevSim *sims, const Tile *tiles, int64_t iter, const QueueView &q, int32_t qsel,
+                       int32_t scan_grid, hipStream_t st);
 hipError_t launch_update(const DevSim *sims, const Tile *tiles, int64_t iter, int64_t partial, double tau_last,
                          const QueueView &q, int32_t qsel, int32_t blocks_per_segment, hipStream_t st);
-hipError_t launch_step(const DevSim *sims, const Tile *tiles, int32_t n_tiles, int64_t iter, int64_t partial,
-                       double tau_last, const QueueView &q, int32_t qsel, int32_t scan_grid,
-                       int32_t blocks_per_segment, hipStream_t st);
-hipError_t launch_advance(DevSim *sims, int32_t n_sims, int64_t by, hipStream_t st);
+hipError_t launch_step(const DevSim *sims, const Tile *tiles, int64_t iter, int64_t partial, double tau_last,
+                       const QueueView &q, int32_t qsel, int32_t scan_grid, int32_t blocks_per_segment,
+                       hipStream_t st);
+hipError_t launch_advance(DevSim *sims, const WorkHeader *hdr, int64_t by, hipStream_t st);
 hipError_t launch_copy(const void *src, void *dst, size_t bytes, hipStream_t st);
 
 

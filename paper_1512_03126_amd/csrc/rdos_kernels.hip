@@ -312,21 +312,20 @@ __device__ __forceinline__ void update_tet(const DevSim &sm, int32_t t, int64_t 
 struct Queue {
     int32_t *tet;     // [qcap]
     int32_t *counts;  // [max species][qcap]
-    int32_t *len;     // [2][nseg]
-    int32_t nseg;
-    int32_t seg_cap;
-    int64_t qcap;     // nseg * seg_cap
+    int32_t *len;     // [2][kMaxSegments] * kLenStride
+    const WorkHeader *hdr;
 };
 
 template <int MAXS>
 __global__ __launch_bounds__(kBlock) void scan_kernel(const DevSim *__restrict__ sims,
-                                                      const Tile *__restrict__ tiles, int32_t n_tiles,
-                                                      int64_t iter, Queue q, int32_t qsel)
+                                                      const Tile *__restrict__ tiles, int64_t iter, Queue q,
+                                                      int32_t qsel)
 {
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
     const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
-    for (int32_t ti = blockIdx.x; ti < n_tiles; ti += gridDim.x) {
+    const WorkHeader h = *q.hdr;
+    for (int32_t ti = blockIdx.x; ti < h.n_tiles; ti += gridDim.x) {
         const Tile tile = tiles[ti];
         const DevSim &sm = sims[tile.sim];
         const int64_t period = sm.step0 + iter;
@@ -367,15 +366,15 @@ __global__ __launch_bounds__(kBlock) void scan_kernel(const DevSim *__restrict__
             total += __popcll(plane[b]);
         }
         if (total == 0) continue;  // uniform over the wavefront
-        const int32_t seg = ti % q.nseg;
+        const int32_t seg = ti % h.nseg;
         int32_t slot = 0;
-        if (lane == 0) slot = atomicAdd(&q.len[(qsel * q.nseg + seg) * kLenStride], total);
+        if (lane == 0) slot = atomicAdd(&q.len[(qsel * kMaxSegments + seg) * kLenStride], total);
         slot = __shfl(slot, 0);
-        if (slot + total > q.seg_cap) {  // cannot happen when len starts at 0; never write past
+        if (slot + total > h.seg_cap) {  // cannot happen when len starts at 0; never write past
             if (lane == 0) atomicOr(sm.flags, 4);
             continue;
         }
-        const int64_t seg_base = (int64_t)seg * q.seg_cap + slot;
+        const int64_t seg_base = (int64_t)seg * h.seg_cap + slot;
 #pragma unroll
         for (int b = 0; b < 4; ++b) {
             if (!((bits >> b) & 1u)) continue;
@@ -386,7 +385,7 @@ __global__ __launch_bounds__(kBlock) void scan_kernel(const DevSim *__restrict__
                 if (s >= S) break;
                 const int32_t cv = b == 0 ? c[s].x : b == 1 ? c[s].y : b == 2 ? c[s].z : c[s].w;
                 if (cv < 0) atomicOr(sm.flags, 1);  // wrapped by an overflowing atomic add
-                q.counts[s * q.qcap + idx] = cv;
+                q.counts[s * h.qcap + idx] = cv;
             }
         }
         // the queued molecules now live in the queue: clear their slots so
@@ -406,14 +405,15 @@ __global__ __launch_bounds__(kBlock) void update_kernel(const DevSim *__restrict
     __shared__ double last[kMaxSpecies * kBlock];
     __shared__ int32_t counts[kMaxSpecies * kBlock];
     const LaneState ls{counts + threadIdx.x, occ + threadIdx.x, last + threadIdx.x};
-    if (blockIdx.x == 0 && threadIdx.x < q.nseg) q.len[((qsel ^ 1) * q.nseg + threadIdx.x) * kLenStride] = 0;
-    const int32_t seg = blockIdx.x % q.nseg;
-    const int32_t per_seg = max(1, (int32_t)(gridDim.x / q.nseg));  // blocks sharing a segment
-    const int32_t part = blockIdx.x / q.nseg;
-    if (part >= per_seg) return;
-    const int32_t n = min(q.len[(qsel * q.nseg + seg) * kLenStride], q.seg_cap);
+    if (blockIdx.x == 0 && threadIdx.x < kMaxSegments) q.len[((qsel ^ 1) * kMaxSegments + threadIdx.x) * kLenStride] = 0;
+    const WorkHeader h = *q.hdr;
+    const int32_t seg = blockIdx.x % kMaxSegments;   // the grid is kMaxSegments * blocks-per-segment
+    const int32_t per_seg = max(1, (int32_t)(gridDim.x / kMaxSegments));
+    const int32_t part = blockIdx.x / kMaxSegments;
+    if (seg >= h.nseg || part >= per_seg) return;
+    const int32_t n = min(q.len[(qsel * kMaxSegments + seg) * kLenStride], h.seg_cap);
     for (int32_t i = part * kBlock + threadIdx.x; i < n; i += per_seg * kBlock) {
-        const int64_t idx = (int64_t)seg * q.seg_cap + i;
+        const int64_t idx = (int64_t)seg * h.seg_cap + i;
         const int32_t entry = q.tet[idx];
         const Tile tile = tiles[entry / kTetsPerTile];
         const DevSim &sm = sims[tile.sim];
@@ -421,43 +421,41 @@ __global__ __launch_bounds__(kBlock) void update_kernel(const DevSim *__restrict
         const double tau_k = period == partial ? tau_last : sm.tau;
         const int64_t Tp = ((int64_t)sm.T + 3) & ~(int64_t)3;
         const int64_t base = (int64_t)tile.realization * sm.S * Tp;
-        for (int s = 0; s < sm.S; ++s) ls.n(s) = q.counts[s * q.qcap + idx];
+        for (int s = 0; s < sm.S; ++s) ls.n(s) = q.counts[s * h.qcap + idx];
         update_tet(sm, tile.tet0 + entry % kTetsPerTile, period, tau_k, sm.key1 ^ (uint32_t)tile.realization,
                    sm.buf[(period + 1) & 1] + base, Tp, ls);
     }
 }
 
-hipError_t launch_scan(const DevSim *sims, const Tile *tiles, int32_t n_tiles, int64_t iter, const QueueView &qv,
-                       int32_t qsel, int32_t scan_grid, hipStream_t st)
+hipError_t launch_scan(const DevSim *sims, const Tile *tiles, int64_t iter, const QueueView &qv, int32_t qsel,
+                       int32_t scan_grid, hipStream_t st)
 {
-    if (n_tiles <= 0) return hipSuccess;
-    const int32_t g = scan_grid > 0 ? (scan_grid < n_tiles ? scan_grid : n_tiles) : n_tiles;
-    const Queue q{qv.tet, qv.counts, qv.len, qv.nseg, qv.seg_cap, (int64_t)qv.nseg * qv.seg_cap};
-    // register arrays sized for the largest species count of the work list
+    if (scan_grid <= 0) return hipErrorInvalidValue;
+    const Queue q{qv.tet, qv.counts, qv.len, qv.hdr};
+    // register arrays sized for the largest species count the queue holds
     if (qv.species <= 2)
-        scan_kernel<2><<<g, kBlock, 0, st>>>(sims, tiles, n_tiles, iter, q, qsel);
+        scan_kernel<2><<<scan_grid, kBlock, 0, st>>>(sims, tiles, iter, q, qsel);
     else if (qv.species <= 4)
-        scan_kernel<4><<<g, kBlock, 0, st>>>(sims, tiles, n_tiles, iter, q, qsel);
+        scan_kernel<4><<<scan_grid, kBlock, 0, st>>>(sims, tiles, iter, q, qsel);
     else
-        scan_kernel<kMaxSpecies><<<g, kBlock, 0, st>>>(sims, tiles, n_tiles, iter, q, qsel);
+        scan_kernel<kMaxSpecies><<<scan_grid, kBlock, 0, st>>>(sims, tiles, iter, q, qsel);
     return hipGetLastError();
 }
 
 hipError_t launch_update(const DevSim *sims, const Tile *tiles, int64_t iter, int64_t partial, double tau_last,
                          const QueueView &qv, int32_t qsel, int32_t blocks_per_segment, hipStream_t st)
 {
-    const Queue q{qv.tet, qv.counts, qv.len, qv.nseg, qv.seg_cap, (int64_t)qv.nseg * qv.seg_cap};
+    const Queue q{qv.tet, qv.counts, qv.len, qv.hdr};
     const int32_t bps = blocks_per_segment > 0 ? blocks_per_segment : 4;
-    update_kernel<<<qv.nseg * bps, kBlock, 0, st>>>(sims, tiles, q, qsel, iter, partial, tau_last);
+    update_kernel<<<kMaxSegments * bps, kBlock, 0, st>>>(sims, tiles, q, qsel, iter, partial, tau_last);
     return hipGetLastError();
 }
 
-hipError_t launch_step(const DevSim *sims, const Tile *tiles, int32_t n_tiles, int64_t iter, int64_t partial,
-                       double tau_last, const QueueView &qv, int32_t qsel, int32_t scan_grid,
-                       int32_t blocks_per_segment, hipStream_t st)
+hipError_t launch_step(const DevSim *sims, const Tile *tiles, int64_t iter, int64_t partial, double tau_last,
+                       const QueueView &qv, int32_t qsel, int32_t scan_grid, int32_t blocks_per_segment,
+                       hipStream_t st)
 {
-    if (n_tiles <= 0) return hipSuccess;
-    hipError_t e = launch_scan(sims, tiles, n_tiles, iter, qv, qsel, scan_grid, st);
+    hipError_t e = launch_scan(sims, tiles, iter, qv, qsel, scan_grid, st);
     if (e != hipSuccess) return e;
     return launch_update(sims, tiles, iter, partial, tau_last, qv, qsel, blocks_per_segment, st);
 }
@@ -491,16 +489,16 @@ hipError_t launch_copy(const void *src, void *dst, size_t bytes, hipStream_t st)
 }
 
 // After a chunk of periods: every simulation's period index moves on.
-__global__ void advance_kernel(DevSim *sims, int32_t n_sims, int64_t by)
+__global__ void advance_kernel(DevSim *sims, const WorkHeader *hdr, int64_t by)
 {
-    const int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n_sims) sims[i].step0 += by;
+    const int32_t n = hdr->n_sims;
+    for (int32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x)
+        sims[i].step0 += by;
 }
 
-hipError_t launch_advance(DevSim *sims, int32_t n_sims, int64_t by, hipStream_t st)
+hipError_t launch_advance(DevSim *sims, const WorkHeader *hdr, int64_t by, hipStream_t st)
 {
-    if (n_sims <= 0) return hipSuccess;
-    advance_kernel<<<(n_sims + 63) / 64, 64, 0, st>>>(sims, n_sims, by);
+    advance_kernel<<<4, 256, 0, st>>>(sims, hdr, by);
     return hipGetLastError();
 }
 

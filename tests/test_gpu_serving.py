@@ -1,0 +1,89 @@
+"""Serving: requests that arrive while others run join the batch, and every
+result is the same as the request run alone (bit for bit, checked against the
+oracle and against a direct run on the GPU)."""
+import sys
+import time
+
+import numpy as np
+import pytest
+
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def note(msg):
+    print(f"[gpu-case] {msg}", flush=True)
+    sys.stdout.flush()
+
+
+def small_request(i):
+    rng = np.random.default_rng([77, i])
+    return W.serving_request(rng, t_lo=300, t_hi=4000, max_species=4)
+
+
+def run_oracle(orc, m, periods):
+    o = orc.OracleSim(m.xyz, m.tets, m.D, m.reactions, seed=m.seed)
+    for q in range(m.n_species):
+        o.set_counts(q, m.init[0, q])
+    o.run_steps(periods)
+    return o.get_counts()
+
+
+def test_served_results_equal_alone(orc):
+    import paper_1512_03126_amd as P
+
+    reqs = [small_request(i) for i in range(8)]
+    periods = [40 + 10 * i for i in range(8)]
+    note("serving: 8 requests arriving while others run")
+    e = P.rdos_engine_create(0, 0)
+    tickets = []
+    for i, (m, n) in enumerate(zip(reqs, periods)):
+        s = P.Simulation(m.xyz, m.tets, m.D, m.reactions, seed=m.seed, tau_scale=None)
+        for q in range(m.n_species):
+            s.set_counts(q, m.init[0, q])
+        tickets.append((P.rdos_engine_submit(e, s.h, n, 1.0), s))
+        time.sleep(0.002 * (i % 3))  # staggered arrivals: some join running chunks
+    P.rdos_engine_drain(e)
+    mixed = []
+    for t, s in tickets:
+        done, lat = P.rdos_engine_poll(e, t)
+        assert done and lat > 0
+        P.rdos_engine_release(e, t)
+        mixed.append(s.get_counts())
+        s.close()
+    P.rdos_engine_destroy(e)
+    note("serving: each request alone (direct stepping) and on the oracle")
+    for m, n, got in zip(reqs, periods, mixed):
+        alone = P.Simulation(m.xyz, m.tets, m.D, m.reactions, seed=m.seed)
+        for q in range(m.n_species):
+            alone.set_counts(q, m.init[0, q])
+        alone.step(n)
+        np.testing.assert_array_equal(alone.get_counts(), got)
+        alone.close()
+        np.testing.assert_array_equal(run_oracle(orc, m, n), got)
+
+
+def test_engine_stall_is_reported_not_hung():
+    import paper_1512_03126_amd as P
+
+    note("serving: budget held by an unreleased finished request")
+    m = small_request(3)
+    e = P.rdos_engine_create(0, 0)
+    s1 = P.Simulation(m.xyz, m.tets, m.D, m.reactions, seed=m.seed, tau_scale=None)
+    need = s1.info()["device_bytes"]
+    P.rdos_engine_destroy(e)
+    e = P.rdos_engine_create(0, int(need * 1.5))
+    s2 = P.Simulation(m.xyz, m.tets, m.D, m.reactions, seed=m.seed + 1, tau_scale=None)
+    t1 = P.rdos_engine_submit(e, s1.h, 10, 1.0)
+    t2 = P.rdos_engine_submit(e, s2.h, 10, 1.0)
+    with pytest.raises(P.RdosError) as ei:
+        P.rdos_engine_drain(e)        # t2 cannot start until t1 is released
+    assert ei.value.status == -2
+    P.rdos_engine_release(e, t1)
+    P.rdos_engine_drain(e)
+    assert P.rdos_engine_poll(e, t2)[0]
+    P.rdos_engine_release(e, t2)
+    s1.close()
+    s2.close()
+    P.rdos_engine_destroy(e)

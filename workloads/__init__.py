@@ -103,9 +103,11 @@ def jitter(xyz: np.ndarray, n: int, a: float, frac: float, seed: int) -> np.ndar
 
 def _tet_volumes(xyz: np.ndarray, tets: np.ndarray) -> np.ndarray:
     """Tet volumes for placing molecules (input recipe only)."""
-    P = xyz[tets]  # [T,4,3]
-    M = P[:, 1:, :] - P[:, :1, :]
-    return np.abs(np.linalg.det(M)) / 6.0
+    p0 = xyz[tets[:, 0]]
+    a = xyz[tets[:, 1]] - p0
+    b = xyz[tets[:, 2]] - p0
+    c = xyz[tets[:, 3]] - p0
+    return np.abs(np.einsum("ij,ij->i", a, np.cross(b, c))) / 6.0
 
 
 def _barycentres(xyz: np.ndarray, tets: np.ndarray) -> np.ndarray:
@@ -192,16 +194,30 @@ def abcd_jittered(n: int = 40, a: float = 0.1e-6, seed: int = 1, t_end: float = 
                  species_names=["A", "B", "C", "D"])
 
 
+_LATTICES = {}
+
+
+def _lattice_cached(n: int, a: float):
+    key = (n, a)
+    if key not in _LATTICES:
+        if len(_LATTICES) > 64:
+            _LATTICES.clear()
+        _LATTICES[key] = kuhn_lattice(n, a)
+    return _LATTICES[key]
+
+
 def serving_request(rng: np.random.Generator, a: float = 0.1e-6, t_lo: float = 1e4,
                     t_hi: float = 1e6, max_species: int = 6) -> Model:
     """One request of the serving mix: jittered lattice with T log-uniform in
     [t_lo, t_hi] tets, 1..max_species species with D log-uniform in
     [1e-13, 1e-11] m^2/s, 0..2S random uni/bimolecular reactions (first order
     log-U [1, 1e3] /s, second order log-U [1e5, 1e8] /(M s)), each species
-    initialised log-U [10 nM, 1 uM] placed by volume."""
+    initialised log-U [10 nM, 1 uM] placed by volume.  A reaction never has
+    more products than reactants (conversions and degradations), so no
+    request can grow without bound."""
     T = math.exp(rng.uniform(math.log(t_lo), math.log(t_hi)))
     n = max(2, int(round((T / 6.0) ** (1.0 / 3.0))))
-    xyz0, tets = kuhn_lattice(n, a)
+    xyz0, tets = _lattice_cached(n, a)
     xyz = jitter(xyz0, n, a, 0.2, int(rng.integers(1, 2**31)))
     S = int(rng.integers(1, max_species + 1))
     D = [float(math.exp(rng.uniform(math.log(1e-13), math.log(1e-11)))) for _ in range(S)]
@@ -214,14 +230,15 @@ def serving_request(rng: np.random.Generator, a: float = 0.1e-6, t_lo: float = 1
         else:
             r = [int(rng.integers(0, S)), int(rng.integers(0, S))]
             k = float(math.exp(rng.uniform(math.log(1e5), math.log(1e8))))
-        n_prod = int(rng.integers(0, 3))
+        n_prod = int(rng.integers(0, len(r) + 1))
         p = [int(rng.integers(0, S)) for _ in range(n_prod)]
         reactions.append((r, p, k))
     vol_total = (n * a) ** 3
     init = np.zeros((1, S, tets.shape[0]), dtype=np.int32)
+    vol = _tet_volumes(xyz, tets)
     for s in range(S):
         c = math.exp(rng.uniform(math.log(10e-9), math.log(1e-6)))
-        init[0, s] = place_by_volume(xyz, tets, count_for(c, vol_total), rng)
+        init[0, s] = place_by_volume(xyz, tets, count_for(c, vol_total), rng, vol=vol)
     return Model(f"serve_{n}cube_S{S}_R{n_reac}", xyz, tets, D, reactions, init,
                  t_end=float("nan"), seed=int(rng.integers(1, 2**31)))
 
