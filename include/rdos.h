@@ -176,10 +176,11 @@ rdos_status rdos_engine_kernel_times(rdos_engine *e, double *scan_ms, int64_t *s
                                      double *update_ms, int64_t *update_launches);
 
 /* The launch shape the tuner settled on for the current work list: periods
- * per graph replay, scan blocks (0 = one per tile), update blocks per queue
- * segment.  Results never depend on it. */
+ * per graph replay, scan blocks, update blocks per queue segment, and 1 or 2
+ * independent chains (halves of the realizations on two streams, so one
+ * half's update overlaps the other's scan).  Results never depend on it. */
 rdos_status rdos_engine_launch_shape(rdos_engine *e, int32_t *chunk, int32_t *scan_grid,
-                                     int32_t *update_bps);
+                                     int32_t *update_bps, int32_t *chains);
 
 /* Measures the device's streaming copy bandwidth (read + write bytes per
  * second / 1e9) with a 16-byte-per-lane copy kernel over `bytes`, `reps`

@@ -15,7 +15,8 @@ from typing import Iterable, Optional, Sequence, Tuple
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "librdos.so")
+# RDOS_LIBRARY may name another build of the same library (for comparing builds)
+LIB_PATH = os.environ.get("RDOS_LIBRARY") or os.path.join(_HERE, "librdos.so")
 
 STATUS = {0: "RDOS_OK", -1: "RDOS_EINVAL", -2: "RDOS_ENOMEM", -3: "RDOS_EDEVICE", -4: "RDOS_ESTATE",
           -5: "RDOS_EOVERFLOW", -6: "RDOS_EBUSY"}
@@ -59,7 +60,8 @@ _SIGS = [
     ("rdos_engine_drain", C.c_int, [C.c_void_p]),
     ("rdos_engine_release", C.c_int, [C.c_void_p, C.c_uint64, _P(C.c_void_p)]),
     ("rdos_engine_stats", C.c_int, [C.c_void_p, _P(C.c_int64), _P(C.c_double), _P(C.c_double)]),
-    ("rdos_engine_launch_shape", C.c_int, [C.c_void_p, _P(C.c_int32), _P(C.c_int32), _P(C.c_int32)]),
+    ("rdos_engine_launch_shape", C.c_int, [C.c_void_p, _P(C.c_int32), _P(C.c_int32), _P(C.c_int32),
+                                           _P(C.c_int32)]),
     ("rdos_engine_set_profiling", C.c_int, [C.c_void_p, C.c_int]),
     ("rdos_engine_kernel_times", C.c_int, [C.c_void_p, _P(C.c_double), _P(C.c_int64), _P(C.c_double),
                                            _P(C.c_int64)]),
@@ -258,9 +260,9 @@ def rdos_engine_stats(engine):
 
 
 def rdos_engine_launch_shape(engine):
-    a, b, c = C.c_int32(), C.c_int32(), C.c_int32()
-    _check(lib().rdos_engine_launch_shape(engine, C.byref(a), C.byref(b), C.byref(c)), engine, True)
-    return dict(chunk=a.value, scan_grid=b.value, update_blocks_per_segment=c.value)
+    a, b, c, d = C.c_int32(), C.c_int32(), C.c_int32(), C.c_int32()
+    _check(lib().rdos_engine_launch_shape(engine, C.byref(a), C.byref(b), C.byref(c), C.byref(d)), engine, True)
+    return dict(chunk=a.value, scan_grid=b.value, update_blocks_per_segment=c.value, chains=d.value)
 
 
 def rdos_engine_set_profiling(engine, on: bool):

@@ -51,9 +51,10 @@ struct Shape {
     int32_t chunk;       // periods per graph replay (even: the queue length halves alternate)
     int32_t scan_grid;   // blocks of the scan launch (grid-stride over the tiles)
     int32_t update_bps;  // update blocks per queue segment
+    int32_t chains;      // 1, or 2 independent halves of the realizations on two streams
     bool operator==(const Shape &o) const
     {
-        return chunk == o.chunk && scan_grid == o.scan_grid && update_bps == o.update_bps;
+        return chunk == o.chunk && scan_grid == o.scan_grid && update_bps == o.update_bps && chains == o.chains;
     }
 };
 
@@ -64,6 +65,8 @@ struct rdos_engine {
     size_t budget = 0;
     size_t used = 0;
     hipStream_t stream = nullptr;
+    hipStream_t stream2 = nullptr;  // second chain of a two-chain chunk
+    hipEvent_t fork = nullptr, join = nullptr;
     std::string error;
 
     std::mutex mu;
@@ -88,11 +91,15 @@ struct rdos_engine {
     int64_t cap_sims = 0;
     Tile *d_tiles = nullptr;
     int64_t cap_tiles = 0;
-    QueueView queue{};
+    QueueView queue{};   // chain 0 (all tiles when there is one chain)
+    QueueView queue2{};  // chain 1
     int32_t n_tiles = 0;
+    int32_t n_sims = 0;
+    int32_t n_tiles0 = 0;   // tiles of chain 0 when split: they come first in d_tiles
+    int32_t hdr_chains = 0; // chain count the queue headers currently describe
     int32_t max_species = 1;
     hipGraphExec_t graph = nullptr;
-    Shape graph_shape{0, 0, 0};
+    Shape graph_shape{0, 0, 0, 0};
     bool graph_stale = true;  // a buffer the graph names was reallocated
     bool rebuild = true;      // the slot set changed
 
@@ -102,7 +109,7 @@ struct rdos_engine {
     std::pair<int, int> bucket{-1, -1};
     size_t trial = 0;
     double best_rate = -1.0;
-    Shape best{16, 2048, 8};
+    Shape best{16, 2048, 8, 1};
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
 
     // per-kernel timing: chunks launched directly with events between launches
@@ -161,8 +168,11 @@ int species_bound(int s) { return s <= 2 ? 2 : (s <= 4 ? 4 : kMaxSpecies); }
 // Rewrites the device work list for the current slots (lock held).
 rdos_status build_work(rdos_engine *e)
 {
+    // Realizations never exchange molecules, so the (simulation, realization)
+    // units split into two independent chains; units are dealt to the chain
+    // with fewer tiles so far, chain 0's tiles first in the list.
     std::vector<DevSim> sims;
-    std::vector<Tile> tiles;
+    std::vector<Tile> part[2];
     int32_t max_species = 1;
     for (size_t i = 0; i < e->slots.size(); ++i) {
         Ticket &tk = e->tickets[e->slots[i]];
@@ -171,27 +181,34 @@ rdos_status build_work(rdos_engine *e)
         d.step0 = s->step;
         d.step_end = tk.end_step;
         sims.push_back(d);
-        for (int32_t r = 0; r < s->Rz; ++r)
+        for (int32_t r = 0; r < s->Rz; ++r) {
+            std::vector<Tile> &dst = part[part[0].size() <= part[1].size() ? 0 : 1];
             for (int32_t t0 = 0; t0 < s->T; t0 += kTetsPerTile)
-                tiles.push_back({(int32_t)i, r, t0, std::min<int32_t>(kTetsPerTile, s->T - t0)});
+                dst.push_back({(int32_t)i, r, t0, std::min<int32_t>(kTetsPerTile, s->T - t0)});
+        }
         max_species = std::max(max_species, (int32_t)s->D.size());
     }
+    std::vector<Tile> tiles = part[0];
+    tiles.insert(tiles.end(), part[1].begin(), part[1].end());
+    e->n_tiles0 = (int32_t)part[0].size();
     rdos_status st = ensure(e, &e->d_sims, &e->cap_sims, (int64_t)std::max<size_t>(sims.size(), 1), "engine slots");
     if (st != RDOS_OK) return st;
     st = ensure(e, &e->d_tiles, &e->cap_tiles, (int64_t)std::max<size_t>(tiles.size(), 1), "engine tiles");
     if (st != RDOS_OK) return st;
-    const int64_t nt = (int64_t)std::max<size_t>(tiles.size(), 1);
-    int32_t nseg, seg_cap;
-    queue_shape(nt, &nseg, &seg_cap);
-    if ((int64_t)nseg * seg_cap > e->queue.qcap || species_bound(max_species) > e->queue.species) {
-        ENGINE_HIP(e, hipStreamSynchronize(e->stream), "drain before reallocating the queue");
-        {
+    // chain 0's queue can hold every tile (one chain); chain 1's the second half
+    const int64_t need[2] = {(int64_t)std::max<size_t>(tiles.size(), 1), (int64_t)std::max<size_t>(part[1].size(), 1)};
+    QueueView *qs[2] = {&e->queue, &e->queue2};
+    for (int c = 0; c < 2; ++c) {
+        int32_t nseg, seg_cap;
+        queue_shape(need[c], &nseg, &seg_cap);
+        if ((int64_t)nseg * seg_cap > qs[c]->qcap || species_bound(max_species) > qs[c]->species) {
+            ENGINE_HIP(e, hipStreamSynchronize(e->stream), "drain before reallocating the queue");
             std::lock_guard<std::mutex> g(device_api_mutex());
-            free_queue(&e->queue);
-            ENGINE_HIP(e, alloc_queue(&e->queue, nt + nt / 2, species_bound(max_species), e->stream),
+            free_queue(qs[c]);
+            ENGINE_HIP(e, alloc_queue(qs[c], need[c] + need[c] / 2, species_bound(max_species), e->stream),
                        "engine queue");
+            e->graph_stale = true;
         }
-        e->graph_stale = true;
     }
     if (!sims.empty())
         ENGINE_HIP(e, hipMemcpyAsync(e->d_sims, sims.data(), sims.size() * sizeof(DevSim), hipMemcpyHostToDevice,
@@ -201,10 +218,24 @@ rdos_status build_work(rdos_engine *e)
         ENGINE_HIP(e, hipMemcpyAsync(e->d_tiles, tiles.data(), tiles.size() * sizeof(Tile), hipMemcpyHostToDevice,
                                      e->stream),
                    "upload tiles");
-    ENGINE_HIP(e, set_queue_work(&e->queue, (int64_t)tiles.size(), (int32_t)sims.size(), e->stream),
-               "work header");
     e->n_tiles = (int32_t)tiles.size();
+    e->n_sims = (int32_t)sims.size();
     e->max_species = max_species;
+    e->hdr_chains = 0;  // headers are written for the chain count of the next chunk
+    return RDOS_OK;
+}
+
+// Points the queue headers at one chain over all tiles or two chains.
+rdos_status set_chains(rdos_engine *e, int32_t chains)
+{
+    if (chains == e->hdr_chains) return RDOS_OK;
+    if (chains == 1) {
+        ENGINE_HIP(e, set_queue_work(&e->queue, e->n_tiles, e->n_sims, e->stream), "work header");
+    } else {
+        ENGINE_HIP(e, set_queue_work(&e->queue, e->n_tiles0, e->n_sims, e->stream), "work header");
+        ENGINE_HIP(e, set_queue_work(&e->queue2, e->n_tiles - e->n_tiles0, e->n_sims, e->stream), "work header");
+    }
+    e->hdr_chains = chains;
     return RDOS_OK;
 }
 
@@ -215,6 +246,22 @@ rdos_status build_work(rdos_engine *e)
 hipError_t enqueue_chunk(rdos_engine *e, const Shape &sh, bool timed)
 {
     hipError_t err = hipSuccess;
+    if (sh.chains == 2) {
+        // two independent chains: fork the second stream off the first, join before the advance
+        err = hipEventRecord(e->fork, e->stream);
+        if (err == hipSuccess) err = hipStreamWaitEvent(e->stream2, e->fork, 0);
+        for (int32_t i = 0; i < sh.chunk && err == hipSuccess; ++i) {
+            err = launch_step(e->d_sims, e->d_tiles, i, -1, 0.0, e->queue, i & 1, sh.scan_grid, sh.update_bps,
+                              e->stream);
+            if (err == hipSuccess)
+                err = launch_step(e->d_sims, e->d_tiles + e->n_tiles0, i, -1, 0.0, e->queue2, i & 1, sh.scan_grid,
+                                  sh.update_bps, e->stream2);
+        }
+        if (err == hipSuccess) err = hipEventRecord(e->join, e->stream2);
+        if (err == hipSuccess) err = hipStreamWaitEvent(e->stream, e->join, 0);
+        if (err == hipSuccess) err = launch_advance(e->d_sims, e->queue.hdr, sh.chunk, e->stream);
+        return err;
+    }
     if (timed) err = hipEventRecord(e->kev[0], e->stream);
     for (int32_t i = 0; i < sh.chunk && err == hipSuccess; ++i) {
         err = launch_scan(e->d_sims, e->d_tiles, i, e->queue, i & 1, sh.scan_grid, e->stream);
@@ -370,8 +417,13 @@ void worker_main(rdos_engine *e)
             }
         }
         // the tuner tries each candidate once per size bucket, then keeps the best
-        const Shape sh = e->trial < e->candidates.size() ? e->candidates[e->trial] : e->best;
+        Shape sh = e->trial < e->candidates.size() ? e->candidates[e->trial] : e->best;
         const bool timed = e->profiling;
+        if (timed || e->n_tiles0 == 0 || e->n_tiles0 == e->n_tiles) sh.chains = 1;  // nothing to split
+        if (set_chains(e, sh.chains) != RDOS_OK) {
+            fail_slots(e);
+            break;
+        }
         if (timed) {
             bool ok = true;
             while (ok && (int32_t)e->kev.size() < 2 * sh.chunk + 1) {
@@ -479,12 +531,15 @@ rdos_status rdos_engine_create(rdos_engine **out, int device, size_t hbm_budget_
     }
     e->budget = hbm_budget_bytes ? hbm_budget_bytes : (size_t)(0.9 * (double)free_b);
     if (hipStreamCreateWithFlags(&e->stream, hipStreamNonBlocking) != hipSuccess ||
+        hipStreamCreateWithFlags(&e->stream2, hipStreamNonBlocking) != hipSuccess ||
+        hipEventCreateWithFlags(&e->fork, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&e->join, hipEventDisableTiming) != hipSuccess ||
         hipEventCreate(&e->ev0) != hipSuccess || hipEventCreate(&e->ev1) != hipSuccess ||
         hipStreamSynchronize(e->stream) != hipSuccess) {
         delete e;
         return RDOS_EDEVICE;
     }
-    e->candidates = {{16, 2048, 8}, {16, 4096, 4}, {16, 8192, 8}, {16, 1024, 4}, {32, 2048, 8}};
+    e->candidates = {{16, 2048, 8, 1}, {16, 8192, 8, 1}, {16, 1024, 8, 2}, {16, 2048, 8, 2}, {16, 4096, 4, 2}};
     e->worker = std::thread(worker_main, e);
     e->admitter = std::thread(admitter_main, e);
     *out = e;
@@ -577,13 +632,15 @@ rdos_status rdos_engine_stats(rdos_engine *e, int64_t *launches, double *updates
     return RDOS_OK;
 }
 
-rdos_status rdos_engine_launch_shape(rdos_engine *e, int32_t *chunk, int32_t *scan_grid, int32_t *update_bps)
+rdos_status rdos_engine_launch_shape(rdos_engine *e, int32_t *chunk, int32_t *scan_grid, int32_t *update_bps,
+                                     int32_t *chains)
 {
     if (!e) return RDOS_EINVAL;
     std::lock_guard<std::mutex> g(e->mu);
     if (chunk) *chunk = e->best.chunk;
     if (scan_grid) *scan_grid = e->best.scan_grid;
     if (update_bps) *update_bps = e->best.update_bps;
+    if (chains) *chains = e->best.chains;
     return RDOS_OK;
 }
 
@@ -664,7 +721,11 @@ void rdos_engine_destroy(rdos_engine *e)
     for (void *q : p)
         if (q) (void)hipFree(q);
     free_queue(&e->queue);
+    free_queue(&e->queue2);
     for (hipEvent_t ev : e->kev) (void)hipEventDestroy(ev);
+    if (e->fork) (void)hipEventDestroy(e->fork);
+    if (e->join) (void)hipEventDestroy(e->join);
+    if (e->stream2) (void)hipStreamDestroy(e->stream2);
     if (e->ev0) (void)hipEventDestroy(e->ev0);
     if (e->ev1) (void)hipEventDestroy(e->ev1);
     if (e->stream) (void)hipStreamDestroy(e->stream);
