@@ -45,6 +45,11 @@ def lib():
         L.orc_tau.restype = f64
         L.orc_tau.argtypes = [C.c_void_p]
         L.orc_set_first_order.argtypes = [C.c_void_p, C.c_int]
+        L.orc_set_split_threshold.argtypes = [C.c_void_p, C.c_int]
+        L.orc_set_tau_outliers.restype = f64
+        L.orc_set_tau_outliers.argtypes = [C.c_void_p, i32]
+        L.orc_set_reaction_region.argtypes = [C.c_void_p, i32, i32, P(i32)]
+        L.orc_split_many_threshold.argtypes = [i64, P(f64), P(i32), u64, i32, i32, P(i64)]
         L.orc_geometry.argtypes = [C.c_void_p, P(i32), P(f64), P(f64), P(f64), P(f64), P(f64)]
         L.orc_set_counts.argtypes = [C.c_void_p, i32, P(i32)]
         L.orc_get_counts.argtypes = [C.c_void_p, i32, P(i32)]
@@ -112,6 +117,16 @@ class OracleSim:
 
     def set_first_order(self, on: bool):
         lib().orc_set_first_order(self._h, 1 if on else 0)
+
+    def set_split_threshold(self, threshold: int):
+        lib().orc_set_split_threshold(self._h, int(threshold))
+
+    def set_tau_outliers(self, k: int) -> float:
+        return lib().orc_set_tau_outliers(self._h, int(k))
+
+    def set_reaction_region(self, reaction: int, tets):
+        t = np.ascontiguousarray(tets, dtype=np.int32)
+        lib().orc_set_reaction_region(self._h, int(reaction), int(t.size), _p(t, C.c_int32))
 
     @property
     def tau(self) -> float:
@@ -189,10 +204,10 @@ def binomial_many(n: int, p: float, seed: int, count: int) -> np.ndarray:
     return out
 
 
-def split_many(n: int, w, nbr, seed: int, count: int) -> np.ndarray:
+def split_many(n: int, w, nbr, seed: int, count: int, threshold: int = 10) -> np.ndarray:
     w = np.ascontiguousarray(w, dtype=np.float64)
     nbr = np.ascontiguousarray(nbr, dtype=np.int32)
     out = np.empty((count, 4), np.int64)
-    lib().orc_split_many(int(n), _p(w, C.c_double), _p(nbr, C.c_int32), int(seed), int(count),
-                         _p(out, C.c_int64))
+    lib().orc_split_many_threshold(int(n), _p(w, C.c_double), _p(nbr, C.c_int32), int(seed), int(count),
+                                   int(threshold), _p(out, C.c_int64))
     return out

@@ -59,6 +59,9 @@ struct orc_sim {
     int64_t anchor_step; /* time(k) = anchor_t + (k - anchor_step) * tau */
     double anchor_t;
     int first_order;     /* 1: n from the count at the end of the period, not Nbar */
+    int split_threshold; /* below this n the split goes molecule by molecule */
+    double tau_scale;
+    uint32_t *allowed;   /* [T] bit r: reaction r may fire in the tet (NULL: everywhere) */
     /* per-step scratch */
     int32_t *nend;       /* [S][T] */
     int32_t *out;        /* [T][S][4] molecules sent across each face */
@@ -335,7 +338,7 @@ int64_t orc_binomial(int64_t n, double p, uint64_t seed, int32_t realization,
 /* draw; otherwise n_i = binomial(n - sum_{j<i} n_j, w_i / (1 - sum_{j<i} w_j)) */
 /* face by face, the last interior face taking the remainder (p = 1).        */
 /* ------------------------------------------------------------------------- */
-static void split(int64_t n, const double *w, const int32_t *nbr, orc_rng *g, int64_t out[4])
+static void split(int64_t n, const double *w, const int32_t *nbr, int threshold, orc_rng *g, int64_t out[4])
 {
     out[0] = out[1] = out[2] = out[3] = 0;
     if (n <= 0) return;
@@ -347,7 +350,7 @@ static void split(int64_t n, const double *w, const int32_t *nbr, orc_rng *g, in
         out[faces[0]] = n;
         return;
     }
-    if (n < ORC_SPLIT_ONE_BY_ONE) {
+    if (n < threshold) {
         for (int64_t i = 0; i < n; ++i) {
             double U = next_u(g);
             int chosen = faces[nf - 1];
@@ -387,7 +390,7 @@ uint32_t orc_split(int64_t n, const double *w, const int32_t *nbr, uint64_t seed
 {
     orc_rng r;
     rng_init(&r, seed, realization, stream, tet, step, j);
-    split(n, w, nbr, &r, out);
+    split(n, w, nbr, ORC_SPLIT_ONE_BY_ONE, &r, out);
     return r.j;
 }
 
@@ -617,6 +620,8 @@ orc_sim *orc_create(int32_t n_verts, const double *xyz, int32_t n_tets,
         return NULL;
     }
     s->tau = tau_scale * best;
+    s->tau_scale = tau_scale;
+    s->split_threshold = ORC_SPLIT_ONE_BY_ONE;
     s->step = 0;
     s->anchor_step = 0;
     s->anchor_t = 0.0;
@@ -641,6 +646,7 @@ void orc_destroy(orc_sim *s)
     free(s->cnt);
     free(s->nend);
     free(s->out);
+    free(s->allowed);
     free(s);
 }
 
@@ -649,6 +655,49 @@ double orc_tau(const orc_sim *s) { return s->tau; }
 /* The paper's comparison method of Sec. III.B (Fig. 7): the diffusive
  * transfer uses the count at the end of the period instead of Nbar. */
 void orc_set_first_order(orc_sim *s, int on) { s->first_order = on ? 1 : 0; }
+
+/* Sec. II.B: the split switches from one-by-one to the multinomial function
+ * at this n (10 in the paper's implementation); any threshold >= 1 gives the
+ * same law, only the draws differ. */
+void orc_set_split_threshold(orc_sim *s, int threshold) { s->split_threshold = threshold < 1 ? 1 : threshold; }
+
+static int cmp_double(const void *a, const void *b)
+{
+    double x = *(const double *)a, y = *(const double *)b;
+    return x < y ? -1 : (x > y ? 1 : 0);
+}
+
+/* Sec. II.A: ignoring the k tet-species with the largest local rates raises
+ * tau; there zeta would exceed 1 and is held at 1.  tau becomes tau_scale
+ * times the (k+1)-th smallest 1/(D_m g_t).  Returns the new tau. */
+double orc_set_tau_outliers(orc_sim *s, int32_t k)
+{
+    size_t cnt = 0;
+    double *v = (double *)malloc(sizeof(double) * (size_t)s->T * (size_t)s->S);
+    for (int m = 0; m < s->S; ++m) {
+        if (!(s->D[m] > 0.0)) continue;
+        for (int32_t t = 0; t < s->T; ++t)
+            if (s->g[t] > 0.0) v[cnt++] = 1.0 / (s->D[m] * s->g[t]);
+    }
+    qsort(v, cnt, sizeof(double), cmp_double);
+    size_t idx = k < 0 ? 0 : (size_t)k;
+    if (idx >= cnt) idx = cnt - 1;
+    s->tau = s->tau_scale * v[idx];
+    free(v);
+    return s->tau;
+}
+
+/* Restricts reaction r to the listed tets (a localized reaction, e.g. the
+ * influx at the ends of the tube of Sec. III.B). */
+void orc_set_reaction_region(orc_sim *s, int32_t r, int32_t n, const int32_t *tets)
+{
+    if (!s->allowed) {
+        s->allowed = (uint32_t *)malloc(sizeof(uint32_t) * (size_t)s->T);
+        for (int32_t t = 0; t < s->T; ++t) s->allowed[t] = 0xFFFFFFFFu;
+    }
+    for (int32_t t = 0; t < s->T; ++t) s->allowed[t] &= ~(1u << r);
+    for (int32_t i = 0; i < n; ++i) s->allowed[tets[i]] |= 1u << r;
+}
 
 void orc_geometry(const orc_sim *s, int32_t *nbr, double *w, double *g, double *nav, double *vol,
                   double *area)
@@ -759,7 +808,7 @@ void orc_step(orc_sim *s, double tau_k, double *nbar_out, int32_t *n_out)
         for (;;) {
             double a0 = 0.0;
             for (int r = 0; r < R; ++r) {
-                av[r] = rate_const(s, r, t) * combos(s, r, N);
+                av[r] = (s->allowed && !((s->allowed[t] >> r) & 1u)) ? 0.0 : rate_const(s, r, t) * combos(s, r, N);
                 a0 = a0 + av[r];
             }
             if (!(a0 > 0.0)) break;
@@ -817,7 +866,7 @@ void orc_step(orc_sim *s, double tau_k, double *nbar_out, int32_t *n_out)
                 if (n > N[m]) n = N[m];
                 /* Step 3.3: multinomial split over the face neighbours */
                 int64_t nf[4];
-                split(n, s->w + 4 * (size_t)t, s->nbr + 4 * (size_t)t, &rd, nf);
+                split(n, s->w + 4 * (size_t)t, s->nbr + 4 * (size_t)t, s->split_threshold, &rd, nf);
                 for (int f = 0; f < 4; ++f) o[f] = (int32_t)nf[f];
                 N[m] -= n;
             }
@@ -860,6 +909,9 @@ void orc_run_until(orc_sim *s, double t_end)
     }
 }
 
+void orc_split_many_threshold(int64_t n, const double *w, const int32_t *nbr, uint64_t seed, int32_t count,
+                              int32_t threshold, int64_t *out);
+
 /* ------------------------------------------------------------------------- */
 /* Batch helpers for the statistical tests: sample i uses the stream          */
 /* (seed, realization 0, stream 0, tet i, step 0) from draw 0.               */
@@ -876,9 +928,15 @@ void orc_binomial_many(int64_t n, double p, uint64_t seed, int32_t count, int64_
 void orc_split_many(int64_t n, const double *w, const int32_t *nbr, uint64_t seed, int32_t count,
                     int64_t *out)
 {
+    orc_split_many_threshold(n, w, nbr, seed, count, ORC_SPLIT_ONE_BY_ONE, out);
+}
+
+void orc_split_many_threshold(int64_t n, const double *w, const int32_t *nbr, uint64_t seed, int32_t count,
+                              int32_t threshold, int64_t *out)
+{
     for (int32_t i = 0; i < count; ++i) {
         orc_rng r;
         rng_init(&r, seed, 0, 0u, (uint32_t)i, 0u, 0u);
-        split(n, w, nbr, &r, out + 4 * (size_t)i);
+        split(n, w, nbr, threshold < 1 ? 1 : threshold, &r, out + 4 * (size_t)i);
     }
 }

@@ -48,6 +48,12 @@ double orc_tau(const orc_sim *s);
 /* Ablation: 1 = "first-order" splitting (n drawn from the count at the end of
  * the period rather than the mean occupancy), the paper's Fig. 7 comparison. */
 void orc_set_first_order(orc_sim *s, int on);
+/* Method options: the one-by-one / multinomial-function switch point
+ * (default 10), tau from the (k+1)-th smallest 1/(D g) (default k = 0;
+ * returns the new tau), and a reaction restricted to a set of tets. */
+void orc_set_split_threshold(orc_sim *s, int threshold);
+double orc_set_tau_outliers(orc_sim *s, int32_t k);
+void orc_set_reaction_region(orc_sim *s, int32_t r, int32_t n, const int32_t *tets);
 void orc_geometry(const orc_sim *s, int32_t *nbr /*[T][4]*/, double *w /*[T][4]*/,
                   double *g /*[T]*/, double *nav /*[T]*/, double *vol /*[T]*/,
                   double *area /*[T][4]*/);
@@ -83,6 +89,8 @@ uint32_t orc_split(int64_t n, const double *w, const int32_t *nbr,
 void orc_binomial_many(int64_t n, double p, uint64_t seed, int32_t count, int64_t *out);
 void orc_split_many(int64_t n, const double *w, const int32_t *nbr, uint64_t seed,
                     int32_t count, int64_t *out /*[count][4]*/);
+void orc_split_many_threshold(int64_t n, const double *w, const int32_t *nbr, uint64_t seed,
+                              int32_t count, int32_t threshold, int64_t *out /*[count][4]*/);
 
 #ifdef __cplusplus
 }

@@ -395,3 +395,74 @@ def test_zeta_one_ring_conserves_parity_imbalance(orc):
             q0 = q if q0 is None else q0
             assert q == q0
             sim.step()
+
+
+def test_tau_outliers_is_the_order_statistic(orc):
+    """Sec. II.A: ignoring the k fastest tet-species sets tau from the
+    (k+1)-th smallest 1/(D g); zeta is held at 1 in those k."""
+    xyz, tets = W.tiny_lattice(3, 0.1e-6, jitter_frac=0.2, seed=12)
+    D = [1e-12, 0.3e-12]
+    for ts in (1.0, 0.6):
+        sim = orc.OracleSim(xyz, tets, D, [], tau_scale=ts)
+        g = sim.geometry()["g"]
+        inv = np.sort(np.concatenate([1.0 / (d * g[g > 0]) for d in D]))
+        assert sim.tau == ts * inv[0]
+        for k in (1, 10, 57):
+            assert sim.set_tau_outliers(k) == ts * inv[k]
+        assert sim.set_tau_outliers(0) == ts * inv[0]
+        assert sim.set_tau_outliers(10 ** 6) == ts * inv[-1]
+
+
+def test_point_source_law_with_tau_outliers(orc):
+    """With zeta held at 1 in the outlier tets the moves are still
+    independent per molecule: counts stay exactly Multinomial(N0, e P^k)."""
+    xyz, tets = W.tiny_lattice(2, 0.2e-6, jitter_frac=0.2, seed=3)
+    D = 1e-12
+    T = tets.shape[0]
+    runs, k_steps, N0, src = 1200, 3, 30, 5
+    agg = np.zeros(T)
+    for r in range(runs):
+        sim = orc.OracleSim(xyz, tets, [D], [], seed=19, realization=r)
+        tau = sim.set_tau_outliers(6)
+        init = np.zeros(T, np.int32)
+        init[src] = N0
+        sim.set_counts(0, init)
+        sim.run_steps(k_steps)
+        agg += sim.get_counts(0)
+    geo = sim.geometry()
+    assert ((tau * D) * geo["g"] > 1.0).sum() >= 1   # some tets are past zeta = 1
+    P = _transition_matrix(geo, D, tau)
+    pi = np.zeros(T)
+    pi[src] = 1.0
+    for _ in range(k_steps):
+        pi = P.T @ pi
+    assert _chi2_pvalue(agg, pi * runs * N0) > 1e-3
+
+
+def test_localized_production(orc):
+    """0 -> A only in a region: the total after one period is Poisson with
+    mean k N_A V_region tau, and every molecule sits in the region or next to it."""
+    xyz, tets = W.tiny_lattice(3, 0.2e-6, jitter_frac=0.2, seed=2)
+    T = tets.shape[0]
+    region = np.arange(0, T, 7, dtype=np.int32)
+    kp = 2e-5
+    runs = 3000
+    totals = np.zeros(runs, np.int64)
+    for r in range(runs):
+        sim = orc.OracleSim(xyz, tets, [1e-12], [([], [0], kp)], seed=41, realization=r)
+        sim.set_reaction_region(0, region)
+        sim.step()
+        c = sim.get_counts(0)
+        totals[r] = c.sum()
+        if r == 0:
+            geo = sim.geometry()
+            near = set(region.tolist())
+            for t in region:
+                near.update(int(u) for u in geo["nbr"][t] if u >= 0)
+        assert all(int(t) in near for t in np.nonzero(c)[0])
+    mean = kp * float(geo["nav"][region].sum()) * sim.tau
+    hi = int(stats.poisson.isf(1e-9, mean))
+    obs = np.bincount(totals, minlength=hi + 1)[: hi + 1]
+    pmf = stats.poisson.pmf(np.arange(hi + 1), mean)
+    pmf[-1] += stats.poisson.sf(hi, mean)
+    assert _chi2_pvalue(obs, pmf * runs) > 1e-3

@@ -175,3 +175,24 @@ def test_split_threshold_is_ten(orc):
     j10 = L.orc_split(10, w.ctypes.data_as(P(C.c_double)), nbr.ctypes.data_as(P(C.c_int32)), 1, 0, 0, 0, 0, 0,
                       o.ctypes.data_as(P(C.c_int64)))
     assert j10 <= 8  # at most 3 binomials of n p < 10 (BINV: one draw each unless it restarts)
+
+
+@pytest.mark.parametrize("threshold,n", [(1, 7), (4, 7), (50, 30), (2, 120)])
+def test_split_law_at_any_threshold(orc, threshold, n):
+    """The switch point between one-by-one and the multinomial function only
+    changes which draws are used (Sec. II.B): every face count stays
+    Binomial(n, w_f)."""
+    w = np.array([0.15, 0.35, 0.0, 0.5])
+    nbr = np.array([2, 5, -1, 9], dtype=np.int32)
+    count = 30000
+    out = orc.split_many(n, w, nbr, seed=313 + threshold, count=count, threshold=threshold)
+    assert (out.sum(axis=1) == n).all() and (out[:, 2] == 0).all()
+    for f in (0, 1, 3):
+        x = out[:, f]
+        lo, hi = int(x.min()), int(x.max())
+        ks = np.arange(lo, hi + 1)
+        pmf = stats.binom.pmf(ks, n, w[f])
+        pmf[0] += stats.binom.cdf(lo - 1, n, w[f]) if lo > 0 else 0.0
+        pmf[-1] += stats.binom.sf(hi, n, w[f])
+        obs = np.bincount(x - lo, minlength=hi - lo + 1)
+        assert _chi2_pvalue(obs, pmf * count) > ALPHA, (threshold, n, f)
