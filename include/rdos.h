@@ -84,6 +84,27 @@ rdos_status rdos_add_species(rdos_sim *s, double D, int32_t *out_id);
 rdos_status rdos_add_reaction(rdos_sim *s, int32_t n_reac, const int32_t *reac, int32_t n_prod,
                               const int32_t *prod, double k, int32_t *out_id);
 
+/* Method options, before finalize (defaults: 1, 10, 0).
+ *   occupancy_correction  1: n = binomial(Nbar, zeta) with Nbar the mean
+ *                         population over the period (Sec. II.C, eqs. 2-3);
+ *                         0: "first-order" splitting, n drawn from the count
+ *                         at the end of the period (the comparison method of
+ *                         Sec. III.B, Fig. 7)
+ *   split_threshold       n below which the split moves molecules one by one
+ *                         (Sec. II.B: 10 in the paper); >= 1.  The law does
+ *                         not depend on it, the draws do.
+ *   tau_outliers          k >= 0: tau from the (k+1)-th smallest 1/(D g)
+ *                         instead of the smallest, so zeta is held at 1 in the
+ *                         k fastest tet-species (outlier relaxation, Sec. II.A).
+ * RDOS_EINVAL for split_threshold < 1 or tau_outliers < 0. */
+rdos_status rdos_set_method(rdos_sim *s, int32_t occupancy_correction, int32_t split_threshold,
+                            int32_t tau_outliers);
+
+/* Restricts reaction `reaction` to the tets tets[0..n_tets) (a localized
+ * reaction, e.g. the influx at both ends of the tube of Sec. III.B);
+ * before finalize.  Without a call a reaction may fire in every tet. */
+rdos_status rdos_set_reaction_region(rdos_sim *s, int32_t reaction, int32_t n_tets, const int32_t *tets);
+
 /* Builds the mesh tables on the device and fixes the period
  *   tau = tau_scale * min over tets t and diffusing species m of 1/(D_m g_t)
  * (Algorithm 1, "precompute tau"; the local rate is d = D g with

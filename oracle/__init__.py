@@ -104,6 +104,8 @@ class OracleSim:
     def from_model(cls, model, realization=0, seed=None):
         sim = cls(model.xyz, model.tets, model.D, model.reactions, model.tau_scale,
                   model.seed if seed is None else seed, realization)
+        for r, tets in (getattr(model, "regions", None) or {}).items():
+            sim.set_reaction_region(r, tets)
         init = model.init[min(realization, model.init.shape[0] - 1)]
         for s in range(sim.S):
             sim.set_counts(s, init[s])

@@ -40,6 +40,8 @@ _SIGS = [
     ("rdos_add_species", C.c_int, [C.c_void_p, C.c_double, _P(C.c_int32)]),
     ("rdos_add_reaction", C.c_int, [C.c_void_p, C.c_int32, _P(C.c_int32), C.c_int32, _P(C.c_int32), C.c_double,
                                     _P(C.c_int32)]),
+    ("rdos_set_method", C.c_int, [C.c_void_p, C.c_int32, C.c_int32, C.c_int32]),
+    ("rdos_set_reaction_region", C.c_int, [C.c_void_p, C.c_int32, C.c_int32, _P(C.c_int32)]),
     ("rdos_finalize", C.c_int, [C.c_void_p, C.c_double, _P(C.c_double)]),
     ("rdos_set_counts", C.c_int, [C.c_void_p, C.c_int32, C.c_int32, _P(C.c_int32)]),
     ("rdos_get_counts", C.c_int, [C.c_void_p, C.c_int32, C.c_int32, _P(C.c_int32)]),
@@ -147,6 +149,16 @@ def rdos_add_reaction(sim, reactants: Sequence[int], products: Sequence[int], k:
     _check(lib().rdos_add_reaction(sim, len(reactants), _ptr(r, C.c_int32), len(products), _ptr(p, C.c_int32),
                                    float(k), C.byref(out)), sim)
     return out.value
+
+
+def rdos_set_method(sim, occupancy_correction: bool = True, split_threshold: int = 10, tau_outliers: int = 0):
+    _check(lib().rdos_set_method(sim, 1 if occupancy_correction else 0, int(split_threshold), int(tau_outliers)),
+           sim)
+
+
+def rdos_set_reaction_region(sim, reaction: int, tets):
+    t = np.ascontiguousarray(tets, dtype=np.int32)
+    _check(lib().rdos_set_reaction_region(sim, int(reaction), int(t.size), _ptr(t, C.c_int32)), sim)
 
 
 def rdos_finalize(sim, tau_scale: float = 1.0) -> float:
@@ -293,7 +305,8 @@ class Simulation:
     """A simulation handle: mesh, species, reactions, counts, stepping."""
 
     def __init__(self, xyz, tets, D: Iterable[float], reactions=(), seed: int = 1, n_realizations: int = 1,
-                 device: int = 0, tau_scale: Optional[float] = 1.0):
+                 device: int = 0, tau_scale: Optional[float] = 1.0, occupancy_correction: bool = True,
+                 split_threshold: int = 10, tau_outliers: int = 0, regions=None):
         self.h = rdos_create(device, seed, n_realizations)
         self.T = int(np.asarray(tets).shape[0])
         self.Rz = int(n_realizations)
@@ -304,15 +317,23 @@ class Simulation:
             self.S += 1
         for re, pr, k in reactions:
             rdos_add_reaction(self.h, re, pr, k)
+        if not occupancy_correction or split_threshold != 10 or tau_outliers:
+            rdos_set_method(self.h, occupancy_correction, split_threshold, tau_outliers)
+        for r, tets_r in (regions or {}).items():
+            rdos_set_reaction_region(self.h, r, tets_r)
         self.tau = None
         if tau_scale is not None:
             self.tau = rdos_finalize(self.h, tau_scale)
 
     @classmethod
-    def from_model(cls, model, device: int = 0, n_realizations: Optional[int] = None, finalize: bool = True):
+    def from_model(cls, model, device: int = 0, n_realizations: Optional[int] = None, finalize: bool = True,
+                   **method):
+        """A handle for a workload model; `method` takes the keyword options
+        of the constructor (occupancy_correction, split_threshold, tau_outliers)."""
         Rz = model.init.shape[0] if n_realizations is None else n_realizations
         sim = cls(model.xyz, model.tets, model.D, model.reactions, seed=model.seed, n_realizations=Rz,
-                  device=device, tau_scale=model.tau_scale if finalize else None)
+                  device=device, tau_scale=model.tau_scale if finalize else None,
+                  regions=getattr(model, "regions", None), **method)
         for r in range(Rz):
             init = model.init[min(r, model.init.shape[0] - 1)]
             for s in range(sim.S):

@@ -107,8 +107,9 @@ size_t state_bytes(const rdos_sim *s)
     const int64_t Tp = padded_tets(s->T);
     const size_t counts = (size_t)s->Rz * s->D.size() * (size_t)Tp * sizeof(int32_t);
     const size_t tiles = (size_t)tiles_of(s) * sizeof(Tile);
+    const size_t masks = s->regions.empty() ? 0 : (size_t)s->T * sizeof(uint32_t);
     return (size_t)s->T * sizeof(MeshRec) + 2 * counts + tiles + queue_bytes(tiles_of(s), (int32_t)s->D.size()) +
-           sizeof(DevSim) + 64;
+           masks + sizeof(DevSim) + 64;
 }
 
 // Face-matching results are cached by mesh connectivity (the tet_verts
@@ -276,11 +277,12 @@ void free_device(rdos_sim *s)
     (void)hipSetDevice(s->device);
     if (s->stream) (void)hipStreamSynchronize(s->stream);
     std::lock_guard<std::mutex> g(device_api_mutex());
-    void *ptrs[] = {s->d_mesh, s->d_buf[0], s->d_buf[1], s->d_flags, s->d_desc, s->d_tiles};
+    void *ptrs[] = {s->d_mesh, s->d_buf[0], s->d_buf[1], s->d_flags, s->d_desc, s->d_tiles, s->d_allowed};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
     free_queue(&s->queue);
     s->d_mesh = nullptr;
+    s->d_allowed = nullptr;
     s->d_buf[0] = s->d_buf[1] = s->d_flags = nullptr;
     s->d_desc = nullptr;
     s->d_tiles = nullptr;
@@ -375,6 +377,33 @@ rdos_status rdos_add_reaction(rdos_sim *s, int32_t n_reac, const int32_t *reac, 
     return RDOS_OK;
 }
 
+rdos_status rdos_set_method(rdos_sim *s, int32_t occupancy_correction, int32_t split_threshold,
+                            int32_t tau_outliers)
+{
+    CHECK_HANDLE(s);
+    if (s->state != SimState::Meshed) return fail(s, RDOS_ESTATE, "set_method needs a mesh and no finalize yet");
+    if (split_threshold < 1 || tau_outliers < 0)
+        return fail(s, RDOS_EINVAL, "split_threshold must be >= 1 and tau_outliers >= 0");
+    s->first_order = occupancy_correction ? 0 : 1;
+    s->split_threshold = split_threshold;
+    s->tau_outliers = tau_outliers;
+    return RDOS_OK;
+}
+
+rdos_status rdos_set_reaction_region(rdos_sim *s, int32_t reaction, int32_t n_tets, const int32_t *tets)
+{
+    CHECK_HANDLE(s);
+    if (s->state != SimState::Meshed)
+        return fail(s, RDOS_ESTATE, "set_reaction_region needs a mesh and no finalize yet");
+    if (reaction < 0 || reaction >= (int32_t)s->rx.size()) return fail(s, RDOS_EINVAL, "reaction id out of range");
+    if (n_tets < 0 || (n_tets > 0 && !tets)) return fail(s, RDOS_EINVAL, "bad tet list");
+    std::vector<int32_t> v(tets, tets + n_tets);
+    for (int32_t t : v)
+        if (t < 0 || t >= s->T) return fail(s, RDOS_EINVAL, "tet id %d out of range", t);
+    s->regions[reaction] = std::move(v);
+    return RDOS_OK;
+}
+
 rdos_status rdos_finalize(rdos_sim *s, double tau_scale, double *out_tau)
 {
     CHECK_HANDLE(s);
@@ -452,7 +481,24 @@ rdos_status rdos_finalize(rdos_sim *s, double tau_scale, double *out_tau)
               "upload D");
     SETUP_TRY(launch_geometry(d_xyz, d_tv, d_nbr, T, d_vol, d_bc, d_area, s->d_mesh, s->d_flags + 1, s->stream),
               "geometry");
-    SETUP_TRY(launch_tau_min(s->d_mesh, T, d_D, S, d_tau, s->stream), "tau");
+    if (s->tau_outliers > 0) {
+        // Sec. II.A outlier relaxation: the (k+1)-th smallest 1/(D g) sets tau
+        void *scratch = nullptr;
+        hipError_t e_sel;
+        {
+            std::lock_guard<std::mutex> g(device_api_mutex());
+            e_sel = hipMalloc(&scratch, tau_select_scratch_bytes(T, S));
+        }
+        if (e_sel == hipSuccess) {
+            e_sel = launch_tau_select(s->d_mesh, T, d_D, S, s->tau_outliers, scratch, d_tau, s->stream);
+            (void)hipStreamSynchronize(s->stream);
+            std::lock_guard<std::mutex> g(device_api_mutex());
+            (void)hipFree(scratch);
+        }
+        SETUP_TRY(e_sel, "tau selection");
+    } else {
+        SETUP_TRY(launch_tau_min(s->d_mesh, T, d_D, S, d_tau, s->stream), "tau");
+    }
     unsigned long long tau_bits = 0;
     int32_t bad[2] = {0, 0};
     SETUP_TRY(hipMemcpyAsync(&tau_bits, d_tau, sizeof tau_bits, hipMemcpyDeviceToHost, s->stream), "read tau");
@@ -492,6 +538,30 @@ rdos_status rdos_finalize(rdos_sim *s, double tau_scale, double *out_tau)
     for (int m = 0; m < S; ++m) {
         d.D[m] = s->D[m];
         if (s->D[m] > 0.0) d.diff_mask |= 1u << m;
+    }
+    d.first_order = s->first_order ? 1u : 0u;
+    d.split_threshold = s->split_threshold;
+    if (!s->regions.empty()) {
+        std::vector<uint32_t> allowed((size_t)T, 0xFFFFFFFFu);
+        for (const auto &kv : s->regions) {
+            const uint32_t bit = 1u << kv.first;
+            for (uint32_t &a : allowed) a &= ~bit;
+            for (int32_t t : kv.second) allowed[t] |= bit;
+        }
+        hipError_t e_al;
+        {
+            std::lock_guard<std::mutex> g(device_api_mutex());
+            e_al = hipMalloc(&s->d_allowed, allowed.size() * sizeof(uint32_t));
+        }
+        if (e_al == hipSuccess)
+            e_al = hipMemcpyAsync(s->d_allowed, allowed.data(), allowed.size() * sizeof(uint32_t),
+                                  hipMemcpyHostToDevice, s->stream);
+        if (e_al == hipSuccess) e_al = hipStreamSynchronize(s->stream);
+        if (e_al != hipSuccess) {
+            free_device(s);
+            return hip_fail(s, e_al, "upload reaction regions");
+        }
+        d.allowed = s->d_allowed;
     }
     for (size_t q = 0; q < s->rx.size(); ++q) {
         const Reaction &r = s->rx[q];

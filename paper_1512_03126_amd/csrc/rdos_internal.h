@@ -40,6 +40,9 @@ struct alignas(16) DevSim {
     double D[kMaxSpecies];
     uint32_t diff_mask;        // species with D > 0
     uint32_t zeroth;           // 1 if some reaction has no reactant (every tet active)
+    uint32_t first_order;      // 1: n from the count at the end of the period instead of Nbar
+    int32_t split_threshold;   // below this n molecules are split one by one (Sec. II.B: 10)
+    const uint32_t *allowed;   // [T] bit r: reaction r may fire in the tet (null: everywhere)
     // reactions
     int32_t rn[kMaxReactions], r0[kMaxReactions], r1[kMaxReactions];
     int32_t pn[kMaxReactions], p0[kMaxReactions], p1[kMaxReactions], p2[kMaxReactions];
@@ -75,6 +78,12 @@ hipError_t launch_geometry(const double *xyz, const int32_t *tet_verts, const in
                            hipStream_t st);
 hipError_t launch_tau_min(const MeshRec *mesh, int32_t T, const double *D, int32_t S,
                           unsigned long long *out_bits, hipStream_t st);
+// Writes the k-th smallest (0-based, clamped to the last) of 1/(D_m g_t)
+// over diffusing species and connected tets to *out_bits (as its bit
+// pattern); scratch must hold tau_select_scratch_bytes(T, S) bytes.
+size_t tau_select_scratch_bytes(int32_t T, int32_t S);
+hipError_t launch_tau_select(const MeshRec *mesh, int32_t T, const double *D, int32_t S, int64_t k, void *scratch,
+                             unsigned long long *out_bits, hipStream_t st);
 // Work-list sizes and queue geometry, read by the kernels from device memory
 // so that a captured graph stays valid when the work list changes.
 struct alignas(16) WorkHeader {

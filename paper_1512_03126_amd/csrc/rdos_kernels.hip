@@ -12,6 +12,8 @@
 
 #include <cstdint>
 
+#include <hipcub/hipcub.hpp>
+
 #include "rdos_internal.h"
 #include "rdos_sampling.h"
 
@@ -148,6 +150,72 @@ hipError_t launch_tau_min(const MeshRec *mesh, int32_t T, const double *D, int32
     return hipGetLastError();
 }
 
+// 1/(D_m g_t) for every (species, tet) as sortable bit patterns; pairs that
+// set no rate (D = 0 or an isolated tet) become all-ones and sort last.
+__global__ __launch_bounds__(256) void tau_values_kernel(const MeshRec *__restrict__ mesh, int32_t T,
+                                                         const double *__restrict__ D, int32_t S,
+                                                         unsigned long long *__restrict__ out,
+                                                         unsigned long long *__restrict__ n_valid)
+{
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= (int64_t)T * S) return;
+    const int32_t m = (int32_t)(i / T), t = (int32_t)(i % T);
+    const double g = mesh[t].g;
+    unsigned long long v = ~0ull;
+    if (D[m] > 0.0 && g > 0.0) {
+        v = (unsigned long long)__double_as_longlong(1.0 / (D[m] * g));
+        atomicAdd(n_valid, 1ull);
+    }
+    out[i] = v;
+}
+
+__global__ void tau_pick_kernel(const unsigned long long *sorted, const unsigned long long *n_valid, int64_t k,
+                                unsigned long long *out_bits)
+{
+    const unsigned long long n = *n_valid;
+    if (n == 0) {
+        *out_bits = ~0ull;
+        return;
+    }
+    const unsigned long long idx = (unsigned long long)k < n ? (unsigned long long)k : n - 1;
+    *out_bits = sorted[idx];
+}
+
+static size_t tau_sort_temp_bytes(int64_t n)
+{
+    size_t bytes = 0;
+    (void)hipcub::DeviceRadixSort::SortKeys(nullptr, bytes, (const unsigned long long *)nullptr,
+                                            (unsigned long long *)nullptr, (int)n, 0, 64);
+    return bytes;
+}
+
+size_t tau_select_scratch_bytes(int32_t T, int32_t S)
+{
+    const int64_t n = (int64_t)T * S;
+    return 2 * (size_t)n * sizeof(unsigned long long) + 256 + tau_sort_temp_bytes(n);
+}
+
+hipError_t launch_tau_select(const MeshRec *mesh, int32_t T, const double *D, int32_t S, int64_t k, void *scratch,
+                             unsigned long long *out_bits, hipStream_t st)
+{
+    const int64_t n = (int64_t)T * S;
+    char *p = static_cast<char *>(scratch);
+    unsigned long long *keys = reinterpret_cast<unsigned long long *>(p);
+    unsigned long long *sorted = keys + n;
+    unsigned long long *n_valid = sorted + n;
+    void *temp = p + 2 * (size_t)n * sizeof(unsigned long long) + 256;
+    size_t temp_bytes = tau_sort_temp_bytes(n);
+    hipError_t e = hipMemsetAsync(n_valid, 0, sizeof(unsigned long long), st);
+    if (e != hipSuccess) return e;
+    tau_values_kernel<<<(int)((n + 255) / 256), 256, 0, st>>>(mesh, T, D, S, keys, n_valid);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    e = hipcub::DeviceRadixSort::SortKeys(temp, temp_bytes, keys, sorted, (int)n, 0, 64, st);
+    if (e != hipSuccess) return e;
+    tau_pick_kernel<<<1, 1, 0, st>>>(sorted, n_valid, k, out_bits);
+    return hipGetLastError();
+}
+
 // ---------------------------------------------------------------------------
 // The period update of one tet (Algorithm 1, Steps 2-3).
 // ---------------------------------------------------------------------------
@@ -160,9 +228,12 @@ struct LaneState {
     __device__ __forceinline__ int32_t &n(int s) const { return N[s * kBlock]; }
 };
 
-// propensity a_r = c_r h_r of reaction q with the tet's counts (mass action)
-__device__ __forceinline__ double propensity(const DevSim &sm, int q, const LaneState &ls, double nav)
+// propensity a_r = c_r h_r of reaction q with the tet's counts (mass action);
+// zero where the reaction is not allowed (bit q of `allow`)
+__device__ __forceinline__ double propensity(const DevSim &sm, int q, const LaneState &ls, double nav,
+                                             uint32_t allow)
 {
+    if (!((allow >> q) & 1u)) return 0.0;
     const int order = sm.rn[q];
     double h;
     if (order == 0) {
@@ -191,6 +262,7 @@ __device__ __forceinline__ void update_tet(const DevSim &sm, int32_t t, int64_t 
     const uint32_t period32 = (uint32_t)period;
     const MeshRec &mr = sm.mesh[t];
     const double nav = mr.nav;
+    const uint32_t allow = sm.allowed ? sm.allowed[t] : 0xFFFFFFFFu;
 
     // Step 2: Gillespie direct method over [0, tau_k); the first event at or
     // past tau_k is discarded.  Step 2.1: on each event the occupancy
@@ -207,7 +279,7 @@ __device__ __forceinline__ void update_tet(const DevSim &sm, int32_t t, int64_t 
                 break;
             }
             double a0 = 0.0;
-            for (int q = 0; q < R; ++q) a0 = a0 + propensity(sm, q, ls, nav);
+            for (int q = 0; q < R; ++q) a0 = a0 + propensity(sm, q, ls, nav, allow);
             if (!(a0 > 0.0)) break;
             const double dt = -log_basic(1.0 - ssa.uniform()) / a0;
             if (now + dt >= tau_k) break;
@@ -216,7 +288,7 @@ __device__ __forceinline__ void update_tet(const DevSim &sm, int32_t t, int64_t 
             int chosen = -1;
             double cum = 0.0;
             for (int q = 0; q < R; ++q) {
-                cum = cum + propensity(sm, q, ls, nav);
+                cum = cum + propensity(sm, q, ls, nav, allow);
                 if (x < cum) {
                     chosen = q;
                     break;
@@ -224,7 +296,7 @@ __device__ __forceinline__ void update_tet(const DevSim &sm, int32_t t, int64_t 
             }
             if (chosen < 0) {  // x rounded up to a0: the last reaction able to fire
                 for (int q = R - 1; q >= 0; --q)
-                    if (propensity(sm, q, ls, nav) > 0.0) {
+                    if (propensity(sm, q, ls, nav, allow) > 0.0) {
                         chosen = q;
                         break;
                     }
@@ -259,7 +331,7 @@ __device__ __forceinline__ void update_tet(const DevSim &sm, int32_t t, int64_t 
     for (int s = 0; s < S; ++s) {
         const int32_t Ns = ls.n(s);
         if (((sm.diff_mask >> s) & 1u) && Ns > 0) {  // Ns == 0: n = min(binomial(.), 0) = 0
-            const bool hit = (touched >> s) & 1u;
+            const bool hit = ((touched >> s) & 1u) && !sm.first_order;
             const double nbar = hit ? (ls.occ[s * kBlock] + (double)Ns * (tau_k - ls.last[s * kBlock])) / tau_k
                                     : (double)Ns;
             Stream rng(sm.key0, key1, (uint32_t)s, (uint32_t)t, period32);
@@ -283,7 +355,7 @@ __device__ __forceinline__ void update_tet(const DevSim &sm, int32_t t, int64_t 
             if (n > Ns) n = Ns;
             if (n > 0) {
                 int64_t out[4];
-                split_over_faces(n, nb, w, rng, out);
+                split_over_faces(n, nb, w, sm.split_threshold, rng, out);
 #pragma unroll
                 for (int f = 0; f < 4; ++f)
                     if (out[f] > 0) atomicAdd(&nxt[s * Tp + nb[f]], (int32_t)out[f]);

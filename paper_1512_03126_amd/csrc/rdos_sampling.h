@@ -246,12 +246,13 @@ __device__ inline int64_t binomial(int64_t n, double p, Stream &rng)
 
 // ---------------------------------------------------------------------------
 // Multinomial split of n leaving molecules over the interior faces
-// (Sec. II.B).  n < 10: one categorical draw per molecule against the running
-// sum of the weights (the last interior face closes the interval); n >= 10:
+// (Sec. II.B).  n < threshold (10 in the paper): one categorical draw per
+// molecule against the running sum of the weights (the last interior face
+// closes the interval); otherwise
 // n_i = Binomial(n - sum_{j<i} n_j, w_i / (1 - sum_{j<i} w_j)) face by face,
 // the last interior face taking what is left.
 // ---------------------------------------------------------------------------
-__device__ inline void split_over_faces(int64_t n, const int32_t nbr[4], const double w[4],
+__device__ inline void split_over_faces(int64_t n, const int32_t nbr[4], const double w[4], int32_t threshold,
                                         Stream &rng, int64_t out[4])
 {
     out[0] = out[1] = out[2] = out[3] = 0;
@@ -270,7 +271,7 @@ __device__ inline void split_over_faces(int64_t n, const int32_t nbr[4], const d
             if (f == last) out[f] = n;
         return;
     }
-    if (n < 10) {
+    if (n < threshold) {
         for (int64_t i = 0; i < n; ++i) {
             const double u = rng.uniform();
             double edge = 0.0;

@@ -38,6 +38,11 @@ struct rdos_sim {
     std::vector<double> D;
     std::vector<rdos::Reaction> rx;
     std::map<int32_t, std::vector<int32_t>> staged;  // (r * kMaxSpecies + s) -> counts before finalize
+    // method options (set before finalize)
+    int32_t first_order = 0;
+    int32_t split_threshold = rdos::kSplitOneByOne;
+    int32_t tau_outliers = 0;
+    std::map<int32_t, std::vector<int32_t>> regions;  // reaction -> tets where it may fire
 
     // time: time(k) = anchor_t + (k - anchor_step) * tau
     double tau = 0.0;
@@ -49,6 +54,7 @@ struct rdos_sim {
     hipStream_t stream = nullptr;
     bool own_stream = false;
     rdos::MeshRec *d_mesh = nullptr;
+    uint32_t *d_allowed = nullptr;  // per-tet reaction masks (only with regions)
     int32_t *d_buf[2] = {nullptr, nullptr};  // counts; the state of period k is d_buf[k & 1]
     int32_t *d_flags = nullptr;
     rdos::DevSim *d_desc = nullptr;

@@ -1,0 +1,61 @@
+"""Method options on the GPU against the oracle, bit for bit: first-order
+splitting, the split threshold, tau outlier relaxation and localized
+reactions (the building blocks of the tube-with-influx validation)."""
+import sys
+
+import numpy as np
+import pytest
+
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+RX = [([0, 1], [2], 3e8), ([2], [0, 1], 400.0), ([], [1], 3e-5), ([0], [], 50.0)]
+D = [1e-12, 2e-12, 0.5e-12]
+
+
+def note(msg):
+    print(f"[gpu-case] {msg}", flush=True)
+    sys.stdout.flush()
+
+
+def pair(P, orc, xyz, tets, init, seed, occ=True, thr=10, k=0, regions=None):
+    T = tets.shape[0]
+    g = P.Simulation(xyz, tets, D, RX, seed=seed, n_realizations=init.shape[0], occupancy_correction=occ,
+                     split_threshold=thr, tau_outliers=k, regions=regions)
+    os_ = []
+    for r in range(init.shape[0]):
+        o = orc.OracleSim(xyz, tets, D, RX, seed=seed, realization=r)
+        o.set_first_order(not occ)
+        o.set_split_threshold(thr)
+        o.set_tau_outliers(k)
+        for rid, tl in (regions or {}).items():
+            o.set_reaction_region(rid, tl)
+        for s in range(len(D)):
+            o.set_counts(s, init[r, s])
+            g.set_counts(s, init[r, s], realization=r)
+        os_.append(o)
+    assert g.tau == os_[0].tau
+    return g, os_
+
+
+@pytest.mark.parametrize("occ,thr,k,use_region", [(False, 10, 0, False), (True, 1, 0, False), (True, 40, 0, True),
+                                                  (True, 10, 9, False), (False, 3, 25, True)])
+def test_method_options_every_period(orc, occ, thr, k, use_region):
+    import paper_1512_03126_amd as P
+
+    xyz, tets = W.tiny_lattice(3, 0.2e-6, jitter_frac=0.2, seed=6)
+    T = tets.shape[0]
+    rng = np.random.default_rng(thr + 7 * k)
+    init = rng.integers(0, 30, size=(2, len(D), T)).astype(np.int32)
+    init[:, 0, ::3] += 200          # some tets with many molecules: the sequential-binomial branch
+    regions = {2: np.arange(0, T, 5, dtype=np.int32), 3: np.arange(T // 2, T, dtype=np.int32)} if use_region else None
+    note(f"method options occ={occ} threshold={thr} outliers={k} regions={use_region}")
+    g, os_ = pair(P, orc, xyz, tets, init, seed=5 + k, occ=occ, thr=thr, k=k, regions=regions)
+    for period in range(30):
+        g.step(1)
+        for r, o in enumerate(os_):
+            o.step()
+            got, want = g.get_counts(None, realization=r), o.get_counts()
+            assert np.array_equal(got, want), (period, r, int((got != want).sum()))
+    g.close()

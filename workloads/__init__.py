@@ -45,6 +45,7 @@ class Model:
     seed: int = 1
     tau_scale: float = 1.0
     species_names: Optional[List[str]] = None
+    regions: Optional[dict] = None  # reaction id -> tets where it may fire
 
     @property
     def n_tets(self) -> int:
@@ -61,18 +62,22 @@ class Model:
 
 def kuhn_lattice(n: int, a: float) -> Tuple[np.ndarray, np.ndarray]:
     """Vertices and tetrahedra of an n^3-cell Kuhn lattice with cell edge a."""
-    m = n + 1
-    idx = np.arange(m)
-    k, j, i = np.meshgrid(idx, idx, idx, indexing="ij")
+    return kuhn_box(n, n, n, a)
+
+
+def kuhn_box(nx: int, ny: int, nz: int, a: float) -> Tuple[np.ndarray, np.ndarray]:
+    """An nx x ny x nz-cell Kuhn lattice (vertex id i + (nx+1)(j + (ny+1)k),
+    tet id 6 (ci + nx (cj + ny ck)) + p)."""
+    mx, my, mz = nx + 1, ny + 1, nz + 1
+    k, j, i = np.meshgrid(np.arange(mz), np.arange(my), np.arange(mx), indexing="ij")
     xyz = np.stack([i.ravel(), j.ravel(), k.ravel()], axis=1).astype(np.float64) * a
 
     def vid(ci, cj, ck):
-        return ci + m * (cj + m * ck)
+        return ci + mx * (cj + my * ck)
 
-    c = np.arange(n)
-    ck, cj, ci = np.meshgrid(c, c, c, indexing="ij")
+    ck, cj, ci = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
     ci, cj, ck = ci.ravel(), cj.ravel(), ck.ravel()
-    tets = np.empty((n * n * n, 6, 4), dtype=np.int64)
+    tets = np.empty((nx * ny * nz, 6, 4), dtype=np.int64)
     for p, perm in enumerate(_PERMS):
         off = np.zeros(3, dtype=np.int64)
         corners = [off.copy()]
@@ -241,6 +246,22 @@ def serving_request(rng: np.random.Generator, a: float = 0.1e-6, t_lo: float = 1
         init[0, s] = place_by_volume(xyz, tets, count_for(c, vol_total), rng, vol=vol)
     return Model(f"serve_{n}cube_S{S}_R{n_reac}", xyz, tets, D, reactions, init,
                  t_end=float("nan"), seed=int(rng.integers(1, 2**31)))
+
+
+def tube_influx(nx: int = 40, ny: int = 2, nz: int = 2, a: float = 0.1e-6, D: float = 1e-12,
+                kp: float = 2e-4, t_end: float = 0.05, n_realizations: int = 1, seed: int = 1) -> Model:
+    """A bar of nx x ny x nz Kuhn cells (a tube along x) with a constant
+    production 0 -> A restricted to the tets of the two end cell layers
+    (constant influx at both ends, as in the validation of Sec. III.B),
+    starting empty.  Model.regions maps the reaction to its tets."""
+    xyz, tets = kuhn_box(nx, ny, nz, a)
+    bc = _barycentres(xyz, tets)
+    ends = np.nonzero((bc[:, 0] < a) | (bc[:, 0] > (nx - 1) * a))[0].astype(np.int32)
+    init = np.zeros((n_realizations, 1, tets.shape[0]), dtype=np.int32)
+    m = Model(f"tube_{nx}x{ny}x{nz}", xyz, tets, [D], [([], [0], kp)], init, t_end, seed,
+              species_names=["A"])
+    m.regions = {0: ends}
+    return m
 
 
 def tiny_lattice(n: int = 2, a: float = 0.2e-6, jitter_frac: float = 0.0, seed: int = 3) -> Tuple[np.ndarray, np.ndarray]:
