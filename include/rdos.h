@@ -122,6 +122,14 @@ rdos_status rdos_set_counts(rdos_sim *s, int32_t realization, int32_t species,
  * RDOS_EOVERFLOW if any count overflowed since the last check. */
 rdos_status rdos_get_counts(rdos_sim *s, int32_t realization, int32_t species, int32_t *out);
 
+/* Zero-copy view: *out is the device address of counts[n_tets] (int32) of
+ * one species in one realization at the current period boundary.  The
+ * library owns the memory; the address is valid until the next step,
+ * run_until, set_state or destroy (the count buffers alternate between
+ * periods).  Work is asynchronous: synchronise the simulation's stream before
+ * reading it.  Writing through it sets the state like set_counts. */
+rdos_status rdos_device_counts(rdos_sim *s, int32_t realization, int32_t species, int32_t **out);
+
 /* Resume support: the period index keys the random streams, so
  * get_counts + get_time on one handle and set_counts + set_state on a new
  * one continue bit-identically.  t is the simulated time of period

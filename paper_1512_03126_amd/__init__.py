@@ -45,6 +45,7 @@ _SIGS = [
     ("rdos_finalize", C.c_int, [C.c_void_p, C.c_double, _P(C.c_double)]),
     ("rdos_set_counts", C.c_int, [C.c_void_p, C.c_int32, C.c_int32, _P(C.c_int32)]),
     ("rdos_get_counts", C.c_int, [C.c_void_p, C.c_int32, C.c_int32, _P(C.c_int32)]),
+    ("rdos_device_counts", C.c_int, [C.c_void_p, C.c_int32, C.c_int32, _P(C.c_void_p)]),
     ("rdos_set_state", C.c_int, [C.c_void_p, C.c_int64, C.c_double]),
     ("rdos_get_time", C.c_int, [C.c_void_p, _P(C.c_double), _P(C.c_int64)]),
     ("rdos_step", C.c_int, [C.c_void_p, C.c_int64]),
@@ -176,6 +177,22 @@ def rdos_get_counts(sim, realization: int, species: int, n_tets: int) -> np.ndar
     out = np.empty(int(n_tets), np.int32)
     _check(lib().rdos_get_counts(sim, int(realization), int(species), _ptr(out, C.c_int32)), sim)
     return out
+
+
+def rdos_device_counts(sim, realization: int, species: int) -> int:
+    """Device address of counts[n_tets] (int32) at the current period boundary."""
+    p = C.c_void_p()
+    _check(lib().rdos_device_counts(sim, int(realization), int(species), C.byref(p)), sim)
+    return int(p.value)
+
+
+class _DeviceArray:
+    """A borrowed int32 device vector exposed through __cuda_array_interface__
+    (torch.as_tensor turns it into a tensor without a copy)."""
+
+    def __init__(self, ptr: int, n: int):
+        self.__cuda_array_interface__ = {"shape": (int(n),), "typestr": "<i4", "data": (ptr, False),
+                                         "version": 2}
 
 
 def rdos_set_state(sim, step_index: int, t: float):
@@ -351,6 +368,14 @@ class Simulation:
         if species is None:
             return np.stack([rdos_get_counts(self.h, realization, s, self.T) for s in range(self.S)])
         return rdos_get_counts(self.h, realization, species, self.T)
+
+    def device_counts(self, species: int, realization: int = 0):
+        """Zero-copy torch view of one species' counts on the device; valid
+        until the next step (synchronise before reading)."""
+        import torch
+
+        ptr = rdos_device_counts(self.h, realization, species)
+        return torch.as_tensor(_DeviceArray(ptr, self.T), device="cuda")
 
     def step(self, n: int = 1):
         rdos_step(self.h, n)

@@ -667,6 +667,18 @@ rdos_status rdos_get_counts(rdos_sim *s, int32_t realization, int32_t species, i
     return check_flags(s);
 }
 
+rdos_status rdos_device_counts(rdos_sim *s, int32_t realization, int32_t species, int32_t **out)
+{
+    CHECK_HANDLE(s);
+    if (!out) return fail(s, RDOS_EINVAL, "null output");
+    *out = nullptr;
+    if (s->state != SimState::Ready) return fail(s, RDOS_ESTATE, "device_counts before finalize");
+    if (realization < 0 || realization >= s->Rz || species < 0 || species >= (int32_t)s->D.size())
+        return fail(s, RDOS_EINVAL, "realization or species out of range");
+    *out = s->d_buf[s->step & 1] + ((int64_t)realization * (int64_t)s->D.size() + species) * padded_tets(s->T);
+    return RDOS_OK;
+}
+
 rdos_status rdos_set_state(rdos_sim *s, int64_t step_index, double t)
 {
     CHECK_HANDLE(s);

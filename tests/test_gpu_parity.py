@@ -269,6 +269,42 @@ def test_torch_stream(P, orc):
     g.close()
 
 
+def test_device_counts_view(P, orc):
+    """The zero-copy view reads what get_counts reads and writes like set_counts."""
+    import torch
+
+    xyz, tets = W.kuhn_lattice(2, 0.1e-6)
+    T = tets.shape[0]
+    note("device counts view")
+    init = np.zeros((2, 2, T), np.int32)
+    init[:, 0, 3] = 120
+    init[1, 1, 40] = 17
+    g, os_ = make_pair(P, orc, xyz, tets, [1e-12, 2e-12], [([0, 1], [], 1e9)], init, seed=8)
+    g.step(5)
+    g.synchronize()
+    for o in os_:
+        o.run_steps(5)
+    for r in range(2):
+        for s in range(2):
+            v = g.device_counts(s, realization=r)
+            assert v.dtype == torch.int32 and v.shape == (T,)
+            assert np.array_equal(v.cpu().numpy(), os_[r].get_counts(s)), (r, s)
+    # write through the view, then continue: same as set_counts on the oracle
+    v = g.device_counts(1, realization=0)
+    v[7] += 5
+    torch.cuda.synchronize()
+    c = os_[0].get_counts(1)
+    c[7] += 5
+    os_[0].set_counts(1, c)
+    g.step(3)
+    for o in os_:
+        o.run_steps(3)
+    assert_same(g, os_, "after writing through the view")
+    with pytest.raises(P.RdosError):
+        P.rdos_device_counts(g.h, 2, 0)
+    g.close()
+
+
 def test_invalid_inputs(P):
     note("invalid inputs")
     xyz, tets = W.kuhn_lattice(1, 0.1e-6)
