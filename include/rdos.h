@@ -127,7 +127,8 @@ rdos_status rdos_get_counts(rdos_sim *s, int32_t realization, int32_t species, i
  * library owns the memory; the address is valid until the next step,
  * run_until, set_state or destroy (the count buffers alternate between
  * periods).  Work is asynchronous: synchronise the simulation's stream before
- * reading it.  Writing through it sets the state like set_counts. */
+ * reading it.  Writing non-negative counts through it sets the state like
+ * set_counts. */
 rdos_status rdos_device_counts(rdos_sim *s, int32_t realization, int32_t species, int32_t **out);
 
 /* Resume support: the period index keys the random streams, so

@@ -187,11 +187,12 @@ def rdos_device_counts(sim, realization: int, species: int) -> int:
 
 
 class _DeviceArray:
-    """A borrowed int32 device vector exposed through __cuda_array_interface__
+    """A borrowed int32 device array exposed through __cuda_array_interface__
     (torch.as_tensor turns it into a tensor without a copy)."""
 
-    def __init__(self, ptr: int, n: int):
-        self.__cuda_array_interface__ = {"shape": (int(n),), "typestr": "<i4", "data": (ptr, False),
+    def __init__(self, ptr: int, shape, strides_bytes):
+        self.__cuda_array_interface__ = {"shape": tuple(int(x) for x in shape), "typestr": "<i4",
+                                         "data": (ptr, False), "strides": tuple(int(x) for x in strides_bytes),
                                          "version": 2}
 
 
@@ -375,7 +376,7 @@ class Simulation:
         import torch
 
         ptr = rdos_device_counts(self.h, realization, species)
-        return torch.as_tensor(_DeviceArray(ptr, self.T), device="cuda")
+        return torch.as_tensor(_DeviceArray(ptr, (self.T,), (4,)), device="cuda")
 
     def step(self, n: int = 1):
         rdos_step(self.h, n)

@@ -108,8 +108,9 @@ size_t state_bytes(const rdos_sim *s)
     const size_t counts = (size_t)s->Rz * s->D.size() * (size_t)Tp * sizeof(int32_t);
     const size_t tiles = (size_t)tiles_of(s) * sizeof(Tile);
     const size_t masks = s->regions.empty() ? 0 : (size_t)s->T * sizeof(uint32_t);
+    const size_t occupancy = 2 * (size_t)s->Rz * mask_stride(Tp);
     return (size_t)s->T * sizeof(MeshRec) + 2 * counts + tiles + queue_bytes(tiles_of(s), (int32_t)s->D.size()) +
-           masks + sizeof(DevSim) + 64;
+           masks + occupancy + sizeof(DevSim) + 64;
 }
 
 // Face-matching results are cached by mesh connectivity (the tet_verts
@@ -238,10 +239,29 @@ rdos_status upload_desc(rdos_sim *s)
 // parity of the period index (the other buffer is all zero between periods).
 rdos_status match_parity(rdos_sim *s)
 {
-    if (s->desc.buf[0] == s->d_buf[0] && s->desc.buf[1] == s->d_buf[1]) return RDOS_OK;
+    if (s->desc.buf[0] == s->d_buf[0] && s->desc.buf[1] == s->d_buf[1] && s->desc.mask[0] == s->d_mask[0] &&
+        s->desc.mask[1] == s->d_mask[1])
+        return RDOS_OK;
     s->desc.buf[0] = s->d_buf[0];
     s->desc.buf[1] = s->d_buf[1];
+    s->desc.mask[0] = s->d_mask[0];
+    s->desc.mask[1] = s->d_mask[1];
     return upload_desc(s);
+}
+
+// The scan reads only count vectors whose occupancy byte is set; after the
+// host wrote counts, the map of the current buffer is rebuilt from them
+// (and the other one cleared) before the next period runs.
+rdos_status ensure_mask(rdos_sim *s)
+{
+    if (!s->mask_dirty) return RDOS_OK;
+    const int64_t Tp = padded_tets(s->T);
+    const int p = (int)(s->step & 1);
+    HIP_TRY(s, launch_mask_build(s->d_buf[p], s->d_mask[p], s->d_mask[p ^ 1], s->Rz, (int32_t)s->D.size(), Tp,
+                                 s->stream),
+            "rebuild occupancy");
+    s->mask_dirty = false;
+    return RDOS_OK;
 }
 
 rdos_status check_flags(rdos_sim *s)
@@ -260,6 +280,8 @@ rdos_status check_flags(rdos_sim *s)
 
 rdos_status enqueue_period(rdos_sim *s, int64_t period, int64_t partial, double tau_last)
 {
+    rdos_status st = ensure_mask(s);
+    if (st != RDOS_OK) return st;
     HIP_TRY(s, launch_step(s->d_desc, s->d_tiles, period, partial, tau_last, s->queue, (int32_t)(s->launches & 1),
                            s->n_tiles, s->update_bps, s->stream),
             "launch period");
@@ -277,10 +299,12 @@ void free_device(rdos_sim *s)
     (void)hipSetDevice(s->device);
     if (s->stream) (void)hipStreamSynchronize(s->stream);
     std::lock_guard<std::mutex> g(device_api_mutex());
-    void *ptrs[] = {s->d_mesh, s->d_buf[0], s->d_buf[1], s->d_flags, s->d_desc, s->d_tiles, s->d_allowed};
+    void *ptrs[] = {s->d_mesh, s->d_buf[0], s->d_buf[1], s->d_mask[0], s->d_mask[1], s->d_flags, s->d_desc,
+                    s->d_tiles, s->d_allowed};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
     free_queue(&s->queue);
+    s->d_mask[0] = s->d_mask[1] = nullptr;
     s->d_mesh = nullptr;
     s->d_allowed = nullptr;
     s->d_buf[0] = s->d_buf[1] = s->d_flags = nullptr;
@@ -426,6 +450,7 @@ rdos_status rdos_finalize(rdos_sim *s, double tau_scale, double *out_tau)
     const int S = (int)s->D.size();
     const int64_t Tp = padded_tets(T);
     const size_t count_bytes = (size_t)s->Rz * S * (size_t)Tp * sizeof(int32_t);
+    const size_t mask_bytes = (size_t)s->Rz * mask_stride(Tp);
 
     // temporary set-up buffers
     double *d_xyz = nullptr, *d_vol = nullptr, *d_bc = nullptr, *d_area = nullptr, *d_D = nullptr;
@@ -454,6 +479,8 @@ rdos_status rdos_finalize(rdos_sim *s, double tau_scale, double *out_tau)
     SETUP_TRY(hipMalloc(&s->d_mesh, (size_t)T * sizeof(MeshRec)), "allocate mesh tables");
     SETUP_TRY(hipMalloc(&s->d_buf[0], count_bytes), "allocate counts");
     SETUP_TRY(hipMalloc(&s->d_buf[1], count_bytes), "allocate counts");
+    SETUP_TRY(hipMalloc(&s->d_mask[0], mask_bytes), "allocate occupancy");
+    SETUP_TRY(hipMalloc(&s->d_mask[1], mask_bytes), "allocate occupancy");
     SETUP_TRY(hipMalloc(&s->d_flags, 64), "allocate flags");
     SETUP_TRY(hipMalloc(&s->d_desc, sizeof(DevSim)), "allocate descriptor");
     SETUP_TRY(alloc_queue(&s->queue, tiles_of(s), S, s->stream), "allocate queue");
@@ -468,6 +495,8 @@ rdos_status rdos_finalize(rdos_sim *s, double tau_scale, double *out_tau)
     alloc_lock.unlock();
     SETUP_TRY(hipMemsetAsync(s->d_buf[0], 0, count_bytes, s->stream), "clear counts");
     SETUP_TRY(hipMemsetAsync(s->d_buf[1], 0, count_bytes, s->stream), "clear counts");
+    SETUP_TRY(hipMemsetAsync(s->d_mask[0], 0, mask_bytes, s->stream), "clear occupancy");
+    SETUP_TRY(hipMemsetAsync(s->d_mask[1], 0, mask_bytes, s->stream), "clear occupancy");
     SETUP_TRY(hipMemsetAsync(s->d_flags, 0, 64, s->stream), "clear flags");
     SETUP_TRY(hipMemsetAsync(d_tau, 0xff, sizeof(unsigned long long), s->stream), "clear tau");
     SETUP_TRY(hipMemcpyAsync(d_xyz, s->xyz.data(), s->xyz.size() * sizeof(double), hipMemcpyHostToDevice, s->stream),
@@ -525,8 +554,11 @@ rdos_status rdos_finalize(rdos_sim *s, double tau_scale, double *out_tau)
     d.mesh = s->d_mesh;
     d.buf[0] = s->d_buf[0];
     d.buf[1] = s->d_buf[1];
+    d.mask[0] = s->d_mask[0];
+    d.mask[1] = s->d_mask[1];
     d.flags = s->d_flags;
     d.T = T;
+    d.mstride = mask_stride(Tp);
     d.S = S;
     d.R = (int32_t)s->rx.size();
     d.Rz = s->Rz;
@@ -621,6 +653,7 @@ rdos_status rdos_finalize(rdos_sim *s, double tau_scale, double *out_tau)
                 "upload counts");
     }
     HIP_TRY(s, hipStreamSynchronize(s->stream), "upload counts");
+    s->mask_dirty = true;
     s->staged.clear();
     s->xyz.clear();
     s->xyz.shrink_to_fit();
@@ -650,6 +683,7 @@ rdos_status rdos_set_counts(rdos_sim *s, int32_t realization, int32_t species, c
     HIP_TRY(s, hipMemcpyAsync(dst, counts, (size_t)s->T * sizeof(int32_t), hipMemcpyHostToDevice, s->stream),
             "upload counts");
     HIP_TRY(s, hipStreamSynchronize(s->stream), "upload counts");
+    s->mask_dirty = true;
     return RDOS_OK;
 }
 
@@ -676,6 +710,7 @@ rdos_status rdos_device_counts(rdos_sim *s, int32_t realization, int32_t species
     if (realization < 0 || realization >= s->Rz || species < 0 || species >= (int32_t)s->D.size())
         return fail(s, RDOS_EINVAL, "realization or species out of range");
     *out = s->d_buf[s->step & 1] + ((int64_t)realization * (int64_t)s->D.size() + species) * padded_tets(s->T);
+    s->mask_dirty = true;  // the caller may write through the view
     return RDOS_OK;
 }
 
@@ -686,7 +721,10 @@ rdos_status rdos_set_state(rdos_sim *s, int64_t step_index, double t)
     if (step_index < 0 || !std::isfinite(t)) return fail(s, RDOS_EINVAL, "bad state");
     HIP_TRY(s, hipSetDevice(s->device), "set device");
     HIP_TRY(s, hipStreamSynchronize(s->stream), "set state");
-    if ((step_index & 1) != (s->step & 1)) std::swap(s->d_buf[0], s->d_buf[1]);  // the state moves with k & 1
+    if ((step_index & 1) != (s->step & 1)) {  // the state moves with k & 1
+        std::swap(s->d_buf[0], s->d_buf[1]);
+        std::swap(s->d_mask[0], s->d_mask[1]);
+    }
     s->step = step_index;
     s->anchor_step = step_index;
     s->anchor_t = t;

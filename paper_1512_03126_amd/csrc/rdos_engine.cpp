@@ -331,14 +331,17 @@ void admitter_main(rdos_engine *e)
                 const double tau_scale = tk.tau_scale;
                 rdos_status st = RDOS_OK;
                 std::string err;
+                lk.unlock();
                 if (s->state != SimState::Ready) {
-                    lk.unlock();
                     s->engine_owned = false;
                     st = rdos_finalize(s, tau_scale, nullptr);
-                    if (st != RDOS_OK) err = s->error;
                     s->engine_owned = true;
-                    lk.lock();
                 }
+                if (st == RDOS_OK) st = ensure_mask(s);  // occupancy of counts set from the host
+                if (st == RDOS_OK && hipStreamSynchronize(s->stream) != hipSuccess)
+                    st = fail(s, RDOS_EDEVICE, "occupancy rebuild failed");
+                if (st != RDOS_OK) err = s->error;
+                lk.lock();
                 --e->admitting;
                 Ticket &t2 = e->tickets[id];
                 if (st == RDOS_OK) {

@@ -6,7 +6,10 @@
 //   buf[2][r][s][Tp]  int32  molecule counts, double-buffered: the state at the
 //                            start of period k is buf[k & 1]; buf[(k + 1) & 1]
 //                            is all zero then and receives, by integer
-//                            atomics, every molecule that stays or arrives
+//                            atomics, every molecule that stays or arrives.
+//                            Species rows are separate so that the atomics of
+//                            one tet's species fall on different cache lines.
+//   mask[2][r][Tp/4]  uint8  occupancy of the four-tet groups of buf[k & 1]
 //   mesh[T]           64 B   neighbours, weights, g, N_A V (one line)
 #include <hip/hip_runtime.h>
 
@@ -255,7 +258,7 @@ __device__ __forceinline__ double propensity(const DevSim &sm, int q, const Lane
 
 __device__ __forceinline__ void update_tet(const DevSim &sm, int32_t t, int64_t period, double tau_k,
                                            uint32_t key1, int32_t *__restrict__ nxt, int64_t Tp,
-                                           const LaneState &ls)
+                                           uint8_t *__restrict__ mnxt, const LaneState &ls)
 {
     const int S = sm.S;
     const int R = sm.R;
@@ -328,6 +331,7 @@ __device__ __forceinline__ void update_tet(const DevSim &sm, int32_t t, int64_t 
     double w[4];
     bool have_faces = false;
     double g = 0.0;
+    bool stay = false;    // some molecules of some species stay in this tet
     for (int s = 0; s < S; ++s) {
         const int32_t Ns = ls.n(s);
         if (((sm.diff_mask >> s) & 1u) && Ns > 0) {  // Ns == 0: n = min(binomial(.), 0) = 0
@@ -358,23 +362,34 @@ __device__ __forceinline__ void update_tet(const DevSim &sm, int32_t t, int64_t 
                 split_over_faces(n, nb, w, sm.split_threshold, rng, out);
 #pragma unroll
                 for (int f = 0; f < 4; ++f)
-                    if (out[f] > 0) atomicAdd(&nxt[s * Tp + nb[f]], (int32_t)out[f]);
+                    if (out[f] > 0) {
+                        atomicAdd(&nxt[s * Tp + nb[f]], (int32_t)out[f]);
+                        mnxt[nb[f] >> 2] = 1;
+                    }
                 ls.n(s) = Ns - (int32_t)n;
             }
         }
-        if (ls.n(s) > 0) atomicAdd(&nxt[s * Tp + t], ls.n(s));  // the molecules that stay
+        if (ls.n(s) > 0) {  // the molecules that stay
+            atomicAdd(&nxt[s * Tp + t], ls.n(s));
+            stay = true;
+        }
     }
+    // occupancy of the next period's buffer: one byte per four tets, set by
+    // plain stores (every writer stores the same value)
+    if (stay) mnxt[t >> 2] = 1;
 }
 
 // Each period is two launches.
-//  scan:   every lane reads four consecutive tets of every species (one
-//          16-byte non-temporal load per species).  Each wavefront compacts
-//          its tets that hold any molecule (all tets if a reaction has no
-//          reactant) with ballots, reserves room with one atomic on its queue
-//          segment, writes the tet and its counts to the queue and clears
-//          those counts, so the buffer is all zero by the time it is refilled.
-//  update: the queued tets run Steps 2-3 with every lane busy and add what
-//          stays and what leaves into the other buffer.
+//  scan:   a lane whose occupancy byte is set reads its four consecutive
+//          tets of every species (one 16-byte non-temporal load per
+//          species); lanes with a clear byte read nothing.  Each wavefront compacts its tets that hold any
+//          molecule (all tets if a reaction has no reactant) with ballots,
+//          reserves room with one atomic on its queue segment, writes the
+//          tet and its counts to the queue and clears those counts and the
+//          byte, so buffer and map are all zero by the time they are refilled.
+//  update: the queued tets run Steps 2-3 with every lane busy, add what
+//          stays and what leaves into the other buffer and set the
+//          occupancy bytes of the tets they added to.
 // The queue has nseg segments of seg_cap entries (tiles ti with
 // ti % nseg == k fill segment k, so seg_cap = tets of those tiles suffices);
 // entry i of segment k is qtet[k * seg_cap + i] with counts
@@ -404,13 +419,20 @@ __global__ __launch_bounds__(kBlock) void scan_kernel(const DevSim *__restrict__
         if (period >= sm.step_end) continue;  // uniform over the block
         const int32_t wave_off = wave * 64 * kTetsPerLane;
         if (wave_off >= tile.ntet) continue;  // uniform over the wavefront
+        const int32_t off = wave_off + lane * kTetsPerLane;
+        const int64_t t4 = tile.tet0 + off;
+        const bool inside = off < tile.ntet;
+        // occupancy byte of this lane's four tets: only flagged lanes read
+        // counts; the byte is cleared for the next use of this buffer
+        uint8_t *mk = sm.mask[period & 1] + (int64_t)tile.realization * sm.mstride + (t4 >> 2);
+        const uint8_t mb = inside ? *mk : (uint8_t)0;
+        if (mb != 0) *mk = 0;
+        const bool mine = inside && (sm.zeroth || mb != 0);  // a reaction without reactants: every tet runs
+        if (__ballot(mine) == 0ull) continue;              // uniform over the wavefront
         const int S = sm.S;
         const int64_t Tp = ((int64_t)sm.T + 3) & ~(int64_t)3;
         const int64_t base = (int64_t)tile.realization * S * Tp;
         int32_t *cur = sm.buf[period & 1] + base;
-        const int32_t off = wave_off + lane * kTetsPerLane;
-        const int64_t t4 = tile.tet0 + off;
-        const bool mine = off < tile.ntet;
         v4i c[MAXS];
 #pragma unroll
         for (int s = 0; s < MAXS; ++s) {
@@ -469,9 +491,10 @@ __global__ __launch_bounds__(kBlock) void scan_kernel(const DevSim *__restrict__
     }
 }
 
-__global__ __launch_bounds__(kBlock) void update_kernel(const DevSim *__restrict__ sims,
-                                                        const Tile *__restrict__ tiles, Queue q, int32_t qsel,
-                                                        int64_t iter, int64_t partial, double tau_last)
+// three wavefronts per SIMD: the register budget that keeps the samplers spill-free
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3))) void update_kernel(
+    const DevSim *__restrict__ sims, const Tile *__restrict__ tiles, Queue q, int32_t qsel, int64_t iter,
+    int64_t partial, double tau_last)
 {
     __shared__ double occ[kMaxSpecies * kBlock];
     __shared__ double last[kMaxSpecies * kBlock];
@@ -495,7 +518,8 @@ __global__ __launch_bounds__(kBlock) void update_kernel(const DevSim *__restrict
         const int64_t base = (int64_t)tile.realization * sm.S * Tp;
         for (int s = 0; s < sm.S; ++s) ls.n(s) = q.counts[s * h.qcap + idx];
         update_tet(sm, tile.tet0 + entry % kTetsPerTile, period, tau_k, sm.key1 ^ (uint32_t)tile.realization,
-                   sm.buf[(period + 1) & 1] + base, Tp, ls);
+                   sm.buf[(period + 1) & 1] + base, Tp,
+                   sm.mask[(period + 1) & 1] + (int64_t)tile.realization * sm.mstride, ls);
     }
 }
 
@@ -557,6 +581,36 @@ hipError_t launch_copy(const void *src, void *dst, size_t bytes, hipStream_t st)
     int64_t blocks = (n + 1023) / 1024;
     if (blocks > 16384) blocks = 16384;
     bandwidth_copy_kernel<<<(int)blocks, 256, 0, st>>>((const int4 *)src, (int4 *)dst, n);
+    return hipGetLastError();
+}
+
+// One thread per occupancy byte: tets 4i .. 4i + 3 of one realization in
+// every species.
+__global__ __launch_bounds__(256) void mask_build_kernel(const int32_t *__restrict__ counts,
+                                                         uint8_t *__restrict__ mask_cur,
+                                                         uint8_t *__restrict__ mask_other, int32_t S, int64_t Tp,
+                                                         int64_t n_bytes)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n_bytes) return;
+    const int64_t per_rz = Tp / 4;
+    const int64_t r = i / per_rz;
+    const int64_t t4 = (i % per_rz) * 4;
+    int32_t any = 0;
+    for (int s = 0; s < S; ++s) {
+        const int4 c = *reinterpret_cast<const int4 *>(counts + (r * S + s) * Tp + t4);
+        any |= c.x | c.y | c.z | c.w;
+    }
+    mask_cur[i] = any != 0 ? 1 : 0;
+    mask_other[i] = 0;
+}
+
+hipError_t launch_mask_build(const int32_t *counts, uint8_t *mask_cur, uint8_t *mask_other, int32_t Rz, int32_t S,
+                             int64_t Tp, hipStream_t st)
+{
+    const int64_t n = (int64_t)Rz * (Tp / 4);
+    if (n <= 0) return hipSuccess;
+    mask_build_kernel<<<(unsigned)((n + 255) / 256), 256, 0, st>>>(counts, mask_cur, mask_other, S, Tp, n);
     return hipGetLastError();
 }
 

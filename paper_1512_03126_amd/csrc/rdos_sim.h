@@ -56,6 +56,8 @@ struct rdos_sim {
     rdos::MeshRec *d_mesh = nullptr;
     uint32_t *d_allowed = nullptr;  // per-tet reaction masks (only with regions)
     int32_t *d_buf[2] = {nullptr, nullptr};  // counts; the state of period k is d_buf[k & 1]
+    uint8_t *d_mask[2] = {nullptr, nullptr};   // occupancy maps of d_buf[0], d_buf[1]
+    bool mask_dirty = false;                 // counts were written from the host: rebuild d_mask
     int32_t *d_flags = nullptr;
     rdos::DevSim *d_desc = nullptr;
     rdos::Tile *d_tiles = nullptr;
@@ -76,6 +78,7 @@ hipError_t alloc_queue(rdos::QueueView *q, int64_t capacity_tiles, int32_t n_spe
 hipError_t set_queue_work(rdos::QueueView *q, int64_t n_tiles, int32_t n_sims, hipStream_t st);
 void free_queue(rdos::QueueView *q);
 rdos_status match_parity(rdos_sim *s);
+rdos_status ensure_mask(rdos_sim *s);
 rdos_status check_flags(rdos_sim *s);
 double time_of(const rdos_sim *s, int64_t k);
 rdos_status rdos_finalize_internal(rdos_sim *s, double tau_scale);
