@@ -109,7 +109,7 @@ struct rdos_engine {
     std::pair<int, int> bucket{-1, -1};
     size_t trial = 0;
     double best_rate = -1.0;
-    Shape best{16, 2048, 8, 1};
+    Shape best{16, 2048, 2, 1};
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
 
     // per-kernel timing: chunks launched directly with events between launches
@@ -542,7 +542,7 @@ rdos_status rdos_engine_create(rdos_engine **out, int device, size_t hbm_budget_
         delete e;
         return RDOS_EDEVICE;
     }
-    e->candidates = {{16, 2048, 8, 1}, {16, 8192, 8, 1}, {16, 1024, 8, 2}, {16, 2048, 8, 2}, {16, 4096, 4, 2}};
+    e->candidates = {{16, 2048, 2, 1}, {16, 8192, 2, 1}, {16, 1024, 2, 2}, {16, 2048, 2, 2}, {16, 4096, 1, 2}};
     e->worker = std::thread(worker_main, e);
     e->admitter = std::thread(admitter_main, e);
     *out = e;

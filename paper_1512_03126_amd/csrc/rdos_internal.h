@@ -35,7 +35,7 @@ struct alignas(16) DevSim {
                                // count of tets 4 (t >> 2) .. 4 (t >> 2) + 3 may be non-zero
     int32_t *flags;            // bit 0: count overflow; bit 1: SSA event cap; bit 2: queue overflow
     int32_t T, S, R, Rz;
-    int32_t mstride;           // occupancy bytes per realization, Tp / 4
+    int32_t mstride;           // occupancy bytes per realization (Tp / 4 rounded up to 16)
     uint32_t key0, key1;       // Philox key words before the realization is mixed in
     double tau;                // full period
     int64_t step0;             // period index of launch iteration 0
@@ -109,7 +109,7 @@ struct QueueView {
     int64_t qcap;       // allocated entries per count row
     int32_t species;    // allocated count rows
 };
-constexpr int kMaxSegments = 256;
+constexpr int kMaxSegments = 1024;
 constexpr int kLenStride = 32;  // 128 bytes between segment lengths: no two share a line
 
 // Queue geometry for a work list of n_tiles tiles: tiles ti with
@@ -138,8 +138,9 @@ hipError_t launch_advance(DevSim *sims, const WorkHeader *hdr, int64_t by, hipSt
 // from the host).
 hipError_t launch_mask_build(const int32_t *counts, uint8_t *mask_cur, uint8_t *mask_other, int32_t Rz, int32_t S,
                              int64_t Tp, hipStream_t st);
-// Bytes of the occupancy map of one realization (one per four tets).
-inline int32_t mask_stride(int64_t Tp) { return (int32_t)(Tp / 4); }
+// Bytes of the occupancy map of one realization: one per four tets, rows
+// padded to 16 bytes so that the scan reads four bytes at a time.
+inline int32_t mask_stride(int64_t Tp) { return (int32_t)(((Tp / 4) + 15) & ~(int64_t)15); }
 hipError_t launch_copy(const void *src, void *dst, size_t bytes, hipStream_t st);
 
 

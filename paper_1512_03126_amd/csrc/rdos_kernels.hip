@@ -380,13 +380,17 @@ __device__ __forceinline__ void update_tet(const DevSim &sm, int32_t t, int64_t 
 }
 
 // Each period is two launches.
-//  scan:   a lane whose occupancy byte is set reads its four consecutive
-//          tets of every species (one 16-byte non-temporal load per
-//          species); lanes with a clear byte read nothing.  Each wavefront compacts its tets that hold any
-//          molecule (all tets if a reaction has no reactant) with ballots,
-//          reserves room with one atomic on its queue segment, writes the
-//          tet and its counts to the queue and clears those counts and the
-//          byte, so buffer and map are all zero by the time they are refilled.
+//  scan:   one wavefront per tile of 1024 tets, 16 consecutive tets per
+//          lane in four groups of four.  A group whose occupancy byte is set
+//          is read with one 16-byte non-temporal load per species; the
+//          others are not read.  The wavefront compacts its tets that hold
+//          any molecule (all tets if a reaction has no reactant) with a
+//          ballot prefix sum, reserves room with one atomic on the tile's
+//          queue segment, writes the tets and their counts to the queue in
+//          tet order and clears those counts and the bytes, so buffer and
+//          map are all zero by the time they are refilled.  A tile per
+//          wavefront keeps the chain of dependent loads (tile, map, counts,
+//          reservation) short relative to the work it covers.
 //  update: the queued tets run Steps 2-3 with every lane busy, add what
 //          stays and what leaves into the other buffer and set the
 //          occupancy bytes of the tets they added to.
@@ -394,7 +398,7 @@ __device__ __forceinline__ void update_tet(const DevSim &sm, int32_t t, int64_t 
 // ti % nseg == k fill segment k, so seg_cap = tets of those tiles suffices);
 // entry i of segment k is qtet[k * seg_cap + i] with counts
 // qcnt[s * qcap + k * seg_cap + i].  Segment lengths live in
-// qcount[qsel * nseg + k]; the update launch clears the other half for the
+// qcount[(qsel * kMaxSegments + k) * kLenStride]; the update launch clears the other half for the
 // next scan, so consecutive launches alternate qsel.
 struct Queue {
     int32_t *tet;     // [qcap]
@@ -408,56 +412,63 @@ __global__ __launch_bounds__(kBlock) void scan_kernel(const DevSim *__restrict__
                                                       const Tile *__restrict__ tiles, int64_t iter, Queue q,
                                                       int32_t qsel)
 {
+    constexpr int kWaves = kBlock / 64;
+    constexpr int kLaneTets = kTetsPerTile / 64;  // 16 consecutive tets, four groups of four
+    constexpr int kGroups = kLaneTets / 4;
     const int lane = threadIdx.x & 63;
-    const int wave = threadIdx.x >> 6;
     const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
     const WorkHeader h = *q.hdr;
-    for (int32_t ti = blockIdx.x; ti < h.n_tiles; ti += gridDim.x) {
+    const int32_t n_waves = (int32_t)gridDim.x * kWaves;
+    // one wavefront per tile; the tile index is uniform over the wavefront
+    for (int32_t ti = __builtin_amdgcn_readfirstlane((int32_t)blockIdx.x * kWaves + (int32_t)(threadIdx.x >> 6));
+         ti < h.n_tiles; ti += n_waves) {
         const Tile tile = tiles[ti];
         const DevSim &sm = sims[tile.sim];
         const int64_t period = sm.step0 + iter;
-        if (period >= sm.step_end) continue;  // uniform over the block
-        const int32_t wave_off = wave * 64 * kTetsPerLane;
-        if (wave_off >= tile.ntet) continue;  // uniform over the wavefront
-        const int32_t off = wave_off + lane * kTetsPerLane;
-        const int64_t t4 = tile.tet0 + off;
-        const bool inside = off < tile.ntet;
-        // occupancy byte of this lane's four tets: only flagged lanes read
-        // counts; the byte is cleared for the next use of this buffer
-        uint8_t *mk = sm.mask[period & 1] + (int64_t)tile.realization * sm.mstride + (t4 >> 2);
-        const uint8_t mb = inside ? *mk : (uint8_t)0;
-        if (mb != 0) *mk = 0;
-        const bool mine = inside && (sm.zeroth || mb != 0);  // a reaction without reactants: every tet runs
-        if (__ballot(mine) == 0ull) continue;              // uniform over the wavefront
+        if (period >= sm.step_end) continue;  // uniform over the wavefront
+        const int32_t off = lane * kLaneTets;
+        const int32_t valid = tile.ntet - off;  // tets of this lane inside the tile (may be <= 0)
+        const int64_t t0 = tile.tet0 + off;
+        // the four occupancy bytes of this lane's groups in one load (rows of
+        // the map are padded to 16 bytes, t0 / 4 is a multiple of 4); only
+        // flagged groups read counts, and the bytes are cleared for the next
+        // use of this buffer
+        uint32_t *mk = reinterpret_cast<uint32_t *>(sm.mask[period & 1] + (int64_t)tile.realization * sm.mstride +
+                                                    (t0 >> 2));
+        const uint32_t mb = valid > 0 ? *mk : 0u;
+        if (mb != 0u) *mk = 0u;
         const int S = sm.S;
         const int64_t Tp = ((int64_t)sm.T + 3) & ~(int64_t)3;
-        const int64_t base = (int64_t)tile.realization * S * Tp;
-        int32_t *cur = sm.buf[period & 1] + base;
-        v4i c[MAXS];
+        int32_t *cur = sm.buf[period & 1] + (int64_t)tile.realization * S * Tp;
+        v4i c[kGroups][MAXS];
+        uint32_t bits = 0;  // bit 4g + b: tet t0 + 4g + b is queued
 #pragma unroll
-        for (int s = 0; s < MAXS; ++s) {
-            c[s] = v4i{0, 0, 0, 0};
-            if (s < S && mine)  // streamed once: non-temporal
-                c[s] = __builtin_nontemporal_load(reinterpret_cast<const v4i *>(cur + s * Tp + t4));
+        for (int g = 0; g < kGroups; ++g) {
+            const bool live = 4 * g < valid && (sm.zeroth || ((mb >> (8 * g)) & 0xFFu) != 0u);
+#pragma unroll
+            for (int s = 0; s < MAXS; ++s) {
+                c[g][s] = v4i{0, 0, 0, 0};
+                if (s < S && live)  // streamed once: non-temporal
+                    c[g][s] = __builtin_nontemporal_load(reinterpret_cast<const v4i *>(cur + s * Tp + t0 + 4 * g));
+            }
+            uint32_t gb = 0;
+#pragma unroll
+            for (int s = 0; s < MAXS; ++s)
+                gb |= (uint32_t)(c[g][s].x != 0) | ((uint32_t)(c[g][s].y != 0) << 1) |
+                      ((uint32_t)(c[g][s].z != 0) << 2) | ((uint32_t)(c[g][s].w != 0) << 3);
+            if (sm.zeroth && live) gb = 0xFu;  // a reaction without reactants: every tet runs
+            bits |= gb << (4 * g);
         }
-        uint32_t bits = 0;
+        if (valid < kLaneTets) bits &= valid > 0 ? (1u << valid) - 1u : 0u;
+        // exclusive prefix of the per-lane counts (0..16) over the wavefront,
+        // from one ballot per bit of the count
+        const uint32_t cnt = (uint32_t)__popc(bits);
+        int32_t before = 0, total = 0;
 #pragma unroll
-        for (int s = 0; s < MAXS; ++s)
-            bits |= (uint32_t)(c[s].x != 0) | ((uint32_t)(c[s].y != 0) << 1) | ((uint32_t)(c[s].z != 0) << 2) |
-                    ((uint32_t)(c[s].w != 0) << 3);
-        if (sm.zeroth) bits = 0xFu;
-        if (!mine) bits = 0;
-        const int32_t valid = tile.ntet - off;  // tets of this lane inside the tile
-        if (valid < 4) bits &= (1u << (valid > 0 ? valid : 0)) - 1u;
-        // positions: bit plane b of all lanes after bit planes < b
-        uint64_t plane[4];
-        int32_t before[4];
-        int32_t total = 0;
-#pragma unroll
-        for (int b = 0; b < 4; ++b) {
-            plane[b] = __ballot((bits >> b) & 1u);
-            before[b] = total;
-            total += __popcll(plane[b]);
+        for (int k = 0; k < 5; ++k) {
+            const uint64_t plane = __ballot((cnt >> k) & 1u);
+            before += __popcll(plane & below) << k;
+            total += __popcll(plane) << k;
         }
         if (total == 0) continue;  // uniform over the wavefront
         const int32_t seg = ti % h.nseg;
@@ -468,26 +479,31 @@ __global__ __launch_bounds__(kBlock) void scan_kernel(const DevSim *__restrict__
             if (lane == 0) atomicOr(sm.flags, 4);
             continue;
         }
-        const int64_t seg_base = (int64_t)seg * h.seg_cap + slot;
+        int64_t idx = (int64_t)seg * h.seg_cap + slot + before;
 #pragma unroll
-        for (int b = 0; b < 4; ++b) {
-            if (!((bits >> b) & 1u)) continue;
-            const int64_t idx = seg_base + before[b] + __popcll(plane[b] & below);
-            q.tet[idx] = ti * kTetsPerTile + off + b;
+        for (int g = 0; g < kGroups; ++g) {
 #pragma unroll
-            for (int s = 0; s < MAXS; ++s) {
-                if (s >= S) break;
-                const int32_t cv = b == 0 ? c[s].x : b == 1 ? c[s].y : b == 2 ? c[s].z : c[s].w;
-                if (cv < 0) atomicOr(sm.flags, 1);  // wrapped by an overflowing atomic add
-                q.counts[s * h.qcap + idx] = cv;
+            for (int b = 0; b < 4; ++b) {
+                if (!((bits >> (4 * g + b)) & 1u)) continue;
+                q.tet[idx] = ti * kTetsPerTile + off + 4 * g + b;
+#pragma unroll
+                for (int s = 0; s < MAXS; ++s) {
+                    if (s >= S) break;
+                    const int32_t cv = b == 0 ? c[g][s].x : b == 1 ? c[g][s].y : b == 2 ? c[g][s].z : c[g][s].w;
+                    if (cv < 0) atomicOr(sm.flags, 1);  // wrapped by an overflowing atomic add
+                    q.counts[s * h.qcap + idx] = cv;
+                }
+                ++idx;
             }
         }
         // the queued molecules now live in the queue: clear their slots so
         // this buffer is all zero when it is next filled
 #pragma unroll
-        for (int s = 0; s < MAXS; ++s)
-            if (s < S && (c[s].x | c[s].y | c[s].z | c[s].w) != 0)
-                *reinterpret_cast<v4i *>(cur + s * Tp + t4) = v4i{0, 0, 0, 0};
+        for (int g = 0; g < kGroups; ++g)
+#pragma unroll
+            for (int s = 0; s < MAXS; ++s)
+                if (s < S && (c[g][s].x | c[g][s].y | c[g][s].z | c[g][s].w) != 0)
+                    *reinterpret_cast<v4i *>(cur + s * Tp + t0 + 4 * g) = v4i{0, 0, 0, 0};
     }
 }
 
@@ -500,7 +516,8 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3))) voi
     __shared__ double last[kMaxSpecies * kBlock];
     __shared__ int32_t counts[kMaxSpecies * kBlock];
     const LaneState ls{counts + threadIdx.x, occ + threadIdx.x, last + threadIdx.x};
-    if (blockIdx.x == 0 && threadIdx.x < kMaxSegments) q.len[((qsel ^ 1) * kMaxSegments + threadIdx.x) * kLenStride] = 0;
+    if (blockIdx.x == 0)
+        for (int k = threadIdx.x; k < kMaxSegments; k += kBlock) q.len[((qsel ^ 1) * kMaxSegments + k) * kLenStride] = 0;
     const WorkHeader h = *q.hdr;
     const int32_t seg = blockIdx.x % kMaxSegments;   // the grid is kMaxSegments * blocks-per-segment
     const int32_t per_seg = max(1, (int32_t)(gridDim.x / kMaxSegments));
@@ -531,6 +548,8 @@ hipError_t launch_scan(const DevSim *sims, const Tile *tiles, int64_t iter, cons
     // register arrays sized for the largest species count the queue holds
     if (qv.species <= 2)
         scan_kernel<2><<<scan_grid, kBlock, 0, st>>>(sims, tiles, iter, q, qsel);
+    else if (qv.species == 3)
+        scan_kernel<3><<<scan_grid, kBlock, 0, st>>>(sims, tiles, iter, q, qsel);
     else if (qv.species <= 4)
         scan_kernel<4><<<scan_grid, kBlock, 0, st>>>(sims, tiles, iter, q, qsel);
     else
@@ -542,7 +561,7 @@ hipError_t launch_update(const DevSim *sims, const Tile *tiles, int64_t iter, in
                          const QueueView &qv, int32_t qsel, int32_t blocks_per_segment, hipStream_t st)
 {
     const Queue q{qv.tet, qv.counts, qv.len, qv.hdr};
-    const int32_t bps = blocks_per_segment > 0 ? blocks_per_segment : 4;
+    const int32_t bps = blocks_per_segment > 0 ? blocks_per_segment : 1;
     update_kernel<<<kMaxSegments * bps, kBlock, 0, st>>>(sims, tiles, q, qsel, iter, partial, tau_last);
     return hipGetLastError();
 }
@@ -584,23 +603,23 @@ hipError_t launch_copy(const void *src, void *dst, size_t bytes, hipStream_t st)
     return hipGetLastError();
 }
 
-// One thread per occupancy byte: tets 4i .. 4i + 3 of one realization in
-// every species.
+// One thread per occupancy byte: tets 4j .. 4j + 3 of one realization in
+// every species (bytes of the row padding past Tp / 4 are zero).
 __global__ __launch_bounds__(256) void mask_build_kernel(const int32_t *__restrict__ counts,
                                                          uint8_t *__restrict__ mask_cur,
                                                          uint8_t *__restrict__ mask_other, int32_t S, int64_t Tp,
-                                                         int64_t n_bytes)
+                                                         int64_t stride, int64_t n_bytes)
 {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n_bytes) return;
-    const int64_t per_rz = Tp / 4;
-    const int64_t r = i / per_rz;
-    const int64_t t4 = (i % per_rz) * 4;
+    const int64_t r = i / stride;
+    const int64_t t4 = (i % stride) * 4;
     int32_t any = 0;
-    for (int s = 0; s < S; ++s) {
-        const int4 c = *reinterpret_cast<const int4 *>(counts + (r * S + s) * Tp + t4);
-        any |= c.x | c.y | c.z | c.w;
-    }
+    if (t4 < Tp)
+        for (int s = 0; s < S; ++s) {
+            const int4 c = *reinterpret_cast<const int4 *>(counts + (r * S + s) * Tp + t4);
+            any |= c.x | c.y | c.z | c.w;
+        }
     mask_cur[i] = any != 0 ? 1 : 0;
     mask_other[i] = 0;
 }
@@ -608,9 +627,10 @@ __global__ __launch_bounds__(256) void mask_build_kernel(const int32_t *__restri
 hipError_t launch_mask_build(const int32_t *counts, uint8_t *mask_cur, uint8_t *mask_other, int32_t Rz, int32_t S,
                              int64_t Tp, hipStream_t st)
 {
-    const int64_t n = (int64_t)Rz * (Tp / 4);
+    const int64_t stride = mask_stride(Tp);
+    const int64_t n = (int64_t)Rz * stride;
     if (n <= 0) return hipSuccess;
-    mask_build_kernel<<<(unsigned)((n + 255) / 256), 256, 0, st>>>(counts, mask_cur, mask_other, S, Tp, n);
+    mask_build_kernel<<<(unsigned)((n + 255) / 256), 256, 0, st>>>(counts, mask_cur, mask_other, S, Tp, stride, n);
     return hipGetLastError();
 }
 

@@ -64,7 +64,7 @@ struct rdos_sim {
     int32_t n_tiles = 0;
     rdos::QueueView queue{};      // occupied tets of one period (tet ids + counts + segment lengths)
     int64_t launches = 0;         // periods launched on this handle (selects the queue length half)
-    int32_t update_bps = 4;       // update blocks per queue segment
+    int32_t update_bps = 1;       // update blocks per queue segment
     rdos::DevSim desc{};
 };
 
