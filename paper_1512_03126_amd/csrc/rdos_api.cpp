@@ -437,6 +437,9 @@ rdos_status rdos_finalize(rdos_sim *s, double tau_scale, double *out_tau)
     for (const Reaction &r : s->rx)
         for (int i = 0; i < r.pn; ++i)
             if (r.p[i] >= (int32_t)s->D.size()) return fail(s, RDOS_EINVAL, "product id out of range");
+    // one realization's counts are addressed with 32-bit byte offsets
+    if ((int64_t)s->D.size() * padded_tets(s->T) * 4 > 0x7fffffff)
+        return fail(s, RDOS_EINVAL, "tets x species of one realization exceed 2^29");
     std::vector<int32_t> nbr;
     rdos_status st = build_topology(s, nbr);
     if (st != RDOS_OK) return st;

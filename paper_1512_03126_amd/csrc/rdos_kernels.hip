@@ -382,7 +382,7 @@ __device__ __forceinline__ void update_tet(const DevSim &sm, int32_t t, int64_t 
 // Each period is two launches.
 //  scan:   one wavefront per tile of 1024 tets, 16 consecutive tets per
 //          lane in four groups of four.  A group whose occupancy byte is set
-//          is read with one 16-byte non-temporal load per species; the
+//          is read with one 16-byte buffer load per species; the
 //          others are not read.  The wavefront compacts its tets that hold
 //          any molecule (all tets if a reaction has no reactant) with a
 //          ballot prefix sum, reserves room with one atomic on the tile's
@@ -406,6 +406,13 @@ struct Queue {
     int32_t *len;     // [2][kMaxSegments] * kLenStride
     const WorkHeader *hdr;
 };
+
+// Raw buffer resource word 3 for gfx950 (untyped 32-bit data) and the cache
+// policy of the scan's count loads: device scope (sc1) without the
+// non-temporal hint, so that a line stays in L2 for the clear that follows
+// (with the hint, more lines were filled twice).
+constexpr int32_t kBufferWord3 = 0x00020000;
+constexpr int32_t kScanLoadPolicy = 16;
 
 template <int MAXS>
 __global__ __launch_bounds__(kBlock) void scan_kernel(const DevSim *__restrict__ sims,
@@ -440,6 +447,10 @@ __global__ __launch_bounds__(kBlock) void scan_kernel(const DevSim *__restrict__
         const int S = sm.S;
         const int64_t Tp = ((int64_t)sm.T + 3) & ~(int64_t)3;
         int32_t *cur = sm.buf[period & 1] + (int64_t)tile.realization * S * Tp;
+        // the realization's counts as a buffer resource (bounds-checked by
+        // the hardware: loads past the block return zero)
+        const __amdgpu_buffer_rsrc_t rs =
+            __builtin_amdgcn_make_buffer_rsrc(cur, (short)0, (int32_t)(S * Tp * 4), kBufferWord3);
         v4i c[kGroups][MAXS];
         uint32_t bits = 0;  // bit 4g + b: tet t0 + 4g + b is queued
 #pragma unroll
@@ -448,8 +459,10 @@ __global__ __launch_bounds__(kBlock) void scan_kernel(const DevSim *__restrict__
 #pragma unroll
             for (int s = 0; s < MAXS; ++s) {
                 c[g][s] = v4i{0, 0, 0, 0};
-                if (s < S && live)  // streamed once: non-temporal
-                    c[g][s] = __builtin_nontemporal_load(reinterpret_cast<const v4i *>(cur + s * Tp + t0 + 4 * g));
+                if (s < S && live)
+                    c[g][s] = __builtin_bit_cast(
+                        v4i, __builtin_amdgcn_raw_buffer_load_b128(rs, (int32_t)((s * Tp + t0 + 4 * g) * 4), 0,
+                                                                   kScanLoadPolicy));
             }
             uint32_t gb = 0;
 #pragma unroll
