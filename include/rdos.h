@@ -212,6 +212,14 @@ rdos_status rdos_engine_kernel_times(rdos_engine *e, double *scan_ms, int64_t *s
 rdos_status rdos_engine_launch_shape(rdos_engine *e, int32_t *chunk, int32_t *scan_grid,
                                      int32_t *update_bps, int32_t *chains);
 
+/* Fixes the launch shape instead of tuning it: chunk (even, 2..1024)
+ * periods per graph, scan_grid (1..2^20) blocks, update_bps (1..64) update
+ * blocks per queue segment, chains 1 or 2.  chunk 0 returns to the tuner.
+ * Results never depend on it; it exists for tests and for callers that
+ * tune offline.  RDOS_EINVAL for values out of range. */
+rdos_status rdos_engine_set_shape(rdos_engine *e, int32_t chunk, int32_t scan_grid, int32_t update_bps,
+                                  int32_t chains);
+
 /* Measures the device's streaming copy bandwidth (read + write bytes per
  * second / 1e9) with a 16-byte-per-lane copy kernel over `bytes`, `reps`
  * times.  The same kernel calibrates hardware byte counters. */

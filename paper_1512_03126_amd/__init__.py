@@ -65,6 +65,7 @@ _SIGS = [
     ("rdos_engine_stats", C.c_int, [C.c_void_p, _P(C.c_int64), _P(C.c_double), _P(C.c_double)]),
     ("rdos_engine_launch_shape", C.c_int, [C.c_void_p, _P(C.c_int32), _P(C.c_int32), _P(C.c_int32),
                                            _P(C.c_int32)]),
+    ("rdos_engine_set_shape", C.c_int, [C.c_void_p, C.c_int32, C.c_int32, C.c_int32, C.c_int32]),
     ("rdos_engine_set_profiling", C.c_int, [C.c_void_p, C.c_int]),
     ("rdos_engine_kernel_times", C.c_int, [C.c_void_p, _P(C.c_double), _P(C.c_int64), _P(C.c_double),
                                            _P(C.c_int64)]),
@@ -293,6 +294,12 @@ def rdos_engine_launch_shape(engine):
     a, b, c, d = C.c_int32(), C.c_int32(), C.c_int32(), C.c_int32()
     _check(lib().rdos_engine_launch_shape(engine, C.byref(a), C.byref(b), C.byref(c), C.byref(d)), engine, True)
     return dict(chunk=a.value, scan_grid=b.value, update_blocks_per_segment=c.value, chains=d.value)
+
+
+def rdos_engine_set_shape(engine, chunk: int, scan_grid: int = 0, update_bps: int = 0, chains: int = 0):
+    """Fix the launch shape (no tuning); chunk 0 returns to the tuner."""
+    _check(lib().rdos_engine_set_shape(engine, int(chunk), int(scan_grid), int(update_bps), int(chains)), engine,
+           True)
 
 
 def rdos_engine_set_profiling(engine, on: bool):

@@ -73,7 +73,7 @@ hipError_t alloc_queue(QueueView *q, int64_t capacity_tiles, int32_t n_species, 
 
 // Points the queue at a work list of n_tiles tiles (<= its capacity) and
 // n_sims descriptors; the kernels read these sizes from q->hdr.
-hipError_t set_queue_work(QueueView *q, int64_t n_tiles, int32_t n_sims, hipStream_t st)
+hipError_t set_queue_work(QueueView *q, int64_t n_tiles, int32_t n_sims, hipStream_t st, int32_t tile0)
 {
     int32_t nseg, seg_cap;
     queue_shape(n_tiles, &nseg, &seg_cap);
@@ -86,6 +86,7 @@ hipError_t set_queue_work(QueueView *q, int64_t n_tiles, int32_t n_sims, hipStre
     h.nseg = nseg;
     h.seg_cap = seg_cap;
     h.qcap = q->qcap;
+    h.tile0 = tile0;
     hipError_t e = hipMemcpyAsync(q->hdr, &h, sizeof h, hipMemcpyHostToDevice, st);
     if (e == hipSuccess) e = hipStreamSynchronize(st);  // h lives on this stack frame
     return e;

@@ -105,6 +105,7 @@ struct rdos_engine {
 
     // tuner: candidates tried once per work-list size bucket, best kept
     std::vector<Shape> candidates;
+    bool fixed_shape = false;  // set_shape: no tuning, always `best`
     std::map<std::pair<int, int>, Shape> tuned;
     std::pair<int, int> bucket{-1, -1};
     size_t trial = 0;
@@ -234,7 +235,8 @@ rdos_status set_chains(rdos_engine *e, int32_t chains)
         ENGINE_HIP(e, set_queue_work(&e->queue, e->n_tiles, e->n_sims, e->stream), "work header");
     } else {
         ENGINE_HIP(e, set_queue_work(&e->queue, e->n_tiles0, e->n_sims, e->stream), "work header");
-        ENGINE_HIP(e, set_queue_work(&e->queue2, e->n_tiles - e->n_tiles0, e->n_sims, e->stream), "work header");
+        ENGINE_HIP(e, set_queue_work(&e->queue2, e->n_tiles - e->n_tiles0, e->n_sims, e->stream, e->n_tiles0),
+                   "work header");
     }
     e->hdr_chains = chains;
     return RDOS_OK;
@@ -255,7 +257,7 @@ hipError_t enqueue_chunk(rdos_engine *e, const Shape &sh, bool timed)
             err = launch_step(e->d_sims, e->d_tiles, i, -1, 0.0, e->queue, i & 1, sh.scan_grid, sh.update_bps,
                               e->stream);
             if (err == hipSuccess)
-                err = launch_step(e->d_sims, e->d_tiles + e->n_tiles0, i, -1, 0.0, e->queue2, i & 1, sh.scan_grid,
+                err = launch_step(e->d_sims, e->d_tiles, i, -1, 0.0, e->queue2, i & 1, sh.scan_grid,
                                   sh.update_bps, e->stream2);
         }
         if (err == hipSuccess) err = hipEventRecord(e->join, e->stream2);
@@ -421,7 +423,7 @@ void worker_main(rdos_engine *e)
             }
         }
         // the tuner tries each candidate once per size bucket, then keeps the best
-        Shape sh = e->trial < e->candidates.size() ? e->candidates[e->trial] : e->best;
+        Shape sh = !e->fixed_shape && e->trial < e->candidates.size() ? e->candidates[e->trial] : e->best;
         const bool timed = e->profiling;
         if (timed || e->n_tiles0 == 0 || e->n_tiles0 == e->n_tiles) sh.chains = 1;  // nothing to split
         if (set_chains(e, sh.chains) != RDOS_OK) {
@@ -478,7 +480,7 @@ void worker_main(rdos_engine *e)
             }
         }
         const double rate = ms > 0.f ? work / (double)ms : 0.0;
-        if (e->trial < e->candidates.size()) {
+        if (!e->fixed_shape && e->trial < e->candidates.size()) {
             if (rate > e->best_rate) {
                 e->best_rate = rate;
                 e->best = sh;
@@ -645,6 +647,25 @@ rdos_status rdos_engine_launch_shape(rdos_engine *e, int32_t *chunk, int32_t *sc
     if (scan_grid) *scan_grid = e->best.scan_grid;
     if (update_bps) *update_bps = e->best.update_bps;
     if (chains) *chains = e->best.chains;
+    return RDOS_OK;
+}
+
+rdos_status rdos_engine_set_shape(rdos_engine *e, int32_t chunk, int32_t scan_grid, int32_t update_bps,
+                                  int32_t chains)
+{
+    if (!e) return RDOS_EINVAL;
+    if (chunk < 0) return efail(e, RDOS_EINVAL, "negative chunk");
+    std::lock_guard<std::mutex> g(e->mu);
+    if (chunk == 0) {  // back to tuning
+        e->fixed_shape = false;
+        e->bucket = {-1, -1};
+        return RDOS_OK;
+    }
+    if (chunk % 2 != 0 || chunk > 1024 || scan_grid < 1 || scan_grid > (1 << 20) || update_bps < 1 ||
+        update_bps > 64 || (chains != 1 && chains != 2))
+        return efail(e, RDOS_EINVAL, "launch shape out of range");
+    e->best = Shape{chunk, scan_grid, update_bps, chains};
+    e->fixed_shape = true;
     return RDOS_OK;
 }
 

@@ -95,6 +95,8 @@ struct alignas(16) WorkHeader {
     int32_t nseg;      // queue segments in use, 1..kMaxSegments
     int32_t seg_cap;   // entries per segment
     int64_t qcap;      // stride between the count rows of the queue (allocated entries)
+    int32_t tile0;     // this work list starts at tiles[tile0] (kernels get the array's base)
+    int32_t pad;
 };
 
 // Occupied-tet queue of one launch pair (device memory, see the scan kernel).

@@ -429,7 +429,7 @@ __global__ __launch_bounds__(kBlock) void scan_kernel(const DevSim *__restrict__
     // one wavefront per tile; the tile index is uniform over the wavefront
     for (int32_t ti = __builtin_amdgcn_readfirstlane((int32_t)blockIdx.x * kWaves + (int32_t)(threadIdx.x >> 6));
          ti < h.n_tiles; ti += n_waves) {
-        const Tile tile = tiles[ti];
+        const Tile tile = tiles[h.tile0 + ti];
         const DevSim &sm = sims[tile.sim];
         const int64_t period = sm.step0 + iter;
         if (period >= sm.step_end) continue;  // uniform over the wavefront
@@ -540,7 +540,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3))) voi
     for (int32_t i = part * kBlock + threadIdx.x; i < n; i += per_seg * kBlock) {
         const int64_t idx = (int64_t)seg * h.seg_cap + i;
         const int32_t entry = q.tet[idx];
-        const Tile tile = tiles[entry / kTetsPerTile];
+        const Tile tile = tiles[h.tile0 + entry / kTetsPerTile];
         const DevSim &sm = sims[tile.sim];
         const int64_t period = sm.step0 + iter;
         const double tau_k = period == partial ? tau_last : sm.tau;

@@ -75,7 +75,7 @@ int64_t padded_tets(int32_t T);
 size_t state_bytes(const rdos_sim *s);
 size_t queue_bytes(int64_t n_tiles, int32_t n_species);
 hipError_t alloc_queue(rdos::QueueView *q, int64_t capacity_tiles, int32_t n_species, hipStream_t st);
-hipError_t set_queue_work(rdos::QueueView *q, int64_t n_tiles, int32_t n_sims, hipStream_t st);
+hipError_t set_queue_work(rdos::QueueView *q, int64_t n_tiles, int32_t n_sims, hipStream_t st, int32_t tile0 = 0);
 void free_queue(rdos::QueueView *q);
 rdos_status match_parity(rdos_sim *s);
 rdos_status ensure_mask(rdos_sim *s);

@@ -87,3 +87,33 @@ def test_engine_stall_is_reported_not_hung():
     s1.close()
     s2.close()
     P.rdos_engine_destroy(e)
+
+
+def test_two_chains_survive_slot_changes(orc):
+    """Two chains with requests joining and leaving mid-run: the second
+    chain's place in the work list moves with every change of the slot set
+    and must be read from the device header, not from the captured graph."""
+    import paper_1512_03126_amd as P
+
+    reqs = [small_request(20 + i) for i in range(10)]
+    periods = [24 + 18 * (i % 4) for i in range(10)]
+    note("serving: fixed two-chain shape, staggered arrivals and departures")
+    e = P.rdos_engine_create(0, 0)
+    P.rdos_engine_set_shape(e, 8, 64, 1, 2)
+    tickets = []
+    for i, (m, n) in enumerate(zip(reqs, periods)):
+        s = P.Simulation(m.xyz, m.tets, m.D, m.reactions, seed=m.seed, tau_scale=None)
+        for q in range(m.n_species):
+            s.set_counts(q, m.init[0, q])
+        tickets.append((P.rdos_engine_submit(e, s.h, n, 1.0), s))
+        time.sleep(0.003 * (i % 4))
+    P.rdos_engine_drain(e)
+    assert P.rdos_engine_launch_shape(e)["chains"] == 2
+    mixed = []
+    for t, s in tickets:
+        P.rdos_engine_release(e, t)
+        mixed.append(s.get_counts())
+        s.close()
+    P.rdos_engine_destroy(e)
+    for m, n, got in zip(reqs, periods, mixed):
+        np.testing.assert_array_equal(run_oracle(orc, m, n), got)
