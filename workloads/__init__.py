@@ -264,6 +264,27 @@ def tube_influx(nx: int = 40, ny: int = 2, nz: int = 2, a: float = 0.1e-6, D: fl
     return m
 
 
+def production_annihilation(n: int = 5, a: float = 0.2e-6, D: float = 1e-11, k2: float = 1e8,
+                            mean: float = 30.0, n_realizations: int = 1, seed: int = 1) -> Model:
+    """Production and second-order degradation (the reaction-diffusion
+    validation of Sec. III.B, Fig. 6): 0 -> A at k1 (M/s) and A + A -> 0 at
+    k2 (1/(M s); 1e8 = 100 / (uM s)) on an n^3 x 6 Kuhn cube.  k1 is chosen
+    so that the well-mixed stationary mean is close to `mean`
+    (lambda = 2 mu mean^2 with mu = k2 / (N_A V), the pair rate of reading
+    R9).  Each realization starts with `mean` molecules placed by volume."""
+    xyz, tets = kuhn_lattice(n, a)
+    vol = _tet_volumes(xyz, tets)
+    nav = 6.02214076e23 * float(vol.sum()) * 1e3
+    mu = k2 / nav
+    k1 = 2.0 * mu * mean * mean / nav
+    init = np.zeros((n_realizations, 1, tets.shape[0]), dtype=np.int32)
+    for r in range(n_realizations):
+        rng = np.random.default_rng([seed, r])
+        init[r, 0] = place_by_volume(xyz, tets, int(round(mean)), rng, vol=vol)
+    return Model(f"prod_annih_{n}cube", xyz, tets, [D], [([], [0], k1), ([0, 0], [], k2)], init, float("nan"),
+                 seed, species_names=["A"])
+
+
 def tiny_lattice(n: int = 2, a: float = 0.2e-6, jitter_frac: float = 0.0, seed: int = 3) -> Tuple[np.ndarray, np.ndarray]:
     """Small meshes for exhaustive tests (n=1: 6 tets, n=2: 48 tets)."""
     xyz, tets = kuhn_lattice(n, a)
