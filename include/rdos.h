@@ -100,6 +100,15 @@ rdos_status rdos_add_reaction(rdos_sim *s, int32_t n_reac, const int32_t *reac, 
 rdos_status rdos_set_method(rdos_sim *s, int32_t occupancy_correction, int32_t split_threshold,
                             int32_t tau_outliers);
 
+/* Transfer form (Sec. II.B, last sentences: "take n as the total population
+ * ... and reduce the weights per direction by the factor zeta ... to give
+ * the same result").  0 (default): n = binomial(SR(Nbar), zeta), then the
+ * multinomial split of Step 3.3.  1: SR(Nbar) split at once over the faces
+ * with weights zeta w_f and "stay" with 1 - zeta; if more than the molecules
+ * present would leave, those present are split as in form 0.  Same law,
+ * different draws.  Before finalize; RDOS_EINVAL for other values. */
+rdos_status rdos_set_transfer_form(rdos_sim *s, int32_t form);
+
 /* Restricts reaction `reaction` to the tets tets[0..n_tets) (a localized
  * reaction, e.g. the influx at both ends of the tube of Sec. III.B);
  * before finalize.  Without a call a reaction may fire in every tet. */

@@ -50,6 +50,8 @@ def lib():
         L.orc_set_tau_outliers.argtypes = [C.c_void_p, i32]
         L.orc_set_reaction_region.argtypes = [C.c_void_p, i32, i32, P(i32)]
         L.orc_split_many_threshold.argtypes = [i64, P(f64), P(i32), u64, i32, i32, P(i64)]
+        L.orc_split_scaled_many.argtypes = [i64, f64, P(f64), P(i32), u64, i32, i32, P(i64)]
+        L.orc_set_transfer_form.argtypes = [C.c_void_p, C.c_int]
         L.orc_geometry.argtypes = [C.c_void_p, P(i32), P(f64), P(f64), P(f64), P(f64), P(f64)]
         L.orc_set_counts.argtypes = [C.c_void_p, i32, P(i32)]
         L.orc_get_counts.argtypes = [C.c_void_p, i32, P(i32)]
@@ -122,6 +124,9 @@ class OracleSim:
 
     def set_split_threshold(self, threshold: int):
         lib().orc_set_split_threshold(self._h, int(threshold))
+
+    def set_transfer_form(self, form: int):
+        lib().orc_set_transfer_form(self._h, int(form))
 
     def set_tau_outliers(self, k: int) -> float:
         return lib().orc_set_tau_outliers(self._h, int(k))
@@ -212,4 +217,15 @@ def split_many(n: int, w, nbr, seed: int, count: int, threshold: int = 10) -> np
     out = np.empty((count, 4), np.int64)
     lib().orc_split_many_threshold(int(n), _p(w, C.c_double), _p(nbr, C.c_int32), int(seed), int(count),
                                    int(threshold), _p(out, C.c_int64))
+    return out
+
+
+def split_scaled_many(n: int, zeta: float, w, nbr, seed: int, count: int, threshold: int = 10) -> np.ndarray:
+    """count samples of the one-multinomial transfer form: n molecules over
+    the faces with weights zeta w_f, the rest staying; [count, 4]."""
+    w = np.ascontiguousarray(w, dtype=np.float64)
+    nbr = np.ascontiguousarray(nbr, dtype=np.int32)
+    out = np.empty((count, 4), np.int64)
+    lib().orc_split_scaled_many(int(n), float(zeta), _p(w, C.c_double), _p(nbr, C.c_int32), int(seed), int(count),
+                                int(threshold), _p(out, C.c_int64))
     return out

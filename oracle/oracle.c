@@ -60,6 +60,7 @@ struct orc_sim {
     double anchor_t;
     int first_order;     /* 1: n from the count at the end of the period, not Nbar */
     int split_threshold; /* below this n the split goes molecule by molecule */
+    int transfer_form;   /* 0: binomial n then split (eq. 3); 1: one split scaled by zeta */
     double tau_scale;
     uint32_t *allowed;   /* [T] bit r: reaction r may fire in the tet (NULL: everywhere) */
     /* per-step scratch */
@@ -384,6 +385,57 @@ static void split(int64_t n, const double *w, const int32_t *nbr, int threshold,
     }
 }
 
+/* ------------------------------------------------------------------------- */
+/* The alternative stated at the end of Sec. II.B: the whole population N    */
+/* split at once over the directions with weights zeta w_i, the molecules    */
+/* that draw no direction (probability 1 - zeta) staying.  Below the          */
+/* threshold one categorical draw per molecule (directions in face order,    */
+/* "stay" last); otherwise sequential binomials with                          */
+/* p_i = zeta w_i / (1 - sum_{j<i} zeta w_j), "stay" taking the rest.  The    */
+/* molecules that leave are Binomial(N, zeta) and, given their number,        */
+/* multinomial over w: the law of Steps 3.2-3.3.  Returns how many leave.     */
+/* ------------------------------------------------------------------------- */
+static int64_t split_scaled(int64_t N, double zeta, const double *w, const int32_t *nbr, int threshold, orc_rng *g,
+                            int64_t out[4])
+{
+    out[0] = out[1] = out[2] = out[3] = 0;
+    if (N <= 0) return 0;
+    int faces[4], nf = 0;
+    for (int f = 0; f < 4; ++f)
+        if (nbr[f] >= 0) faces[nf++] = f;
+    if (nf == 0) return 0;
+    int64_t moved = 0;
+    if (N < threshold) {
+        for (int64_t i = 0; i < N; ++i) {
+            double U = next_u(g);
+            double c = 0.0;
+            for (int q = 0; q < nf; ++q) {
+                c = c + zeta * w[faces[q]];
+                if (U < c) {
+                    out[faces[q]] += 1;
+                    moved += 1;
+                    break;
+                }
+            }
+        }
+        return moved;
+    }
+    int64_t rem = N;
+    double Sz = 0.0;
+    for (int q = 0; q < nf; ++q) {
+        int f = faces[q];
+        double p = (zeta * w[f]) / (1.0 - Sz);
+        if (p > 1.0) p = 1.0;
+        int64_t nfc = binomial(rem, p, g);
+        out[f] = nfc;
+        moved += nfc;
+        rem -= nfc;
+        Sz = Sz + zeta * w[f];
+        if (rem == 0) break;
+    }
+    return moved;
+}
+
 uint32_t orc_split(int64_t n, const double *w, const int32_t *nbr, uint64_t seed,
                    int32_t realization, uint32_t stream, uint32_t tet, uint32_t step,
                    uint32_t j, int64_t *out)
@@ -660,6 +712,7 @@ void orc_set_first_order(orc_sim *s, int on) { s->first_order = on ? 1 : 0; }
  * at this n (10 in the paper's implementation); any threshold >= 1 gives the
  * same law, only the draws differ. */
 void orc_set_split_threshold(orc_sim *s, int threshold) { s->split_threshold = threshold < 1 ? 1 : threshold; }
+void orc_set_transfer_form(orc_sim *s, int form) { s->transfer_form = form == 1 ? 1 : 0; }
 
 static int cmp_double(const void *a, const void *b)
 {
@@ -862,11 +915,23 @@ void orc_step(orc_sim *s, double tau_k, double *nbar_out, int32_t *n_out)
                 /* Step 3.2: n = binomial(Nbar, zeta), zeta = tau_k d = tau_k D g */
                 double zeta = (tau_k * s->D[m]) * s->g[t];
                 if (zeta > 1.0) zeta = 1.0;
-                n = binomial(Ni, zeta, &rd);
-                if (n > N[m]) n = N[m];
-                /* Step 3.3: multinomial split over the face neighbours */
                 int64_t nf[4];
-                split(n, s->w + 4 * (size_t)t, s->nbr + 4 * (size_t)t, s->split_threshold, &rd, nf);
+                if (s->transfer_form == 1) {
+                    /* one multinomial over the directions scaled by zeta; more
+                       than the molecules present leave: the present ones are
+                       split as in Step 3.3 (the same law as min(., N)) */
+                    n = split_scaled(Ni, zeta, s->w + 4 * (size_t)t, s->nbr + 4 * (size_t)t, s->split_threshold,
+                                     &rd, nf);
+                    if (n > N[m]) {
+                        n = N[m];
+                        split(n, s->w + 4 * (size_t)t, s->nbr + 4 * (size_t)t, s->split_threshold, &rd, nf);
+                    }
+                } else {
+                    n = binomial(Ni, zeta, &rd);
+                    if (n > N[m]) n = N[m];
+                    /* Step 3.3: multinomial split over the face neighbours */
+                    split(n, s->w + 4 * (size_t)t, s->nbr + 4 * (size_t)t, s->split_threshold, &rd, nf);
+                }
                 for (int f = 0; f < 4; ++f) o[f] = (int32_t)nf[f];
                 N[m] -= n;
             }
@@ -929,6 +994,16 @@ void orc_split_many(int64_t n, const double *w, const int32_t *nbr, uint64_t see
                     int64_t *out)
 {
     orc_split_many_threshold(n, w, nbr, seed, count, ORC_SPLIT_ONE_BY_ONE, out);
+}
+
+void orc_split_scaled_many(int64_t n, double zeta, const double *w, const int32_t *nbr, uint64_t seed,
+                           int32_t count, int32_t threshold, int64_t *out)
+{
+    for (int32_t i = 0; i < count; ++i) {
+        orc_rng r;
+        rng_init(&r, seed, 0, 0u, (uint32_t)i, 0u, 0u);
+        (void)split_scaled(n, zeta, w, nbr, threshold < 1 ? 1 : threshold, &r, out + 4 * (size_t)i);
+    }
 }
 
 void orc_split_many_threshold(int64_t n, const double *w, const int32_t *nbr, uint64_t seed, int32_t count,

@@ -52,6 +52,12 @@ void orc_set_first_order(orc_sim *s, int on);
  * (default 10), tau from the (k+1)-th smallest 1/(D g) (default k = 0;
  * returns the new tau), and a reaction restricted to a set of tets. */
 void orc_set_split_threshold(orc_sim *s, int threshold);
+/* Transfer form (Sec. II.B, last sentences): 0 (default) draws n =
+ * binomial(SR(Nbar), zeta) and splits it over the faces; 1 splits SR(Nbar) at
+ * once over the faces with weights zeta w_f and "stay" with 1 - zeta (if
+ * more than the molecules present would leave, those present are split as in
+ * form 0).  Same law, different draws. */
+void orc_set_transfer_form(orc_sim *s, int form);
 double orc_set_tau_outliers(orc_sim *s, int32_t k);
 void orc_set_reaction_region(orc_sim *s, int32_t r, int32_t n, const int32_t *tets);
 void orc_geometry(const orc_sim *s, int32_t *nbr /*[T][4]*/, double *w /*[T][4]*/,
@@ -89,6 +95,9 @@ uint32_t orc_split(int64_t n, const double *w, const int32_t *nbr,
 void orc_binomial_many(int64_t n, double p, uint64_t seed, int32_t count, int64_t *out);
 void orc_split_many(int64_t n, const double *w, const int32_t *nbr, uint64_t seed,
                     int32_t count, int64_t *out /*[count][4]*/);
+/* count samples of the form-1 split of n molecules with zeta, out[count][4] */
+void orc_split_scaled_many(int64_t n, double zeta, const double *w, const int32_t *nbr, uint64_t seed,
+                           int32_t count, int32_t threshold, int64_t *out);
 void orc_split_many_threshold(int64_t n, const double *w, const int32_t *nbr, uint64_t seed,
                               int32_t count, int32_t threshold, int64_t *out /*[count][4]*/);
 

@@ -41,6 +41,7 @@ _SIGS = [
     ("rdos_add_reaction", C.c_int, [C.c_void_p, C.c_int32, _P(C.c_int32), C.c_int32, _P(C.c_int32), C.c_double,
                                     _P(C.c_int32)]),
     ("rdos_set_method", C.c_int, [C.c_void_p, C.c_int32, C.c_int32, C.c_int32]),
+    ("rdos_set_transfer_form", C.c_int, [C.c_void_p, C.c_int32]),
     ("rdos_set_reaction_region", C.c_int, [C.c_void_p, C.c_int32, C.c_int32, _P(C.c_int32)]),
     ("rdos_finalize", C.c_int, [C.c_void_p, C.c_double, _P(C.c_double)]),
     ("rdos_set_counts", C.c_int, [C.c_void_p, C.c_int32, C.c_int32, _P(C.c_int32)]),
@@ -156,6 +157,10 @@ def rdos_add_reaction(sim, reactants: Sequence[int], products: Sequence[int], k:
 def rdos_set_method(sim, occupancy_correction: bool = True, split_threshold: int = 10, tau_outliers: int = 0):
     _check(lib().rdos_set_method(sim, 1 if occupancy_correction else 0, int(split_threshold), int(tau_outliers)),
            sim)
+
+
+def rdos_set_transfer_form(sim, form: int):
+    _check(lib().rdos_set_transfer_form(sim, int(form)), sim)
 
 
 def rdos_set_reaction_region(sim, reaction: int, tets):
@@ -331,7 +336,7 @@ class Simulation:
 
     def __init__(self, xyz, tets, D: Iterable[float], reactions=(), seed: int = 1, n_realizations: int = 1,
                  device: int = 0, tau_scale: Optional[float] = 1.0, occupancy_correction: bool = True,
-                 split_threshold: int = 10, tau_outliers: int = 0, regions=None):
+                 split_threshold: int = 10, tau_outliers: int = 0, regions=None, transfer_form: int = 0):
         self.h = rdos_create(device, seed, n_realizations)
         self.T = int(np.asarray(tets).shape[0])
         self.Rz = int(n_realizations)
@@ -344,6 +349,8 @@ class Simulation:
             rdos_add_reaction(self.h, re, pr, k)
         if not occupancy_correction or split_threshold != 10 or tau_outliers:
             rdos_set_method(self.h, occupancy_correction, split_threshold, tau_outliers)
+        if transfer_form:
+            rdos_set_transfer_form(self.h, transfer_form)
         for r, tets_r in (regions or {}).items():
             rdos_set_reaction_region(self.h, r, tets_r)
         self.tau = None
@@ -354,7 +361,8 @@ class Simulation:
     def from_model(cls, model, device: int = 0, n_realizations: Optional[int] = None, finalize: bool = True,
                    **method):
         """A handle for a workload model; `method` takes the keyword options
-        of the constructor (occupancy_correction, split_threshold, tau_outliers)."""
+        of the constructor (occupancy_correction, split_threshold, tau_outliers,
+        transfer_form)."""
         Rz = model.init.shape[0] if n_realizations is None else n_realizations
         sim = cls(model.xyz, model.tets, model.D, model.reactions, seed=model.seed, n_realizations=Rz,
                   device=device, tau_scale=model.tau_scale if finalize else None,

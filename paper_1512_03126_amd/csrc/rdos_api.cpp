@@ -415,6 +415,16 @@ rdos_status rdos_set_method(rdos_sim *s, int32_t occupancy_correction, int32_t s
     return RDOS_OK;
 }
 
+rdos_status rdos_set_transfer_form(rdos_sim *s, int32_t form)
+{
+    CHECK_HANDLE(s);
+    if (s->state != SimState::Meshed)
+        return fail(s, RDOS_ESTATE, "set_transfer_form needs a mesh and no finalize yet");
+    if (form != 0 && form != 1) return fail(s, RDOS_EINVAL, "transfer form must be 0 or 1");
+    s->transfer_form = form;
+    return RDOS_OK;
+}
+
 rdos_status rdos_set_reaction_region(rdos_sim *s, int32_t reaction, int32_t n_tets, const int32_t *tets)
 {
     CHECK_HANDLE(s);
@@ -577,6 +587,8 @@ rdos_status rdos_finalize(rdos_sim *s, double tau_scale, double *out_tau)
     }
     d.first_order = s->first_order ? 1u : 0u;
     d.split_threshold = s->split_threshold;
+    d.transfer_form = s->transfer_form;
+    s->queue.scaled = s->transfer_form == 1 ? 1 : 0;
     if (!s->regions.empty()) {
         std::vector<uint32_t> allowed((size_t)T, 0xFFFFFFFFu);
         for (const auto &kv : s->regions) {

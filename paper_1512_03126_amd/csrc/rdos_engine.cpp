@@ -176,6 +176,7 @@ rdos_status build_work(rdos_engine *e)
     std::vector<DevSim> sims;
     std::vector<Tile> part[2];
     int32_t max_species = 1;
+    int32_t any_scaled = 0;  // some slot uses transfer form 1: the update kernel instance that handles it
     for (size_t i = 0; i < e->slots.size(); ++i) {
         Ticket &tk = e->tickets[e->slots[i]];
         rdos_sim *s = tk.sim;
@@ -189,6 +190,7 @@ rdos_status build_work(rdos_engine *e)
                 dst.push_back({(int32_t)i, r, t0, std::min<int32_t>(kTetsPerTile, s->T - t0)});
         }
         max_species = std::max(max_species, (int32_t)s->D.size());
+        if (s->desc.transfer_form == 1) any_scaled = 1;
     }
     std::vector<Tile> tiles = part[0];
     tiles.insert(tiles.end(), part[1].begin(), part[1].end());
@@ -209,6 +211,10 @@ rdos_status build_work(rdos_engine *e)
             free_queue(qs[c]);
             ENGINE_HIP(e, alloc_queue(qs[c], need[c] + need[c] / 2, species_bound(max_species), e->stream),
                        "engine queue");
+            e->graph_stale = true;
+        }
+        if (qs[c]->scaled != any_scaled) {  // the captured graph names the other kernel instance
+            qs[c]->scaled = any_scaled;
             e->graph_stale = true;
         }
     }

@@ -45,6 +45,7 @@ struct alignas(16) DevSim {
     uint32_t zeroth;           // 1 if some reaction has no reactant (every tet active)
     uint32_t first_order;      // 1: n from the count at the end of the period instead of Nbar
     int32_t split_threshold;   // below this n molecules are split one by one (Sec. II.B: 10)
+    int32_t transfer_form;     // 0: n = binomial then split (eq. 3); 1: one split scaled by zeta
     const uint32_t *allowed;   // [T] bit r: reaction r may fire in the tet (null: everywhere)
     // reactions
     int32_t rn[kMaxReactions], r0[kMaxReactions], r1[kMaxReactions];
@@ -110,6 +111,7 @@ struct QueueView {
     int32_t seg_cap;
     int64_t qcap;       // allocated entries per count row
     int32_t species;    // allocated count rows
+    int32_t scaled;     // some simulation of the work list uses transfer form 1 (picks the update kernel)
 };
 constexpr int kMaxSegments = 1024;
 constexpr int kLenStride = 32;  // 128 bytes between segment lengths: no two share a line

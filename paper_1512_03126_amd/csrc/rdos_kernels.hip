@@ -256,6 +256,7 @@ __device__ __forceinline__ double propensity(const DevSim &sm, int q, const Lane
     return c * h;
 }
 
+template <bool ANY_SCALED>
 __device__ __forceinline__ void update_tet(const DevSim &sm, int32_t t, int64_t period, double tau_k,
                                            uint32_t key1, int32_t *__restrict__ nxt, int64_t Tp,
                                            uint8_t *__restrict__ mnxt, const LaneState &ls)
@@ -355,11 +356,33 @@ __device__ __forceinline__ void update_tet(const DevSim &sm, int32_t t, int64_t 
             }
             double zeta = (tau_k * sm.D[s]) * g;
             if (zeta > 1.0) zeta = 1.0;
-            int64_t n = binomial(ni, zeta, rng);
-            if (n > Ns) n = Ns;
+            // Step 3.2-3.3: n = min(binomial(SR(Nbar), zeta), N) split over the
+            // faces; or (transfer form 1) SR(Nbar) split at once with weights
+            // zeta w_f, and if more would leave than are present, those
+            // present split as in Step 3.3.  The second form is compiled only
+            // into the kernel instance launched when some simulation uses it,
+            // so the first keeps its registers.
+            int64_t out[4];
+            int64_t n;
+            if constexpr (ANY_SCALED) {
+                bool scaled = sm.transfer_form == 1;
+                int64_t pop = ni;
+                if (!scaled) {
+                    pop = binomial(ni, zeta, rng);
+                    if (pop > Ns) pop = Ns;
+                }
+                for (;;) {
+                    n = split_faces(pop, nb, w, scaled ? zeta : 1.0, scaled, sm.split_threshold, rng, out);
+                    if (!(scaled && n > Ns)) break;
+                    pop = Ns;
+                    scaled = false;
+                }
+            } else {
+                n = binomial(ni, zeta, rng);
+                if (n > Ns) n = Ns;
+                if (n > 0) split_over_faces(n, nb, w, sm.split_threshold, rng, out);
+            }
             if (n > 0) {
-                int64_t out[4];
-                split_over_faces(n, nb, w, sm.split_threshold, rng, out);
 #pragma unroll
                 for (int f = 0; f < 4; ++f)
                     if (out[f] > 0) {
@@ -521,6 +544,7 @@ __global__ __launch_bounds__(kBlock) void scan_kernel(const DevSim *__restrict__
 }
 
 // three wavefronts per SIMD: the register budget that keeps the samplers spill-free
+template <bool ANY_SCALED>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3))) void update_kernel(
     const DevSim *__restrict__ sims, const Tile *__restrict__ tiles, Queue q, int32_t qsel, int64_t iter,
     int64_t partial, double tau_last)
@@ -547,7 +571,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3))) voi
         const int64_t Tp = ((int64_t)sm.T + 3) & ~(int64_t)3;
         const int64_t base = (int64_t)tile.realization * sm.S * Tp;
         for (int s = 0; s < sm.S; ++s) ls.n(s) = q.counts[s * h.qcap + idx];
-        update_tet(sm, tile.tet0 + entry % kTetsPerTile, period, tau_k, sm.key1 ^ (uint32_t)tile.realization,
+        update_tet<ANY_SCALED>(sm, tile.tet0 + entry % kTetsPerTile, period, tau_k, sm.key1 ^ (uint32_t)tile.realization,
                    sm.buf[(period + 1) & 1] + base, Tp,
                    sm.mask[(period + 1) & 1] + (int64_t)tile.realization * sm.mstride, ls);
     }
@@ -575,7 +599,10 @@ hipError_t launch_update(const DevSim *sims, const Tile *tiles, int64_t iter, in
 {
     const Queue q{qv.tet, qv.counts, qv.len, qv.hdr};
     const int32_t bps = blocks_per_segment > 0 ? blocks_per_segment : 1;
-    update_kernel<<<kMaxSegments * bps, kBlock, 0, st>>>(sims, tiles, q, qsel, iter, partial, tau_last);
+    if (qv.scaled)
+        update_kernel<true><<<kMaxSegments * bps, kBlock, 0, st>>>(sims, tiles, q, qsel, iter, partial, tau_last);
+    else
+        update_kernel<false><<<kMaxSegments * bps, kBlock, 0, st>>>(sims, tiles, q, qsel, iter, partial, tau_last);
     return hipGetLastError();
 }
 

@@ -308,4 +308,81 @@ __device__ inline void split_over_faces(int64_t n, const int32_t nbr[4], const d
     }
 }
 
+// ---------------------------------------------------------------------------
+// The same split with both transfer forms in one body (the kernel instance
+// that serves simulations using the second form calls it; the first form
+// alone uses split_over_faces above, which needs fewer registers).
+// n_i = Binomial(n - sum_{j<i} n_j, z w_i / (1 - sum_{j<i} z w_j)) face by
+// face, or one categorical draw per molecule below the threshold:
+//  * Step 3.3 (scaled = false, z = 1): n molecules all leave; the last
+//    interior face closes the interval / takes what is left (a single
+//    interior face takes everything without a draw);
+//  * the alternative at the end of Sec. II.B (scaled = true, z = zeta): the
+//    whole population, weights zeta w_i, and a molecule that draws no face
+//    stays (probability 1 - zeta).
+// 1.0 * w == w exactly, so the first form is bit-identical to the plain
+// weights.  Returns the molecules that leave.
+// ---------------------------------------------------------------------------
+__device__ inline int64_t split_faces(int64_t n, const int32_t nbr[4], const double w[4], double z, bool scaled,
+                                      int32_t threshold, Stream &rng, int64_t out[4])
+{
+    out[0] = out[1] = out[2] = out[3] = 0;
+    if (n <= 0) return 0;
+    int last = -1, interior = 0;
+#pragma unroll
+    for (int f = 0; f < 4; ++f)
+        if (nbr[f] >= 0) {
+            last = f;
+            ++interior;
+        }
+    if (interior == 0) return 0;
+    if (!scaled && interior == 1) {
+#pragma unroll
+        for (int f = 0; f < 4; ++f)
+            if (f == last) out[f] = n;
+        return n;
+    }
+    const int open = scaled ? -1 : last;  // where a molecule goes when no face's interval holds its draw
+    int64_t moved = 0;
+    if (n < threshold) {
+        for (int64_t i = 0; i < n; ++i) {
+            const double u = rng.uniform();
+            double edge = 0.0;
+            int dest = open;
+#pragma unroll
+            for (int f = 0; f < 4; ++f) {
+                if (nbr[f] >= 0 && (scaled || f < last) && dest == open) {
+                    edge = edge + z * w[f];
+                    if (u < edge) dest = f;
+                }
+            }
+#pragma unroll
+            for (int f = 0; f < 4; ++f)
+                if (f == dest) out[f] += 1;
+            moved += dest >= 0 ? 1 : 0;
+        }
+        return moved;
+    }
+    int64_t left = n;
+    double taken = 0.0;
+#pragma unroll
+    for (int f = 0; f < 4; ++f) {
+        if (nbr[f] < 0 || left == 0) continue;
+        if (!scaled && f == last) {
+            out[f] = left;
+            moved += left;
+            left = 0;
+            continue;
+        }
+        double pf = (z * w[f]) / (1.0 - taken);
+        if (pf > 1.0) pf = 1.0;
+        const int64_t nf = binomial(left, pf, rng);
+        out[f] = nf;
+        moved += nf;
+        left -= nf;
+        taken = taken + z * w[f];
+    }
+    return moved;
+}
+
 }  // namespace rdos

@@ -42,6 +42,7 @@ struct rdos_sim {
     int32_t first_order = 0;
     int32_t split_threshold = rdos::kSplitOneByOne;
     int32_t tau_outliers = 0;
+    int32_t transfer_form = 0;
     std::map<int32_t, std::vector<int32_t>> regions;  // reaction -> tets where it may fire
 
     // time: time(k) = anchor_t + (k - anchor_step) * tau

@@ -1,6 +1,7 @@
 """Method options on the GPU against the oracle, bit for bit: first-order
-splitting, the split threshold, tau outlier relaxation and localized
-reactions (the building blocks of the tube-with-influx validation)."""
+splitting, the split threshold, tau outlier relaxation, localized reactions
+(the building blocks of the tube-with-influx validation) and the
+one-multinomial transfer form."""
 import sys
 
 import numpy as np
@@ -19,15 +20,16 @@ def note(msg):
     sys.stdout.flush()
 
 
-def pair(P, orc, xyz, tets, init, seed, occ=True, thr=10, k=0, regions=None):
+def pair(P, orc, xyz, tets, init, seed, occ=True, thr=10, k=0, regions=None, form=0):
     T = tets.shape[0]
     g = P.Simulation(xyz, tets, D, RX, seed=seed, n_realizations=init.shape[0], occupancy_correction=occ,
-                     split_threshold=thr, tau_outliers=k, regions=regions)
+                     split_threshold=thr, tau_outliers=k, regions=regions, transfer_form=form)
     os_ = []
     for r in range(init.shape[0]):
         o = orc.OracleSim(xyz, tets, D, RX, seed=seed, realization=r)
         o.set_first_order(not occ)
         o.set_split_threshold(thr)
+        o.set_transfer_form(form)
         o.set_tau_outliers(k)
         for rid, tl in (regions or {}).items():
             o.set_reaction_region(rid, tl)
@@ -39,9 +41,11 @@ def pair(P, orc, xyz, tets, init, seed, occ=True, thr=10, k=0, regions=None):
     return g, os_
 
 
-@pytest.mark.parametrize("occ,thr,k,use_region", [(False, 10, 0, False), (True, 1, 0, False), (True, 40, 0, True),
-                                                  (True, 10, 9, False), (False, 3, 25, True)])
-def test_method_options_every_period(orc, occ, thr, k, use_region):
+@pytest.mark.parametrize("occ,thr,k,use_region,form", [(False, 10, 0, False, 0), (True, 1, 0, False, 0),
+                                                       (True, 40, 0, True, 0), (True, 10, 9, False, 0),
+                                                       (False, 3, 25, True, 0), (True, 10, 0, False, 1),
+                                                       (True, 2, 0, True, 1), (False, 60, 7, False, 1)])
+def test_method_options_every_period(orc, occ, thr, k, use_region, form):
     import paper_1512_03126_amd as P
 
     xyz, tets = W.tiny_lattice(3, 0.2e-6, jitter_frac=0.2, seed=6)
@@ -50,8 +54,8 @@ def test_method_options_every_period(orc, occ, thr, k, use_region):
     init = rng.integers(0, 30, size=(2, len(D), T)).astype(np.int32)
     init[:, 0, ::3] += 200          # some tets with many molecules: the sequential-binomial branch
     regions = {2: np.arange(0, T, 5, dtype=np.int32), 3: np.arange(T // 2, T, dtype=np.int32)} if use_region else None
-    note(f"method options occ={occ} threshold={thr} outliers={k} regions={use_region}")
-    g, os_ = pair(P, orc, xyz, tets, init, seed=5 + k, occ=occ, thr=thr, k=k, regions=regions)
+    note(f"method options occ={occ} threshold={thr} outliers={k} regions={use_region} transfer form={form}")
+    g, os_ = pair(P, orc, xyz, tets, init, seed=5 + k, occ=occ, thr=thr, k=k, regions=regions, form=form)
     for period in range(30):
         g.step(1)
         for r, o in enumerate(os_):

@@ -80,8 +80,12 @@ def test_conservation_diffusion_and_reactions(orc):
     assert fired
 
 
-@pytest.mark.parametrize("N0,tau_scale", [(4, 1.0), (300, 1.0), (40, 0.3)])
-def test_point_source_is_exactly_multinomial(orc, N0, tau_scale):
+@pytest.mark.parametrize("N0,tau_scale,form", [(4, 1.0, 0), (300, 1.0, 0), (40, 0.3, 0),
+                                               (6, 0.5, 1), (300, 0.6, 1), (40, 1.0, 1)])
+def test_point_source_is_exactly_multinomial(orc, N0, tau_scale, form):
+    """Pure diffusion from one tet: after k periods every molecule has made k
+    independent moves of the chain P (stay 1 - zeta, face f zeta w_f), so the
+    aggregate is Multinomial(N0, e P^k), in both transfer forms."""
     xyz, tets = W.tiny_lattice(2, 0.2e-6, jitter_frac=0.2, seed=3)
     D = 1e-12
     T = tets.shape[0]
@@ -89,7 +93,8 @@ def test_point_source_is_exactly_multinomial(orc, N0, tau_scale):
     agg = np.zeros(T)
     src = 5
     for r in range(runs):
-        sim = orc.OracleSim(xyz, tets, [D], [], tau_scale=tau_scale, seed=17, realization=r)
+        sim = orc.OracleSim(xyz, tets, [D], [], tau_scale=tau_scale, seed=17 + form, realization=r)
+        sim.set_transfer_form(form)
         init = np.zeros(T, np.int32)
         init[src] = N0
         sim.set_counts(0, init)
@@ -466,3 +471,39 @@ def test_localized_production(orc):
     pmf = stats.poisson.pmf(np.arange(hi + 1), mean)
     pmf[-1] += stats.poisson.sf(hi, mean)
     assert _chi2_pvalue(obs, pmf * runs) > 1e-3
+
+
+def test_transfer_forms_agree_when_the_cap_binds(orc):
+    """A -> 0 fast enough that Nbar often exceeds the molecules left at the
+    end of the period, so n = min(binomial(SR(Nbar), zeta), N_end) is capped.
+    One period from a point source: the counts that reach each neighbour and
+    stay must have the same law in both transfer forms (two-sample tests)."""
+    xyz, tets = W.tiny_lattice(2, 0.2e-6, jitter_frac=0.2, seed=3)
+    T = tets.shape[0]
+    D, src, N0, runs = 1e-12, 5, 20, 6000
+    out, binding = {}, 0
+    for form in (0, 1):
+        rows = []
+        for r in range(runs):
+            sim = orc.OracleSim(xyz, tets, [D], [([0], [], 3000.0)], tau_scale=0.6, seed=90 + form, realization=r)
+            sim.set_transfer_form(form)
+            init = np.zeros(T, np.int32)
+            init[src] = N0
+            sim.set_counts(0, init)
+            nbar, n = sim.step(record=True)
+            c = sim.get_counts(0)
+            rows.append(c)
+            if form == 0:
+                zeta = min(1.0, sim.tau * D * sim.geometry()["g"][src]) if r == 0 else zeta
+                n_end = int(c[src]) + int(n[0, src])  # the neighbours start empty: nothing arrives at src
+                binding += zeta * nbar[0, src] > n_end
+        out[form] = np.array(rows)
+    nb = [u for u in orc.OracleSim(xyz, tets, [D], []).geometry()["nbr"][src] if u >= 0]
+    for t in [src] + nb:
+        a, b = out[0][:, t], out[1][:, t]
+        hi = int(max(a.max(), b.max()))
+        table = np.array([np.bincount(a, minlength=hi + 1), np.bincount(b, minlength=hi + 1)])
+        table = table[:, table.sum(axis=0) >= 10]
+        assert stats.chi2_contingency(table)[1] > 1e-3, t
+    # in a good share of runs the expected departures zeta * Nbar exceed the molecules left
+    assert binding > runs // 10, binding

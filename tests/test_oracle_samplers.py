@@ -196,3 +196,38 @@ def test_split_law_at_any_threshold(orc, threshold, n):
         pmf[-1] += stats.binom.sf(hi, n, w[f])
         obs = np.bincount(x - lo, minlength=hi - lo + 1)
         assert _chi2_pvalue(obs, pmf * count) > ALPHA, (threshold, n, f)
+
+
+@pytest.mark.parametrize("n,zeta,threshold", [(7, 0.4, 10), (9, 1.0, 10), (60, 0.25, 10), (500, 0.8, 10),
+                                               (30, 0.6, 50), (12, 0.9, 1)])
+def test_split_scaled_is_the_same_law(orc, n, zeta, threshold):
+    """The one-multinomial transfer form (Sec. II.B, last sentences): face f
+    receives Binomial(n, zeta w_f), the total leaving is Binomial(n, zeta),
+    and face counts have covariance -n zeta^2 w_i w_j -- the law of
+    binomial(n, zeta) followed by the multinomial split."""
+    w = np.array([0.15, 0.35, 0.0, 0.5])
+    nbr = np.array([2, 5, -1, 9], dtype=np.int32)
+    count = 30000
+    out = orc.split_scaled_many(n, zeta, w, nbr, seed=4242 + n, count=count, threshold=threshold)
+    assert (out[:, 2] == 0).all() and (out.sum(axis=1) <= n).all()
+
+    def check(x, p):
+        lo, hi = int(x.min()), int(x.max())
+        ks = np.arange(lo, hi + 1)
+        pmf = stats.binom.pmf(ks, n, p)
+        pmf[0] += stats.binom.cdf(lo - 1, n, p) if lo > 0 else 0.0
+        pmf[-1] += stats.binom.sf(hi, n, p)
+        obs = np.bincount(x - lo, minlength=hi - lo + 1)
+        return _chi2_pvalue(obs, pmf * count)
+
+    for f in (0, 1, 3):
+        assert check(out[:, f], zeta * w[f]) > ALPHA, (n, zeta, f)
+    if zeta < 1.0:
+        assert check(out.sum(axis=1), zeta) > ALPHA
+    else:
+        assert (out.sum(axis=1) == n).all() or (out.sum(axis=1) >= n - 1).mean() > 0.999
+    cov = np.cov(out.astype(np.float64).T)
+    for i, j in ((0, 1), (0, 3), (1, 3)):
+        want = -n * zeta * zeta * w[i] * w[j]
+        se = n * np.sqrt(zeta * w[i] * zeta * w[j] * (1 + zeta * w[i] * zeta * w[j]) / count) * 1.2 + 1e-9
+        assert abs(cov[i, j] - want) < 5 * se, (i, j, cov[i, j], want)
