@@ -52,10 +52,10 @@ def scan_bytes(sims, models):
     """Bytes the occupancy-driven scan must move in the period that starts
     from the current state of every realization (the units and per-unit
     figures of the roofline):
-      one map byte per four tets (read),
-      4 B per 16-tet lane with a set byte (the map clear),
-      16 B per species per flagged four-tet group (the count reads),
-      16 B per non-zero four-tet vector of one species (the count clear),
+      one map byte per four tets and species (read),
+      4 B per 16-tet lane and species with a set byte (the map clear),
+      16 B per flagged four-tet vector of one species (the count read),
+      16 B per such vector again (its clear),
       4 + 4 S B per tet with molecules (its queue entry)."""
     import numpy as np
 
@@ -67,11 +67,10 @@ def scan_bytes(sims, models):
         for r in range(m.n_realizations):
             c = np.zeros((S, Tp), np.int32)
             c[:, :T] = sim.get_counts(None, realization=r)
-            vec = (c != 0).reshape(S, Tp // 4, 4).any(axis=2)   # [S][groups]: non-zero vectors
-            grp = vec.any(axis=0)                                # flagged groups
-            lanes = np.unique(np.nonzero(grp)[0] // 4).size
+            vec = (c != 0).reshape(S, Tp // 4, 4).any(axis=2)   # [S][groups]: flagged vectors
+            lanes = sum(np.unique(np.nonzero(vec[q])[0] // 4).size for q in range(S))
             tets = int((c != 0).any(axis=0).sum())
-            total += stride + 4 * lanes + 16 * S * int(grp.sum()) + 16 * int(vec.sum()) + (4 + 4 * S) * tets
+            total += S * stride + 4 * lanes + 32 * int(vec.sum()) + (4 + 4 * S) * tets
     return total
 
 

@@ -109,7 +109,7 @@ size_t state_bytes(const rdos_sim *s)
     const size_t counts = (size_t)s->Rz * s->D.size() * (size_t)Tp * sizeof(int32_t);
     const size_t tiles = (size_t)tiles_of(s) * sizeof(Tile);
     const size_t masks = s->regions.empty() ? 0 : (size_t)s->T * sizeof(uint32_t);
-    const size_t occupancy = 2 * (size_t)s->Rz * mask_stride(Tp);
+    const size_t occupancy = 2 * (size_t)s->Rz * s->D.size() * mask_stride(Tp);
     return (size_t)s->T * sizeof(MeshRec) + 2 * counts + tiles + queue_bytes(tiles_of(s), (int32_t)s->D.size()) +
            masks + occupancy + sizeof(DevSim) + 64;
 }
@@ -464,7 +464,7 @@ rdos_status rdos_finalize(rdos_sim *s, double tau_scale, double *out_tau)
     const int S = (int)s->D.size();
     const int64_t Tp = padded_tets(T);
     const size_t count_bytes = (size_t)s->Rz * S * (size_t)Tp * sizeof(int32_t);
-    const size_t mask_bytes = (size_t)s->Rz * mask_stride(Tp);
+    const size_t mask_bytes = (size_t)s->Rz * S * mask_stride(Tp);
 
     // temporary set-up buffers
     double *d_xyz = nullptr, *d_vol = nullptr, *d_bc = nullptr, *d_area = nullptr, *d_D = nullptr;

@@ -31,11 +31,11 @@ static_assert(sizeof(MeshRec) == 64, "MeshRec must be one cache line");
 struct alignas(16) DevSim {
     const MeshRec *mesh;       // [T]
     int32_t *buf[2];           // [Rz][S][Tp] counts; period k reads buf[k & 1] and fills buf[(k + 1) & 1]
-    uint8_t *mask[2];          // [Rz][Tp / 4] occupancy of buf[k & 1]: byte t >> 2 is non-zero when a
-                               // count of tets 4 (t >> 2) .. 4 (t >> 2) + 3 may be non-zero
+    uint8_t *mask[2];          // [Rz][S][mstride] occupancy of buf[k & 1]: byte t >> 2 of row (r, s) is
+                               // non-zero when species s of tets 4 (t >> 2) .. + 3 may be non-zero
     int32_t *flags;            // bit 0: count overflow; bit 1: SSA event cap; bit 2: queue overflow
     int32_t T, S, R, Rz;
-    int32_t mstride;           // occupancy bytes per realization (Tp / 4 rounded up to 16)
+    int32_t mstride;           // occupancy bytes per species row (Tp / 4 rounded up to 16)
     uint32_t key0, key1;       // Philox key words before the realization is mixed in
     double tau;                // full period
     int64_t step0;             // period index of launch iteration 0
@@ -138,12 +138,12 @@ hipError_t launch_step(const DevSim *sims, const Tile *tiles, int64_t iter, int6
                        hipStream_t st);
 hipError_t launch_advance(DevSim *sims, const WorkHeader *hdr, int64_t by, hipStream_t st);
 // Rebuilds the occupancy bytes of buf[parity] from the counts of every
-// realization and clears those of the other buffer (after counts were set
-// from the host).
+// realization and species and clears those of the other buffer (after
+// counts were set from the host).
 hipError_t launch_mask_build(const int32_t *counts, uint8_t *mask_cur, uint8_t *mask_other, int32_t Rz, int32_t S,
                              int64_t Tp, hipStream_t st);
-// Bytes of the occupancy map of one realization: one per four tets, rows
-// padded to 16 bytes so that the scan reads four bytes at a time.
+// Bytes of one species row of the occupancy map: one per four tets, padded
+// to 16 bytes so that the scan reads four bytes at a time.
 inline int32_t mask_stride(int64_t Tp) { return (int32_t)(((Tp / 4) + 15) & ~(int64_t)15); }
 hipError_t launch_copy(const void *src, void *dst, size_t bytes, hipStream_t st);
 

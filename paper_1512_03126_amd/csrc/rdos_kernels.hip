@@ -9,7 +9,7 @@
 //                            atomics, every molecule that stays or arrives.
 //                            Species rows are separate so that the atomics of
 //                            one tet's species fall on different cache lines.
-//   mask[2][r][Tp/4]  uint8  occupancy of the four-tet groups of buf[k & 1]
+//   mask[2][r][s][Tp/4]  uint8  occupancy of the four-tet groups of buf[k & 1], per species
 //   mesh[T]           64 B   neighbours, weights, g, N_A V (one line)
 #include <hip/hip_runtime.h>
 
@@ -256,9 +256,12 @@ __device__ __forceinline__ double propensity(const DevSim &sm, int q, const Lane
     return c * h;
 }
 
+// nxt and mnxt point at one realization's counts and occupancy rows; the
+// offsets into them are 32-bit (finalize keeps S Tp below 2^29), which keeps
+// the kernel within its register budget.
 template <bool ANY_SCALED>
 __device__ __forceinline__ void update_tet(const DevSim &sm, int32_t t, int64_t period, double tau_k,
-                                           uint32_t key1, int32_t *__restrict__ nxt, int64_t Tp,
+                                           uint32_t key1, int32_t *__restrict__ nxt, int32_t Tp,
                                            uint8_t *__restrict__ mnxt, const LaneState &ls)
 {
     const int S = sm.S;
@@ -332,7 +335,6 @@ __device__ __forceinline__ void update_tet(const DevSim &sm, int32_t t, int64_t 
     double w[4];
     bool have_faces = false;
     double g = 0.0;
-    bool stay = false;    // some molecules of some species stay in this tet
     for (int s = 0; s < S; ++s) {
         const int32_t Ns = ls.n(s);
         if (((sm.diff_mask >> s) & 1u) && Ns > 0) {  // Ns == 0: n = min(binomial(.), 0) = 0
@@ -386,20 +388,17 @@ __device__ __forceinline__ void update_tet(const DevSim &sm, int32_t t, int64_t 
 #pragma unroll
                 for (int f = 0; f < 4; ++f)
                     if (out[f] > 0) {
-                        atomicAdd(&nxt[s * Tp + nb[f]], (int32_t)out[f]);
-                        mnxt[nb[f] >> 2] = 1;
+                        atomicAdd(&nxt[(uint32_t)(s * Tp + nb[f])], (int32_t)out[f]);
+                        mnxt[(uint32_t)(s * sm.mstride + (nb[f] >> 2))] = 1;
                     }
                 ls.n(s) = Ns - (int32_t)n;
             }
         }
         if (ls.n(s) > 0) {  // the molecules that stay
-            atomicAdd(&nxt[s * Tp + t], ls.n(s));
-            stay = true;
+            atomicAdd(&nxt[(uint32_t)(s * Tp + t)], ls.n(s));
+            mnxt[(uint32_t)(s * sm.mstride + (t >> 2))] = 1;
         }
     }
-    // occupancy of the next period's buffer: one byte per four tets, set by
-    // plain stores (every writer stores the same value)
-    if (stay) mnxt[t >> 2] = 1;
 }
 
 // Each period is two launches.
@@ -459,15 +458,22 @@ __global__ __launch_bounds__(kBlock) void scan_kernel(const DevSim *__restrict__
         const int32_t off = lane * kLaneTets;
         const int32_t valid = tile.ntet - off;  // tets of this lane inside the tile (may be <= 0)
         const int64_t t0 = tile.tet0 + off;
-        // the four occupancy bytes of this lane's groups in one load (rows of
-        // the map are padded to 16 bytes, t0 / 4 is a multiple of 4); only
-        // flagged groups read counts, and the bytes are cleared for the next
-        // use of this buffer
-        uint32_t *mk = reinterpret_cast<uint32_t *>(sm.mask[period & 1] + (int64_t)tile.realization * sm.mstride +
-                                                    (t0 >> 2));
-        const uint32_t mb = valid > 0 ? *mk : 0u;
-        if (mb != 0u) *mk = 0u;
         const int S = sm.S;
+        // per species, the four occupancy bytes of this lane's groups in one
+        // load (rows of the map are padded to 16 bytes, t0 / 4 is a multiple
+        // of 4); only flagged (group, species) vectors are read, and the
+        // bytes are cleared for the next use of this buffer
+        uint8_t *mrow = sm.mask[period & 1] + (int64_t)tile.realization * S * sm.mstride + (t0 >> 2);
+        uint32_t mb[MAXS];
+#pragma unroll
+        for (int s = 0; s < MAXS; ++s) {
+            mb[s] = 0u;
+            if (s < S && valid > 0) {
+                uint32_t *mk = reinterpret_cast<uint32_t *>(mrow + (int64_t)s * sm.mstride);
+                mb[s] = *mk;
+                if (mb[s] != 0u) *mk = 0u;
+            }
+        }
         const int64_t Tp = ((int64_t)sm.T + 3) & ~(int64_t)3;
         int32_t *cur = sm.buf[period & 1] + (int64_t)tile.realization * S * Tp;
         // the realization's counts as a buffer resource (bounds-checked by
@@ -478,11 +484,11 @@ __global__ __launch_bounds__(kBlock) void scan_kernel(const DevSim *__restrict__
         uint32_t bits = 0;  // bit 4g + b: tet t0 + 4g + b is queued
 #pragma unroll
         for (int g = 0; g < kGroups; ++g) {
-            const bool live = 4 * g < valid && (sm.zeroth || ((mb >> (8 * g)) & 0xFFu) != 0u);
+            const bool inside = 4 * g < valid;
 #pragma unroll
             for (int s = 0; s < MAXS; ++s) {
                 c[g][s] = v4i{0, 0, 0, 0};
-                if (s < S && live)
+                if (s < S && inside && (sm.zeroth || ((mb[s] >> (8 * g)) & 0xFFu) != 0u))
                     c[g][s] = __builtin_bit_cast(
                         v4i, __builtin_amdgcn_raw_buffer_load_b128(rs, (int32_t)((s * Tp + t0 + 4 * g) * 4), 0,
                                                                    kScanLoadPolicy));
@@ -492,7 +498,7 @@ __global__ __launch_bounds__(kBlock) void scan_kernel(const DevSim *__restrict__
             for (int s = 0; s < MAXS; ++s)
                 gb |= (uint32_t)(c[g][s].x != 0) | ((uint32_t)(c[g][s].y != 0) << 1) |
                       ((uint32_t)(c[g][s].z != 0) << 2) | ((uint32_t)(c[g][s].w != 0) << 3);
-            if (sm.zeroth && live) gb = 0xFu;  // a reaction without reactants: every tet runs
+            if (sm.zeroth && inside) gb = 0xFu;  // a reaction without reactants: every tet runs
             bits |= gb << (4 * g);
         }
         if (valid < kLaneTets) bits &= valid > 0 ? (1u << valid) - 1u : 0u;
@@ -572,8 +578,8 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3))) voi
         const int64_t base = (int64_t)tile.realization * sm.S * Tp;
         for (int s = 0; s < sm.S; ++s) ls.n(s) = q.counts[s * h.qcap + idx];
         update_tet<ANY_SCALED>(sm, tile.tet0 + entry % kTetsPerTile, period, tau_k, sm.key1 ^ (uint32_t)tile.realization,
-                   sm.buf[(period + 1) & 1] + base, Tp,
-                   sm.mask[(period + 1) & 1] + (int64_t)tile.realization * sm.mstride, ls);
+                   sm.buf[(period + 1) & 1] + base, (int32_t)Tp,
+                   sm.mask[(period + 1) & 1] + (int64_t)tile.realization * sm.S * sm.mstride, ls);
     }
 }
 
@@ -643,23 +649,22 @@ hipError_t launch_copy(const void *src, void *dst, size_t bytes, hipStream_t st)
     return hipGetLastError();
 }
 
-// One thread per occupancy byte: tets 4j .. 4j + 3 of one realization in
-// every species (bytes of the row padding past Tp / 4 are zero).
+// One thread per occupancy byte: tets 4j .. 4j + 3 of one species of one
+// realization (bytes of the row padding past Tp / 4 are zero).
 __global__ __launch_bounds__(256) void mask_build_kernel(const int32_t *__restrict__ counts,
                                                          uint8_t *__restrict__ mask_cur,
-                                                         uint8_t *__restrict__ mask_other, int32_t S, int64_t Tp,
-                                                         int64_t stride, int64_t n_bytes)
+                                                         uint8_t *__restrict__ mask_other, int64_t Tp, int64_t stride,
+                                                         int64_t n_bytes)
 {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n_bytes) return;
-    const int64_t r = i / stride;
+    const int64_t row = i / stride;  // realization * S + species, as in the counts
     const int64_t t4 = (i % stride) * 4;
     int32_t any = 0;
-    if (t4 < Tp)
-        for (int s = 0; s < S; ++s) {
-            const int4 c = *reinterpret_cast<const int4 *>(counts + (r * S + s) * Tp + t4);
-            any |= c.x | c.y | c.z | c.w;
-        }
+    if (t4 < Tp) {
+        const int4 c = *reinterpret_cast<const int4 *>(counts + row * Tp + t4);
+        any = c.x | c.y | c.z | c.w;
+    }
     mask_cur[i] = any != 0 ? 1 : 0;
     mask_other[i] = 0;
 }
@@ -668,9 +673,9 @@ hipError_t launch_mask_build(const int32_t *counts, uint8_t *mask_cur, uint8_t *
                              int64_t Tp, hipStream_t st)
 {
     const int64_t stride = mask_stride(Tp);
-    const int64_t n = (int64_t)Rz * stride;
+    const int64_t n = (int64_t)Rz * S * stride;
     if (n <= 0) return hipSuccess;
-    mask_build_kernel<<<(unsigned)((n + 255) / 256), 256, 0, st>>>(counts, mask_cur, mask_other, S, Tp, stride, n);
+    mask_build_kernel<<<(unsigned)((n + 255) / 256), 256, 0, st>>>(counts, mask_cur, mask_other, Tp, stride, n);
     return hipGetLastError();
 }
 
