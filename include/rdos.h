@@ -229,6 +229,17 @@ rdos_status rdos_engine_launch_shape(rdos_engine *e, int32_t *chunk, int32_t *sc
 rdos_status rdos_engine_set_shape(rdos_engine *e, int32_t chunk, int32_t scan_grid, int32_t update_bps,
                                   int32_t chains);
 
+/* Sec. II.B: the split switches from one categorical draw per molecule to
+ * sequential binomials at a threshold (10 in the paper, measured on its
+ * hardware).  This measures both methods on the device for n = 1..n_max
+ * (2..256) molecules over a tet with four interior faces and writes the
+ * switch point to *threshold: the smallest n from which the binomial chain
+ * is never slower (n_max + 1 if it never wins).  The per-launch times (ms)
+ * go to ms_one_by_one[n_max] and ms_sequential[n_max] when non-NULL.  Pass
+ * the result to rdos_set_method; any threshold gives the same law. */
+rdos_status rdos_tune_split_threshold(int device, int32_t n_max, int32_t *threshold, double *ms_one_by_one,
+                                      double *ms_sequential);
+
 /* Measures the device's streaming copy bandwidth (read + write bytes per
  * second / 1e9) with a 16-byte-per-lane copy kernel over `bytes`, `reps`
  * times.  The same kernel calibrates hardware byte counters. */

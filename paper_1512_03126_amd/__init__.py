@@ -71,6 +71,7 @@ _SIGS = [
     ("rdos_engine_kernel_times", C.c_int, [C.c_void_p, _P(C.c_double), _P(C.c_int64), _P(C.c_double),
                                            _P(C.c_int64)]),
     ("rdos_bandwidth_probe", C.c_int, [C.c_int, C.c_size_t, C.c_int, _P(C.c_double)]),
+    ("rdos_tune_split_threshold", C.c_int, [C.c_int, C.c_int32, _P(C.c_int32), _P(C.c_double), _P(C.c_double)]),
     ("rdos_engine_last_error", C.c_char_p, [C.c_void_p]),
     ("rdos_engine_destroy", None, [C.c_void_p]),
 ]
@@ -316,6 +317,17 @@ def rdos_engine_kernel_times(engine):
     b, d = C.c_int64(), C.c_int64()
     _check(lib().rdos_engine_kernel_times(engine, C.byref(a), C.byref(b), C.byref(c), C.byref(d)), engine, True)
     return dict(scan_ms=a.value, scan_launches=b.value, update_ms=c.value, update_launches=d.value)
+
+
+def rdos_tune_split_threshold(device: int = 0, n_max: int = 48):
+    """Measured switch point of the split (Sec. II.B) and the per-launch
+    times of both methods for n = 1..n_max."""
+    t = C.c_int32()
+    one = np.zeros(int(n_max), np.float64)
+    seq = np.zeros(int(n_max), np.float64)
+    _check(lib().rdos_tune_split_threshold(int(device), int(n_max), C.byref(t), _ptr(one, C.c_double),
+                                           _ptr(seq, C.c_double)))
+    return dict(threshold=t.value, ms_one_by_one=one, ms_sequential=seq)
 
 
 def rdos_bandwidth_probe(device: int = 0, nbytes: int = 1 << 30, reps: int = 20) -> float:

@@ -706,7 +706,12 @@ rdos_status rdos_bandwidth_probe(int device, size_t bytes, int reps, double *gbp
     hipEvent_t e0 = nullptr, e1 = nullptr;
     rdos_status rc = RDOS_OK;
     float ms = 0.f;
-    if (hipMalloc(&a, bytes) != hipSuccess || hipMalloc(&b, bytes) != hipSuccess) {
+    bool allocated;
+    {
+        std::lock_guard<std::mutex> g(device_api_mutex());
+        allocated = hipMalloc(&a, bytes) == hipSuccess && hipMalloc(&b, bytes) == hipSuccess;
+    }
+    if (!allocated) {
         rc = RDOS_ENOMEM;
     } else if (hipStreamCreateWithFlags(&st, hipStreamNonBlocking) != hipSuccess || hipEventCreate(&e0) != hipSuccess ||
                hipEventCreate(&e1) != hipSuccess || hipMemsetAsync(a, 1, bytes, st) != hipSuccess ||
@@ -723,9 +728,62 @@ rdos_status rdos_bandwidth_probe(int device, size_t bytes, int reps, double *gbp
     if (e0) (void)hipEventDestroy(e0);
     if (e1) (void)hipEventDestroy(e1);
     if (st) (void)hipStreamDestroy(st);
-    if (a) (void)hipFree(a);
-    if (b) (void)hipFree(b);
+    {
+        std::lock_guard<std::mutex> g(device_api_mutex());
+        if (a) (void)hipFree(a);
+        if (b) (void)hipFree(b);
+    }
     return rc;
+}
+
+rdos_status rdos_tune_split_threshold(int device, int32_t n_max, int32_t *threshold, double *ms_one_by_one,
+                                      double *ms_sequential)
+{
+    if (!threshold || n_max < 2 || n_max > 256) return RDOS_EINVAL;
+    if (hipSetDevice(device) != hipSuccess) return RDOS_EDEVICE;
+    constexpr int32_t kBlocks = 1024, kReps = 4;
+    int64_t *sink = nullptr;
+    hipStream_t st = nullptr;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    std::vector<double> one((size_t)n_max + 1, 0.0), seq((size_t)n_max + 1, 0.0);
+    rdos_status rc = RDOS_OK;
+    {
+        std::lock_guard<std::mutex> g(device_api_mutex());
+        if (hipMalloc(&sink, (size_t)kBlocks * 256 * sizeof(int64_t)) != hipSuccess) rc = RDOS_ENOMEM;
+    }
+    if (rc == RDOS_OK && (hipStreamCreateWithFlags(&st, hipStreamNonBlocking) != hipSuccess ||
+                          hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess))
+        rc = RDOS_EDEVICE;
+    // warm-up, then each method at each n, timed on its own
+    if (rc == RDOS_OK && (launch_split_cost(true, 8, kReps, sink, kBlocks, st) != hipSuccess ||
+                          launch_split_cost(false, 8, kReps, sink, kBlocks, st) != hipSuccess))
+        rc = RDOS_EDEVICE;
+    for (int32_t n = 1; n <= n_max && rc == RDOS_OK; ++n)
+        for (int m = 0; m < 2 && rc == RDOS_OK; ++m) {
+            float ms = 0.f;
+            if (hipEventRecord(e0, st) != hipSuccess || launch_split_cost(m == 0, n, kReps, sink, kBlocks, st) != hipSuccess ||
+                hipEventRecord(e1, st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+                hipEventElapsedTime(&ms, e0, e1) != hipSuccess)
+                rc = RDOS_EDEVICE;
+            (m == 0 ? one : seq)[(size_t)n] = ms;
+        }
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    if (st) (void)hipStreamDestroy(st);
+    if (sink) {
+        std::lock_guard<std::mutex> g(device_api_mutex());
+        (void)hipFree(sink);
+    }
+    if (rc != RDOS_OK) return rc;
+    // the switch point: from here on the binomial chain is never slower
+    int32_t t = n_max + 1;
+    for (int32_t n = n_max; n >= 1 && seq[(size_t)n] <= one[(size_t)n]; --n) t = n;
+    *threshold = t;
+    for (int32_t n = 1; n <= n_max; ++n) {
+        if (ms_one_by_one) ms_one_by_one[n - 1] = one[(size_t)n];
+        if (ms_sequential) ms_sequential[n - 1] = seq[(size_t)n];
+    }
+    return RDOS_OK;
 }
 
 const char *rdos_engine_last_error(const rdos_engine *e) { return e ? e->error.c_str() : "null engine"; }

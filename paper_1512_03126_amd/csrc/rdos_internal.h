@@ -146,6 +146,9 @@ hipError_t launch_mask_build(const int32_t *counts, uint8_t *mask_cur, uint8_t *
 // to 16 bytes so that the scan reads four bytes at a time.
 inline int32_t mask_stride(int64_t Tp) { return (int32_t)(((Tp / 4) + 15) & ~(int64_t)15); }
 hipError_t launch_copy(const void *src, void *dst, size_t bytes, hipStream_t st);
+// blocks x 256 lanes each split n molecules reps times, one-by-one or by
+// sequential binomials; sink holds blocks * 256 int64.
+hipError_t launch_split_cost(bool one_by_one, int64_t n, int32_t reps, int64_t *sink, int32_t blocks, hipStream_t st);
 
 
 }  // namespace rdos

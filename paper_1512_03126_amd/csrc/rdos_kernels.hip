@@ -649,6 +649,35 @@ hipError_t launch_copy(const void *src, void *dst, size_t bytes, hipStream_t st)
     return hipGetLastError();
 }
 
+// Cost of splitting n molecules by each method of Sec. II.B (one categorical
+// draw per molecule, or sequential binomials), for the tuner of the switch
+// point: every lane splits n molecules `reps` times over a tet with four
+// interior faces, each time from its own counter; the sink keeps the work.
+template <bool ONE_BY_ONE>
+__global__ __launch_bounds__(256) void split_cost_kernel(int64_t n, int32_t reps, int64_t *__restrict__ sink)
+{
+    const int32_t nbr[4] = {1, 2, 3, 4};
+    const double w[4] = {0.3, 0.2, 0.2, 0.3};
+    const uint32_t lane = blockIdx.x * blockDim.x + threadIdx.x;
+    int64_t acc = 0;
+    for (int32_t r = 0; r < reps; ++r) {
+        Stream rng(0x2545F491u, 0x9E3779B9u, 0x80000001u, lane, (uint32_t)r);
+        int64_t out[4];
+        split_over_faces(n, nbr, w, ONE_BY_ONE ? (int32_t)(n + 1) : 1, rng, out);
+        acc += out[0] + 2 * out[1] + 3 * out[2] + 4 * out[3];
+    }
+    sink[lane] = acc;
+}
+
+hipError_t launch_split_cost(bool one_by_one, int64_t n, int32_t reps, int64_t *sink, int32_t blocks, hipStream_t st)
+{
+    if (one_by_one)
+        split_cost_kernel<true><<<blocks, 256, 0, st>>>(n, reps, sink);
+    else
+        split_cost_kernel<false><<<blocks, 256, 0, st>>>(n, reps, sink);
+    return hipGetLastError();
+}
+
 // One thread per occupancy byte: tets 4j .. 4j + 3 of one species of one
 // realization (bytes of the row padding past Tp / 4 are zero).
 __global__ __launch_bounds__(256) void mask_build_kernel(const int32_t *__restrict__ counts,

@@ -63,3 +63,25 @@ def test_method_options_every_period(orc, occ, thr, k, use_region, form):
             got, want = g.get_counts(None, realization=r), o.get_counts()
             assert np.array_equal(got, want), (period, r, int((got != want).sum()))
     g.close()
+
+
+def test_split_threshold_tuner():
+    """The measured switch point of the split (Sec. II.B): from the returned
+    threshold on, the sequential binomials are never slower than one draw
+    per molecule, whose cost grows with n."""
+    import paper_1512_03126_amd as P
+
+    note("split threshold tuner")
+    n_max = 160
+    r = P.rdos_tune_split_threshold(0, n_max)
+    one, seq, t = r["ms_one_by_one"], r["ms_sequential"], r["threshold"]
+    note(f"switch point {t}; n=1,10,{n_max}: one-by-one {one[[0, 9, n_max - 1]]} ms, "
+         f"sequential {seq[[0, 9, n_max - 1]]} ms")
+    assert 1 <= t <= n_max + 1
+    assert (one > 0).all() and (seq > 0).all()
+    assert (seq[t - 1:] <= one[t - 1:]).all()
+    if t > 1:
+        assert seq[t - 2] > one[t - 2]
+    assert one[n_max - 1] > 4 * one[3]    # one draw per molecule: cost grows with n
+    with pytest.raises(P.RdosError):
+        P.rdos_tune_split_threshold(0, 1)
