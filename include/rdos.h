@@ -75,6 +75,18 @@ rdos_status rdos_create(rdos_sim **out, int device, uint64_t seed, int32_t n_rea
 rdos_status rdos_set_mesh(rdos_sim *s, int32_t n_verts, const double *xyz, int32_t n_tets,
                           const int32_t *tet_verts);
 
+/* A surface instead of a volume (the transfer between surface triangles of
+ * Sec. III.A, Fig. 5(c)-(d)): xyz[n_verts][3] (m), tri_verts[n_tris][3].
+ * Triangles are the subvolumes: neighbours across edges (edge e opposite
+ * local vertex e), r_e = L_e / (A delta_e), g = sum r_e, w_e = r_e / g, and
+ * the unit of amount is N_A A with A in m^2, so reaction rates are SI per
+ * area: mol/(m^2 s) (0th order), 1/s (1st), m^2/(mol s) (2nd).  Everything
+ * else (species, reactions, counts, stepping, engine) is the same as for a
+ * volume mesh.  RDOS_EINVAL for bad ids; finalize rejects degenerate
+ * triangles and edges on three triangles.  Call instead of rdos_set_mesh. */
+rdos_status rdos_set_surface_mesh(rdos_sim *s, int32_t n_verts, const double *xyz, int32_t n_tris,
+                                  const int32_t *tri_verts);
+
 /* A species with diffusion coefficient D >= 0 (0 = immobile). */
 rdos_status rdos_add_species(rdos_sim *s, double D, int32_t *out_id);
 

@@ -41,6 +41,8 @@ def lib():
         L.orc_create.restype = C.c_void_p
         L.orc_create.argtypes = [i32, P(f64), i32, P(i32), i32, P(f64), i32, P(i32), P(i32),
                                  P(i32), P(i32), P(f64), f64, u64, i32, C.c_char_p]
+        L.orc_create_surface.restype = C.c_void_p
+        L.orc_create_surface.argtypes = L.orc_create.argtypes
         L.orc_destroy.argtypes = [C.c_void_p]
         L.orc_tau.restype = f64
         L.orc_tau.argtypes = [C.c_void_p]
@@ -80,7 +82,9 @@ def _p(a, ct):
 
 
 class OracleSim:
-    """One realization of one model, stepped on the CPU."""
+    """One realization of one model, stepped on the CPU.  `tets` with 4
+    columns is a tetrahedral volume mesh; with 3 columns, a surface of
+    triangles (surface diffusion)."""
 
     def __init__(self, xyz, tets, D, reactions, tau_scale=1.0, seed=1, realization=0):
         from workloads import reaction_arrays
@@ -93,7 +97,10 @@ class OracleSim:
         D = np.ascontiguousarray(D, dtype=np.float64)
         rn, rid, pn, pid, k = reaction_arrays(reactions)
         err = C.create_string_buffer(256)
-        h = L.orc_create(int(self._xyz.shape[0]), _p(self._xyz, C.c_double), self.T,
+        if self._tets.ndim != 2 or self._tets.shape[1] not in (3, 4):
+            raise ValueError("oracle: cells must have 3 (triangles) or 4 (tetrahedra) vertices")
+        create = L.orc_create_surface if self._tets.shape[1] == 3 else L.orc_create
+        h = create(int(self._xyz.shape[0]), _p(self._xyz, C.c_double), self.T,
                          _p(self._tets, C.c_int32), self.S, _p(D, C.c_double), len(reactions),
                          _p(rn, C.c_int32), _p(rid, C.c_int32), _p(pn, C.c_int32),
                          _p(pid, C.c_int32), _p(k, C.c_double), float(tau_scale), int(seed),

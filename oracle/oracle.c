@@ -498,13 +498,20 @@ static void set_err(char *err, const char *msg)
     if (err) snprintf(err, 256, "%s", msg);
 }
 
-orc_sim *orc_create(int32_t n_verts, const double *xyz, int32_t n_tets,
-                    const int32_t *tet_verts, int32_t n_species, const double *D,
-                    int32_t n_reac, const int32_t *reac_n, const int32_t *reac_ids,
-                    const int32_t *prod_n, const int32_t *prod_ids, const double *k,
-                    double tau_scale, uint64_t seed, int32_t realization, char *err)
+/* Cells are tetrahedra (nv = 4, volume diffusion) or triangles (nv = 3,     */
+/* surface diffusion, the transfer between surface triangles of Sec. III.A). */
+/* A triangle is the 2D subvolume: its "faces" are its edges (edge e         */
+/* opposite local vertex e), r_e = L_e / (A delta_e) with L_e the edge        */
+/* length, A the area and delta_e the distance between barycentres, and the  */
+/* unit of amount is N_A A (mol per m^2) instead of N_A V.  Slot 3 of a       */
+/* triangle is always a boundary.                                             */
+static orc_sim *create_cells(int nv, int32_t n_verts, const double *xyz, int32_t n_tets,
+                             const int32_t *tet_verts, int32_t n_species, const double *D,
+                             int32_t n_reac, const int32_t *reac_n, const int32_t *reac_ids,
+                             const int32_t *prod_n, const int32_t *prod_ids, const double *k,
+                             double tau_scale, uint64_t seed, int32_t realization, char *err)
 {
-    if (n_verts < 4 || n_tets < 1 || n_species < 1 || n_species > ORC_MAX_SPECIES || n_reac < 0) {
+    if (n_verts < nv || n_tets < 1 || n_species < 1 || n_species > ORC_MAX_SPECIES || n_reac < 0) {
         set_err(err, "bad sizes");
         return NULL;
     }
@@ -512,7 +519,7 @@ orc_sim *orc_create(int32_t n_verts, const double *xyz, int32_t n_tets,
         set_err(err, "tau_scale must be in (0,1]");
         return NULL;
     }
-    for (int64_t i = 0; i < 4LL * n_tets; ++i) {
+    for (int64_t i = 0; i < (int64_t)nv * n_tets; ++i) {
         if (tet_verts[i] < 0 || tet_verts[i] >= n_verts) {
             set_err(err, "vertex id out of range");
             return NULL;
@@ -569,7 +576,36 @@ orc_sim *orc_create(int32_t n_verts, const double *xyz, int32_t n_tets,
 
     /* volumes, barycentres, face areas; face f is opposite local vertex f */
     double *bc = (double *)malloc(sizeof(double) * 3 * (size_t)T);
-    for (int32_t t = 0; t < T; ++t) {
+    for (int32_t t = 0; t < T && nv == 3; ++t) {
+        /* triangle: area, barycentre, edge lengths (edge e opposite vertex e) */
+        const double *P[3];
+        for (int v = 0; v < 3; ++v) P[v] = xyz + 3 * (size_t)tet_verts[3 * (size_t)t + v];
+        double e1[3], e2[3], cr[3];
+        sub3(P[1], P[0], e1);
+        sub3(P[2], P[0], e2);
+        cross3(e1, e2, cr);
+        double A = 0.5 * norm3(cr);
+        if (!(A > 0.0)) {
+            set_err(err, "degenerate triangle");
+            free(bc);
+            orc_destroy(s);
+            return NULL;
+        }
+        s->vol[t] = A;
+        s->nav[t] = ORC_NA * A;
+        for (int d = 0; d < 3; ++d) bc[3 * (size_t)t + d] = ((P[0][d] + P[1][d]) + P[2][d]) / 3.0;
+        for (int f = 0; f < 3; ++f) {
+            const double *Q[2];
+            int qi = 0;
+            for (int v = 0; v < 3; ++v)
+                if (v != f) Q[qi++] = P[v];
+            double dd[3];
+            sub3(Q[1], Q[0], dd);
+            s->area[4 * (size_t)t + f] = norm3(dd);
+        }
+        s->area[4 * (size_t)t + 3] = 0.0;
+    }
+    for (int32_t t = 0; t < T && nv == 4; ++t) {
         const double *P[4];
         for (int v = 0; v < 4; ++v) P[v] = xyz + 3 * (size_t)tet_verts[4 * (size_t)t + v];
         double e1[3], e2[3], e3[3], cr[3];
@@ -601,28 +637,31 @@ orc_sim *orc_create(int32_t n_verts, const double *xyz, int32_t n_tets,
         }
     }
 
-    /* face matching: sort all 4T faces by their vertex triple */
-    orc_face *faces = (orc_face *)malloc(sizeof(orc_face) * 4 * (size_t)T);
+    /* face matching: sort all faces by their sorted vertices (a triangle's */
+    /* edges carry -1 as third vertex) */
+    orc_face *faces = (orc_face *)malloc(sizeof(orc_face) * (size_t)nv * (size_t)T);
     for (int32_t t = 0; t < T; ++t) {
-        for (int f = 0; f < 4; ++f) {
-            orc_face *F = &faces[4 * (size_t)t + f];
+        for (int f = 0; f < 4; ++f) s->nbr[4 * (size_t)t + f] = -1;
+        for (int f = 0; f < nv; ++f) {
+            orc_face *F = &faces[(size_t)nv * t + f];
             int qi = 0;
-            for (int v = 0; v < 4; ++v)
-                if (v != f) F->v[qi++] = tet_verts[4 * (size_t)t + v];
+            F->v[2] = -1;
+            for (int v = 0; v < nv; ++v)
+                if (v != f) F->v[qi++] = tet_verts[(size_t)nv * t + v];
             sort3(F->v);
             F->tet = t;
             F->face = f;
-            s->nbr[4 * (size_t)t + f] = -1;
         }
     }
-    qsort(faces, 4 * (size_t)T, sizeof(orc_face), face_cmp);
-    size_t nF = 4 * (size_t)T;
+    qsort(faces, (size_t)nv * T, sizeof(orc_face), face_cmp);
+    size_t nF = (size_t)nv * T;
     for (size_t i = 0; i < nF;) {
         size_t jn = i + 1;
         while (jn < nF && memcmp(faces[jn].v, faces[i].v, sizeof faces[i].v) == 0) ++jn;
         size_t mult = jn - i;
         if (mult > 2 || (mult == 2 && faces[i].tet == faces[i + 1].tet)) {
-            set_err(err, "face shared by more than two tetrahedra (or repeated in one)");
+            set_err(err, nv == 4 ? "face shared by more than two tetrahedra (or repeated in one)"
+                                 : "edge shared by more than two triangles (or repeated in one)");
             free(faces);
             free(bc);
             orc_destroy(s);
@@ -667,7 +706,7 @@ orc_sim *orc_create(int32_t n_verts, const double *xyz, int32_t n_tets,
         }
     }
     if (!(best < INFINITY)) {
-        set_err(err, "no diffusing species on a connected tetrahedron: tau undefined");
+        set_err(err, "no diffusing species on a connected cell: tau undefined");
         orc_destroy(s);
         return NULL;
     }
@@ -678,6 +717,24 @@ orc_sim *orc_create(int32_t n_verts, const double *xyz, int32_t n_tets,
     s->anchor_step = 0;
     s->anchor_t = 0.0;
     return s;
+}
+
+orc_sim *orc_create(int32_t n_verts, const double *xyz, int32_t n_tets, const int32_t *tet_verts,
+                    int32_t n_species, const double *D, int32_t n_reac, const int32_t *reac_n,
+                    const int32_t *reac_ids, const int32_t *prod_n, const int32_t *prod_ids, const double *k,
+                    double tau_scale, uint64_t seed, int32_t realization, char *err)
+{
+    return create_cells(4, n_verts, xyz, n_tets, tet_verts, n_species, D, n_reac, reac_n, reac_ids, prod_n,
+                        prod_ids, k, tau_scale, seed, realization, err);
+}
+
+orc_sim *orc_create_surface(int32_t n_verts, const double *xyz, int32_t n_tris, const int32_t *tri_verts,
+                            int32_t n_species, const double *D, int32_t n_reac, const int32_t *reac_n,
+                            const int32_t *reac_ids, const int32_t *prod_n, const int32_t *prod_ids,
+                            const double *k, double tau_scale, uint64_t seed, int32_t realization, char *err)
+{
+    return create_cells(3, n_verts, xyz, n_tris, tri_verts, n_species, D, n_reac, reac_n, reac_ids, prod_n,
+                        prod_ids, k, tau_scale, seed, realization, err);
 }
 
 void orc_destroy(orc_sim *s)

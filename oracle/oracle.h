@@ -42,6 +42,15 @@ orc_sim *orc_create(int32_t n_verts, const double *xyz, int32_t n_tets,
                     const int32_t *prod_ids, const double *k,
                     double tau_scale, uint64_t seed, int32_t realization,
                     char *err);
+/* The same for a surface of triangles (surface diffusion, Sec. III.A):
+ * tri_verts[n_tris][3]; edge e is opposite local vertex e and slot 3 is a
+ * boundary.  r_e = L_e / (A delta_e), the unit of amount is N_A A with A in
+ * m^2, so rates are k in mol/(m^2 s) (0th order), 1/s (1st), m^2/(mol s)
+ * (2nd).  Errors as above (degenerate triangle, edge on three triangles). */
+orc_sim *orc_create_surface(int32_t n_verts, const double *xyz, int32_t n_tris, const int32_t *tri_verts,
+                            int32_t n_species, const double *D, int32_t n_reac, const int32_t *reac_n,
+                            const int32_t *reac_ids, const int32_t *prod_n, const int32_t *prod_ids,
+                            const double *k, double tau_scale, uint64_t seed, int32_t realization, char *err);
 void orc_destroy(orc_sim *s);
 
 double orc_tau(const orc_sim *s);

@@ -37,6 +37,7 @@ _P = C.POINTER
 _SIGS = [
     ("rdos_create", C.c_int, [_P(C.c_void_p), C.c_int, C.c_uint64, C.c_int32]),
     ("rdos_set_mesh", C.c_int, [C.c_void_p, C.c_int32, _P(C.c_double), C.c_int32, _P(C.c_int32)]),
+    ("rdos_set_surface_mesh", C.c_int, [C.c_void_p, C.c_int32, _P(C.c_double), C.c_int32, _P(C.c_int32)]),
     ("rdos_add_species", C.c_int, [C.c_void_p, C.c_double, _P(C.c_int32)]),
     ("rdos_add_reaction", C.c_int, [C.c_void_p, C.c_int32, _P(C.c_int32), C.c_int32, _P(C.c_int32), C.c_double,
                                     _P(C.c_int32)]),
@@ -138,6 +139,13 @@ def rdos_set_mesh(sim, xyz, tet_verts):
     tv = np.ascontiguousarray(tet_verts, dtype=np.int32)
     _check(lib().rdos_set_mesh(sim, int(xyz.shape[0]), _ptr(xyz, C.c_double), int(tv.shape[0]),
                                _ptr(tv, C.c_int32)), sim)
+
+
+def rdos_set_surface_mesh(sim, xyz, tri_verts):
+    xyz = np.ascontiguousarray(xyz, dtype=np.float64)
+    tv = np.ascontiguousarray(tri_verts, dtype=np.int32)
+    _check(lib().rdos_set_surface_mesh(sim, int(xyz.shape[0]), _ptr(xyz, C.c_double), int(tv.shape[0]),
+                                       _ptr(tv, C.c_int32)), sim)
 
 
 def rdos_add_species(sim, D: float) -> int:
@@ -344,7 +352,8 @@ def rdos_engine_destroy(engine):
 # Object wrappers
 # ---------------------------------------------------------------------------
 class Simulation:
-    """A simulation handle: mesh, species, reactions, counts, stepping."""
+    """A simulation handle: mesh (tetrahedra, or a surface of triangles when
+    the cells have 3 vertices), species, reactions, counts, stepping."""
 
     def __init__(self, xyz, tets, D: Iterable[float], reactions=(), seed: int = 1, n_realizations: int = 1,
                  device: int = 0, tau_scale: Optional[float] = 1.0, occupancy_correction: bool = True,
@@ -352,7 +361,13 @@ class Simulation:
         self.h = rdos_create(device, seed, n_realizations)
         self.T = int(np.asarray(tets).shape[0])
         self.Rz = int(n_realizations)
-        rdos_set_mesh(self.h, xyz, tets)
+        cells = np.asarray(tets)
+        if cells.ndim != 2 or cells.shape[1] not in (3, 4):
+            raise ValueError("cells must have 3 (surface triangles) or 4 (tetrahedra) vertices")
+        if cells.shape[1] == 3:
+            rdos_set_surface_mesh(self.h, xyz, cells)
+        else:
+            rdos_set_mesh(self.h, xyz, cells)
         self.S = 0
         for d in D:
             rdos_add_species(self.h, d)

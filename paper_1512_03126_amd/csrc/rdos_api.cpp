@@ -118,6 +118,7 @@ size_t state_bytes(const rdos_sim *s)
 // array): requests that share a lattice but move its vertices reuse them.
 struct TopologyCache {
     struct Entry {
+        int32_t cell_verts = 4;
         std::vector<int32_t> tet_verts;
         std::shared_ptr<const std::vector<int32_t>> nbr;
         uint64_t last_use = 0;
@@ -148,12 +149,12 @@ rdos_status build_topology_uncached(rdos_sim *s, std::vector<int32_t> &nbr);
 rdos_status build_topology(rdos_sim *s, std::vector<int32_t> &nbr)
 {
     TopologyCache &c = topology_cache();
-    const uint64_t h = hash_tets(s->tet_verts);
+    const uint64_t h = hash_tets(s->tet_verts) ^ (uint64_t)s->cell_verts;
     {
         std::lock_guard<std::mutex> g(c.mu);
         auto range = c.entries.equal_range(h);
         for (auto it = range.first; it != range.second; ++it)
-            if (it->second.tet_verts == s->tet_verts) {
+            if (it->second.cell_verts == s->cell_verts && it->second.tet_verts == s->tet_verts) {
                 it->second.last_use = ++c.clock;
                 nbr = *it->second.nbr;
                 return RDOS_OK;
@@ -172,6 +173,7 @@ rdos_status build_topology(rdos_sim *s, std::vector<int32_t> &nbr)
     }
     if (add <= TopologyCache::kMaxBytes) {
         TopologyCache::Entry en;
+        en.cell_verts = s->cell_verts;
         en.tet_verts = s->tet_verts;
         en.nbr = std::make_shared<const std::vector<int32_t>>(nbr);
         en.last_use = ++c.clock;
@@ -181,10 +183,50 @@ rdos_status build_topology(rdos_sim *s, std::vector<int32_t> &nbr)
     return RDOS_OK;
 }
 
+// Edge matching for a surface of triangles: each edge (opposite local vertex
+// e) keyed by its sorted vertex pair; slot 3 of every triangle is a boundary.
+static rdos_status build_edges(rdos_sim *s, std::vector<int32_t> &nbr)
+{
+    struct EdgeKey {
+        int32_t a, b;
+        int32_t slot;  // 4 * triangle + edge
+    };
+    const int32_t T = s->T;
+    std::vector<EdgeKey> keys((size_t)T * 3);
+    for (int32_t t = 0; t < T; ++t) {
+        const int32_t *v = &s->tet_verts[3 * (size_t)t];
+        for (int e = 0; e < 3; ++e) {
+            const int32_t p = v[e == 0 ? 1 : 0], q = v[e <= 1 ? 2 : 1];
+            keys[3 * (size_t)t + e] = {std::min(p, q), std::max(p, q), 4 * t + e};
+        }
+    }
+    std::sort(keys.begin(), keys.end(), [](const EdgeKey &x, const EdgeKey &y) {
+        if (x.a != y.a) return x.a < y.a;
+        if (x.b != y.b) return x.b < y.b;
+        return x.slot < y.slot;
+    });
+    nbr.assign((size_t)T * 4, -1);
+    for (size_t i = 0; i < keys.size();) {
+        size_t j = i + 1;
+        while (j < keys.size() && keys[j].a == keys[i].a && keys[j].b == keys[i].b) ++j;
+        if (j - i > 2)
+            return fail(s, RDOS_EINVAL, "edge (%d,%d) is shared by %zu triangles", keys[i].a, keys[i].b, j - i);
+        if (j - i == 2) {
+            const int32_t t0 = keys[i].slot / 4, t1 = keys[i + 1].slot / 4;
+            if (t0 == t1) return fail(s, RDOS_EINVAL, "triangle %d repeats an edge", t0);
+            nbr[keys[i].slot] = t1;
+            nbr[keys[i + 1].slot] = t0;
+        }
+        i = j;
+    }
+    return RDOS_OK;
+}
+
 // Face matching: each face is keyed by its sorted vertex triple; two tets with
 // the same key are neighbours across it.  A key seen three times is an error.
 rdos_status build_topology_uncached(rdos_sim *s, std::vector<int32_t> &nbr)
 {
+    if (s->cell_verts == 3) return build_edges(s, nbr);
     struct FaceKey {
         int32_t a, b, c;
         int32_t slot;  // 4 * tet + face
@@ -364,6 +406,27 @@ rdos_status rdos_set_mesh(rdos_sim *s, int32_t n_verts, const double *xyz, int32
     return RDOS_OK;
 }
 
+rdos_status rdos_set_surface_mesh(rdos_sim *s, int32_t n_verts, const double *xyz, int32_t n_tris,
+                                  const int32_t *tri_verts)
+{
+    CHECK_HANDLE(s);
+    if (s->state != SimState::Created) return fail(s, RDOS_ESTATE, "set_surface_mesh after the mesh was set");
+    if (n_verts < 3 || n_tris < 1 || !xyz || !tri_verts)
+        return fail(s, RDOS_EINVAL, "surface needs >= 3 vertices and >= 1 triangle");
+    for (int64_t i = 0; i < 3 * (int64_t)n_verts; ++i)
+        if (!std::isfinite(xyz[i])) return fail(s, RDOS_EINVAL, "vertex coordinate %lld is not finite", (long long)i);
+    for (int64_t i = 0; i < 3 * (int64_t)n_tris; ++i)
+        if (tri_verts[i] < 0 || tri_verts[i] >= n_verts)
+            return fail(s, RDOS_EINVAL, "vertex id %d out of range at %lld", tri_verts[i], (long long)i);
+    s->xyz.assign(xyz, xyz + 3 * (size_t)n_verts);
+    s->tet_verts.assign(tri_verts, tri_verts + 3 * (size_t)n_tris);
+    s->cell_verts = 3;
+    s->n_verts = n_verts;
+    s->T = n_tris;
+    s->state = SimState::Meshed;
+    return RDOS_OK;
+}
+
 rdos_status rdos_add_species(rdos_sim *s, double D, int32_t *out_id)
 {
     CHECK_HANDLE(s);
@@ -522,8 +585,13 @@ rdos_status rdos_finalize(rdos_sim *s, double tau_scale, double *out_tau)
               "upload neighbours");
     SETUP_TRY(hipMemcpyAsync(d_D, s->D.data(), (size_t)S * sizeof(double), hipMemcpyHostToDevice, s->stream),
               "upload D");
-    SETUP_TRY(launch_geometry(d_xyz, d_tv, d_nbr, T, d_vol, d_bc, d_area, s->d_mesh, s->d_flags + 1, s->stream),
-              "geometry");
+    if (s->cell_verts == 3)
+        SETUP_TRY(launch_geometry_tri(d_xyz, d_tv, d_nbr, T, d_vol, d_bc, d_area, s->d_mesh, s->d_flags + 1,
+                                      s->stream),
+                  "geometry");
+    else
+        SETUP_TRY(launch_geometry(d_xyz, d_tv, d_nbr, T, d_vol, d_bc, d_area, s->d_mesh, s->d_flags + 1, s->stream),
+                  "geometry");
     if (s->tau_outliers > 0) {
         // Sec. II.A outlier relaxation: the (k+1)-th smallest 1/(D g) sets tau
         void *scratch = nullptr;
@@ -552,11 +620,12 @@ rdos_status rdos_finalize(rdos_sim *s, double tau_scale, double *out_tau)
 #undef SETUP_TRY
     if (bad[1]) {
         free_device(s);
-        return fail(s, RDOS_EINVAL, "degenerate tetrahedron (zero volume)");
+        return fail(s, RDOS_EINVAL, s->cell_verts == 3 ? "degenerate triangle (zero area)"
+                                                       : "degenerate tetrahedron (zero volume)");
     }
     if (tau_bits == ~0ull) {
         free_device(s);
-        return fail(s, RDOS_EINVAL, "no diffusing species on a connected tetrahedron: tau is undefined");
+        return fail(s, RDOS_EINVAL, "no diffusing species on a connected cell: tau is undefined");
     }
     double tmin;
     std::memcpy(&tmin, &tau_bits, sizeof tmin);

@@ -80,6 +80,11 @@ hipError_t launch_geometry(const double *xyz, const int32_t *tet_verts, const in
                            int32_t T, double *scratch_vol, double *scratch_bc,
                            double *scratch_area, MeshRec *mesh, int32_t *bad_volume,
                            hipStream_t st);
+// The same for triangles (surface diffusion): area instead of volume, edge
+// lengths instead of face areas, N_A A as the unit of amount.
+hipError_t launch_geometry_tri(const double *xyz, const int32_t *tri_verts, const int32_t *nbr, int32_t T,
+                               double *scratch_area, double *scratch_bc, double *scratch_len, MeshRec *mesh,
+                               int32_t *bad_area, hipStream_t st);
 hipError_t launch_tau_min(const MeshRec *mesh, int32_t T, const double *D, int32_t S,
                           unsigned long long *out_bits, hipStream_t st);
 // Writes the k-th smallest (0-based, clamped to the last) of 1/(D_m g_t)

@@ -106,6 +106,51 @@ __global__ __launch_bounds__(256) void geometry_pass2(const int32_t *__restrict_
     m.g = g;
 }
 
+// Triangles (surface diffusion): area, barycentre and edge lengths, edge e
+// opposite local vertex e; slot 3 is a boundary (length 0).  The unit of
+// amount is N_A A (A in m^2).  Pass 2 is shared: r_e = L_e / (A d_e).
+__global__ __launch_bounds__(256) void geometry_tri_pass1(const double *__restrict__ xyz,
+                                                          const int32_t *__restrict__ tri_verts, int32_t T,
+                                                          double *__restrict__ area, double *__restrict__ bc,
+                                                          double *__restrict__ len, MeshRec *__restrict__ mesh,
+                                                          int32_t *__restrict__ bad)
+{
+    const int32_t t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= T) return;
+    V3 P[3];
+#pragma unroll
+    for (int v = 0; v < 3; ++v) {
+        const int64_t id = tri_verts[3 * (int64_t)t + v];
+        P[v] = {xyz[3 * id], xyz[3 * id + 1], xyz[3 * id + 2]};
+    }
+    const double A = 0.5 * vnorm(vcross(vsub(P[1], P[0]), vsub(P[2], P[0])));
+    if (!(A > 0.0)) atomicOr(bad, 1);
+    area[t] = A;
+    mesh[t].nav = kAvogadro * A;
+    bc[3 * (int64_t)t + 0] = ((P[0].x + P[1].x) + P[2].x) / 3.0;
+    bc[3 * (int64_t)t + 1] = ((P[0].y + P[1].y) + P[2].y) / 3.0;
+    bc[3 * (int64_t)t + 2] = ((P[0].z + P[1].z) + P[2].z) / 3.0;
+#pragma unroll
+    for (int e = 0; e < 3; ++e) {
+        // the edge opposite vertex e, its end points in increasing local order
+        const V3 a = P[e == 0 ? 1 : 0];
+        const V3 b = P[e <= 1 ? 2 : 1];
+        len[4 * (int64_t)t + e] = vnorm(vsub(b, a));
+    }
+    len[4 * (int64_t)t + 3] = 0.0;
+}
+
+hipError_t launch_geometry_tri(const double *xyz, const int32_t *tri_verts, const int32_t *nbr, int32_t T,
+                               double *scratch_area, double *scratch_bc, double *scratch_len, MeshRec *mesh,
+                               int32_t *bad_area, hipStream_t st)
+{
+    const int grid = (T + 255) / 256;
+    geometry_tri_pass1<<<grid, 256, 0, st>>>(xyz, tri_verts, T, scratch_area, scratch_bc, scratch_len, mesh,
+                                             bad_area);
+    geometry_pass2<<<grid, 256, 0, st>>>(nbr, T, scratch_area, scratch_bc, scratch_len, mesh);
+    return hipGetLastError();
+}
+
 hipError_t launch_geometry(const double *xyz, const int32_t *tet_verts, const int32_t *nbr, int32_t T,
                            double *scratch_vol, double *scratch_bc, double *scratch_area, MeshRec *mesh,
                            int32_t *bad_volume, hipStream_t st)

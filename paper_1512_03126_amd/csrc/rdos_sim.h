@@ -34,7 +34,8 @@ struct rdos_sim {
     // model (host copy)
     int32_t n_verts = 0, T = 0;
     std::vector<double> xyz;
-    std::vector<int32_t> tet_verts;
+    std::vector<int32_t> tet_verts;  // cells: [T][4] tetrahedra, or [T][3] triangles of a surface
+    int32_t cell_verts = 4;
     std::vector<double> D;
     std::vector<rdos::Reaction> rx;
     std::map<int32_t, std::vector<int32_t>> staged;  // (r * kMaxSpecies + s) -> counts before finalize

@@ -285,6 +285,45 @@ def production_annihilation(n: int = 5, a: float = 0.2e-6, D: float = 1e-11, k2:
                  seed, species_names=["A"])
 
 
+def triangle_lattice(nx: int, ny: int, a: float, jitter_frac: float = 0.0, seed: int = 1) -> Tuple[np.ndarray, np.ndarray]:
+    """A planar surface (z = 0) of nx x ny square cells of edge a, each cut
+    into two right triangles along a diagonal that alternates like a
+    checkerboard (so the walk has no preferred diagonal).  Interior vertices
+    move uniformly within +-jitter_frac * a in x and y (numpy PCG64).
+    Vertex i + (nx + 1) j; cell (i, j) gives triangles 2 (i + nx j) and + 1."""
+    ii, jj = np.meshgrid(np.arange(nx + 1), np.arange(ny + 1), indexing="xy")
+    xyz = np.stack([ii.ravel() * a, jj.ravel() * a, np.zeros(ii.size)], axis=1).astype(np.float64)
+    tris = []
+    for j in range(ny):
+        for i in range(nx):
+            v00, v10 = i + (nx + 1) * j, i + 1 + (nx + 1) * j
+            v01, v11 = i + (nx + 1) * (j + 1), i + 1 + (nx + 1) * (j + 1)
+            if (i + j) % 2 == 0:
+                tris += [(v00, v10, v11), (v00, v11, v01)]
+            else:
+                tris += [(v00, v10, v01), (v10, v11, v01)]
+    if jitter_frac > 0:
+        rng = np.random.default_rng(seed)
+        inner = (ii.ravel() > 0) & (ii.ravel() < nx) & (jj.ravel() > 0) & (jj.ravel() < ny)
+        xyz[inner, :2] += rng.uniform(-jitter_frac * a, jitter_frac * a, size=(int(inner.sum()), 2))
+    return xyz, np.array(tris, dtype=np.int32)
+
+
+def box_surface(n: int, a: float) -> Tuple[np.ndarray, np.ndarray]:
+    """The closed surface of the n^3 x 6 Kuhn cube: its boundary faces (faces
+    on one tet only) as triangles, on the cube's vertices (unused ones
+    dropped).  Every edge lies on exactly two triangles."""
+    xyz, tets = kuhn_lattice(n, a)
+    faces = {}
+    for t in range(tets.shape[0]):
+        for f in range(4):
+            tri = tuple(sorted(int(v) for k, v in enumerate(tets[t]) if k != f))
+            faces[tri] = faces.get(tri, 0) + 1
+    tris = np.array([tri for tri, c in faces.items() if c == 1], dtype=np.int32)
+    used, inv = np.unique(tris, return_inverse=True)
+    return xyz[used].copy(), inv.reshape(tris.shape).astype(np.int32)
+
+
 def tiny_lattice(n: int = 2, a: float = 0.2e-6, jitter_frac: float = 0.0, seed: int = 3) -> Tuple[np.ndarray, np.ndarray]:
     """Small meshes for exhaustive tests (n=1: 6 tets, n=2: 48 tets)."""
     xyz, tets = kuhn_lattice(n, a)
