@@ -35,10 +35,10 @@ def kernel_source_hash():
     return h.hexdigest()[:16]
 
 
-def traffic_from_profile(workload, steps_key):
-    """HBM bytes per scan launch measured by rocprofv3 counters for this
-    workload, if the kernel sources have not changed since."""
-    path = os.path.join(ROOT, "profiles", f"scan_kernel_{workload}_traffic.json")
+def traffic_from_profile(kernel, workload):
+    """HBM bytes per launch of `kernel` measured by rocprofv3 counters for
+    this workload, if the kernel sources have not changed since."""
+    path = os.path.join(ROOT, "profiles", f"{kernel}_{workload}_traffic.json")
     if not os.path.exists(path):
         return None
     with open(path) as f:
@@ -214,6 +214,67 @@ def run_serving(P, args):
     return res
 
 
+def write_traffic(fetch_csv, write_csv, launches, command):
+    """Turns two rocprofv3 --pmc runs of this script (FETCH_SIZE, then
+    WRITE_SIZE) into profiles/<kernel>_batched_traffic.json for both step
+    kernels: the mean over the last `launches` dispatches of each kernel (the
+    timing pass, launched directly), in bytes, each counter scaled so that the
+    1 GiB copy of the bandwidth probe in the same run reads 1 GiB and writes
+    1 GiB."""
+    import collections
+    import csv
+
+    per = {}
+    for counter, path in (("FETCH_SIZE", fetch_csv), ("WRITE_SIZE", write_csv)):
+        disp = collections.defaultdict(float)
+        name = {}
+        with open(path) as f:
+            for r in csv.DictReader(f):
+                if r["Counter_Name"] != counter:
+                    continue
+                d = int(r["Dispatch_Id"])
+                disp[d] += float(r["Counter_Value"])
+                name[d] = r["Kernel_Name"]
+        def mean_kib(k, n):
+            ds = sorted(d for d in disp if k in name[d])[-n:]
+            if not ds:
+                raise SystemExit(f"no {k} dispatches in {path}")
+            return sum(disp[d] for d in ds) / len(ds), len(ds)
+        copy_kib, _ = mean_kib("bandwidth_copy_kernel", 5)
+        scale = (1 << 30) / 1024 / copy_kib
+        per[counter] = {k: mean_kib(k, launches) for k in ("scan_kernel", "update_kernel")}
+        per[counter]["scale"] = scale
+        per[counter]["copy_kib"] = copy_kib
+    for k in ("scan_kernel", "update_kernel"):
+        fb = per["FETCH_SIZE"][k][0] * 1024 * per["FETCH_SIZE"]["scale"]
+        wb = per["WRITE_SIZE"][k][0] * 1024 * per["WRITE_SIZE"]["scale"]
+        out = {"kernel": k, "workload": "batched A+B<->C: 256 x 384000-tet + 64 x 48000-tet realizations, 3 species",
+               "kernel_sources": kernel_source_hash(), "bytes_per_launch": int(round(fb + wb)),
+               "fetch_bytes_per_launch": int(round(fb)), "write_bytes_per_launch": int(round(wb)),
+               "scale": {c: round(per[c]["scale"], 4) for c in per},
+               "calibration": "bandwidth_copy_kernel copying 1 GiB reads FETCH_SIZE "
+                              f"{per['FETCH_SIZE']['copy_kib']:,.0f} KiB and WRITE_SIZE "
+                              f"{per['WRITE_SIZE']['copy_kib']:,.0f} KiB per dispatch",
+               "launches_averaged": per["FETCH_SIZE"][k][1], "commands": command,
+               "note": f"per dispatch of the last {launches} {k} launches (the single-chain timing pass, one "
+                       "launch per period over all realizations); counter KiB x 1024 x scale"}
+        path = os.path.join(ROOT, "profiles", f"{k}_batched_traffic.json")
+        with open(path, "w") as f:
+            json.dump(out, f, indent=1)
+            f.write("\n")
+        log(f"{path}: {out['bytes_per_launch']:.4g} B per launch")
+
+
+def update_bytes(work, species):
+    """Bytes the update kernel must move for the work it counted on the
+    device (the units and per-unit figures of its roofline):
+      4 + 4 S B per queued tet (its queue entry: index and S counts),
+      64 B per queued tet (its mesh record: neighbours, weights, g, N_A V),
+      9 B per count addition into the next buffer (the 4 B read and 4 B
+      write of the atomic, and the byte it sets in the occupancy map)."""
+    return work["tets"] * (4 + 4 * species + 64) + 9 * work["additions"]
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -228,7 +289,17 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-plain", action="store_true", help="skip the plain one-realization comparison")
     ap.add_argument("--cpu-periods", type=int, default=1014, help="oracle sample length (periods; 1014 = 0.3 s)")
+    ap.add_argument("--traffic-from", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
+                    help="no run: write the kernels' HBM traffic files from two rocprofv3 --pmc runs of "
+                         "`bench.py --steps K --no-cpu-baseline --no-plain` (K = --steps here)")
     args = ap.parse_args()
+
+    if args.traffic_from:
+        cmd = [f"timeout -s KILL 300 rocprofv3 --pmc {c} --output-format csv -d gpurun_out/pmc_{c.lower()} "
+               f"-o {c.lower()} -- python3 bench.py --steps {args.steps} --warmup {args.warmup} "
+               "--no-cpu-baseline --no-plain" for c in ("FETCH_SIZE", "WRITE_SIZE")]
+        write_traffic(*args.traffic_from, args.steps, cmd)
+        return
 
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); realizations and requests shard "
@@ -290,31 +361,40 @@ def main():
         ms_step = dt / K * 1e3
         # per-kernel durations: the same periods again, launched directly with
         # HIP events between the scan and update launches; the scan's
-        # algorithmic bytes are counted on the state before and after them
+        # algorithmic bytes are counted on the state before and after them,
+        # the update's from the work it tallies on the device in these launches
         alg0 = scan_bytes(sims, models)
         P.rdos_engine_set_profiling(e, True)
         run_engine(P, e, sims, K)
         kt = P.rdos_engine_kernel_times(e)
+        work = P.rdos_engine_work_counts(e)
         P.rdos_engine_set_profiling(e, False)
         alg1 = scan_bytes(sims, models)
-        alg = 0.5 * (alg0 + alg1)
-        n_scan = kt["scan_launches"]
+        n_scan, n_upd = kt["scan_launches"], kt["update_launches"]
         scan_ms = kt["scan_ms"] / max(n_scan, 1)
-        upd_ms = kt["update_ms"] / max(kt["update_launches"], 1)
+        upd_ms = kt["update_ms"] / max(n_upd, 1)
         log(f"batched: {value:.3e} upd/s, {ms_step:.3f} ms/period; scan {scan_ms:.3f} ms, update {upd_ms:.3f} ms "
-            f"per launch ({n_scan} launches)")
-        achieved = alg / (scan_ms * 1e-3) / 1e9
-        traffic = traffic_from_profile("batched", K)
-        roof = {"bound": "hbm", "kernel": "scan_kernel", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBPS,
-                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBPS, 4),
-                "traffic": traffic,
-                "algorithmic_bytes_per_launch": int(alg), "avg_launch_ms": round(scan_ms, 4),
-                "traffic_GBps": round(traffic / (scan_ms * 1e-3) / 1e9, 1) if traffic else None,
-                "update_kernel_avg_ms": round(upd_ms, 4),
+            f"per launch ({n_scan} launches); update work {work}")
+        kern = {}
+        for name, ms, alg in (("scan_kernel", scan_ms, 0.5 * (alg0 + alg1)),
+                              ("update_kernel", upd_ms, update_bytes(work, models[0].n_species) / max(n_upd, 1))):
+            ach = alg / (ms * 1e-3) / 1e9
+            tr = traffic_from_profile(name, "batched")
+            kern[name] = {"avg_launch_ms": round(ms, 4), "algorithmic_bytes_per_launch": int(alg),
+                          "achieved": round(ach, 1), "frac": round(ach / HBM_PEAK_GBPS, 4), "traffic": tr,
+                          "traffic_GBps": round(tr / (ms * 1e-3) / 1e9, 1) if tr else None}
+            log(f"{name}: {alg:.4g} algorithmic B per launch, {ach:.1f} GB/s, measured traffic {tr}")
+        kern["update_kernel"]["queued_tets_per_launch"] = round(work["tets"] / max(n_upd, 1), 1)
+        kern["update_kernel"]["additions_per_launch"] = round(work["additions"] / max(n_upd, 1), 1)
+        dom = max(kern, key=lambda k: kern[k]["avg_launch_ms"])  # the longer kernel sets the roofline
+        d = kern[dom]
+        roof = {"bound": "hbm", "kernel": dom, "achieved": d["achieved"], "peak": HBM_PEAK_GBPS, "unit": "GB/s",
+                "frac": d["frac"], "traffic": d["traffic"],
+                "algorithmic_bytes_per_launch": d["algorithmic_bytes_per_launch"],
+                "avg_launch_ms": d["avg_launch_ms"], "traffic_GBps": d["traffic_GBps"], "kernels": kern,
                 "dense_bytes_per_period": bytes_per_period,
                 "dense_period_frac": round(bytes_per_period / (ms_step * 1e-3) / 1e9 / HBM_PEAK_GBPS, 4)}
-        log(f"scan algorithmic bytes {alg:.4g} per launch ({achieved:.1f} GB/s); dense-equivalent period "
-            f"fraction {roof['dense_period_frac']}")
+        log(f"dominant kernel {dom}; dense-equivalent period fraction {roof['dense_period_frac']}")
         try:
             roof["copy_probe_GBps"] = round(P.rdos_bandwidth_probe(0, 1 << 30, 20), 1)
         except Exception as ex:  # informational only

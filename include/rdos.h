@@ -226,6 +226,13 @@ rdos_status rdos_engine_set_profiling(rdos_engine *e, int on);
 rdos_status rdos_engine_kernel_times(rdos_engine *e, double *scan_ms, int64_t *scan_launches,
                                      double *update_ms, int64_t *update_launches);
 
+/* Work the timed update launches did since profiling was switched on, counted
+ * on the device: `tets` tet-realization entries taken from the queue (Step 2
+ * of Algorithm 1 then Step 3 for every species), `additions` molecule-count
+ * additions into the next buffer (the synchronous application of Step 4, one
+ * per non-empty destination).  Both are zero when profiling never ran. */
+rdos_status rdos_engine_work_counts(rdos_engine *e, int64_t *tets, int64_t *additions);
+
 /* The launch shape the tuner settled on for the current work list: periods
  * per graph replay, scan blocks, update blocks per queue segment, and 1 or 2
  * independent chains (halves of the realizations on two streams, so one

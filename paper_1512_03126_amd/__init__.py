@@ -69,6 +69,7 @@ _SIGS = [
                                            _P(C.c_int32)]),
     ("rdos_engine_set_shape", C.c_int, [C.c_void_p, C.c_int32, C.c_int32, C.c_int32, C.c_int32]),
     ("rdos_engine_set_profiling", C.c_int, [C.c_void_p, C.c_int]),
+    ("rdos_engine_work_counts", C.c_int, [C.c_void_p, _P(C.c_int64), _P(C.c_int64)]),
     ("rdos_engine_kernel_times", C.c_int, [C.c_void_p, _P(C.c_double), _P(C.c_int64), _P(C.c_double),
                                            _P(C.c_int64)]),
     ("rdos_bandwidth_probe", C.c_int, [C.c_int, C.c_size_t, C.c_int, _P(C.c_double)]),
@@ -325,6 +326,12 @@ def rdos_engine_kernel_times(engine):
     b, d = C.c_int64(), C.c_int64()
     _check(lib().rdos_engine_kernel_times(engine, C.byref(a), C.byref(b), C.byref(c), C.byref(d)), engine, True)
     return dict(scan_ms=a.value, scan_launches=b.value, update_ms=c.value, update_launches=d.value)
+
+
+def rdos_engine_work_counts(engine):
+    a, b = C.c_int64(), C.c_int64()
+    _check(lib().rdos_engine_work_counts(engine, C.byref(a), C.byref(b)), engine, True)
+    return dict(tets=a.value, additions=b.value)
 
 
 def rdos_tune_split_threshold(device: int = 0, n_max: int = 48):

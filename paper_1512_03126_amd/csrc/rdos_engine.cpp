@@ -118,6 +118,7 @@ struct rdos_engine {
     std::vector<hipEvent_t> kev;
     double scan_ms = 0.0, update_ms = 0.0;
     int64_t scan_n = 0, update_n = 0;
+    unsigned long long *d_work = nullptr;  // [2] tets updated, count additions (timing pass only)
 
     // stats
     int64_t launches = 0;
@@ -436,6 +437,8 @@ void worker_main(rdos_engine *e)
             fail_slots(e);
             break;
         }
+        // the timing pass launches directly and tallies its work; captured graphs never do
+        e->queue.work = e->queue2.work = timed ? e->d_work : nullptr;
         if (timed) {
             bool ok = true;
             while (ok && (int32_t)e->kev.size() < 2 * sh.chunk + 1) {
@@ -679,9 +682,35 @@ rdos_status rdos_engine_set_profiling(rdos_engine *e, int on)
 {
     if (!e) return RDOS_EINVAL;
     std::lock_guard<std::mutex> g(e->mu);
+    if (on && !e->d_work) {
+        hipError_t err;
+        {
+            std::lock_guard<std::mutex> dg(device_api_mutex());
+            err = hipMalloc(&e->d_work, 2 * sizeof(unsigned long long));
+        }
+        if (err != hipSuccess) return efail(e, RDOS_ENOMEM, "work counters: %s", hipGetErrorString(err));
+    }
+    if (on) {
+        ENGINE_HIP(e, hipMemsetAsync(e->d_work, 0, 2 * sizeof(unsigned long long), e->stream), "clear work counters");
+        ENGINE_HIP(e, hipStreamSynchronize(e->stream), "clear work counters");
+    }
     e->profiling = on != 0;
     e->scan_ms = e->update_ms = 0.0;
     e->scan_n = e->update_n = 0;
+    return RDOS_OK;
+}
+
+rdos_status rdos_engine_work_counts(rdos_engine *e, int64_t *tets, int64_t *additions)
+{
+    if (!e) return RDOS_EINVAL;
+    std::lock_guard<std::mutex> g(e->mu);
+    unsigned long long w[2] = {0, 0};
+    if (e->d_work) {
+        ENGINE_HIP(e, hipMemcpyAsync(w, e->d_work, sizeof w, hipMemcpyDeviceToHost, e->stream), "read work counters");
+        ENGINE_HIP(e, hipStreamSynchronize(e->stream), "read work counters");
+    }
+    if (tets) *tets = (int64_t)w[0];
+    if (additions) *additions = (int64_t)w[1];
     return RDOS_OK;
 }
 
@@ -806,7 +835,7 @@ void rdos_engine_destroy(rdos_engine *e)
         rdos_destroy(kv.second.sim);
     }
     if (e->graph) (void)hipGraphExecDestroy(e->graph);
-    void *p[] = {e->d_sims, e->d_tiles};
+    void *p[] = {e->d_sims, e->d_tiles, e->d_work};
     for (void *q : p)
         if (q) (void)hipFree(q);
     free_queue(&e->queue);

@@ -117,6 +117,7 @@ struct QueueView {
     int64_t qcap;       // allocated entries per count row
     int32_t species;    // allocated count rows
     int32_t scaled;     // some simulation of the work list uses transfer form 1 (picks the update kernel)
+    unsigned long long *work;  // null, or [2] device totals the update kernel adds to: tets, count additions
 };
 constexpr int kMaxSegments = 1024;
 constexpr int kLenStride = 32;  // 128 bytes between segment lengths: no two share a line

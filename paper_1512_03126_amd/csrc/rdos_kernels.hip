@@ -269,6 +269,9 @@ hipError_t launch_tau_select(const MeshRec *mesh, int32_t T, const double *D, in
 // ---------------------------------------------------------------------------
 // Per-lane working state lives in LDS slots with a stride of kBlock between
 // species, so species can be indexed at run time without private memory.
+// per-block tallies of the update kernel in the timing pass (its queue's `work` set)
+__shared__ uint32_t block_tets, block_adds;
+
 struct LaneState {
     int32_t *N;     // counts during the period
     double *occ;    // occupancy integral since the start of the period
@@ -307,7 +310,7 @@ __device__ __forceinline__ double propensity(const DevSim &sm, int q, const Lane
 template <bool ANY_SCALED>
 __device__ __forceinline__ void update_tet(const DevSim &sm, int32_t t, int64_t period, double tau_k,
                                            uint32_t key1, int32_t *__restrict__ nxt, int32_t Tp,
-                                           uint8_t *__restrict__ mnxt, const LaneState &ls)
+                                           uint8_t *__restrict__ mnxt, const LaneState &ls, bool tally)
 {
     const int S = sm.S;
     const int R = sm.R;
@@ -376,13 +379,21 @@ __device__ __forceinline__ void update_tet(const DevSim &sm, int32_t t, int64_t 
     // Step 3, per diffusing species: mean occupancy (eq. 2), stochastic
     // rounding to an integer population, n = binomial(Nbar, zeta) (eq. 3)
     // limited to the molecules present, then the multinomial split.
+    // Each lane walks only the species its tet holds (lowest first), so the
+    // wavefront runs as many rounds as its busiest lane has species, not S;
+    // every species draws from its own stream, so the order is immaterial.
     int32_t nb[4];
     double w[4];
     bool have_faces = false;
     double g = 0.0;
-    for (int s = 0; s < S; ++s) {
+    uint32_t present = 0;
+    for (int s = 0; s < S; ++s)
+        if (ls.n(s) > 0) present |= 1u << s;
+    while (present) {
+        const int s = __builtin_ctz(present);
+        present &= present - 1u;
         const int32_t Ns = ls.n(s);
-        if (((sm.diff_mask >> s) & 1u) && Ns > 0) {  // Ns == 0: n = min(binomial(.), 0) = 0
+        if ((sm.diff_mask >> s) & 1u) {  // Ns == 0 never gets here: n = min(binomial(.), 0) = 0
             const bool hit = ((touched >> s) & 1u) && !sm.first_order;
             const double nbar = hit ? (ls.occ[s * kBlock] + (double)Ns * (tau_k - ls.last[s * kBlock])) / tau_k
                                     : (double)Ns;
@@ -435,6 +446,7 @@ __device__ __forceinline__ void update_tet(const DevSim &sm, int32_t t, int64_t 
                     if (out[f] > 0) {
                         atomicAdd(&nxt[(uint32_t)(s * Tp + nb[f])], (int32_t)out[f]);
                         mnxt[(uint32_t)(s * sm.mstride + (nb[f] >> 2))] = 1;
+                        if (tally) atomicAdd(&block_adds, 1u);
                     }
                 ls.n(s) = Ns - (int32_t)n;
             }
@@ -442,6 +454,7 @@ __device__ __forceinline__ void update_tet(const DevSim &sm, int32_t t, int64_t 
         if (ls.n(s) > 0) {  // the molecules that stay
             atomicAdd(&nxt[(uint32_t)(s * Tp + t)], ls.n(s));
             mnxt[(uint32_t)(s * sm.mstride + (t >> 2))] = 1;
+            if (tally) atomicAdd(&block_adds, 1u);
         }
     }
 }
@@ -472,6 +485,7 @@ struct Queue {
     int32_t *counts;  // [max species][qcap]
     int32_t *len;     // [2][kMaxSegments] * kLenStride
     const WorkHeader *hdr;
+    unsigned long long *work;  // null, or [2] totals of the timing pass: tets updated, count additions
 };
 
 // Raw buffer resource word 3 for gfx950 (untyped 32-bit data) and the cache
@@ -610,21 +624,47 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3))) voi
     const int32_t seg = blockIdx.x % kMaxSegments;   // the grid is kMaxSegments * blocks-per-segment
     const int32_t per_seg = max(1, (int32_t)(gridDim.x / kMaxSegments));
     const int32_t part = blockIdx.x / kMaxSegments;
-    if (seg >= h.nseg || part >= per_seg) return;
+    if (seg >= h.nseg || part >= per_seg) return;  // uniform over the block
+    const bool tally = q.work != nullptr;
+    if (tally) {
+        if (threadIdx.x == 0) block_tets = block_adds = 0;
+        __syncthreads();
+    }
     const int32_t n = min(q.len[(qsel * kMaxSegments + seg) * kLenStride], h.seg_cap);
     for (int32_t i = part * kBlock + threadIdx.x; i < n; i += per_seg * kBlock) {
+        if (tally) atomicAdd(&block_tets, 1u);
         const int64_t idx = (int64_t)seg * h.seg_cap + i;
         const int32_t entry = q.tet[idx];
         const Tile tile = tiles[h.tile0 + entry / kTetsPerTile];
-        const DevSim &sm = sims[tile.sim];
-        const int64_t period = sm.step0 + iter;
-        const double tau_k = period == partial ? tau_last : sm.tau;
-        const int64_t Tp = ((int64_t)sm.T + 3) & ~(int64_t)3;
-        const int64_t base = (int64_t)tile.realization * sm.S * Tp;
-        for (int s = 0; s < sm.S; ++s) ls.n(s) = q.counts[s * h.qcap + idx];
-        update_tet<ANY_SCALED>(sm, tile.tet0 + entry % kTetsPerTile, period, tau_k, sm.key1 ^ (uint32_t)tile.realization,
-                   sm.buf[(period + 1) & 1] + base, (int32_t)Tp,
-                   sm.mask[(period + 1) & 1] + (int64_t)tile.realization * sm.S * sm.mstride, ls);
+        // lanes of one simulation run together with a wavefront-uniform
+        // descriptor (one round when the wavefront holds one simulation);
+        // descriptors do not change during a launch, so they are read as
+        // constant memory, which lets the uniform reads be scalar loads
+        using ConstSim = const __attribute__((address_space(4))) DevSim;
+        for (uint64_t todo = __ballot(1); todo;) {
+            const int32_t first = __builtin_amdgcn_readlane(tile.sim, (int32_t)__builtin_ctzll(todo));
+            // branch on the lane's ballot bit, not on the equality, so that the
+            // compiler cannot put the lane's own index in place of `first`
+            const uint64_t same = __ballot(tile.sim == first);
+            todo &= ~same;
+            if (!((same >> __lane_id()) & 1ull)) continue;
+            const DevSim &sm = *(const DevSim *)((ConstSim *)sims + first);
+            const int64_t period = sm.step0 + iter;
+            const double tau_k = period == partial ? tau_last : sm.tau;
+            const int64_t Tp = ((int64_t)sm.T + 3) & ~(int64_t)3;
+            const int64_t base = (int64_t)tile.realization * sm.S * Tp;
+            for (int s = 0; s < sm.S; ++s) ls.n(s) = q.counts[s * h.qcap + idx];
+            update_tet<ANY_SCALED>(sm, tile.tet0 + entry % kTetsPerTile, period, tau_k, sm.key1 ^ (uint32_t)tile.realization,
+                       sm.buf[(period + 1) & 1] + base, (int32_t)Tp,
+                       sm.mask[(period + 1) & 1] + (int64_t)tile.realization * sm.S * sm.mstride, ls, tally);
+        }
+    }
+    if (tally) {
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            atomicAdd(&q.work[0], (unsigned long long)block_tets);
+            atomicAdd(&q.work[1], (unsigned long long)block_adds);
+        }
     }
 }
 
@@ -632,7 +672,7 @@ hipError_t launch_scan(const DevSim *sims, const Tile *tiles, int64_t iter, cons
                        int32_t scan_grid, hipStream_t st)
 {
     if (scan_grid <= 0) return hipErrorInvalidValue;
-    const Queue q{qv.tet, qv.counts, qv.len, qv.hdr};
+    const Queue q{qv.tet, qv.counts, qv.len, qv.hdr, qv.work};
     // register arrays sized for the largest species count the queue holds
     if (qv.species <= 2)
         scan_kernel<2><<<scan_grid, kBlock, 0, st>>>(sims, tiles, iter, q, qsel);
@@ -648,7 +688,7 @@ hipError_t launch_scan(const DevSim *sims, const Tile *tiles, int64_t iter, cons
 hipError_t launch_update(const DevSim *sims, const Tile *tiles, int64_t iter, int64_t partial, double tau_last,
                          const QueueView &qv, int32_t qsel, int32_t blocks_per_segment, hipStream_t st)
 {
-    const Queue q{qv.tet, qv.counts, qv.len, qv.hdr};
+    const Queue q{qv.tet, qv.counts, qv.len, qv.hdr, qv.work};
     const int32_t bps = blocks_per_segment > 0 ? blocks_per_segment : 1;
     if (qv.scaled)
         update_kernel<true><<<kMaxSegments * bps, kBlock, 0, st>>>(sims, tiles, q, qsel, iter, partial, tau_last);

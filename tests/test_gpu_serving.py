@@ -117,3 +117,45 @@ def test_two_chains_survive_slot_changes(orc):
     P.rdos_engine_destroy(e)
     for m, n, got in zip(reqs, periods, mixed):
         np.testing.assert_array_equal(run_oracle(orc, m, n), got)
+
+
+def test_timing_pass_counts_work(orc):
+    """The timing pass launches the kernels directly, tallies the update
+    kernel's work on the device and leaves results unchanged: the tets it
+    updated are, in every period, the tet-realizations holding molecules at
+    the start of the period (all of them under a reaction without reactants),
+    and every count that is non-zero at the end of a period came from at least
+    one of its additions."""
+    import paper_1512_03126_amd as P
+
+    m = small_request(41)
+    n = 24
+    note(f"timing pass work counters: {m.n_tets} tets, {m.n_species} species, {n} periods")
+    rn = W.reaction_arrays(m.reactions)[0]
+    o = orc.OracleSim(m.xyz, m.tets, m.D, m.reactions, seed=m.seed)
+    for q in range(m.n_species):
+        o.set_counts(q, m.init[0, q])
+    tets = nnz_end = 0
+    for _ in range(n):
+        c = o.get_counts()
+        tets += m.n_tets if (rn == 0).any() else int((c != 0).any(axis=0).sum())
+        o.run_steps(1)
+        nnz_end += int((o.get_counts() != 0).sum())
+    e = P.rdos_engine_create(0, 0)
+    P.rdos_engine_set_profiling(e, True)
+    s = P.Simulation(m.xyz, m.tets, m.D, m.reactions, seed=m.seed, tau_scale=None)
+    for q in range(m.n_species):
+        s.set_counts(q, m.init[0, q])
+    t = P.rdos_engine_submit(e, s.h, n, 1.0)
+    P.rdos_engine_drain(e)
+    P.rdos_engine_release(e, t)
+    kt = P.rdos_engine_kernel_times(e)
+    work = P.rdos_engine_work_counts(e)
+    P.rdos_engine_destroy(e)
+    got = s.get_counts()
+    s.close()
+    np.testing.assert_array_equal(o.get_counts(), got)
+    # whole chunks are launched; periods past a request's end update nothing
+    assert kt["update_launches"] == kt["scan_launches"] >= n
+    assert work["tets"] == tets
+    assert nnz_end <= work["additions"] <= 5 * m.n_species * tets
