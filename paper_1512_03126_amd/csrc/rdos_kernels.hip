@@ -398,7 +398,7 @@ __device__ __forceinline__ void update_tet(const DevSim &sm, int32_t t, int64_t 
             const double nbar = hit ? (ls.occ[s * kBlock] + (double)Ns * (tau_k - ls.last[s * kBlock])) / tau_k
                                     : (double)Ns;
             Stream rng(sm.key0, key1, (uint32_t)s, (uint32_t)t, period32);
-            int64_t ni = (int64_t)floor(nbar);
+            int32_t ni = (int32_t)floor(nbar);
             const double frac = nbar - (double)ni;
             if (frac > 0.0 && rng.uniform() < frac) ni += 1;
             if (!have_faces) {
@@ -420,11 +420,11 @@ __device__ __forceinline__ void update_tet(const DevSim &sm, int32_t t, int64_t 
             // present split as in Step 3.3.  The second form is compiled only
             // into the kernel instance launched when some simulation uses it,
             // so the first keeps its registers.
-            int64_t out[4];
-            int64_t n;
+            int32_t out[4];
+            int32_t n;
             if constexpr (ANY_SCALED) {
                 bool scaled = sm.transfer_form == 1;
-                int64_t pop = ni;
+                int32_t pop = ni;
                 if (!scaled) {
                     pop = binomial(ni, zeta, rng);
                     if (pop > Ns) pop = Ns;
@@ -608,15 +608,18 @@ __global__ __launch_bounds__(kBlock) void scan_kernel(const DevSim *__restrict__
     }
 }
 
-// three wavefronts per SIMD: the register budget that keeps the samplers spill-free
-template <bool ANY_SCALED>
-__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3))) void update_kernel(
-    const DevSim *__restrict__ sims, const Tile *__restrict__ tiles, Queue q, int32_t qsel, int64_t iter,
-    int64_t partial, double tau_last)
+// Per-lane state for up to KS species in LDS (20 KS bytes per lane).  With
+// KS = 4 and the default transfer form the kernel fits 128 VGPRs without
+// spilling, and the LDS allows it, so it runs four wavefronts per SIMD;
+// the other instances keep the register budget of three.
+template <bool ANY_SCALED, int KS>
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(KS <= 4 && !ANY_SCALED ? 4 : 3))) void
+update_kernel(const DevSim *__restrict__ sims, const Tile *__restrict__ tiles, Queue q, int32_t qsel, int64_t iter,
+              int64_t partial, double tau_last)
 {
-    __shared__ double occ[kMaxSpecies * kBlock];
-    __shared__ double last[kMaxSpecies * kBlock];
-    __shared__ int32_t counts[kMaxSpecies * kBlock];
+    __shared__ double occ[KS * kBlock];
+    __shared__ double last[KS * kBlock];
+    __shared__ int32_t counts[KS * kBlock];
     const LaneState ls{counts + threadIdx.x, occ + threadIdx.x, last + threadIdx.x};
     if (blockIdx.x == 0)
         for (int k = threadIdx.x; k < kMaxSegments; k += kBlock) q.len[((qsel ^ 1) * kMaxSegments + k) * kLenStride] = 0;
@@ -690,10 +693,19 @@ hipError_t launch_update(const DevSim *sims, const Tile *tiles, int64_t iter, in
 {
     const Queue q{qv.tet, qv.counts, qv.len, qv.hdr, qv.work};
     const int32_t bps = blocks_per_segment > 0 ? blocks_per_segment : 1;
-    if (qv.scaled)
-        update_kernel<true><<<kMaxSegments * bps, kBlock, 0, st>>>(sims, tiles, q, qsel, iter, partial, tau_last);
-    else
-        update_kernel<false><<<kMaxSegments * bps, kBlock, 0, st>>>(sims, tiles, q, qsel, iter, partial, tau_last);
+    const dim3 grid(kMaxSegments * bps);
+    // the queue's species rows bound the species of every simulation it serves
+    if (qv.species <= 4) {
+        if (qv.scaled)
+            update_kernel<true, 4><<<grid, kBlock, 0, st>>>(sims, tiles, q, qsel, iter, partial, tau_last);
+        else
+            update_kernel<false, 4><<<grid, kBlock, 0, st>>>(sims, tiles, q, qsel, iter, partial, tau_last);
+    } else {
+        if (qv.scaled)
+            update_kernel<true, kMaxSpecies><<<grid, kBlock, 0, st>>>(sims, tiles, q, qsel, iter, partial, tau_last);
+        else
+            update_kernel<false, kMaxSpecies><<<grid, kBlock, 0, st>>>(sims, tiles, q, qsel, iter, partial, tau_last);
+    }
     return hipGetLastError();
 }
 
@@ -747,8 +759,8 @@ __global__ __launch_bounds__(256) void split_cost_kernel(int64_t n, int32_t reps
     int64_t acc = 0;
     for (int32_t r = 0; r < reps; ++r) {
         Stream rng(0x2545F491u, 0x9E3779B9u, 0x80000001u, lane, (uint32_t)r);
-        int64_t out[4];
-        split_over_faces(n, nbr, w, ONE_BY_ONE ? (int32_t)(n + 1) : 1, rng, out);
+        int32_t out[4];
+        split_over_faces((int32_t)n, nbr, w, ONE_BY_ONE ? (int32_t)(n + 1) : 1, rng, out);
         acc += out[0] + 2 * out[1] + 3 * out[2] + 4 * out[3];
     }
     sink[lane] = acc;

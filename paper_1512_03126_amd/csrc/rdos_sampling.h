@@ -37,26 +37,22 @@ __device__ __forceinline__ uint4 philox4x32_10(uint4 x, uint32_t k0, uint32_t k1
 // One counter-based stream: counter (draw block, stream id, tet, period),
 // key (k0, k1).  Draw j takes the block j/2 and, within it, words (x, y)
 // for even j or (z, w) for odd j, mapped to a 53-bit uniform in [0, 1).
+// Draws are taken in order, so a new block is generated exactly at even j.
 struct Stream {
     uint32_t k0, k1, id, tet, period;
     uint32_t j;
-    uint32_t blk;
     uint4 words;
 
     __device__ __forceinline__ Stream(uint32_t key0, uint32_t key1, uint32_t stream_id,
                                       uint32_t tet_id, uint32_t period_id)
         : k0(key0), k1(key1), id(stream_id), tet(tet_id), period(period_id), j(0),
-          blk(0xFFFFFFFFu), words(make_uint4(0, 0, 0, 0))
+          words(make_uint4(0, 0, 0, 0))
     {
     }
 
     __device__ __forceinline__ double uniform()
     {
-        const uint32_t b = j >> 1;
-        if (b != blk) {
-            words = philox4x32_10(make_uint4(b, id, tet, period), k0, k1);
-            blk = b;
-        }
+        if (!(j & 1u)) words = philox4x32_10(make_uint4(j >> 1, id, tet, period), k0, k1);
         const uint32_t hi = (j & 1u) ? words.z : words.x;
         const uint32_t lo = (j & 1u) ? words.w : words.y;
         ++j;
@@ -109,7 +105,7 @@ __device__ __forceinline__ double log_basic(double x)
 //         otherwise;
 // p > 1/2 is sampled as n - Binomial(n, 1 - p).
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ double pow_by_squaring(double q, int64_t n)
+__device__ __forceinline__ double pow_by_squaring(double q, int32_t n)
 {
     double acc = 1.0;
     double sq = q;
@@ -121,7 +117,7 @@ __device__ __forceinline__ double pow_by_squaring(double q, int64_t n)
     return acc;
 }
 
-__device__ inline int64_t binomial_inversion(int64_t n, double p, Stream &rng)
+__device__ inline int32_t binomial_inversion(int32_t n, double p, Stream &rng)
 {
     const double q = 1.0 - p;
     const double odds = p / q;
@@ -130,7 +126,7 @@ __device__ inline int64_t binomial_inversion(int64_t n, double p, Stream &rng)
     for (;;) {
         double u = rng.uniform();
         double pk = p_zero;
-        int64_t x = 0;
+        int32_t x = 0;
         bool restart = false;
         while (u > pk) {
             u = u - pk;
@@ -154,7 +150,7 @@ __constant__ const double kStirlingExact[10] = {
     0x1.2f4871b12ab64p-7, 0x1.10f9d4c0743a7p-7,
 };
 
-__device__ __forceinline__ double stirling_tail(int64_t k)
+__device__ __forceinline__ double stirling_tail(int32_t k)
 {
     if (k < 10) return kStirlingExact[k];
     const double v = 1.0 / (double)(k + 1);
@@ -162,30 +158,33 @@ __device__ __forceinline__ double stirling_tail(int64_t k)
     return (1.0 / 12.0 - (1.0 / 360.0 - (1.0 / 1260.0) * v2) * v2) * v;
 }
 
-__device__ inline int64_t binomial_btrd(int64_t n, double p, Stream &rng)
+// The set-up values are recomputed on every pass of the rejection loop
+// instead of being held across it: `carry` is +0 after a rejected pass (0
+// times a finite uniform), so p + carry == p and every value is bit for bit
+// the same, but the compiler cannot hoist them out of the loop, which keeps
+// them out of the registers the callers need.  Most draws take one pass.
+__device__ inline int32_t binomial_btrd(int32_t n, double p_in, Stream &rng)
 {
     const double nd = (double)n;
-    const double q = 1.0 - p;
-    const double mode = floor((nd + 1.0) * p);
-    const double r = p / q;
-    const double nr = (nd + 1.0) * r;
-    const double npq = (nd * p) * q;
-    const double spq = sqrt(npq);
-    const double b = 1.15 + 2.53 * spq;
-    const double a = (-0.0873 + 0.0248 * b) + 0.01 * p;
-    const double c = nd * p + 0.5;
-    const double alpha = (2.83 + 5.1 / b) * spq;
-    const double vr = 0.92 - 4.2 / b;
-    const double urvr = 0.86 * vr;
-
+    double carry = 0.0;
     for (;;) {
+        const double p = p_in + carry;
+        const double q = 1.0 - p;
+        const double npq = (nd * p) * q;
+        const double spq = sqrt(npq);
+        const double b = 1.15 + 2.53 * spq;
+        const double a = (-0.0873 + 0.0248 * b) + 0.01 * p;
+        const double c = nd * p + 0.5;
+        const double vr = 0.92 - 4.2 / b;
+        const double urvr = 0.86 * vr;
         double v = rng.uniform();
+        carry = 0.0 * v;
         double u;
         if (v <= urvr) {  // inside the box: accept at once
             u = v / vr - 0.43;
             const double kd = floor(((2.0 * a) / (0.5 - fabs(u)) + b) * u + c);
             if (kd < 0.0 || kd > nd) continue;
-            return (int64_t)kd;
+            return (int32_t)kd;
         }
         if (v >= vr) {
             u = rng.uniform() - 0.5;
@@ -197,10 +196,14 @@ __device__ inline int64_t binomial_btrd(int64_t n, double p, Stream &rng)
         const double us = 0.5 - fabs(u);
         const double kd = floor(((2.0 * a) / us + b) * u + c);
         if (kd < 0.0 || kd > nd) continue;
+        const double alpha = (2.83 + 5.1 / b) * spq;
         v = v * alpha / (a / (us * us) + b);
+        const double mode = floor((nd + 1.0) * p);
+        const double r = p / q;
         const double km = fabs(kd - mode);
         if (km <= 15.0) {
             // ratio f(k)/f(mode) by the recurrence f(i)/f(i-1) = nr/i - r
+            const double nr = (nd + 1.0) * r;
             double f = 1.0;
             if (mode < kd) {
                 double i = mode;
@@ -215,15 +218,15 @@ __device__ inline int64_t binomial_btrd(int64_t n, double p, Stream &rng)
                     v = v * (nr / i - r);
                 } while (i != mode);
             }
-            if (v <= f) return (int64_t)kd;
+            if (v <= f) return (int32_t)kd;
             continue;
         }
         v = log_basic(v);
         const double rho = (km / npq) * (((km / 3.0 + 0.625) * km + 1.0 / 6.0) / npq + 0.5);
         const double t = -(km * km) / (2.0 * npq);
-        if (v < t - rho) return (int64_t)kd;
+        if (v < t - rho) return (int32_t)kd;
         if (v > t + rho) continue;
-        const int64_t m_i = (int64_t)mode, k_i = (int64_t)kd;
+        const int32_t m_i = (int32_t)mode, k_i = (int32_t)kd;
         const double nm = nd - mode + 1.0;
         const double h = (mode + 0.5) * log_basic((mode + 1.0) / (r * nm)) + stirling_tail(m_i) +
                          stirling_tail(n - m_i);
@@ -234,13 +237,13 @@ __device__ inline int64_t binomial_btrd(int64_t n, double p, Stream &rng)
     }
 }
 
-__device__ inline int64_t binomial(int64_t n, double p, Stream &rng)
+__device__ inline int32_t binomial(int32_t n, double p, Stream &rng)
 {
     if (n <= 0 || p <= 0.0) return 0;
     if (p >= 1.0) return n;
     const bool reflect = p > 0.5;
     const double pp = reflect ? 1.0 - p : p;
-    const int64_t x = ((double)n * pp < 10.0) ? binomial_inversion(n, pp, rng) : binomial_btrd(n, pp, rng);
+    const int32_t x = ((double)n * pp < 10.0) ? binomial_inversion(n, pp, rng) : binomial_btrd(n, pp, rng);
     return reflect ? n - x : x;
 }
 
@@ -252,8 +255,8 @@ __device__ inline int64_t binomial(int64_t n, double p, Stream &rng)
 // n_i = Binomial(n - sum_{j<i} n_j, w_i / (1 - sum_{j<i} w_j)) face by face,
 // the last interior face taking what is left.
 // ---------------------------------------------------------------------------
-__device__ inline void split_over_faces(int64_t n, const int32_t nbr[4], const double w[4], int32_t threshold,
-                                        Stream &rng, int64_t out[4])
+__device__ inline void split_over_faces(int32_t n, const int32_t nbr[4], const double w[4], int32_t threshold,
+                                        Stream &rng, int32_t out[4])
 {
     out[0] = out[1] = out[2] = out[3] = 0;
     if (n <= 0) return;
@@ -272,7 +275,7 @@ __device__ inline void split_over_faces(int64_t n, const int32_t nbr[4], const d
         return;
     }
     if (n < threshold) {
-        for (int64_t i = 0; i < n; ++i) {
+        for (int32_t i = 0; i < n; ++i) {
             const double u = rng.uniform();
             double edge = 0.0;
             int dest = last;
@@ -289,7 +292,7 @@ __device__ inline void split_over_faces(int64_t n, const int32_t nbr[4], const d
         }
         return;
     }
-    int64_t left = n;
+    int32_t left = n;
     double taken = 0.0;
 #pragma unroll
     for (int f = 0; f < 4; ++f) {
@@ -301,7 +304,7 @@ __device__ inline void split_over_faces(int64_t n, const int32_t nbr[4], const d
         }
         double pf = w[f] / (1.0 - taken);
         if (pf > 1.0) pf = 1.0;
-        const int64_t nf = binomial(left, pf, rng);
+        const int32_t nf = binomial(left, pf, rng);
         out[f] = nf;
         left -= nf;
         taken = taken + w[f];
@@ -323,8 +326,8 @@ __device__ inline void split_over_faces(int64_t n, const int32_t nbr[4], const d
 // 1.0 * w == w exactly, so the first form is bit-identical to the plain
 // weights.  Returns the molecules that leave.
 // ---------------------------------------------------------------------------
-__device__ inline int64_t split_faces(int64_t n, const int32_t nbr[4], const double w[4], double z, bool scaled,
-                                      int32_t threshold, Stream &rng, int64_t out[4])
+__device__ inline int32_t split_faces(int32_t n, const int32_t nbr[4], const double w[4], double z, bool scaled,
+                                      int32_t threshold, Stream &rng, int32_t out[4])
 {
     out[0] = out[1] = out[2] = out[3] = 0;
     if (n <= 0) return 0;
@@ -343,9 +346,9 @@ __device__ inline int64_t split_faces(int64_t n, const int32_t nbr[4], const dou
         return n;
     }
     const int open = scaled ? -1 : last;  // where a molecule goes when no face's interval holds its draw
-    int64_t moved = 0;
+    int32_t moved = 0;
     if (n < threshold) {
-        for (int64_t i = 0; i < n; ++i) {
+        for (int32_t i = 0; i < n; ++i) {
             const double u = rng.uniform();
             double edge = 0.0;
             int dest = open;
@@ -363,7 +366,7 @@ __device__ inline int64_t split_faces(int64_t n, const int32_t nbr[4], const dou
         }
         return moved;
     }
-    int64_t left = n;
+    int32_t left = n;
     double taken = 0.0;
 #pragma unroll
     for (int f = 0; f < 4; ++f) {
@@ -376,7 +379,7 @@ __device__ inline int64_t split_faces(int64_t n, const int32_t nbr[4], const dou
         }
         double pf = (z * w[f]) / (1.0 - taken);
         if (pf > 1.0) pf = 1.0;
-        const int64_t nf = binomial(left, pf, rng);
+        const int32_t nf = binomial(left, pf, rng);
         out[f] = nf;
         moved += nf;
         left -= nf;
