@@ -26,6 +26,17 @@ namespace rdos {
 
 typedef int32_t v4i __attribute__((ext_vector_type(4)));
 
+// A pointer into device (global) memory.  Accesses through generic pointers
+// become flat instructions, which also count against the scalar-load wait
+// counter, so a wait for a scalar load would wait for them too.
+template <typename T>
+using gptr = __attribute__((address_space(1))) T *;
+template <typename T>
+__device__ __forceinline__ gptr<T> global(T *p)
+{
+    return (gptr<T>)p;
+}
+
 // ---------------------------------------------------------------------------
 // Set-up (Sec. II.A): volumes, face areas, barycentres, then per face
 // r_f = A_f / (V delta_f), g = sum_f r_f, w_f = r_f / g.
@@ -522,19 +533,22 @@ __global__ __launch_bounds__(kBlock) void scan_kernel(const DevSim *__restrict__
         // load (rows of the map are padded to 16 bytes, t0 / 4 is a multiple
         // of 4); only flagged (group, species) vectors are read, and the
         // bytes are cleared for the next use of this buffer
-        uint8_t *mrow = sm.mask[period & 1] + (int64_t)tile.realization * S * sm.mstride + (t0 >> 2);
+        // (all species are loaded before any is cleared, so the loads are in
+        // flight together)
+        gptr<uint8_t> mrow = global(sm.mask[period & 1]) + (int64_t)tile.realization * S * sm.mstride + (t0 >> 2);
         uint32_t mb[MAXS];
 #pragma unroll
         for (int s = 0; s < MAXS; ++s) {
             mb[s] = 0u;
-            if (s < S && valid > 0) {
-                uint32_t *mk = reinterpret_cast<uint32_t *>(mrow + (int64_t)s * sm.mstride);
-                mb[s] = *mk;
-                if (mb[s] != 0u) *mk = 0u;
-            }
+            if (s < S && valid > 0) mb[s] = *(gptr<const uint32_t>)(mrow + (int64_t)s * sm.mstride);
         }
+#pragma unroll
+        for (int s = 0; s < MAXS; ++s)
+            if (mb[s] != 0u) *(gptr<uint32_t>)(mrow + (int64_t)s * sm.mstride) = 0u;
         const int64_t Tp = ((int64_t)sm.T + 3) & ~(int64_t)3;
         int32_t *cur = sm.buf[period & 1] + (int64_t)tile.realization * S * Tp;
+        const gptr<int32_t> qtet = global(q.tet);
+        const gptr<int32_t> qcnt = global(q.counts);
         // the realization's counts as a buffer resource (bounds-checked by
         // the hardware: loads past the block return zero)
         const __amdgpu_buffer_rsrc_t rs =
@@ -586,13 +600,13 @@ __global__ __launch_bounds__(kBlock) void scan_kernel(const DevSim *__restrict__
 #pragma unroll
             for (int b = 0; b < 4; ++b) {
                 if (!((bits >> (4 * g + b)) & 1u)) continue;
-                q.tet[idx] = ti * kTetsPerTile + off + 4 * g + b;
+                qtet[idx] = ti * kTetsPerTile + off + 4 * g + b;
 #pragma unroll
                 for (int s = 0; s < MAXS; ++s) {
                     if (s >= S) break;
                     const int32_t cv = b == 0 ? c[g][s].x : b == 1 ? c[g][s].y : b == 2 ? c[g][s].z : c[g][s].w;
                     if (cv < 0) atomicOr(sm.flags, 1);  // wrapped by an overflowing atomic add
-                    q.counts[s * h.qcap + idx] = cv;
+                    qcnt[s * h.qcap + idx] = cv;
                 }
                 ++idx;
             }
@@ -604,7 +618,7 @@ __global__ __launch_bounds__(kBlock) void scan_kernel(const DevSim *__restrict__
 #pragma unroll
             for (int s = 0; s < MAXS; ++s)
                 if (s < S && (c[g][s].x | c[g][s].y | c[g][s].z | c[g][s].w) != 0)
-                    *reinterpret_cast<v4i *>(cur + s * Tp + t0 + 4 * g) = v4i{0, 0, 0, 0};
+                    *(gptr<v4i>)(global(cur) + s * Tp + t0 + 4 * g) = v4i{0, 0, 0, 0};
     }
 }
 
