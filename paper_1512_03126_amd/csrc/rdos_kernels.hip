@@ -594,6 +594,13 @@ __global__ __launch_bounds__(kBlock) void scan_kernel(const DevSim *__restrict__
             if (lane == 0) atomicOr(sm.flags, 4);
             continue;
         }
+        // a negative count was wrapped by an overflowing atomic add
+        int32_t sign = 0;
+#pragma unroll
+        for (int g = 0; g < kGroups; ++g)
+#pragma unroll
+            for (int s = 0; s < MAXS; ++s) sign |= c[g][s].x | c[g][s].y | c[g][s].z | c[g][s].w;
+        if (sign < 0) atomicOr(sm.flags, 1);
         int64_t idx = (int64_t)seg * h.seg_cap + slot + before;
 #pragma unroll
         for (int g = 0; g < kGroups; ++g) {
@@ -604,9 +611,7 @@ __global__ __launch_bounds__(kBlock) void scan_kernel(const DevSim *__restrict__
 #pragma unroll
                 for (int s = 0; s < MAXS; ++s) {
                     if (s >= S) break;
-                    const int32_t cv = b == 0 ? c[g][s].x : b == 1 ? c[g][s].y : b == 2 ? c[g][s].z : c[g][s].w;
-                    if (cv < 0) atomicOr(sm.flags, 1);  // wrapped by an overflowing atomic add
-                    qcnt[s * h.qcap + idx] = cv;
+                    qcnt[s * h.qcap + idx] = b == 0 ? c[g][s].x : b == 1 ? c[g][s].y : b == 2 ? c[g][s].z : c[g][s].w;
                 }
                 ++idx;
             }
