@@ -513,6 +513,10 @@ __global__ __launch_bounds__(kBlock) void scan_kernel(const DevSim *__restrict__
 {
     constexpr int kWaves = kBlock / 64;
     constexpr int kLaneTets = kTetsPerTile / 64;  // 16 consecutive tets, four groups of four
+    // queue entries a wavefront stages in LDS (up to four species; with more,
+    // the registers staging needs would cost a wavefront per SIMD)
+    constexpr int kStageCap = MAXS <= 4 ? 256 : 0;
+    __shared__ int32_t stage[kWaves][1 + MAXS][kStageCap > 0 ? kStageCap : 1];
     constexpr int kGroups = kLaneTets / 4;
     const int lane = threadIdx.x & 63;
     const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
@@ -601,19 +605,60 @@ __global__ __launch_bounds__(kBlock) void scan_kernel(const DevSim *__restrict__
 #pragma unroll
             for (int s = 0; s < MAXS; ++s) sign |= c[g][s].x | c[g][s].y | c[g][s].z | c[g][s].w;
         if (sign < 0) atomicOr(sm.flags, 1);
-        int64_t idx = (int64_t)seg * h.seg_cap + slot + before;
+        // Each lane puts its entries at their ranks in the wavefront's LDS
+        // rows; the rows then go out with one coalesced store per row and 64
+        // entries, where writing from the lanes takes one store instruction
+        // per tet position with a handful of lanes active in each.  A crowded
+        // tile writes from the lanes.
+        const int64_t base = (int64_t)seg * h.seg_cap + slot;
+        if (total <= kStageCap) {
+            int32_t(*st)[kStageCap > 0 ? kStageCap : 1] = stage[threadIdx.x >> 6];
+            int32_t k = before;
 #pragma unroll
-        for (int g = 0; g < kGroups; ++g) {
+            for (int g = 0; g < kGroups; ++g) {
 #pragma unroll
-            for (int b = 0; b < 4; ++b) {
-                if (!((bits >> (4 * g + b)) & 1u)) continue;
-                qtet[idx] = ti * kTetsPerTile + off + 4 * g + b;
+                for (int b = 0; b < 4; ++b) {
+                    if (!((bits >> (4 * g + b)) & 1u)) continue;
+                    st[0][k] = ti * kTetsPerTile + off + 4 * g + b;
 #pragma unroll
-                for (int s = 0; s < MAXS; ++s) {
-                    if (s >= S) break;
-                    qcnt[s * h.qcap + idx] = b == 0 ? c[g][s].x : b == 1 ? c[g][s].y : b == 2 ? c[g][s].z : c[g][s].w;
+                    for (int s = 0; s < MAXS; ++s) {
+                        if (s >= S) break;
+                        st[1 + s][k] = b == 0 ? c[g][s].x : b == 1 ? c[g][s].y : b == 2 ? c[g][s].z : c[g][s].w;
+                    }
+                    ++k;
                 }
-                ++idx;
+            }
+            // LDS operations of one wavefront complete in order; the fences
+            // keep the compiler from moving the reads above the writes (and,
+            // below, the next tile's writes above these reads)
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+            for (int32_t e = lane; e < total; e += 64) {
+                qtet[base + e] = st[0][e];
+#pragma unroll
+                for (int s = 0; s < MAXS; ++s)
+                    if (s < S) qcnt[s * h.qcap + base + e] = st[1 + s][e];
+            }
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        } else {  // a crowded tile
+            int64_t idx = base + before;
+#pragma unroll
+            for (int g = 0; g < kGroups; ++g) {
+#pragma unroll
+                for (int b = 0; b < 4; ++b) {
+                    if (!((bits >> (4 * g + b)) & 1u)) continue;
+                    qtet[idx] = ti * kTetsPerTile + off + 4 * g + b;
+#pragma unroll
+                    for (int s = 0; s < MAXS; ++s) {
+                        if (s >= S) break;
+                        qcnt[s * h.qcap + idx] =
+                            b == 0 ? c[g][s].x : b == 1 ? c[g][s].y : b == 2 ? c[g][s].z : c[g][s].w;
+                    }
+                    ++idx;
+                }
             }
         }
         // the queued molecules now live in the queue: clear their slots so
