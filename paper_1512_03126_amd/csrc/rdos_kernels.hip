@@ -512,16 +512,21 @@ __global__ __launch_bounds__(kBlock) void scan_kernel(const DevSim *__restrict__
                                                       int32_t qsel)
 {
     constexpr int kWaves = kBlock / 64;
-    constexpr int kLaneTets = kTetsPerTile / 64;  // 16 consecutive tets, four groups of four
-    // queue entries a wavefront stages in LDS (up to four species; with more,
-    // the registers staging needs would cost a wavefront per SIMD)
-    constexpr int kStageCap = MAXS <= 4 ? 256 : 0;
-    __shared__ int32_t stage[kWaves][1 + MAXS][kStageCap > 0 ? kStageCap : 1];
-    constexpr int kGroups = kLaneTets / 4;
+    constexpr int kLaneTets = kTetsPerTile / 64;   // 16 consecutive tets per lane in the map sweep
+    constexpr int kGroups = kLaneTets / 4;           // its four-tet groups
+    constexpr int kTileGroups = kTetsPerTile / 4;    // 256 groups per tile
+    // Per wavefront: the tile's flagged groups (group | species mask << 8) in
+    // tet order, and the queue entries of one chunk of 64 groups (at most 256
+    // tets) staged at their ranks.
+    __shared__ int32_t glist[kWaves][kTileGroups];
+    __shared__ int32_t stage[kWaves][1 + MAXS][kTileGroups];
     const int lane = threadIdx.x & 63;
+    const int wv = threadIdx.x >> 6;
     const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
     const WorkHeader h = *q.hdr;
     const int32_t n_waves = (int32_t)gridDim.x * kWaves;
+    const gptr<int32_t> qtet = global(q.tet);
+    const gptr<int32_t> qcnt = global(q.counts);
     // one wavefront per tile; the tile index is uniform over the wavefront
     for (int32_t ti = __builtin_amdgcn_readfirstlane((int32_t)blockIdx.x * kWaves + (int32_t)(threadIdx.x >> 6));
          ti < h.n_tiles; ti += n_waves) {
@@ -533,12 +538,10 @@ __global__ __launch_bounds__(kBlock) void scan_kernel(const DevSim *__restrict__
         const int32_t valid = tile.ntet - off;  // tets of this lane inside the tile (may be <= 0)
         const int64_t t0 = tile.tet0 + off;
         const int S = sm.S;
-        // per species, the four occupancy bytes of this lane's groups in one
-        // load (rows of the map are padded to 16 bytes, t0 / 4 is a multiple
-        // of 4); only flagged (group, species) vectors are read, and the
-        // bytes are cleared for the next use of this buffer
-        // (all species are loaded before any is cleared, so the loads are in
-        // flight together)
+        // Map sweep: per species, the four occupancy bytes of this lane's
+        // groups in one load (rows are padded to 16 bytes, t0 / 4 is a
+        // multiple of 4), all species before any is cleared, so the loads are
+        // in flight together; the bytes are cleared for the next use.
         gptr<uint8_t> mrow = global(sm.mask[period & 1]) + (int64_t)tile.realization * S * sm.mstride + (t0 >> 2);
         uint32_t mb[MAXS];
 #pragma unroll
@@ -549,126 +552,133 @@ __global__ __launch_bounds__(kBlock) void scan_kernel(const DevSim *__restrict__
 #pragma unroll
         for (int s = 0; s < MAXS; ++s)
             if (mb[s] != 0u) *(gptr<uint32_t>)(mrow + (int64_t)s * sm.mstride) = 0u;
+        // this lane's flagged groups and the species flagged in each (all of
+        // them in every group if a reaction has no reactants: every tet runs)
+        uint32_t sp[kGroups];
+        uint32_t fl = 0;
+#pragma unroll
+        for (int k = 0; k < kGroups; ++k) {
+            sp[k] = 0u;
+#pragma unroll
+            for (int s = 0; s < MAXS; ++s)
+                if (s < S && ((mb[s] >> (8 * k)) & 0xFFu) != 0u) sp[k] |= 1u << s;
+            if (sm.zeroth) sp[k] = (1u << S) - 1u;
+            if (4 * k >= valid) sp[k] = 0u;
+            if (sp[k] != 0u) fl |= 1u << k;
+        }
+        // rank the flagged groups over the wavefront (lane order, then group
+        // order: tet order) and list them in LDS
+        const uint32_t fc = (uint32_t)__popc(fl);
+        int32_t fbefore = 0, F = 0;
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            const uint64_t plane = __ballot((fc >> k) & 1u);
+            fbefore += __popcll(plane & below) << k;
+            F += __popcll(plane) << k;
+        }
+        if (F == 0) continue;  // uniform over the wavefront
+        {
+            int32_t r = fbefore;
+#pragma unroll
+            for (int k = 0; k < kGroups; ++k)
+                if (sp[k] != 0u) {
+                    glist[wv][r] = (lane * kGroups + k) | (int32_t)(sp[k] << 8);
+                    ++r;
+                }
+        }
+        // LDS operations of one wavefront complete in order; the fences keep
+        // the compiler from moving LDS reads and writes across each other
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
         const int64_t Tp = ((int64_t)sm.T + 3) & ~(int64_t)3;
         int32_t *cur = sm.buf[period & 1] + (int64_t)tile.realization * S * Tp;
-        const gptr<int32_t> qtet = global(q.tet);
-        const gptr<int32_t> qcnt = global(q.counts);
         // the realization's counts as a buffer resource (bounds-checked by
         // the hardware: loads past the block return zero)
         const __amdgpu_buffer_rsrc_t rs =
             __builtin_amdgcn_make_buffer_rsrc(cur, (short)0, (int32_t)(S * Tp * 4), kBufferWord3);
-        v4i c[kGroups][MAXS];
-        uint32_t bits = 0;  // bit 4g + b: tet t0 + 4g + b is queued
-#pragma unroll
-        for (int g = 0; g < kGroups; ++g) {
-            const bool inside = 4 * g < valid;
+        const int32_t seg = ti % h.nseg;
+        // Chunks of 64 flagged groups, one per lane: the lane reads the
+        // group's flagged count vectors, its occupied tets are ranked over the
+        // wavefront, staged at their ranks and written to the queue with one
+        // coalesced store per row; the vectors read are then cleared.
+        for (int32_t c0 = 0; c0 < F; c0 += 64) {
+            const bool act = c0 + lane < F;
+            const int32_t gl = act ? glist[wv][c0 + lane] : 0;
+            const int32_t gid = gl & 0xFF;
+            const uint32_t gsp = act ? ((uint32_t)gl >> 8) : 0u;
+            const int32_t tg = tile.tet0 + 4 * gid;  // the group's first tet
+            v4i c[MAXS];
+            uint32_t bits = 0;
 #pragma unroll
             for (int s = 0; s < MAXS; ++s) {
-                c[g][s] = v4i{0, 0, 0, 0};
-                if (s < S && inside && (sm.zeroth || ((mb[s] >> (8 * g)) & 0xFFu) != 0u))
-                    c[g][s] = __builtin_bit_cast(
-                        v4i, __builtin_amdgcn_raw_buffer_load_b128(rs, (int32_t)((s * Tp + t0 + 4 * g) * 4), 0,
-                                                                   kScanLoadPolicy));
+                c[s] = v4i{0, 0, 0, 0};
+                if ((gsp >> s) & 1u)
+                    c[s] = __builtin_bit_cast(v4i, __builtin_amdgcn_raw_buffer_load_b128(
+                                                       rs, (int32_t)((s * Tp + tg) * 4), 0, kScanLoadPolicy));
+                bits |= (uint32_t)(c[s].x != 0) | ((uint32_t)(c[s].y != 0) << 1) | ((uint32_t)(c[s].z != 0) << 2) |
+                        ((uint32_t)(c[s].w != 0) << 3);
             }
-            uint32_t gb = 0;
+            if (sm.zeroth && act) bits = 0xFu;  // a reaction without reactants: every tet runs
+            const int32_t in_group = tile.ntet - 4 * gid;
+            if (in_group < 4) bits &= in_group > 0 ? (1u << in_group) - 1u : 0u;
+            // a negative count was wrapped by an overflowing atomic add
+            int32_t sign = 0;
 #pragma unroll
-            for (int s = 0; s < MAXS; ++s)
-                gb |= (uint32_t)(c[g][s].x != 0) | ((uint32_t)(c[g][s].y != 0) << 1) |
-                      ((uint32_t)(c[g][s].z != 0) << 2) | ((uint32_t)(c[g][s].w != 0) << 3);
-            if (sm.zeroth && inside) gb = 0xFu;  // a reaction without reactants: every tet runs
-            bits |= gb << (4 * g);
-        }
-        if (valid < kLaneTets) bits &= valid > 0 ? (1u << valid) - 1u : 0u;
-        // exclusive prefix of the per-lane counts (0..16) over the wavefront,
-        // from one ballot per bit of the count
-        const uint32_t cnt = (uint32_t)__popc(bits);
-        int32_t before = 0, total = 0;
+            for (int s = 0; s < MAXS; ++s) sign |= c[s].x | c[s].y | c[s].z | c[s].w;
+            if (sign < 0) atomicOr(sm.flags, 1);
+            const uint32_t cnt = (uint32_t)__popc(bits);
+            int32_t before = 0, total = 0;
 #pragma unroll
-        for (int k = 0; k < 5; ++k) {
-            const uint64_t plane = __ballot((cnt >> k) & 1u);
-            before += __popcll(plane & below) << k;
-            total += __popcll(plane) << k;
-        }
-        if (total == 0) continue;  // uniform over the wavefront
-        const int32_t seg = ti % h.nseg;
-        int32_t slot = 0;
-        if (lane == 0) slot = atomicAdd(&q.len[(qsel * kMaxSegments + seg) * kLenStride], total);
-        slot = __shfl(slot, 0);
-        if (slot + total > h.seg_cap) {  // cannot happen when len starts at 0; never write past
-            if (lane == 0) atomicOr(sm.flags, 4);
-            continue;
-        }
-        // a negative count was wrapped by an overflowing atomic add
-        int32_t sign = 0;
-#pragma unroll
-        for (int g = 0; g < kGroups; ++g)
-#pragma unroll
-            for (int s = 0; s < MAXS; ++s) sign |= c[g][s].x | c[g][s].y | c[g][s].z | c[g][s].w;
-        if (sign < 0) atomicOr(sm.flags, 1);
-        // Each lane puts its entries at their ranks in the wavefront's LDS
-        // rows; the rows then go out with one coalesced store per row and 64
-        // entries, where writing from the lanes takes one store instruction
-        // per tet position with a handful of lanes active in each.  A crowded
-        // tile writes from the lanes.
-        const int64_t base = (int64_t)seg * h.seg_cap + slot;
-        if (total <= kStageCap) {
-            int32_t(*st)[kStageCap > 0 ? kStageCap : 1] = stage[threadIdx.x >> 6];
+            for (int k = 0; k < 3; ++k) {
+                const uint64_t plane = __ballot((cnt >> k) & 1u);
+                before += __popcll(plane & below) << k;
+                total += __popcll(plane) << k;
+            }
+            if (total == 0) continue;  // uniform; every vector read was zero
+            int32_t slot = 0;
+            if (lane == 0) slot = atomicAdd(&q.len[(qsel * kMaxSegments + seg) * kLenStride], total);
+            slot = __shfl(slot, 0);
+            if (slot + total > h.seg_cap) {  // cannot happen when len starts at 0; never write past
+                if (lane == 0) atomicOr(sm.flags, 4);
+                continue;
+            }
             int32_t k = before;
 #pragma unroll
-            for (int g = 0; g < kGroups; ++g) {
+            for (int b = 0; b < 4; ++b) {
+                if (!((bits >> b) & 1u)) continue;
+                stage[wv][0][k] = 4 * gid + b;
 #pragma unroll
-                for (int b = 0; b < 4; ++b) {
-                    if (!((bits >> (4 * g + b)) & 1u)) continue;
-                    st[0][k] = ti * kTetsPerTile + off + 4 * g + b;
-#pragma unroll
-                    for (int s = 0; s < MAXS; ++s) {
-                        if (s >= S) break;
-                        st[1 + s][k] = b == 0 ? c[g][s].x : b == 1 ? c[g][s].y : b == 2 ? c[g][s].z : c[g][s].w;
-                    }
-                    ++k;
+                for (int s = 0; s < MAXS; ++s) {
+                    if (s >= S) break;
+                    stage[wv][1 + s][k] = b == 0 ? c[s].x : b == 1 ? c[s].y : b == 2 ? c[s].z : c[s].w;
                 }
+                ++k;
             }
-            // LDS operations of one wavefront complete in order; the fences
-            // keep the compiler from moving the reads above the writes (and,
-            // below, the next tile's writes above these reads)
             __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
             __builtin_amdgcn_wave_barrier();
             __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+            const int64_t base = (int64_t)seg * h.seg_cap + slot;
             for (int32_t e = lane; e < total; e += 64) {
-                qtet[base + e] = st[0][e];
+                qtet[base + e] = ti * kTetsPerTile + stage[wv][0][e];
 #pragma unroll
                 for (int s = 0; s < MAXS; ++s)
-                    if (s < S) qcnt[s * h.qcap + base + e] = st[1 + s][e];
+                    if (s < S) qcnt[s * h.qcap + base + e] = stage[wv][1 + s][e];
             }
             __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
             __builtin_amdgcn_wave_barrier();
             __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-        } else {  // a crowded tile
-            int64_t idx = base + before;
-#pragma unroll
-            for (int g = 0; g < kGroups; ++g) {
-#pragma unroll
-                for (int b = 0; b < 4; ++b) {
-                    if (!((bits >> (4 * g + b)) & 1u)) continue;
-                    qtet[idx] = ti * kTetsPerTile + off + 4 * g + b;
-#pragma unroll
-                    for (int s = 0; s < MAXS; ++s) {
-                        if (s >= S) break;
-                        qcnt[s * h.qcap + idx] =
-                            b == 0 ? c[g][s].x : b == 1 ? c[g][s].y : b == 2 ? c[g][s].z : c[g][s].w;
-                    }
-                    ++idx;
-                }
-            }
-        }
-        // the queued molecules now live in the queue: clear their slots so
-        // this buffer is all zero when it is next filled
-#pragma unroll
-        for (int g = 0; g < kGroups; ++g)
+            // the queued molecules now live in the queue: clear the vectors
+            // read so this buffer is all zero when it is next filled
 #pragma unroll
             for (int s = 0; s < MAXS; ++s)
-                if (s < S && (c[g][s].x | c[g][s].y | c[g][s].z | c[g][s].w) != 0)
-                    *(gptr<v4i>)(global(cur) + s * Tp + t0 + 4 * g) = v4i{0, 0, 0, 0};
+                if ((c[s].x | c[s].y | c[s].z | c[s].w) != 0)
+                    *(gptr<v4i>)(global(cur) + s * Tp + tg) = v4i{0, 0, 0, 0};
+        }
+        // the next tile's list must not overtake this tile's reads
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     }
 }
 
