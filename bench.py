@@ -296,7 +296,8 @@ def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=338, help="timed periods (338 = 0.1 s of the A+B<->C system)")
-    ap.add_argument("--warmup", type=int, default=96, help="untimed periods first (also tunes launch shapes)")
+    ap.add_argument("--warmup", type=int, default=192,
+                    help="untimed periods first (the tuner's 10 chunks of 16 periods fall in them)")
     ap.add_argument("--workload", choices=["batched", "plain", "serving"], default="batched")
     ap.add_argument("--rate", type=float, default=20.0, help="serving: mean arrivals per second")
     ap.add_argument("--duration", type=float, default=60.0, help="serving: seconds of arrivals")

@@ -103,12 +103,13 @@ struct rdos_engine {
     bool graph_stale = true;  // a buffer the graph names was reallocated
     bool rebuild = true;      // the slot set changed
 
-    // tuner: candidates tried once per work-list size bucket, best kept
+    // tuner: each candidate runs two chunks per work-list size bucket (the
+    // first replays a freshly captured graph and is not scored), best kept
     std::vector<Shape> candidates;
     bool fixed_shape = false;  // set_shape: no tuning, always `best`
     std::map<std::pair<int, int>, Shape> tuned;
     std::pair<int, int> bucket{-1, -1};
-    size_t trial = 0;
+    size_t trial = 0;  // chunks of tuning done in this bucket: candidate trial / 2
     double best_rate = -1.0;
     Shape best{16, 2048, 2, 1};
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
@@ -422,15 +423,16 @@ void worker_main(rdos_engine *e)
                 auto hit = e->tuned.find(b);
                 if (hit != e->tuned.end()) {
                     e->best = hit->second;
-                    e->trial = e->candidates.size();
+                    e->trial = 2 * e->candidates.size();
                 } else {
                     e->trial = 0;
                     e->best_rate = -1.0;
                 }
             }
         }
-        // the tuner tries each candidate once per size bucket, then keeps the best
-        Shape sh = !e->fixed_shape && e->trial < e->candidates.size() ? e->candidates[e->trial] : e->best;
+        // the tuner tries each candidate per size bucket, then keeps the best
+        const bool tuning = !e->fixed_shape && e->trial < 2 * e->candidates.size();
+        Shape sh = tuning ? e->candidates[e->trial / 2] : e->best;
         const bool timed = e->profiling;
         if (timed || e->n_tiles0 == 0 || e->n_tiles0 == e->n_tiles) sh.chains = 1;  // nothing to split
         if (set_chains(e, sh.chains) != RDOS_OK) {
@@ -489,13 +491,13 @@ void worker_main(rdos_engine *e)
             }
         }
         const double rate = ms > 0.f ? work / (double)ms : 0.0;
-        if (!e->fixed_shape && e->trial < e->candidates.size()) {
-            if (rate > e->best_rate) {
+        if (tuning) {
+            if ((e->trial & 1) && rate > e->best_rate) {  // the candidate's second chunk
                 e->best_rate = rate;
                 e->best = sh;
             }
             ++e->trial;
-            if (e->trial == e->candidates.size()) e->tuned[e->bucket] = e->best;
+            if (e->trial == 2 * e->candidates.size()) e->tuned[e->bucket] = e->best;
         }
         e->launches += sh.chunk;
         e->updates += work;
