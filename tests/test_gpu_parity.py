@@ -140,14 +140,29 @@ def test_abc_lattice_full_size(P, orc):
     g.close()
 
 
-def test_abcd_jittered_full_size_truncated(P, orc):
+def test_abcd_jittered_full_size(P, orc):
+    """The jittered mesh with D decay at full size: every count against the
+    oracle after 60 and 500 periods (the oracle takes about 10 ms a period
+    here, the whole 0.05 s is about 5000 periods), then the GPU alone to the
+    end with what holds at any length: A + C and B + C are conserved, and the
+    first-order decay of D is exact under the splitting (each D molecule
+    survives 0.05 s with probability exp(-0.05), whatever it diffuses), so the
+    D total is Binomial(D0, exp(-0.05))."""
     m = W.abcd_jittered()
-    note(f"A+B<->C + D decay, jittered 40^3x6 T={m.n_tets}, 60 periods")
+    note(f"A+B<->C + D decay, jittered 40^3x6 T={m.n_tets}: 500 periods against the oracle")
     g, os_ = make_pair(P, orc, m.xyz, m.tets, m.D, m.reactions, m.init, seed=m.seed)
-    for _ in range(3):
-        g.step(20)
-        os_[0].run_steps(20)
+    for n in (60, 440):
+        g.step(n)
+        os_[0].run_steps(n)
         assert_same(g, os_, "jittered")
+    note(f"A+B<->C + D decay: to t = {m.t_end} on the GPU")
+    g.run_until(m.t_end)
+    c = g.get_counts()
+    a0, b0, d0 = (int(m.init[0, q].sum()) for q in (0, 1, 3))
+    assert c[0].sum() + c[2].sum() == a0 and c[1].sum() + c[2].sum() == b0
+    p = math.exp(-1.0 * m.t_end)
+    sd = math.sqrt(d0 * p * (1 - p))
+    assert abs(int(c[3].sum()) - d0 * p) < 4 * sd, (int(c[3].sum()), d0 * p, sd)
     g.close()
 
 
