@@ -28,10 +28,17 @@ def log(msg):
 
 
 def kernel_source_hash():
+    """Hash of the device code's tokens: comments and layout do not count,
+    so a measured traffic file stays valid across edits that change neither."""
+    import re
+
     h = hashlib.sha256()
     for f in ("rdos_kernels.hip", "rdos_sampling.h", "rdos_internal.h"):
-        with open(os.path.join(ROOT, "paper_1512_03126_amd", "csrc", f), "rb") as fh:
-            h.update(fh.read())
+        with open(os.path.join(ROOT, "paper_1512_03126_amd", "csrc", f)) as fh:
+            text = fh.read()
+        text = re.sub(r"/\*.*?\*/", " ", text, flags=re.S)
+        text = re.sub(r"//[^\n]*", " ", text)
+        h.update(" ".join(text.split()).encode())
     return h.hexdigest()[:16]
 
 

@@ -471,17 +471,20 @@ __device__ __forceinline__ void update_tet(const DevSim &sm, int32_t t, int64_t 
 }
 
 // Each period is two launches.
-//  scan:   one wavefront per tile of 1024 tets, 16 consecutive tets per
-//          lane in four groups of four.  A group whose occupancy byte is set
-//          is read with one 16-byte buffer load per species; the
-//          others are not read.  The wavefront compacts its tets that hold
-//          any molecule (all tets if a reaction has no reactant) with a
-//          ballot prefix sum, reserves room with one atomic on the tile's
-//          queue segment, writes the tets and their counts to the queue in
-//          tet order and clears those counts and the bytes, so buffer and
-//          map are all zero by the time they are refilled.  A tile per
-//          wavefront keeps the chain of dependent loads (tile, map, counts,
-//          reservation) short relative to the work it covers.
+//  scan:   one wavefront per tile of 1024 tets.  Each lane sweeps the
+//          occupancy bytes of 16 tets (four groups of four) and clears them;
+//          the tile's flagged groups are ranked over the wavefront and
+//          listed in LDS, and the lanes then take the listed groups in turn:
+//          a lane reads its group's flagged count vectors (16 bytes per
+//          species), the group's tets that hold any molecule (all of them if
+//          a reaction has no reactant) are ranked with ballots, staged in LDS
+//          and written to the queue in tet order with coalesced stores after
+//          an atomic reservation on the tile's segment (one per chunk of 64
+//          groups), and the vectors read
+//          are cleared, so buffer and map are all zero by the time they are
+//          refilled.  A tile per wavefront keeps the chain of dependent loads
+//          (tile, map, counts, reservation) short relative to the work it
+//          covers.
 //  update: the queued tets run Steps 2-3 with every lane busy, add what
 //          stays and what leaves into the other buffer and set the
 //          occupancy bytes of the tets they added to.
