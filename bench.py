@@ -238,7 +238,7 @@ def run_serving(P, args):
     return res
 
 
-def write_traffic(fetch_csv, write_csv, launches, command):
+def write_traffic(fetch_csv, write_csv, launches, command, out_dir=None):
     """Turns two rocprofv3 --pmc runs of this script (FETCH_SIZE, then
     WRITE_SIZE) into profiles/<kernel>_batched_traffic.json for both step
     kernels: the mean over the last `launches` dispatches of each kernel (the
@@ -282,7 +282,7 @@ def write_traffic(fetch_csv, write_csv, launches, command):
                "launches_averaged": per["FETCH_SIZE"][k][1], "commands": command,
                "note": f"per dispatch of the last {launches} {k} launches (the single-chain timing pass, one "
                        "launch per period over all realizations); counter KiB x 1024 x scale"}
-        path = os.path.join(ROOT, "profiles", f"{k}_batched_traffic.json")
+        path = os.path.join(out_dir or os.path.join(ROOT, "profiles"), f"{k}_batched_traffic.json")
         with open(path, "w") as f:
             json.dump(out, f, indent=1)
             f.write("\n")
