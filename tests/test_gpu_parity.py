@@ -350,6 +350,46 @@ def test_invalid_inputs(P):
         P.Simulation(xyz, tets, [0.0], [])
 
 
+MAX_D = [1e-12, 2e-12, 0.5e-12, 0.0, 1.5e-12, 1e-12, 0.2e-12, 2e-12]   # 8 species, one not diffusing
+MAX_REACTIONS = [  # 16 reactions: every order, homodimers, up to three products
+    ([], [0], 2e-3), ([], [4], 1e-3), ([0], [1], 20.0), ([1], [0], 5.0),
+    ([0, 1], [2], 2e3), ([2], [0, 1], 30.0), ([3], [5], 8.0), ([5, 5], [6], 5e3),
+    ([6], [5, 5], 12.0), ([4], [], 3.0), ([7, 0], [7, 1], 1e3), ([2, 2], [3], 4e3),
+    ([6], [4, 5, 7], 2.0), ([1, 4], [], 1e3), ([7], [7, 7], 1.0), ([7, 7], [7], 3e3),
+]
+
+
+def test_maximum_species_and_reactions(P, orc):
+    """The limits of one simulation, 8 species and 16 reactions, every
+    species present: the widest kernel instances, bit for bit; one more
+    species or reaction, or a third reactant, is refused."""
+    assert len(MAX_D) == 8 and len(MAX_REACTIONS) == 16
+    xyz, tets = W.tiny_lattice(6, 0.2e-6, jitter_frac=0.2, seed=21)   # 1296 tets: two tiles, ragged
+    rng = np.random.default_rng(21)
+    init = rng.integers(0, 12, size=(2, 8, tets.shape[0])).astype(np.int32)
+    note(f"maximum sizes: 8 species, 16 reactions, T={tets.shape[0]}, 2 realizations, 40 periods")
+    g, os_ = make_pair(P, orc, xyz, tets, MAX_D, MAX_REACTIONS, init, seed=21)
+    for _ in range(2):
+        g.step(20)
+        for o in os_:
+            o.run_steps(20)
+        assert_same(g, os_, "maximum sizes")
+    g.close()
+    h = P.rdos_create(0, 1, 1)
+    P.rdos_set_mesh(h, xyz, tets)
+    for d in MAX_D:
+        P.rdos_add_species(h, d)
+    with pytest.raises(P.RdosError, match="at most 8 species"):
+        P.rdos_add_species(h, 1e-12)
+    for r, p_, k in MAX_REACTIONS:
+        P.rdos_add_reaction(h, r, p_, k)
+    with pytest.raises(P.RdosError, match="at most 16 reactions"):
+        P.rdos_add_reaction(h, [0], [1], 1.0)
+    with pytest.raises(P.RdosError, match="0..2 reactants"):
+        P.rdos_add_reaction(h, [0, 1, 2], [], 1.0)
+    P.rdos_destroy(h)
+
+
 # ---------------------------------------------------------------------------
 # Batching / serving engine
 # ---------------------------------------------------------------------------
