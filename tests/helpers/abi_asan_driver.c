@@ -1,5 +1,6 @@
-/* The public C ABI under AddressSanitizer (host code only: the library is
- * built with -Xarch_host -fsanitize=address; device code is not instrumented).
+/* The public C ABI under AddressSanitizer and UndefinedBehaviorSanitizer
+ * (host code only: the library is built with -Xarch_host -fsanitize=...;
+ * device code is not instrumented).
  * Plain stepping of 2 realizations (40 periods, then a shortened last period)
  * and an engine serving three requests of different lengths, every result
  * against the oracle.  Build with build_abi_asan_driver.sh, run on a GPU with
