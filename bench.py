@@ -154,6 +154,73 @@ def run_engine(P, e, sims, periods):
         P.rdos_engine_release(e, t)
 
 
+def variant_models(name):
+    """Models and method options of the widened rows, each timed like the
+    batched mix: the same 256 + 64 realizations with another method option,
+    a surface of the same size and occupancy, and six species."""
+    import numpy as np
+
+    import workloads as W
+
+    if name in ("reference", "transfer_form_1", "first_order", "tau_outliers_10"):
+        opts = {"transfer_form_1": {"transfer_form": 1}, "first_order": {"occupancy_correction": False},
+                "tau_outliers_10": {"tau_outliers": 10}}.get(name, {})
+        return build_batched(), opts
+    if name == "six_species":
+        # A+B<->C plus D -> E -> F -> D at 1/s, D, E, F as many as A, placed elsewhere
+        out = []
+        for m in build_batched():
+            init = np.concatenate([m.init] + [np.roll(m.init[:, 0:1], 7919 * (q + 1), axis=2) for q in range(3)],
+                                  axis=1)
+            out.append(W.Model(m.name + "_six", m.xyz, m.tets, list(m.D) + [1e-12, 1e-12, 1e-12],
+                               list(m.reactions) + [([3], [4], 1.0), ([4], [5], 1.0), ([5], [3], 1.0)],
+                               np.ascontiguousarray(init), m.t_end, m.seed))
+        return out, {}
+    if name == "surface":
+        # 400 x 480 cells of 0.1 um, two triangles each (384,000), 3854 A and 3854 B
+        # per realization placed uniformly (equal areas); surface A+B<->C with
+        # about the pair and decay rates of the volume mix
+        xyz, tris = W.triangle_lattice(400, 480, 0.1e-6)
+        T = tris.shape[0]
+        rng = np.random.default_rng(5)
+        init = np.zeros((256, 3, T), np.int32)
+        for r in range(256):
+            for q in range(2):
+                np.add.at(init[r, q], rng.integers(0, T, 3854), 1)
+        area = 0.5 * (0.1e-6) ** 2
+        k2 = 10.0 * W.N_A * area  # m^2/(mol s): 10 /s per pair in one triangle
+        m = W.Model("surface_abc_384k", xyz, tris, [1e-12, 1e-12, 0.5e-12], [([0, 1], [2], k2), ([2], [0, 1], 10.0)],
+                    init, 0.1, 1)
+        return [m], {}
+    raise ValueError(name)
+
+
+def run_variants(P, args):
+    """Throughput of the widened rows on the engine (the default launch-shape
+    tuning, warm-up, then --steps timed periods each)."""
+    res = {}
+    for name in ("reference", "transfer_form_1", "first_order", "tau_outliers_10", "six_species", "surface"):
+        models, opts = variant_models(name)
+        sims = []
+        for m in models:
+            sims.append(P.Simulation.from_model(m, **opts))
+        upd = sum(m.n_realizations * m.n_tets * m.n_species for m in models)
+        e = P.rdos_engine_create(0, 0)
+        run_engine(P, e, sims, args.warmup)
+        t0 = time.perf_counter()
+        run_engine(P, e, sims, args.steps)
+        dt = time.perf_counter() - t0
+        shape = P.rdos_engine_launch_shape(e)
+        P.rdos_engine_destroy(e)
+        for x in sims:
+            x.close()
+        res[name] = {"updates_per_s": round(args.steps * upd / dt, 1), "ms_per_period": round(dt / args.steps * 1e3, 4),
+                     "updates_per_period": upd, "species": models[0].n_species, "cells": [m.n_tets for m in models],
+                     "realizations": [m.n_realizations for m in models], "launch_shape": shape}
+        log(f"{name}: {res[name]['updates_per_s']:.3e} upd/s, {res[name]['ms_per_period']:.4f} ms/period")
+    return res
+
+
 def run_serving(P, args):
     """Poisson arrivals of independent requests (jittered lattices of 1e4-1e6
     tets, 1-6 species, random reactions), each asking for a fixed number of
@@ -305,7 +372,9 @@ def main():
     ap.add_argument("--steps", type=int, default=338, help="timed periods (338 = 0.1 s of the A+B<->C system)")
     ap.add_argument("--warmup", type=int, default=192,
                     help="untimed periods first (the tuner's 10 chunks of 16 periods fall in them)")
-    ap.add_argument("--workload", choices=["batched", "plain", "serving"], default="batched")
+    ap.add_argument("--workload", choices=["batched", "plain", "serving", "variants"], default="batched",
+                    help="variants: throughput of the method options, a surface and six species (not the "
+                         "headline line)")
     ap.add_argument("--rate", type=float, default=20.0, help="serving: mean arrivals per second")
     ap.add_argument("--duration", type=float, default=60.0, help="serving: seconds of arrivals")
     ap.add_argument("--request-steps", type=int, default=1000, help="serving: periods per request")
@@ -337,6 +406,12 @@ def main():
     P.lib()
     K, Wm = args.steps, args.warmup
     result = {}
+
+    if args.workload == "variants":
+        res = run_variants(P, args)
+        print(json.dumps({"metric": "tet-species updates/s per variant", "unit": "tet-species updates/s",
+                          "n_gpus": 1, "steps": K, "warmup": Wm, "data": "synthetic", "variants": res}), flush=True)
+        return
 
     if args.workload == "serving":
         res = run_serving(P, args)
