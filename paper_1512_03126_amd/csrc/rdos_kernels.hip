@@ -686,11 +686,11 @@ __global__ __launch_bounds__(kBlock) void scan_kernel(const DevSim *__restrict__
 }
 
 // Per-lane state for up to KS species in LDS (20 KS bytes per lane).  With
-// KS = 4 and the default transfer form the kernel fits 128 VGPRs without
-// spilling, and the LDS allows it, so it runs four wavefronts per SIMD;
-// the other instances keep the register budget of three.
+// the default transfer form the kernel fits 128 VGPRs without spilling; for
+// KS <= 6 the LDS allows four blocks per CU too, so it runs four wavefronts
+// per SIMD.  The other instances keep the register budget of three.
 template <bool ANY_SCALED, int KS>
-__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(KS <= 4 && !ANY_SCALED ? 4 : 3))) void
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(KS <= 6 && !ANY_SCALED ? 4 : 3))) void
 update_kernel(const DevSim *__restrict__ sims, const Tile *__restrict__ tiles, Queue q, int32_t qsel, int64_t iter,
               int64_t partial, double tau_last)
 {
@@ -760,6 +760,8 @@ hipError_t launch_scan(const DevSim *sims, const Tile *tiles, int64_t iter, cons
         scan_kernel<3><<<scan_grid, kBlock, 0, st>>>(sims, tiles, iter, q, qsel);
     else if (qv.species <= 4)
         scan_kernel<4><<<scan_grid, kBlock, 0, st>>>(sims, tiles, iter, q, qsel);
+    else if (qv.species <= 6)
+        scan_kernel<6><<<scan_grid, kBlock, 0, st>>>(sims, tiles, iter, q, qsel);
     else
         scan_kernel<kMaxSpecies><<<scan_grid, kBlock, 0, st>>>(sims, tiles, iter, q, qsel);
     return hipGetLastError();
@@ -777,6 +779,11 @@ hipError_t launch_update(const DevSim *sims, const Tile *tiles, int64_t iter, in
             update_kernel<true, 4><<<grid, kBlock, 0, st>>>(sims, tiles, q, qsel, iter, partial, tau_last);
         else
             update_kernel<false, 4><<<grid, kBlock, 0, st>>>(sims, tiles, q, qsel, iter, partial, tau_last);
+    } else if (qv.species <= 6) {
+        if (qv.scaled)
+            update_kernel<true, 6><<<grid, kBlock, 0, st>>>(sims, tiles, q, qsel, iter, partial, tau_last);
+        else
+            update_kernel<false, 6><<<grid, kBlock, 0, st>>>(sims, tiles, q, qsel, iter, partial, tau_last);
     } else {
         if (qv.scaled)
             update_kernel<true, kMaxSpecies><<<grid, kBlock, 0, st>>>(sims, tiles, q, qsel, iter, partial, tau_last);
