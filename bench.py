@@ -379,6 +379,9 @@ def main():
     ap.add_argument("--duration", type=float, default=60.0, help="serving: seconds of arrivals")
     ap.add_argument("--request-steps", type=int, default=1000, help="serving: periods per request")
     ap.add_argument("--budget-gb", type=float, default=8.0, help="serving: HBM budget of the engine")
+    ap.add_argument("--shape", default=None, metavar="CHUNK,SCAN_GRID,UPDATE_BPS,CHAINS",
+                    help="batched: fix the engine's launch shape instead of tuning it (for profiled runs, where "
+                         "the profiler's own cost can change the tuner's choice)")
     ap.add_argument("--seed", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-plain", action="store_true", help="skip the plain one-realization comparison")
@@ -391,7 +394,8 @@ def main():
     if args.traffic_from:
         cmd = [f"timeout -s KILL 300 rocprofv3 --pmc {c} --output-format csv -d gpurun_out/pmc_{c.lower()} "
                f"-o {c.lower()} -- python3 bench.py --steps {args.steps} --warmup {args.warmup} "
-               "--no-cpu-baseline --no-plain" for c in ("FETCH_SIZE", "WRITE_SIZE")]
+               "--no-cpu-baseline --no-plain" + (f" --shape {args.shape}" if args.shape else "")
+               for c in ("FETCH_SIZE", "WRITE_SIZE")]
         write_traffic(*args.traffic_from, args.steps, cmd)
         return
 
@@ -453,6 +457,8 @@ def main():
         upd_per_period = sum(m.n_realizations * m.n_tets * m.n_species for m in models)
         bytes_per_period = 8 * sum(m.n_realizations * m.n_tets * m.n_species for m in models)
         e = P.rdos_engine_create(0, 0)
+        if args.shape:
+            P.rdos_engine_set_shape(e, *(int(v) for v in args.shape.split(",")))
         run_engine(P, e, sims, Wm)
         t0 = time.perf_counter()
         run_engine(P, e, sims, K)
@@ -501,7 +507,7 @@ def main():
             log(f"bandwidth probe failed: {ex}")
         st = P.rdos_engine_stats(e)
         shape = P.rdos_engine_launch_shape(e)
-        log(f"tuned launch shape: {shape}")
+        log(f"launch shape ({'fixed' if args.shape else 'tuned'}): {shape}")
         P.rdos_engine_destroy(e)
         for s in sims:
             s.close()
@@ -510,7 +516,8 @@ def main():
         config = {"workload": workload, "tets": [384000, 48000], "realizations": [256, 64], "species": 3,
                   "periods": K, "tau_s": 2.958758547680654e-4, "updates_per_period": upd_per_period,
                   "realizations_per_s": round(320.0 / (ms_step * 1e-3 * 338), 3),
-                  "engine_launches": st["launches"], "launch_shape": shape}
+                  "engine_launches": st["launches"], "launch_shape": shape,
+                  "launch_shape_source": "fixed (--shape)" if args.shape else "tuned"}
         if plain:
             config["plain_updates_per_s"] = round(plain["value"], 1)
             config["plain_ms_per_step"] = round(plain["ms_per_step"], 4)
