@@ -496,10 +496,11 @@ __device__ __forceinline__ void update_tet(const DevSim &sm, int32_t t, int64_t 
 // next scan, so consecutive launches alternate qsel.
 struct Queue {
     int32_t *tet;     // [qcap]
-    int32_t *counts;  // [max species][qcap]
+    int32_t *counts;  // [rows][qcap]
     int32_t *len;     // [2][kMaxSegments] * kLenStride
     const WorkHeader *hdr;
     unsigned long long *work;  // null, or [2] totals of the timing pass: tets updated, count additions
+    int32_t rows;     // count rows allocated: at least the species of every simulation served
 };
 
 // Raw buffer resource word 3 for gfx950 (untyped 32-bit data) and the cache
@@ -715,6 +716,15 @@ update_kernel(const DevSim *__restrict__ sims, const Tile *__restrict__ tiles, Q
         if (tally) atomicAdd(&block_tets, 1u);
         const int64_t idx = (int64_t)seg * h.seg_cap + i;
         const int32_t entry = q.tet[idx];
+        // the entry's count rows are read together with it, not after the
+        // simulation is known: rows past a simulation's S hold stale values
+        // that it never reads
+        int32_t cn[KS];
+#pragma unroll
+        for (int s = 0; s < KS; ++s) cn[s] = s < q.rows ? q.counts[s * h.qcap + idx] : 0;
+#pragma unroll
+        for (int s = 0; s < KS; ++s)
+            if (s < q.rows) ls.n(s) = cn[s];
         const Tile tile = tiles[h.tile0 + entry / kTetsPerTile];
         // lanes of one simulation run together with a wavefront-uniform
         // descriptor (one round when the wavefront holds one simulation);
@@ -733,7 +743,6 @@ update_kernel(const DevSim *__restrict__ sims, const Tile *__restrict__ tiles, Q
             const double tau_k = period == partial ? tau_last : sm.tau;
             const int64_t Tp = ((int64_t)sm.T + 3) & ~(int64_t)3;
             const int64_t base = (int64_t)tile.realization * sm.S * Tp;
-            for (int s = 0; s < sm.S; ++s) ls.n(s) = q.counts[s * h.qcap + idx];
             update_tet<ANY_SCALED>(sm, tile.tet0 + entry % kTetsPerTile, period, tau_k, sm.key1 ^ (uint32_t)tile.realization,
                        sm.buf[(period + 1) & 1] + base, (int32_t)Tp,
                        sm.mask[(period + 1) & 1] + (int64_t)tile.realization * sm.S * sm.mstride, ls, tally);
@@ -752,7 +761,7 @@ hipError_t launch_scan(const DevSim *sims, const Tile *tiles, int64_t iter, cons
                        int32_t scan_grid, hipStream_t st)
 {
     if (scan_grid <= 0) return hipErrorInvalidValue;
-    const Queue q{qv.tet, qv.counts, qv.len, qv.hdr, qv.work};
+    const Queue q{qv.tet, qv.counts, qv.len, qv.hdr, qv.work, qv.species};
     // register arrays sized for the largest species count the queue holds
     if (qv.species <= 2)
         scan_kernel<2><<<scan_grid, kBlock, 0, st>>>(sims, tiles, iter, q, qsel);
@@ -770,7 +779,7 @@ hipError_t launch_scan(const DevSim *sims, const Tile *tiles, int64_t iter, cons
 hipError_t launch_update(const DevSim *sims, const Tile *tiles, int64_t iter, int64_t partial, double tau_last,
                          const QueueView &qv, int32_t qsel, int32_t blocks_per_segment, hipStream_t st)
 {
-    const Queue q{qv.tet, qv.counts, qv.len, qv.hdr, qv.work};
+    const Queue q{qv.tet, qv.counts, qv.len, qv.hdr, qv.work, qv.species};
     const int32_t bps = blocks_per_segment > 0 ? blocks_per_segment : 1;
     const dim3 grid(kMaxSegments * bps);
     // the queue's species rows bound the species of every simulation it serves
