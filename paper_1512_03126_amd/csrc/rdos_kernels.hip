@@ -291,11 +291,13 @@ struct LaneState {
 };
 
 // propensity a_r = c_r h_r of reaction q with the tet's counts (mass action);
-// zero where the reaction is not allowed (bit q of `allow`)
-__device__ __forceinline__ double propensity(const DevSim &sm, int q, const LaneState &ls, double nav,
-                                             uint32_t allow)
+// zero where the reaction is not allowed in tet t (bit q of its `allowed`
+// word).  The counts are tested first, and the tet's N_A V and allowed word
+// are read from memory only when they matter: most tets hold no reactant
+// pair, and then their update does not wait for those loads.
+__device__ __forceinline__ double propensity(const DevSim &sm, int q, const LaneState &ls, const MeshRec &mr,
+                                             int32_t t)
 {
-    if (!((allow >> q) & 1u)) return 0.0;
     const int order = sm.rn[q];
     double h;
     if (order == 0) {
@@ -311,7 +313,10 @@ __device__ __forceinline__ double propensity(const DevSim &sm, int q, const Lane
         }
     }
     if (h == 0.0) return 0.0;  // c_r * 0 == 0 for every finite c_r
-    const double c = order == 0 ? sm.k[q] * nav : (order == 1 ? sm.k[q] : sm.k[q] / nav);
+    if (sm.allowed && !((sm.allowed[t] >> q) & 1u)) return 0.0;
+    if (order == 1) return sm.k[q] * h;
+    const double nav = mr.nav;
+    const double c = order == 0 ? sm.k[q] * nav : sm.k[q] / nav;
     return c * h;
 }
 
@@ -327,8 +332,6 @@ __device__ __forceinline__ void update_tet(const DevSim &sm, int32_t t, int64_t 
     const int R = sm.R;
     const uint32_t period32 = (uint32_t)period;
     const MeshRec &mr = sm.mesh[t];
-    const double nav = mr.nav;
-    const uint32_t allow = sm.allowed ? sm.allowed[t] : 0xFFFFFFFFu;
 
     // Step 2: Gillespie direct method over [0, tau_k); the first event at or
     // past tau_k is discarded.  Step 2.1: on each event the occupancy
@@ -345,7 +348,7 @@ __device__ __forceinline__ void update_tet(const DevSim &sm, int32_t t, int64_t 
                 break;
             }
             double a0 = 0.0;
-            for (int q = 0; q < R; ++q) a0 = a0 + propensity(sm, q, ls, nav, allow);
+            for (int q = 0; q < R; ++q) a0 = a0 + propensity(sm, q, ls, mr, t);
             if (!(a0 > 0.0)) break;
             const double dt = -log_basic(1.0 - ssa.uniform()) / a0;
             if (now + dt >= tau_k) break;
@@ -354,7 +357,7 @@ __device__ __forceinline__ void update_tet(const DevSim &sm, int32_t t, int64_t 
             int chosen = -1;
             double cum = 0.0;
             for (int q = 0; q < R; ++q) {
-                cum = cum + propensity(sm, q, ls, nav, allow);
+                cum = cum + propensity(sm, q, ls, mr, t);
                 if (x < cum) {
                     chosen = q;
                     break;
@@ -362,16 +365,25 @@ __device__ __forceinline__ void update_tet(const DevSim &sm, int32_t t, int64_t 
             }
             if (chosen < 0) {  // x rounded up to a0: the last reaction able to fire
                 for (int q = R - 1; q >= 0; --q)
-                    if (propensity(sm, q, ls, nav, allow) > 0.0) {
+                    if (propensity(sm, q, ls, mr, t) > 0.0) {
                         chosen = q;
                         break;
                     }
             }
-            const uint32_t inv = sm.involved[chosen];
-            const int rn = sm.rn[chosen], pn = sm.pn[chosen];
-            const int a = rn > 0 ? sm.r0[chosen] : -1, b = rn > 1 ? sm.r1[chosen] : -1;
-            const int c0 = pn > 0 ? sm.p0[chosen] : -1, c1 = pn > 1 ? sm.p1[chosen] : -1;
-            const int c2 = pn > 2 ? sm.p2[chosen] : -1;
+            // the chosen reaction's fields, read with a wavefront-uniform index
+            // (scalar loads) and selected per lane
+            uint32_t inv = 0;
+            int a = -1, b = -1, c0 = -1, c1 = -1, c2 = -1;
+            for (int q = 0; q < R; ++q) {
+                const int rn = sm.rn[q], pn = sm.pn[q];
+                const bool is = q == chosen;
+                inv = is ? sm.involved[q] : inv;
+                a = is && rn > 0 ? sm.r0[q] : a;
+                b = is && rn > 1 ? sm.r1[q] : b;
+                c0 = is && pn > 0 ? sm.p0[q] : c0;
+                c1 = is && pn > 1 ? sm.p1[q] : c1;
+                c2 = is && pn > 2 ? sm.p2[q] : c2;
+            }
             for (int s = 0; s < S; ++s) {
                 if (!((inv >> s) & 1u)) continue;
                 const bool seen = (touched >> s) & 1u;
