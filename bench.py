@@ -392,10 +392,14 @@ def main():
     args = ap.parse_args()
 
     if args.traffic_from:
-        cmd = [f"timeout -s KILL 300 rocprofv3 --pmc {c} --output-format csv -d gpurun_out/pmc_{c.lower()} "
-               f"-o {c.lower()} -- python3 bench.py --steps {args.steps} --warmup {args.warmup} "
-               "--no-cpu-baseline --no-plain" + (f" --shape {args.shape}" if args.shape else "")
-               for c in ("FETCH_SIZE", "WRITE_SIZE")]
+        # the profiler commands that wrote the two files, reconstructed from their paths
+        cmd = []
+        for c, csv_path in zip(("FETCH_SIZE", "WRITE_SIZE"), args.traffic_from):
+            out_dir, name = os.path.split(csv_path)
+            cmd.append(f"timeout -s KILL 300 rocprofv3 --pmc {c} --output-format csv -d {out_dir or '.'} "
+                       f"-o {name.replace('_counter_collection.csv', '')} -- python3 bench.py --steps {args.steps} "
+                       f"--warmup {args.warmup} --no-cpu-baseline --no-plain"
+                       + (f" --shape {args.shape}" if args.shape else ""))
         write_traffic(*args.traffic_from, args.steps, cmd)
         return
 
