@@ -35,6 +35,9 @@ def test_served_results_equal_alone(orc):
 
     reqs = [small_request(i) for i in range(8)]
     periods = [40 + 10 * i for i in range(8)]
+    # simulations with fewer species than the queue has rows share it: the
+    # update reads every row beside a queue entry and must use only its own
+    assert len({m.n_species for m in reqs}) > 1
     note("serving: 8 requests arriving while others run")
     e = P.rdos_engine_create(0, 0)
     tickets = []
