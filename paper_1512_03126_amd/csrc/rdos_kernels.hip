@@ -295,7 +295,7 @@ struct LaneState {
 // word).  The counts are tested first, and the tet's N_A V and allowed word
 // are read from memory only when they matter: most tets hold no reactant
 // pair, and then their update does not wait for those loads.
-__device__ __forceinline__ double propensity(const DevSim &sm, int q, const LaneState &ls, const MeshRec &mr,
+__device__ __forceinline__ double propensity(const DevSim &sm, int q, const LaneState &ls, const MeshRec *mr,
                                              int32_t t)
 {
     const int order = sm.rn[q];
@@ -315,7 +315,7 @@ __device__ __forceinline__ double propensity(const DevSim &sm, int q, const Lane
     if (h == 0.0) return 0.0;  // c_r * 0 == 0 for every finite c_r
     if (sm.allowed && !((sm.allowed[t] >> q) & 1u)) return 0.0;
     if (order == 1) return sm.k[q] * h;
-    const double nav = mr.nav;
+    const double nav = mr->nav;
     const double c = order == 0 ? sm.k[q] * nav : sm.k[q] / nav;
     return c * h;
 }
@@ -331,7 +331,10 @@ __device__ __forceinline__ void update_tet(const DevSim &sm, int32_t t, int64_t 
     const int S = sm.S;
     const int R = sm.R;
     const uint32_t period32 = (uint32_t)period;
-    const MeshRec &mr = sm.mesh[t];
+    // a pointer, not a reference: a reference would tell the compiler the
+    // record may be read anywhere, and the SSA's conditional read of N_A V
+    // would then be made for every tet
+    const MeshRec *mr = sm.mesh + t;
 
     // Step 2: Gillespie direct method over [0, tau_k); the first event at or
     // past tau_k is discarded.  Step 2.1: on each event the occupancy
@@ -425,17 +428,23 @@ __device__ __forceinline__ void update_tet(const DevSim &sm, int32_t t, int64_t 
             const double frac = nbar - (double)ni;
             if (frac > 0.0 && rng.uniform() < frac) ni += 1;
             if (!have_faces) {
-                const int4 n4 = *reinterpret_cast<const int4 *>(mr.nbr);
+                const int4 n4 = *reinterpret_cast<const int4 *>(mr->nbr);
                 nb[0] = n4.x;
                 nb[1] = n4.y;
                 nb[2] = n4.z;
                 nb[3] = n4.w;
 #pragma unroll
-                for (int f = 0; f < 4; ++f) w[f] = mr.w[f];
-                g = mr.g;
+                for (int f = 0; f < 4; ++f) w[f] = mr->w[f];
+                g = mr->g;
                 have_faces = true;
             }
-            double zeta = (tau_k * sm.D[s]) * g;
+            // D of species s, read with uniform indices (scalar loads) and
+            // selected per lane, instead of one vector load per species
+            double Ds = 0.0;
+#pragma unroll
+            for (int k = 0; k < kMaxSpecies; ++k)
+                if (k < S) Ds = k == s ? sm.D[k] : Ds;
+            double zeta = (tau_k * Ds) * g;
             if (zeta > 1.0) zeta = 1.0;
             // Step 3.2-3.3: n = min(binomial(SR(Nbar), zeta), N) split over the
             // faces; or (transfer form 1) SR(Nbar) split at once with weights
