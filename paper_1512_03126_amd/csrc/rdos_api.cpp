@@ -514,6 +514,10 @@ rdos_status rdos_finalize(rdos_sim *s, double tau_scale, double *out_tau)
     // one realization's counts are addressed with 32-bit byte offsets
     if ((int64_t)s->D.size() * padded_tets(s->T) * 4 > 0x7fffffff)
         return fail(s, RDOS_EINVAL, "tets x species of one realization exceed 2^29");
+    // queue entries are int32 (tile * kTetsPerTile + offset): the tiled work
+    // list, not only realizations x tets, must stay below 2^31
+    if (tiles_of(s) * kTetsPerTile > 0x7fffffff)
+        return fail(s, RDOS_EINVAL, "realizations x tiled tets exceed 2^31");
     std::vector<int32_t> nbr;
     rdos_status st = build_topology(s, nbr);
     if (st != RDOS_OK) return st;

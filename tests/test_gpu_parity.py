@@ -350,6 +350,18 @@ def test_invalid_inputs(P):
         P.Simulation(xyz, tets, [0.0], [])
 
 
+def test_tiled_work_list_bound(P):
+    # queue entries are int32 (tile * 1024 + offset): 1296 tets take two
+    # 1024-tet tiles, so 1.2e6 realizations pass the realizations x tets bound
+    # (1.56e9) but not the tiled one (2.46e9), and finalize refuses them
+    # before allocating anything
+    note("finalize: tiled work list over 2^31 tets")
+    xyz, tets = W.kuhn_lattice(6, 0.1e-6)
+    assert tets.shape[0] == 1296
+    with pytest.raises(P.RdosError, match="tiled tets"):
+        P.Simulation(xyz, tets, [1e-12], [], n_realizations=1_200_000)
+
+
 MAX_D = [1e-12, 2e-12, 0.5e-12, 0.0, 1.5e-12, 1e-12, 0.2e-12, 2e-12]   # 8 species, one not diffusing
 MAX_REACTIONS = [  # 16 reactions: every order, homodimers, up to three products
     ([], [0], 2e-3), ([], [4], 1e-3), ([0], [1], 20.0), ([1], [0], 5.0),
