@@ -733,20 +733,26 @@ update_kernel(const DevSim *__restrict__ sims, const Tile *__restrict__ tiles, Q
         __syncthreads();
     }
     const int32_t n = min(q.len[(qsel * kMaxSegments + seg) * kLenStride], h.seg_cap);
-    for (int32_t i = part * kBlock + threadIdx.x; i < n; i += per_seg * kBlock) {
+    const int32_t stride = per_seg * kBlock;
+    const int64_t seg0 = (int64_t)seg * h.seg_cap;
+    // each lane's next queue entry is read one tet ahead, so that it arrives
+    // with the loads of the tet before it instead of starting a round trip
+    int32_t next = part * kBlock + (int32_t)threadIdx.x < n ? q.tet[seg0 + part * kBlock + threadIdx.x] : 0;
+    for (int32_t i = part * kBlock + threadIdx.x; i < n; i += stride) {
         if (tally) atomicAdd(&block_tets, 1u);
-        const int64_t idx = (int64_t)seg * h.seg_cap + i;
-        const int32_t entry = q.tet[idx];
-        // the entry's count rows are read together with it, not after the
-        // simulation is known: rows past a simulation's S hold stale values
-        // that it never reads
+        const int64_t idx = seg0 + i;
+        const int32_t entry = next;
+        // the entry's count rows are read with its tile and the next entry,
+        // not after the simulation is known.  Every load is issued (slots past
+        // the queue's rows repeat its last row), so none waits behind a
+        // branch; slots past a simulation's S hold values it never reads.
         int32_t cn[KS];
 #pragma unroll
-        for (int s = 0; s < KS; ++s) cn[s] = s < q.rows ? q.counts[s * h.qcap + idx] : 0;
-#pragma unroll
-        for (int s = 0; s < KS; ++s)
-            if (s < q.rows) ls.n(s) = cn[s];
+        for (int s = 0; s < KS; ++s) cn[s] = q.counts[min(s, q.rows - 1) * h.qcap + idx];
         const Tile tile = tiles[h.tile0 + entry / kTetsPerTile];
+        next = i + stride < n ? q.tet[idx + stride] : 0;
+#pragma unroll
+        for (int s = 0; s < KS; ++s) ls.n(s) = cn[s];
         // lanes of one simulation run together with a wavefront-uniform
         // descriptor (one round when the wavefront holds one simulation);
         // descriptors do not change during a launch, so they are read as
