@@ -506,15 +506,16 @@ __device__ __forceinline__ void update_tet(const DevSim &sm, int32_t t, int64_t 
 //          refilled.  A tile per wavefront keeps the chain of dependent loads
 //          (tile, map, counts, reservation) short relative to the work it
 //          covers.
-//  update: the queued tets run Steps 2-3 with every lane busy, add what
-//          stays and what leaves into the other buffer and set the
-//          occupancy bytes of the tets they added to.
+//  update: each lane takes queued tets of its segment in turn (reading the
+//          next entry one tet ahead), runs Steps 2-3 on them, adds what
+//          stays and what leaves into the other buffer and sets the
+//          occupancy bytes of the tets it added to.
 // The queue has nseg segments of seg_cap entries (tiles ti with
 // ti % nseg == k fill segment k, so seg_cap = tets of those tiles suffices);
 // entry i of segment k is qtet[k * seg_cap + i] with counts
 // qcnt[s * qcap + k * seg_cap + i].  Segment lengths live in
-// qcount[(qsel * kMaxSegments + k) * kLenStride]; the update launch clears the other half for the
-// next scan, so consecutive launches alternate qsel.
+// len[(qsel * kMaxSegments + k) * kLenStride]; the update launch clears the
+// other half for the next scan, so consecutive launches alternate qsel.
 struct Queue {
     int32_t *tet;     // [qcap]
     int32_t *counts;  // [rows][qcap]
