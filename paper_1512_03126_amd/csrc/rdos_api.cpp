@@ -300,8 +300,8 @@ rdos_status ensure_mask(rdos_sim *s)
     if (!s->mask_dirty) return RDOS_OK;
     const int64_t Tp = padded_tets(s->T);
     const int p = (int)(s->step & 1);
-    HIP_TRY(s, launch_mask_build(s->d_buf[p], s->d_mask[p], s->d_mask[p ^ 1], s->Rz, (int32_t)s->D.size(), Tp,
-                                 s->stream),
+    HIP_TRY(s, launch_mask_build(s->d_buf[p], s->d_mask[p], s->d_mask[p ^ 1], occupancy_tag(s->step), s->Rz,
+                                 (int32_t)s->D.size(), Tp, s->stream),
             "rebuild occupancy");
     s->mask_dirty = false;
     return RDOS_OK;
@@ -817,6 +817,7 @@ rdos_status rdos_set_state(rdos_sim *s, int64_t step_index, double t)
     s->step = step_index;
     s->anchor_step = step_index;
     s->anchor_t = t;
+    s->mask_dirty = true;  // the occupancy bytes hold tags of the period index
     return match_parity(s);
 }
 

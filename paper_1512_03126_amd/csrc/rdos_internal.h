@@ -27,12 +27,21 @@ struct alignas(64) MeshRec {
 };
 static_assert(sizeof(MeshRec) == 64, "MeshRec must be one cache line");
 
+// The value an occupancy byte holds to mark period k (1..255, never 0).
+// Bytes are not cleared after they are read: a byte marks its group only in
+// the period whose tag it holds.  A byte left from 510 periods earlier (the
+// tags repeat every 255 periods, and each of the two maps serves every other
+// period) can match again; the scan then reads an all-zero count vector and
+// queues nothing, so a stale byte costs a read, never a result.
+__host__ __device__ inline uint8_t occupancy_tag(int64_t period) { return (uint8_t)(period % 255 + 1); }
+
 // One simulation as the step kernel sees it (device memory).
 struct alignas(16) DevSim {
     const MeshRec *mesh;       // [T]
     int32_t *buf[2];           // [Rz][S][Tp] counts; period k reads buf[k & 1] and fills buf[(k + 1) & 1]
-    uint8_t *mask[2];          // [Rz][S][mstride] occupancy of buf[k & 1]: byte t >> 2 of row (r, s) is
-                               // non-zero when species s of tets 4 (t >> 2) .. + 3 may be non-zero
+    uint8_t *mask[2];          // [Rz][S][mstride] occupancy of buf[k & 1]: byte t >> 2 of row (r, s)
+                               // equals occupancy_tag(k) when species s of tets 4 (t >> 2) .. + 3 may
+                               // be non-zero in period k
     int32_t *flags;            // bit 0: count overflow; bit 1: SSA event cap; bit 2: queue overflow
     int32_t T, S, R, Rz;
     int32_t mstride;           // occupancy bytes per species row (Tp / 4 rounded up to 16)
@@ -146,7 +155,8 @@ hipError_t launch_advance(DevSim *sims, const WorkHeader *hdr, int64_t by, hipSt
 // Rebuilds the occupancy bytes of buf[parity] from the counts of every
 // realization and species and clears those of the other buffer (after
 // counts were set from the host).
-hipError_t launch_mask_build(const int32_t *counts, uint8_t *mask_cur, uint8_t *mask_other, int32_t Rz, int32_t S,
+hipError_t launch_mask_build(const int32_t *counts, uint8_t *mask_cur, uint8_t *mask_other, uint8_t tag, int32_t Rz,
+                             int32_t S,
                              int64_t Tp, hipStream_t st);
 // Bytes of one species row of the occupancy map: one per four tets, padded
 // to 16 bytes so that the scan reads four bytes at a time.

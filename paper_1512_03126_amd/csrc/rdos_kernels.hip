@@ -9,7 +9,8 @@
 //                            atomics, every molecule that stays or arrives.
 //                            Species rows are separate so that the atomics of
 //                            one tet's species fall on different cache lines.
-//   mask[2][r][s][Tp/4]  uint8  occupancy of the four-tet groups of buf[k & 1], per species
+//   mask[2][r][s][Tp/4]  uint8  occupancy of the four-tet groups of buf[k & 1], per species:
+//                            a byte marks period k when it holds occupancy_tag(k)
 //   mesh[T]           64 B   neighbours, weights, g, N_A V (one line)
 #include <hip/hip_runtime.h>
 
@@ -326,7 +327,8 @@ __device__ __forceinline__ double propensity(const DevSim &sm, int q, const Lane
 template <bool ANY_SCALED>
 __device__ __forceinline__ void update_tet(const DevSim &sm, int32_t t, int64_t period, double tau_k,
                                            uint32_t key1, int32_t *__restrict__ nxt, int32_t Tp,
-                                           uint8_t *__restrict__ mnxt, const LaneState &ls, bool tally)
+                                           uint8_t *__restrict__ mnxt, uint8_t mark, const LaneState &ls,
+                                           bool tally)
 {
     const int S = sm.S;
     const int R = sm.R;
@@ -477,7 +479,7 @@ __device__ __forceinline__ void update_tet(const DevSim &sm, int32_t t, int64_t 
                 for (int f = 0; f < 4; ++f)
                     if (out[f] > 0) {
                         atomicAdd(&nxt[(uint32_t)(s * Tp + nb[f])], (int32_t)out[f]);
-                        mnxt[(uint32_t)(s * sm.mstride + (nb[f] >> 2))] = 1;
+                        mnxt[(uint32_t)(s * sm.mstride + (nb[f] >> 2))] = mark;
                         if (tally) atomicAdd(&block_adds, 1u);
                     }
                 ls.n(s) = Ns - (int32_t)n;
@@ -485,7 +487,7 @@ __device__ __forceinline__ void update_tet(const DevSim &sm, int32_t t, int64_t 
         }
         if (ls.n(s) > 0) {  // the molecules that stay
             atomicAdd(&nxt[(uint32_t)(s * Tp + t)], ls.n(s));
-            mnxt[(uint32_t)(s * sm.mstride + (t >> 2))] = 1;
+            mnxt[(uint32_t)(s * sm.mstride + (t >> 2))] = mark;
             if (tally) atomicAdd(&block_adds, 1u);
         }
     }
@@ -502,8 +504,9 @@ __device__ __forceinline__ void update_tet(const DevSim &sm, int32_t t, int64_t 
 //          and written to the queue in tet order with coalesced stores after
 //          an atomic reservation on the tile's segment (one per chunk of 64
 //          groups), and the vectors read
-//          are cleared, so buffer and map are all zero by the time they are
-//          refilled.  A tile per wavefront keeps the chain of dependent loads
+//          are cleared, so the buffer is all zero by the time it is refilled.
+//          The map is not cleared: a byte marks its group in the period
+//          whose tag it holds.  A tile per wavefront keeps the chain of dependent loads
 //          (tile, map, counts, reservation) short relative to the work it
 //          covers.
 //  update: each lane takes queued tets of its segment in turn (reading the
@@ -566,18 +569,17 @@ __global__ __launch_bounds__(kBlock) void scan_kernel(const DevSim *__restrict__
         const int S = sm.S;
         // Map sweep: per species, the four occupancy bytes of this lane's
         // groups in one load (rows are padded to 16 bytes, t0 / 4 is a
-        // multiple of 4), all species before any is cleared, so the loads are
-        // in flight together; the bytes are cleared for the next use.
-        gptr<uint8_t> mrow = global(sm.mask[period & 1]) + (int64_t)tile.realization * S * sm.mstride + (t0 >> 2);
+        // multiple of 4), all species together.  A byte flags its group when
+        // it holds this period's tag; nothing is cleared.
+        const gptr<const uint8_t> mrow =
+            global((const uint8_t *)sm.mask[period & 1]) + (int64_t)tile.realization * S * sm.mstride + (t0 >> 2);
+        const uint32_t tag = occupancy_tag(period);
         uint32_t mb[MAXS];
 #pragma unroll
         for (int s = 0; s < MAXS; ++s) {
             mb[s] = 0u;
             if (s < S && valid > 0) mb[s] = *(gptr<const uint32_t>)(mrow + (int64_t)s * sm.mstride);
         }
-#pragma unroll
-        for (int s = 0; s < MAXS; ++s)
-            if (mb[s] != 0u) *(gptr<uint32_t>)(mrow + (int64_t)s * sm.mstride) = 0u;
         // this lane's flagged groups and the species flagged in each (all of
         // them in every group if a reaction has no reactants: every tet runs)
         uint32_t sp[kGroups];
@@ -587,7 +589,7 @@ __global__ __launch_bounds__(kBlock) void scan_kernel(const DevSim *__restrict__
             sp[k] = 0u;
 #pragma unroll
             for (int s = 0; s < MAXS; ++s)
-                if (s < S && ((mb[s] >> (8 * k)) & 0xFFu) != 0u) sp[k] |= 1u << s;
+                if (s < S && ((mb[s] >> (8 * k)) & 0xFFu) == tag) sp[k] |= 1u << s;
             if (sm.zeroth) sp[k] = (1u << S) - 1u;
             if (4 * k >= valid) sp[k] = 0u;
             if (sp[k] != 0u) fl |= 1u << k;
@@ -773,7 +775,8 @@ update_kernel(const DevSim *__restrict__ sims, const Tile *__restrict__ tiles, Q
             const int64_t base = (int64_t)tile.realization * sm.S * Tp;
             update_tet<ANY_SCALED>(sm, tile.tet0 + entry % kTetsPerTile, period, tau_k, sm.key1 ^ (uint32_t)tile.realization,
                        sm.buf[(period + 1) & 1] + base, (int32_t)Tp,
-                       sm.mask[(period + 1) & 1] + (int64_t)tile.realization * sm.S * sm.mstride, ls, tally);
+                       sm.mask[(period + 1) & 1] + (int64_t)tile.realization * sm.S * sm.mstride,
+                       occupancy_tag(period + 1), ls, tally);
         }
     }
     if (tally) {
@@ -897,11 +900,12 @@ hipError_t launch_split_cost(bool one_by_one, int64_t n, int32_t reps, int64_t *
 }
 
 // One thread per occupancy byte: tets 4j .. 4j + 3 of one species of one
-// realization (bytes of the row padding past Tp / 4 are zero).
+// realization (bytes of the row padding past Tp / 4 are zero).  The current
+// map gets the current period's tag where the counts are non-zero.
 __global__ __launch_bounds__(256) void mask_build_kernel(const int32_t *__restrict__ counts,
                                                          uint8_t *__restrict__ mask_cur,
-                                                         uint8_t *__restrict__ mask_other, int64_t Tp, int64_t stride,
-                                                         int64_t n_bytes)
+                                                         uint8_t *__restrict__ mask_other, uint8_t tag, int64_t Tp,
+                                                         int64_t stride, int64_t n_bytes)
 {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n_bytes) return;
@@ -912,17 +916,18 @@ __global__ __launch_bounds__(256) void mask_build_kernel(const int32_t *__restri
         const int4 c = *reinterpret_cast<const int4 *>(counts + row * Tp + t4);
         any = c.x | c.y | c.z | c.w;
     }
-    mask_cur[i] = any != 0 ? 1 : 0;
+    mask_cur[i] = any != 0 ? tag : 0;
     mask_other[i] = 0;
 }
 
-hipError_t launch_mask_build(const int32_t *counts, uint8_t *mask_cur, uint8_t *mask_other, int32_t Rz, int32_t S,
-                             int64_t Tp, hipStream_t st)
+hipError_t launch_mask_build(const int32_t *counts, uint8_t *mask_cur, uint8_t *mask_other, uint8_t tag, int32_t Rz,
+                             int32_t S, int64_t Tp, hipStream_t st)
 {
     const int64_t stride = mask_stride(Tp);
     const int64_t n = (int64_t)Rz * S * stride;
     if (n <= 0) return hipSuccess;
-    mask_build_kernel<<<(unsigned)((n + 255) / 256), 256, 0, st>>>(counts, mask_cur, mask_other, Tp, stride, n);
+    mask_build_kernel<<<(unsigned)((n + 255) / 256), 256, 0, st>>>(counts, mask_cur, mask_other, tag, Tp, stride,
+                                                                    n);
     return hipGetLastError();
 }
 

@@ -244,6 +244,28 @@ def test_resume_is_bit_identical(P, orc):
     h.close()
 
 
+def test_set_state_alone_moves_the_period(P, orc):
+    # set_state without new counts: the occupancy bytes carry the period's
+    # tag, so the map is rebuilt for the new index (else no tet would be
+    # queued and the molecules would be lost); the run then matches the
+    # oracle moved to the same period index
+    xyz, tets = W.tiny_lattice(2, 0.2e-6, jitter_frac=0.2, seed=8)
+    T = tets.shape[0]
+    note("set_state alone, to an index of the other parity and a new tag")
+    init = rich_init(T, 1, 23)
+    g, os_ = make_pair(P, orc, xyz, tets, RICH_D, RICH_REACTIONS, init, seed=23)
+    g.step(5)
+    os_[0].run_steps(5)
+    assert_same(g, os_, "before set_state")
+    t0 = g.time()[0]
+    g.set_state(300, t0)
+    os_[0].set_state(300, t0)
+    g.step(9)
+    os_[0].run_steps(9)
+    assert_same(g, os_, "after set_state")
+    g.close()
+
+
 def test_counts_can_be_reset_between_periods(P, orc):
     xyz, tets = W.kuhn_lattice(2, 0.1e-6)
     T = tets.shape[0]
