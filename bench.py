@@ -59,8 +59,8 @@ def scan_bytes(sims, models):
     """Bytes the occupancy-driven scan must move in the period that starts
     from the current state of every realization (the units and per-unit
     figures of the roofline):
-      one map byte per four tets and species (read),
-      4 B per 16-tet lane and species with a set byte (the map clear),
+      one map byte per four tets and species (read; the map is not cleared:
+      its bytes carry the tag of the period they mark),
       16 B per flagged four-tet vector of one species (the count read),
       16 B per such vector again (its clear),
       4 + 4 S B per tet with molecules (its queue entry)."""
@@ -75,9 +75,8 @@ def scan_bytes(sims, models):
             c = np.zeros((S, Tp), np.int32)
             c[:, :T] = sim.get_counts(None, realization=r)
             vec = (c != 0).reshape(S, Tp // 4, 4).any(axis=2)   # [S][groups]: flagged vectors
-            lanes = sum(np.unique(np.nonzero(vec[q])[0] // 4).size for q in range(S))
             tets = int((c != 0).any(axis=0).sum())
-            total += S * stride + 4 * lanes + 32 * int(vec.sum()) + (4 + 4 * S) * tets
+            total += S * stride + 32 * int(vec.sum()) + (4 + 4 * S) * tets
     return total
 
 

@@ -31,11 +31,10 @@ def test_scan_bytes_by_hand():
     c[0, 0, 69] = 2     # group 17 (lane 4), species 0
     c[1, 1, 17] = 5     # realization 1: group 4 (lane 1), species 1
     got = bench.scan_bytes([_Sim(c)], [_Model(T, S, 2)])
-    map_bytes = 2 * (S * 32)
-    lanes = 4   # lanes with a set byte, per species: r0: s0 {0, 4}, s1 {0}; r1: s1 {1}
+    map_bytes = 2 * (S * 32)   # read only: the map is not cleared
     vec = 4     # flagged four-tet vectors, per species: r0: s0 {0, 17}, s1 {0}; r1: s1 {4}
     tets = 4    # tets 0, 1, 69 and (r1) 17
-    assert got == map_bytes + 4 * lanes + 32 * vec + (4 + 4 * S) * tets
+    assert got == map_bytes + 32 * vec + (4 + 4 * S) * tets
 
 
 def test_update_bytes():
