@@ -153,6 +153,22 @@ def run_engine(P, e, sims, periods):
         P.rdos_engine_release(e, t)
 
 
+def settle_engine(P, e, sims, max_rounds=8):
+    """Untimed: runs the work until the engine's tuner has settled on a
+    launch shape for it (each round is long enough for the tuner's whole
+    candidate list), then one more chunk so that the graph of the chosen
+    shape is captured before anything is timed.  Returns the periods run."""
+    periods = 0
+    for _ in range(max_rounds):
+        if P.rdos_engine_launch_shape(e)["source"] != "default":
+            break
+        run_engine(P, e, sims, 192)
+        periods += 192
+    chunk = P.rdos_engine_launch_shape(e)["chunk"]
+    run_engine(P, e, sims, 2 * chunk)
+    return periods + 2 * chunk
+
+
 def variant_models(name):
     """Models and method options of the widened rows, each timed like the
     batched mix: the same 256 + 64 realizations with another method option,
@@ -205,7 +221,8 @@ def run_variants(P, args):
             sims.append(P.Simulation.from_model(m, **opts))
         upd = sum(m.n_realizations * m.n_tets * m.n_species for m in models)
         e = P.rdos_engine_create(0, 0)
-        run_engine(P, e, sims, args.warmup)
+        run_engine(P, e, sims, max(args.warmup, 1))
+        settle_engine(P, e, sims)
         t0 = time.perf_counter()
         run_engine(P, e, sims, args.steps)
         dt = time.perf_counter() - t0
@@ -356,8 +373,8 @@ def write_traffic(fetch_csv, write_csv, launches, command, out_dir=None):
 
 
 def update_bytes(work, species):
-    """Bytes the update kernel must move for the work it counted on the
-    device (the units and per-unit figures of its roofline):
+    """Bytes the update kernel moves for the work it counted on the device,
+    in this implementation's own units:
       4 + 4 S B per queued tet (its queue entry: index and S counts),
       64 B per queued tet (its mesh record: neighbours, weights, g, N_A V),
       9 B per count addition into the next buffer (the 4 B read and 4 B
@@ -365,12 +382,45 @@ def update_bytes(work, species):
     return work["tets"] * (4 + 4 * species + 64) + 9 * work["additions"]
 
 
+def method_bytes(work, species, mesh_tets):
+    """Algorithmic bytes of the method's per-period update for the work
+    counted on the device (the roofline's units): 8 B per tet-species held
+    in the queue (an int32 count read and written once), 64 B per tet of
+    each distinct mesh (neighbours, weights, g, N_A V), read once per period
+    whatever the number of realizations sharing it, and 8 B per non-zero
+    transfer across a face."""
+    return 8 * species * work["tets"] + 64 * mesh_tets + 8 * work["transfers"]
+
+
+def run_small_mesh(P, W):
+    """The 1 um diffusion cube (750 tets, one species, 1000 molecules at the
+    centre) run plainly to 0.5 s: the last period is shortened to end there
+    (423 periods); a work list this small is bound by launch latency."""
+    m = W.diffusion_cube()
+    sim = P.Simulation.from_model(m)
+    sim.run_until(m.t_end)  # warm-up pass, then the same run again from the initial state
+    sim.synchronize()
+    for q in range(m.n_species):
+        sim.set_counts(q, m.init[0, q])
+    sim.set_state(0, 0.0)
+    t0 = time.perf_counter()
+    sim.run_until(m.t_end)
+    sim.synchronize()
+    dt = time.perf_counter() - t0
+    periods = sim.time()[1]
+    sim.close()
+    return {"workload": "1 um cube, 5^3 x 6 Kuhn lattice (750 tets), 1 species, 1000 molecules at the centre, "
+                        "run to 0.5 s (422 periods + 1 shortened)", "periods": periods,
+            "ms_per_period": round(dt / periods * 1e3, 5), "updates_per_s": round(periods * m.n_tets / dt, 1),
+            "wall_ms": round(dt * 1e3, 3)}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=338, help="timed periods (338 = 0.1 s of the A+B<->C system)")
-    ap.add_argument("--warmup", type=int, default=192,
-                    help="untimed periods first (the tuner's 10 chunks of 16 periods fall in them)")
+    ap.add_argument("--warmup", type=int, default=5,
+                    help="untimed periods first; the launch-shape tuner then settles in an untimed phase of its own")
     ap.add_argument("--workload", choices=["batched", "plain", "serving", "variants"], default="batched",
                     help="variants: throughput of the method options, a surface and six species (not the "
                          "headline line)")
@@ -384,6 +434,9 @@ def main():
     ap.add_argument("--seed", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-plain", action="store_true", help="skip the plain one-realization comparison")
+    ap.add_argument("--no-small", action="store_true", help="skip the small-mesh (750-tet cube) latency figure")
+    ap.add_argument("--serving-seconds", type=float, default=12.0,
+                    help="length of the serving leg of the default line (Poisson arrivals at --rate); 0 skips it")
     ap.add_argument("--cpu-periods", type=int, default=1014, help="oracle sample length (periods; 1014 = 0.3 s)")
     ap.add_argument("--traffic-from", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
                     help="no run: write the kernels' HBM traffic files from two rocprofv3 --pmc runs of "
@@ -438,7 +491,7 @@ def main():
     if args.workload == "plain" or not args.no_plain:
         m2 = W.abc_lattice()
         (s2,) = make_sims(P, [m2])
-        s2.step(Wm)
+        s2.step(max(Wm, 1))
         s2.synchronize()
         t0 = time.perf_counter()
         s2.step(K)
@@ -458,20 +511,29 @@ def main():
         models = build_batched()
         sims = make_sims(P, models)
         upd_per_period = sum(m.n_realizations * m.n_tets * m.n_species for m in models)
-        bytes_per_period = 8 * sum(m.n_realizations * m.n_tets * m.n_species for m in models)
+        bytes_per_period = 8 * upd_per_period
+        mesh_tets = sum(m.n_tets for m in models)  # tets of the distinct meshes
         e = P.rdos_engine_create(0, 0)
         if args.shape:
             P.rdos_engine_set_shape(e, *(int(v) for v in args.shape.split(",")))
-        run_engine(P, e, sims, Wm)
+        if Wm > 0:
+            run_engine(P, e, sims, Wm)
+        # untimed: the tuner settles and the chosen shape's graph is captured
+        tuning_periods = settle_engine(P, e, sims)
+        shape = P.rdos_engine_launch_shape(e)
+        log(f"launch shape ({shape['source']}) after {tuning_periods} untimed tuning periods: {shape}")
+        st0 = P.rdos_engine_stats(e)
         t0 = time.perf_counter()
         run_engine(P, e, sims, K)
         dt = time.perf_counter() - t0
+        st1 = P.rdos_engine_stats(e)
         value = K * upd_per_period / dt
         ms_step = dt / K * 1e3
-        # per-kernel durations: the same periods again, launched directly with
-        # HIP events between the scan and update launches; the scan's
-        # algorithmic bytes are counted on the state before and after them,
-        # the update's from the work it tallies on the device in these launches
+        # per-kernel durations: the same number of periods again, launched
+        # directly with HIP events between the scan and update launches (one
+        # launch of each per period, none idle); the scan's algorithmic bytes
+        # are counted on the state before and after them, the update's from
+        # the work it tallies on the device in these launches
         alg0 = scan_bytes(sims, models)
         P.rdos_engine_set_profiling(e, True)
         run_engine(P, e, sims, K)
@@ -480,51 +542,71 @@ def main():
         P.rdos_engine_set_profiling(e, False)
         alg1 = scan_bytes(sims, models)
         n_scan, n_upd = kt["scan_launches"], kt["update_launches"]
-        scan_ms = kt["scan_ms"] / max(n_scan, 1)
-        upd_ms = kt["update_ms"] / max(n_upd, 1)
-        log(f"batched: {value:.3e} upd/s, {ms_step:.3f} ms/period; scan {scan_ms:.3f} ms, update {upd_ms:.3f} ms "
-            f"per launch ({n_scan} launches); update work {work}")
+        if n_scan != K or n_upd != K:
+            raise SystemExit(f"timing pass launched {n_scan} scans and {n_upd} updates for {K} periods")
+        scan_ms = kt["scan_ms"] / n_scan
+        upd_ms = kt["update_ms"] / n_upd
+        log(f"batched: {value:.3e} upd/s, {ms_step:.4f} ms/period; scan {scan_ms:.4f} ms, update {upd_ms:.4f} ms "
+            f"per launch ({n_upd} launches); update work {work}")
         kern = {}
         for name, ms, alg in (("scan_kernel", scan_ms, 0.5 * (alg0 + alg1)),
-                              ("update_kernel", upd_ms, update_bytes(work, models[0].n_species) / max(n_upd, 1))):
+                              ("update_kernel", upd_ms, update_bytes(work, models[0].n_species) / n_upd)):
             ach = alg / (ms * 1e-3) / 1e9
             tr = traffic_from_profile(name, "batched")
-            kern[name] = {"avg_launch_ms": round(ms, 4), "algorithmic_bytes_per_launch": int(alg),
-                          "achieved": round(ach, 1), "frac": round(ach / HBM_PEAK_GBPS, 4), "traffic": tr,
-                          "traffic_GBps": round(tr / (ms * 1e-3) / 1e9, 1) if tr else None}
-            log(f"{name}: {alg:.4g} algorithmic B per launch, {ach:.1f} GB/s, measured traffic {tr}")
-        kern["update_kernel"]["queued_tets_per_launch"] = round(work["tets"] / max(n_upd, 1), 1)
-        kern["update_kernel"]["additions_per_launch"] = round(work["additions"] / max(n_upd, 1), 1)
-        dom = max(kern, key=lambda k: kern[k]["avg_launch_ms"])  # the longer kernel sets the roofline
-        d = kern[dom]
-        roof = {"bound": "hbm", "kernel": dom, "achieved": d["achieved"], "peak": HBM_PEAK_GBPS, "unit": "GB/s",
-                "frac": d["frac"], "traffic": d["traffic"],
-                "algorithmic_bytes_per_launch": d["algorithmic_bytes_per_launch"],
-                "avg_launch_ms": d["avg_launch_ms"], "traffic_GBps": d["traffic_GBps"], "kernels": kern,
+            kern[name] = {"avg_launch_ms": round(ms, 4), "own_units_bytes_per_launch": int(alg),
+                          "own_units_GBps": round(ach, 1), "own_units_frac": round(ach / HBM_PEAK_GBPS, 4),
+                          "traffic": tr, "traffic_GBps": round(tr / (ms * 1e-3) / 1e9, 1) if tr else None}
+            log(f"{name}: {alg:.4g} B per launch in its own units, {ach:.1f} GB/s, measured traffic {tr}")
+        up = kern["update_kernel"]
+        up["queued_tets_per_launch"] = round(work["tets"] / n_upd, 1)
+        up["additions_per_launch"] = round(work["additions"] / n_upd, 1)
+        up["transfers_per_launch"] = round(work["transfers"] / n_upd, 1)
+        # the roofline: the update (the longer kernel) in the method's units
+        alg = method_bytes(work, models[0].n_species, mesh_tets * n_upd) / n_upd
+        ach = alg / (upd_ms * 1e-3) / 1e9
+        roof = {"bound": "hbm", "kernel": "update_kernel", "achieved": round(ach, 1), "peak": HBM_PEAK_GBPS,
+                "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBPS, 4), "traffic": up["traffic"],
+                "algorithmic_bytes_per_launch": int(alg),
+                "units": "8 B per queued tet-species + 64 B per tet of each distinct mesh + 8 B per face transfer",
+                "avg_launch_ms": up["avg_launch_ms"], "kernels": kern,
                 "dense_bytes_per_period": bytes_per_period,
                 "dense_period_frac": round(bytes_per_period / (ms_step * 1e-3) / 1e9 / HBM_PEAK_GBPS, 4)}
-        log(f"dominant kernel {dom}; dense-equivalent period fraction {roof['dense_period_frac']}")
+        log(f"update_kernel: {alg:.4g} algorithmic B per launch (method units), {ach:.1f} GB/s, "
+            f"frac {roof['frac']}")
         try:
             roof["copy_probe_GBps"] = round(P.rdos_bandwidth_probe(0, 1 << 30, 20), 1)
         except Exception as ex:  # informational only
             log(f"bandwidth probe failed: {ex}")
-        st = P.rdos_engine_stats(e)
-        shape = P.rdos_engine_launch_shape(e)
-        log(f"launch shape ({'fixed' if args.shape else 'tuned'}): {shape}")
         P.rdos_engine_destroy(e)
-        for s in sims:
-            s.close()
+        for x in sims:
+            x.close()
         workload = ("batched A+B<->C: 256 realizations x 40^3x6 Kuhn lattice (384000 tets) + 64 x 20^3x6 "
-                    "(48000 tets), 3 species, one hipGraph-captured launch pair per period")
+                    "(48000 tets), 3 species, hipGraph-captured chunks of periods")
         config = {"workload": workload, "tets": [384000, 48000], "realizations": [256, 64], "species": 3,
                   "periods": K, "tau_s": 2.958758547680654e-4, "updates_per_period": upd_per_period,
                   "realizations_per_s": round(320.0 / (ms_step * 1e-3 * 338), 3),
-                  "engine_launches": st["launches"], "launch_shape": shape,
-                  "launch_shape_source": "fixed (--shape)" if args.shape else "tuned"}
+                  "engine_launches_timed": st1["launches"] - st0["launches"], "launch_shape": shape,
+                  "launch_shape_source": shape["source"], "tuning_periods_untimed": tuning_periods}
         if plain:
             config["plain_updates_per_s"] = round(plain["value"], 1)
             config["plain_ms_per_step"] = round(plain["ms_per_step"], 4)
             config["batched_over_plain"] = round(value / plain["value"], 2)
+
+    small = None
+    if not args.no_small:
+        small = run_small_mesh(P, W)
+        log(f"small mesh: {small['ms_per_period']:.4f} ms/period ({small['periods']} periods)")
+
+    served = None
+    if args.serving_seconds > 0:
+        sargs = argparse.Namespace(seed=args.seed, rate=args.rate, duration=args.serving_seconds,
+                                   request_steps=args.request_steps, budget_gb=args.budget_gb)
+        res = run_serving(P, sargs)
+        served = {"workload": f"Poisson {args.rate}/s arrivals for {args.serving_seconds:g} s, jittered Kuhn lattices "
+                              f"1e4-1e6 tets (log-uniform), 1-6 species, random reactions, "
+                              f"{args.request_steps} periods each, HBM budget {args.budget_gb:g} GB",
+                  **{k: (round(v, 3) if isinstance(v, float) else v) for k, v in res.items()}}
+        served["updates_per_s"] = served.pop("value")
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -550,6 +632,10 @@ def main():
         out["roofline"] = roof
     if cpu:
         out["cpu_baseline"] = cpu
+    if served:
+        out["serving"] = served
+    if small:
+        out["small_mesh"] = small
     print(json.dumps(out), flush=True)
 
 

@@ -62,7 +62,15 @@ typedef enum {
 #define RDOS_MAX_REACTIONS 16
 
 /* New simulation on HIP device `device` with n_realizations independent
- * realizations (realization r uses Philox key (seed, r)). */
+ * realizations (realization r uses Philox key (seed, r)).  Each realization is
+ * one run of Algorithm 1 from its own initial counts; the validations of
+ * Sec. III average over many such runs of one model.
+ *   out             receives the handle (NULL on failure); the caller frees it
+ *                   with rdos_destroy
+ *   n_realizations  >= 1
+ * RDOS_EINVAL for a null out or n_realizations < 1, RDOS_EDEVICE for a
+ * device index that does not exist.  No device memory is taken until
+ * rdos_finalize. */
 rdos_status rdos_create(rdos_sim **out, int device, uint64_t seed, int32_t n_realizations);
 
 /* Tetrahedral mesh (Sec. II.A: subvolumes with up to 4 face neighbours).
@@ -87,12 +95,26 @@ rdos_status rdos_set_mesh(rdos_sim *s, int32_t n_verts, const double *xyz, int32
 rdos_status rdos_set_surface_mesh(rdos_sim *s, int32_t n_verts, const double *xyz, int32_t n_tris,
                                   const int32_t *tri_verts);
 
-/* A species with diffusion coefficient D >= 0 (0 = immobile). */
+/* A species with diffusion coefficient D >= 0 in m^2/s (0 = immobile).
+ * Sec. II.A: in subvolume t the species' local diffusion rate is
+ * d = D g_t (g_t from the mesh, see rdos_finalize); the period tau and the
+ * transfer probability zeta = tau d follow from it, and Step 3 of
+ * Algorithm 1 runs for every species with D > 0.  Writes the species id
+ * (0, 1, ... in call order) to *out_id when non-NULL.  Between set_mesh and
+ * finalize; RDOS_ESTATE otherwise, RDOS_EINVAL for D < 0, a non-finite D or
+ * more than RDOS_MAX_SPECIES species. */
 rdos_status rdos_add_species(rdos_sim *s, double D, int32_t *out_id);
 
 /* A mass-action reaction with 0..2 reactants and 0..3 products (species
  * ids), rate constant k >= 0.  A reactant listed twice is a homodimer
- * reaction with k[A]^2 kinetics (propensity k N (N-1) / (N_A V)). */
+ * reaction with k[A]^2 kinetics (propensity k N (N-1) / (N_A V)).
+ * These are the reactions each subvolume's SSA fires during a period
+ * (Algorithm 1, Step 2; Sec. II.C): propensity c h with h the reactant
+ * count product and c = k N_A V (no reactant), k (one), k / (N_A V) (two),
+ * V in litres.  reac[n_reac] and prod[n_prod] are read during the call only.
+ * Writes the reaction id to *out_id when non-NULL.  Between set_mesh and
+ * finalize; RDOS_EINVAL for ids out of range, k < 0 or non-finite, or more
+ * than RDOS_MAX_REACTIONS reactions. */
 rdos_status rdos_add_reaction(rdos_sim *s, int32_t n_reac, const int32_t *reac, int32_t n_prod,
                               const int32_t *prod, double k, int32_t *out_id);
 
@@ -112,10 +134,10 @@ rdos_status rdos_add_reaction(rdos_sim *s, int32_t n_reac, const int32_t *reac, 
 rdos_status rdos_set_method(rdos_sim *s, int32_t occupancy_correction, int32_t split_threshold,
                             int32_t tau_outliers);
 
-/* Transfer form (Sec. II.B, last sentences: "take n as the total population
- * ... and reduce the weights per direction by the factor zeta ... to give
- * the same result").  0 (default): n = binomial(SR(Nbar), zeta), then the
- * multinomial split of Step 3.3.  1: SR(Nbar) split at once over the faces
+/* Transfer form (the alternative named at the end of Sec. II.B: the whole
+ * population of the subvolume is split at once, each direction's weight
+ * scaled down by zeta, which has the same law).  0 (default):
+ * n = binomial(SR(Nbar), zeta), then the multinomial split of Step 3.3.  1: SR(Nbar) split at once over the faces
  * with weights zeta w_f and "stay" with 1 - zeta; if more than the molecules
  * present would leave, those present are split as in form 0.  Same law,
  * different draws.  Before finalize; RDOS_EINVAL for other values. */
@@ -134,13 +156,21 @@ rdos_status rdos_set_reaction_region(rdos_sim *s, int32_t reaction, int32_t n_te
  * Writes tau to *out_tau when non-NULL. */
 rdos_status rdos_finalize(rdos_sim *s, double tau_scale, double *out_tau);
 
-/* Counts of one species in one realization, counts[n_tets] >= 0.  Sets the
- * state at the current period boundary. */
+/* Counts of one species in one realization, counts[n_tets] >= 0: the
+ * population N of the species in every subvolume (Sec. II.C), the state
+ * that Step 2 (SSA) and Step 3 (diffusion) of Algorithm 1 act on.  Sets the
+ * state at the current period boundary; before finalize the counts are
+ * staged on the host.  counts is copied during the call.  RDOS_EINVAL for a
+ * negative count or ids out of range, RDOS_EOVERFLOW for more than 2^30
+ * molecules of one species in one realization. */
 rdos_status rdos_set_counts(rdos_sim *s, int32_t realization, int32_t species,
                             const int32_t *counts);
 
-/* Reads counts[n_tets] at the current period boundary (synchronises).
- * RDOS_EOVERFLOW if any count overflowed since the last check. */
+/* Reads the population N of one species in every subvolume (Sec. II.C)
+ * into out[n_tets] at the current period boundary, i.e. after Step 4 of
+ * the last period run (synchronises).  RDOS_ESTATE before finalize,
+ * RDOS_EINVAL for ids out of range, RDOS_EOVERFLOW if any count overflowed
+ * since the last check. */
 rdos_status rdos_get_counts(rdos_sim *s, int32_t realization, int32_t species, int32_t *out);
 
 /* Zero-copy view: *out is the device address of counts[n_tets] (int32) of
@@ -152,10 +182,15 @@ rdos_status rdos_get_counts(rdos_sim *s, int32_t realization, int32_t species, i
  * set_counts. */
 rdos_status rdos_device_counts(rdos_sim *s, int32_t realization, int32_t species, int32_t **out);
 
-/* Resume support: the period index keys the random streams, so
- * get_counts + get_time on one handle and set_counts + set_state on a new
- * one continue bit-identically.  t is the simulated time of period
- * step_index; full periods after it end at t + i tau. */
+/* Time bookkeeping of Algorithm 1, Step 4 (t += tau after each period) and
+ * resume support.  rdos_get_time writes the simulated time t and the index
+ * of the next period to run; rdos_set_state sets both.  The period index
+ * keys the random streams, so get_counts + get_time on one handle and
+ * set_counts + set_state on a new one continue bit-identically.  t is the
+ * simulated time of period step_index; full periods after it end at
+ * t + i tau.  RDOS_EBUSY while an engine owns the simulation; set_state
+ * needs a finalized simulation (RDOS_ESTATE) and step_index >= 0, finite t
+ * (RDOS_EINVAL). */
 rdos_status rdos_set_state(rdos_sim *s, int64_t step_index, double t);
 rdos_status rdos_get_time(rdos_sim *s, double *t, int64_t *step_index);
 
@@ -229,16 +264,33 @@ rdos_status rdos_engine_kernel_times(rdos_engine *e, double *scan_ms, int64_t *s
 /* Work the timed update launches did since profiling was switched on, counted
  * on the device: `tets` tet-realization entries taken from the queue (Step 2
  * of Algorithm 1 then Step 3 for every species), `additions` molecule-count
- * additions into the next buffer (the synchronous application of Step 4, one
- * per non-empty destination).  Both are zero when profiling never ran. */
-rdos_status rdos_engine_work_counts(rdos_engine *e, int64_t *tets, int64_t *additions);
+ * additions into the next buffer (the synchronous application of all
+ * transfers of Step 3, one per non-empty destination, the molecules that stay
+ * included), `transfers` the additions across a face (Step 3.3's non-zero
+ * n_i).  All are zero when profiling never ran.  Any pointer may be NULL. */
+rdos_status rdos_engine_work_counts(rdos_engine *e, int64_t *tets, int64_t *additions, int64_t *transfers);
 
-/* The launch shape the tuner settled on for the current work list: periods
- * per graph replay, scan blocks, update blocks per queue segment, and 1 or 2
- * independent chains (halves of the realizations on two streams, so one
- * half's update overlaps the other's scan).  Results never depend on it. */
+/* Where an engine's launch shape comes from. */
+enum {
+    RDOS_SHAPE_DEFAULT = 0,  /* the tuner has not finished on this work-list size: built-in
+                                default, or the best candidate so far                    */
+    RDOS_SHAPE_TUNED = 1,    /* tuned by this engine on live work of this size           */
+    RDOS_SHAPE_CACHED = 2,   /* tuned earlier in this process (any engine) for this size */
+    RDOS_SHAPE_FIXED = 3     /* fixed by rdos_engine_set_shape                           */
+};
+
+/* The launch shape of the current work list: periods per graph replay, scan
+ * blocks, update blocks per queue segment, 1 or 2 independent chains
+ * (halves of the realizations on two streams, so one half's update overlaps
+ * the other's scan), and where it comes from (RDOS_SHAPE_*).  The tuner
+ * scores each candidate on full graph-replayed chunks of live work, per
+ * work-list size bucket (power of two of the tile count, species bound).
+ * Grids are clamped to the size bucket: never more scan wavefronts than
+ * tiles nor update block columns than queue segments.  A run's last
+ * periods, fewer than a chunk, are launched directly, as many as are left.
+ * Results never depend on the shape.  Any pointer may be NULL. */
 rdos_status rdos_engine_launch_shape(rdos_engine *e, int32_t *chunk, int32_t *scan_grid,
-                                     int32_t *update_bps, int32_t *chains);
+                                     int32_t *update_bps, int32_t *chains, int32_t *source);
 
 /* Fixes the launch shape instead of tuning it: chunk (even, 2..1024)
  * periods per graph, scan_grid (1..2^20) blocks, update_bps (1..64) update

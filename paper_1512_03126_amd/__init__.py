@@ -66,10 +66,10 @@ _SIGS = [
     ("rdos_engine_release", C.c_int, [C.c_void_p, C.c_uint64, _P(C.c_void_p)]),
     ("rdos_engine_stats", C.c_int, [C.c_void_p, _P(C.c_int64), _P(C.c_double), _P(C.c_double)]),
     ("rdos_engine_launch_shape", C.c_int, [C.c_void_p, _P(C.c_int32), _P(C.c_int32), _P(C.c_int32),
-                                           _P(C.c_int32)]),
+                                           _P(C.c_int32), _P(C.c_int32)]),
     ("rdos_engine_set_shape", C.c_int, [C.c_void_p, C.c_int32, C.c_int32, C.c_int32, C.c_int32]),
     ("rdos_engine_set_profiling", C.c_int, [C.c_void_p, C.c_int]),
-    ("rdos_engine_work_counts", C.c_int, [C.c_void_p, _P(C.c_int64), _P(C.c_int64)]),
+    ("rdos_engine_work_counts", C.c_int, [C.c_void_p, _P(C.c_int64), _P(C.c_int64), _P(C.c_int64)]),
     ("rdos_engine_kernel_times", C.c_int, [C.c_void_p, _P(C.c_double), _P(C.c_int64), _P(C.c_double),
                                            _P(C.c_int64)]),
     ("rdos_bandwidth_probe", C.c_int, [C.c_int, C.c_size_t, C.c_int, _P(C.c_double)]),
@@ -305,10 +305,15 @@ def rdos_engine_stats(engine):
     return dict(launches=n.value, updates=u.value, busy_s=b.value)
 
 
+SHAPE_SOURCES = {0: "default", 1: "tuned", 2: "cached", 3: "fixed"}
+
+
 def rdos_engine_launch_shape(engine):
-    a, b, c, d = C.c_int32(), C.c_int32(), C.c_int32(), C.c_int32()
-    _check(lib().rdos_engine_launch_shape(engine, C.byref(a), C.byref(b), C.byref(c), C.byref(d)), engine, True)
-    return dict(chunk=a.value, scan_grid=b.value, update_blocks_per_segment=c.value, chains=d.value)
+    a, b, c, d, src = C.c_int32(), C.c_int32(), C.c_int32(), C.c_int32(), C.c_int32()
+    _check(lib().rdos_engine_launch_shape(engine, C.byref(a), C.byref(b), C.byref(c), C.byref(d), C.byref(src)),
+           engine, True)
+    return dict(chunk=a.value, scan_grid=b.value, update_blocks_per_segment=c.value, chains=d.value,
+                source=SHAPE_SOURCES.get(src.value, src.value))
 
 
 def rdos_engine_set_shape(engine, chunk: int, scan_grid: int = 0, update_bps: int = 0, chains: int = 0):
@@ -329,9 +334,9 @@ def rdos_engine_kernel_times(engine):
 
 
 def rdos_engine_work_counts(engine):
-    a, b = C.c_int64(), C.c_int64()
-    _check(lib().rdos_engine_work_counts(engine, C.byref(a), C.byref(b)), engine, True)
-    return dict(tets=a.value, additions=b.value)
+    a, b, c = C.c_int64(), C.c_int64(), C.c_int64()
+    _check(lib().rdos_engine_work_counts(engine, C.byref(a), C.byref(b), C.byref(c)), engine, True)
+    return dict(tets=a.value, additions=b.value, transfers=c.value)
 
 
 def rdos_tune_split_threshold(device: int = 0, n_max: int = 48):

@@ -326,7 +326,7 @@ rdos_status enqueue_period(rdos_sim *s, int64_t period, int64_t partial, double 
     rdos_status st = ensure_mask(s);
     if (st != RDOS_OK) return st;
     HIP_TRY(s, launch_step(s->d_desc, s->d_tiles, period, partial, tau_last, s->queue, (int32_t)(s->launches & 1),
-                           s->n_tiles, s->update_bps, s->stream),
+                           scan_blocks_for(s->n_tiles), s->update_bps, s->queue.nseg, s->stream),
             "launch period");
     s->launches += 1;
     return RDOS_OK;
@@ -823,7 +823,7 @@ rdos_status rdos_set_state(rdos_sim *s, int64_t step_index, double t)
 
 rdos_status rdos_get_time(rdos_sim *s, double *t, int64_t *step_index)
 {
-    if (!s) return RDOS_EINVAL;
+    CHECK_HANDLE(s);  // an engine's worker moves the period index of the simulations it owns
     if (t) *t = time_of(s, s->step);
     if (step_index) *step_index = s->step;
     return RDOS_OK;

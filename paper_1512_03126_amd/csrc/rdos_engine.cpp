@@ -58,6 +58,19 @@ struct Shape {
     }
 };
 
+// Tuning results shared by every engine of the process, by work-list size
+// bucket: an engine that meets a bucket another engine has tuned starts
+// with its shape instead of tuning again.
+struct TuneCache {
+    std::mutex mu;
+    std::map<std::pair<int, int>, Shape> shapes;
+};
+TuneCache &tune_cache()
+{
+    static TuneCache c;
+    return c;
+}
+
 }  // namespace
 
 struct rdos_engine {
@@ -100,6 +113,9 @@ struct rdos_engine {
     int32_t max_species = 1;
     hipGraphExec_t graph = nullptr;
     Shape graph_shape{0, 0, 0, 0};
+    int32_t graph_grid_tiles = 0;  // grid_tiles the captured graph was sized for
+    int32_t grid_tiles = 1;        // launch grids serve work lists of up to this many tiles (size bucket)
+    int32_t qphase = 0;            // queue half (qsel) of the next period; graphs start at 0
     bool graph_stale = true;  // a buffer the graph names was reallocated
     bool rebuild = true;      // the slot set changed
 
@@ -112,6 +128,7 @@ struct rdos_engine {
     size_t trial = 0;  // chunks of tuning done in this bucket: candidate trial / 2
     double best_rate = -1.0;
     Shape best{16, 2048, 2, 1};
+    int32_t shape_source = RDOS_SHAPE_DEFAULT;  // where `best` comes from
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
 
     // per-kernel timing: chunks launched directly with events between launches
@@ -119,7 +136,7 @@ struct rdos_engine {
     std::vector<hipEvent_t> kev;
     double scan_ms = 0.0, update_ms = 0.0;
     int64_t scan_n = 0, update_n = 0;
-    unsigned long long *d_work = nullptr;  // [2] tets updated, count additions (timing pass only)
+    unsigned long long *d_work = nullptr;  // [3] tets updated, count additions, face transfers (timing pass only)
 
     // stats
     int64_t launches = 0;
@@ -250,38 +267,48 @@ rdos_status set_chains(rdos_engine *e, int32_t chains)
     return RDOS_OK;
 }
 
-// The launches of one chunk: a scan and an update launch per period, then
-// one launch that moves every slot's period index on by the chunk length.
-// With `timed`, events separate every launch (direct launches only: event
-// records are not captured into the graph).
-hipError_t enqueue_chunk(rdos_engine *e, const Shape &sh, bool timed)
+// Launch grids for the current size bucket: no more scan wavefronts than
+// tiles, no more update block columns than queue segments.
+int32_t scan_grid_of(const rdos_engine *e, const Shape &sh)
+{
+    return std::min(sh.scan_grid, scan_blocks_for(e->grid_tiles));
+}
+int32_t update_segments_of(const rdos_engine *e) { return std::min<int32_t>(e->grid_tiles, kMaxSegments); }
+
+// The launches of `len` periods: a scan and an update launch per period, the
+// first on queue half `phase`, then one launch that moves every slot's
+// period index on by `len`.  With `timed`, events separate every launch
+// (direct launches only: event records are not captured into the graph).
+hipError_t enqueue_periods(rdos_engine *e, const Shape &sh, int32_t len, int32_t phase, bool timed)
 {
     hipError_t err = hipSuccess;
+    const int32_t sg = scan_grid_of(e, sh), gseg = update_segments_of(e);
     if (sh.chains == 2) {
         // two independent chains: fork the second stream off the first, join before the advance
         err = hipEventRecord(e->fork, e->stream);
         if (err == hipSuccess) err = hipStreamWaitEvent(e->stream2, e->fork, 0);
-        for (int32_t i = 0; i < sh.chunk && err == hipSuccess; ++i) {
-            err = launch_step(e->d_sims, e->d_tiles, i, -1, 0.0, e->queue, i & 1, sh.scan_grid, sh.update_bps,
-                              e->stream);
+        for (int32_t i = 0; i < len && err == hipSuccess; ++i) {
+            const int32_t qs = (phase + i) & 1;
+            err = launch_step(e->d_sims, e->d_tiles, i, -1, 0.0, e->queue, qs, sg, sh.update_bps, gseg, e->stream);
             if (err == hipSuccess)
-                err = launch_step(e->d_sims, e->d_tiles, i, -1, 0.0, e->queue2, i & 1, sh.scan_grid,
-                                  sh.update_bps, e->stream2);
+                err = launch_step(e->d_sims, e->d_tiles, i, -1, 0.0, e->queue2, qs, sg, sh.update_bps, gseg,
+                                  e->stream2);
         }
         if (err == hipSuccess) err = hipEventRecord(e->join, e->stream2);
         if (err == hipSuccess) err = hipStreamWaitEvent(e->stream, e->join, 0);
-        if (err == hipSuccess) err = launch_advance(e->d_sims, e->queue.hdr, sh.chunk, e->stream);
+        if (err == hipSuccess) err = launch_advance(e->d_sims, e->queue.hdr, len, e->stream);
         return err;
     }
     if (timed) err = hipEventRecord(e->kev[0], e->stream);
-    for (int32_t i = 0; i < sh.chunk && err == hipSuccess; ++i) {
-        err = launch_scan(e->d_sims, e->d_tiles, i, e->queue, i & 1, sh.scan_grid, e->stream);
+    for (int32_t i = 0; i < len && err == hipSuccess; ++i) {
+        const int32_t qs = (phase + i) & 1;
+        err = launch_scan(e->d_sims, e->d_tiles, i, e->queue, qs, sg, e->stream);
         if (err == hipSuccess && timed) err = hipEventRecord(e->kev[2 * i + 1], e->stream);
         if (err == hipSuccess)
-            err = launch_update(e->d_sims, e->d_tiles, i, -1, 0.0, e->queue, i & 1, sh.update_bps, e->stream);
+            err = launch_update(e->d_sims, e->d_tiles, i, -1, 0.0, e->queue, qs, sh.update_bps, gseg, e->stream);
         if (err == hipSuccess && timed) err = hipEventRecord(e->kev[2 * i + 2], e->stream);
     }
-    if (err == hipSuccess) err = launch_advance(e->d_sims, e->queue.hdr, sh.chunk, e->stream);
+    if (err == hipSuccess) err = launch_advance(e->d_sims, e->queue.hdr, len, e->stream);
     return err;
 }
 
@@ -294,7 +321,7 @@ rdos_status capture(rdos_engine *e, const Shape &sh)
     }
     hipGraph_t g = nullptr;
     ENGINE_HIP(e, hipStreamBeginCapture(e->stream, hipStreamCaptureModeThreadLocal), "begin capture");
-    hipError_t err = enqueue_chunk(e, sh, false);
+    hipError_t err = enqueue_periods(e, sh, sh.chunk, 0, false);
     hipError_t err2 = hipStreamEndCapture(e->stream, &g);
     if (err != hipSuccess || err2 != hipSuccess) {
         if (g) (void)hipGraphDestroy(g);
@@ -304,6 +331,7 @@ rdos_status capture(rdos_engine *e, const Shape &sh)
     (void)hipGraphDestroy(g);
     if (err != hipSuccess) return efail(e, RDOS_EDEVICE, "instantiate: %s", hipGetErrorString(err));
     e->graph_shape = sh;
+    e->graph_grid_tiles = e->grid_tiles;
     e->graph_stale = false;
     return RDOS_OK;
 }
@@ -416,17 +444,37 @@ void worker_main(rdos_engine *e)
                 break;
             }
             e->rebuild = false;
-            const std::pair<int, int> b{(int)std::ilogb((double)std::max(e->n_tiles, 1)),
-                                        species_bound(e->max_species)};
+            const int lg = (int)std::ilogb((double)std::max(e->n_tiles, 1));
+            const std::pair<int, int> b{lg, species_bound(e->max_species)};
+            // launch grids cover every work list of this size bucket
+            e->grid_tiles = (int32_t)std::min<int64_t>(int64_t(1) << (lg + 1), int64_t(1) << 30);
             if (b != e->bucket) {
                 e->bucket = b;
                 auto hit = e->tuned.find(b);
-                if (hit != e->tuned.end()) {
-                    e->best = hit->second;
+                bool found = hit != e->tuned.end();
+                Shape cached{};
+                if (found) {
+                    cached = hit->second;
+                } else {
+                    TuneCache &tc = tune_cache();
+                    std::lock_guard<std::mutex> g(tc.mu);
+                    auto it = tc.shapes.find(b);
+                    if (it != tc.shapes.end()) {
+                        found = true;
+                        cached = it->second;
+                        e->tuned[b] = cached;
+                    }
+                }
+                if (found) {
+                    if (!e->fixed_shape) {
+                        e->best = cached;
+                        e->shape_source = RDOS_SHAPE_CACHED;
+                    }
                     e->trial = 2 * e->candidates.size();
                 } else {
                     e->trial = 0;
                     e->best_rate = -1.0;
+                    if (!e->fixed_shape) e->shape_source = RDOS_SHAPE_DEFAULT;
                 }
             }
         }
@@ -439,11 +487,24 @@ void worker_main(rdos_engine *e)
             fail_slots(e);
             break;
         }
+        // A full chunk replays the captured graph, which starts on queue half
+        // 0.  The last periods of the slots (fewer than a chunk) are launched
+        // directly, as many as are left, so no launch runs idle; after an odd
+        // number of them one direct period puts the queue halves back in step
+        // with the graph.  The timing pass always launches directly.
+        int64_t left_max = 1;
+        for (uint64_t id : e->slots) {
+            const Ticket &tk = e->tickets[id];
+            left_max = std::max<int64_t>(left_max, tk.end_step - tk.sim->step);
+        }
+        bool replay = !timed && e->qphase == 0 && left_max >= sh.chunk;
+        int32_t len = replay ? sh.chunk : (int32_t)std::min<int64_t>(left_max, sh.chunk);
+        if (!replay && !timed && e->qphase == 1 && left_max >= sh.chunk) len = 1;
         // the timing pass launches directly and tallies its work; captured graphs never do
         e->queue.work = e->queue2.work = timed ? e->d_work : nullptr;
         if (timed) {
             bool ok = true;
-            while (ok && (int32_t)e->kev.size() < 2 * sh.chunk + 1) {
+            while (ok && (int32_t)e->kev.size() < 2 * len + 1) {
                 hipEvent_t ev;
                 ok = hipEventCreate(&ev) == hipSuccess;
                 if (ok) e->kev.push_back(ev);
@@ -453,7 +514,8 @@ void worker_main(rdos_engine *e)
                 fail_slots(e);
                 break;
             }
-        } else if (!e->graph || e->graph_stale || !(sh == e->graph_shape)) {
+        } else if (replay && (!e->graph || e->graph_stale || !(sh == e->graph_shape) ||
+                              e->graph_grid_tiles != e->grid_tiles)) {
             if (capture(e, sh) != RDOS_OK) {
                 fail_slots(e);
                 break;
@@ -463,11 +525,13 @@ void worker_main(rdos_engine *e)
         for (uint64_t id : e->slots) {
             Ticket &tk = e->tickets[id];
             const int64_t left = tk.end_step - tk.sim->step;
-            work += slot_updates(tk.sim) * (double)std::min<int64_t>(left, sh.chunk);
+            work += slot_updates(tk.sim) * (double)std::min<int64_t>(left, len);
         }
+        const int32_t phase = e->qphase;
         lk.unlock();
         hipError_t err = hipEventRecord(e->ev0, e->stream);
-        if (err == hipSuccess) err = timed ? enqueue_chunk(e, sh, true) : hipGraphLaunch(e->graph, e->stream);
+        if (err == hipSuccess)
+            err = replay ? hipGraphLaunch(e->graph, e->stream) : enqueue_periods(e, sh, len, phase, timed);
         if (err == hipSuccess) err = hipEventRecord(e->ev1, e->stream);
         if (err == hipSuccess) err = hipEventSynchronize(e->ev1);
         float ms = 0.f;
@@ -478,8 +542,9 @@ void worker_main(rdos_engine *e)
             fail_slots(e);
             break;
         }
+        e->qphase = (phase + len) & 1;
         if (timed) {
-            for (int32_t i = 0; i < sh.chunk; ++i) {
+            for (int32_t i = 0; i < len; ++i) {
                 float a = 0.f, b = 0.f;
                 if (hipEventElapsedTime(&a, e->kev[2 * i], e->kev[2 * i + 1]) == hipSuccess &&
                     hipEventElapsedTime(&b, e->kev[2 * i + 1], e->kev[2 * i + 2]) == hipSuccess) {
@@ -491,15 +556,21 @@ void worker_main(rdos_engine *e)
             }
         }
         const double rate = ms > 0.f ? work / (double)ms : 0.0;
-        if (tuning) {
+        if (tuning && replay) {  // only full graph-replayed chunks are scored
             if ((e->trial & 1) && rate > e->best_rate) {  // the candidate's second chunk
                 e->best_rate = rate;
                 e->best = sh;
             }
             ++e->trial;
-            if (e->trial == 2 * e->candidates.size()) e->tuned[e->bucket] = e->best;
+            if (e->trial == 2 * e->candidates.size()) {
+                e->tuned[e->bucket] = e->best;
+                e->shape_source = RDOS_SHAPE_TUNED;
+                TuneCache &tc = tune_cache();
+                std::lock_guard<std::mutex> g(tc.mu);
+                tc.shapes[e->bucket] = e->best;
+            }
         }
-        e->launches += sh.chunk;
+        e->launches += len;
         e->updates += work;
         e->busy_s += ms * 1e-3;
         // progress and retirement
@@ -508,7 +579,7 @@ void worker_main(rdos_engine *e)
         for (uint64_t id : e->slots) {
             Ticket &tk = e->tickets[id];
             rdos_sim *s = tk.sim;
-            s->step = std::min<int64_t>(s->step + sh.chunk, tk.end_step);
+            s->step = std::min<int64_t>(s->step + len, tk.end_step);
             if (s->step >= tk.end_step) {
                 tk.done = true;
                 tk.finished = now;
@@ -650,7 +721,7 @@ rdos_status rdos_engine_stats(rdos_engine *e, int64_t *launches, double *updates
 }
 
 rdos_status rdos_engine_launch_shape(rdos_engine *e, int32_t *chunk, int32_t *scan_grid, int32_t *update_bps,
-                                     int32_t *chains)
+                                     int32_t *chains, int32_t *source)
 {
     if (!e) return RDOS_EINVAL;
     std::lock_guard<std::mutex> g(e->mu);
@@ -658,6 +729,7 @@ rdos_status rdos_engine_launch_shape(rdos_engine *e, int32_t *chunk, int32_t *sc
     if (scan_grid) *scan_grid = e->best.scan_grid;
     if (update_bps) *update_bps = e->best.update_bps;
     if (chains) *chains = e->best.chains;
+    if (source) *source = e->shape_source;
     return RDOS_OK;
 }
 
@@ -670,6 +742,8 @@ rdos_status rdos_engine_set_shape(rdos_engine *e, int32_t chunk, int32_t scan_gr
     if (chunk == 0) {  // back to tuning
         e->fixed_shape = false;
         e->bucket = {-1, -1};
+        e->rebuild = true;  // the worker re-enters the size bucket (cache or tuner)
+        e->shape_source = RDOS_SHAPE_DEFAULT;
         return RDOS_OK;
     }
     if (chunk % 2 != 0 || chunk > 1024 || scan_grid < 1 || scan_grid > (1 << 20) || update_bps < 1 ||
@@ -677,6 +751,7 @@ rdos_status rdos_engine_set_shape(rdos_engine *e, int32_t chunk, int32_t scan_gr
         return efail(e, RDOS_EINVAL, "launch shape out of range");
     e->best = Shape{chunk, scan_grid, update_bps, chains};
     e->fixed_shape = true;
+    e->shape_source = RDOS_SHAPE_FIXED;
     return RDOS_OK;
 }
 
@@ -688,12 +763,12 @@ rdos_status rdos_engine_set_profiling(rdos_engine *e, int on)
         hipError_t err;
         {
             std::lock_guard<std::mutex> dg(device_api_mutex());
-            err = hipMalloc(&e->d_work, 2 * sizeof(unsigned long long));
+            err = hipMalloc(&e->d_work, 3 * sizeof(unsigned long long));
         }
         if (err != hipSuccess) return efail(e, RDOS_ENOMEM, "work counters: %s", hipGetErrorString(err));
     }
     if (on) {
-        ENGINE_HIP(e, hipMemsetAsync(e->d_work, 0, 2 * sizeof(unsigned long long), e->stream), "clear work counters");
+        ENGINE_HIP(e, hipMemsetAsync(e->d_work, 0, 3 * sizeof(unsigned long long), e->stream), "clear work counters");
         ENGINE_HIP(e, hipStreamSynchronize(e->stream), "clear work counters");
     }
     e->profiling = on != 0;
@@ -702,17 +777,18 @@ rdos_status rdos_engine_set_profiling(rdos_engine *e, int on)
     return RDOS_OK;
 }
 
-rdos_status rdos_engine_work_counts(rdos_engine *e, int64_t *tets, int64_t *additions)
+rdos_status rdos_engine_work_counts(rdos_engine *e, int64_t *tets, int64_t *additions, int64_t *transfers)
 {
     if (!e) return RDOS_EINVAL;
     std::lock_guard<std::mutex> g(e->mu);
-    unsigned long long w[2] = {0, 0};
+    unsigned long long w[3] = {0, 0, 0};
     if (e->d_work) {
         ENGINE_HIP(e, hipMemcpyAsync(w, e->d_work, sizeof w, hipMemcpyDeviceToHost, e->stream), "read work counters");
         ENGINE_HIP(e, hipStreamSynchronize(e->stream), "read work counters");
     }
     if (tets) *tets = (int64_t)w[0];
     if (additions) *additions = (int64_t)w[1];
+    if (transfers) *transfers = (int64_t)w[2];
     return RDOS_OK;
 }
 

@@ -126,7 +126,8 @@ struct QueueView {
     int64_t qcap;       // allocated entries per count row
     int32_t species;    // allocated count rows
     int32_t scaled;     // some simulation of the work list uses transfer form 1 (picks the update kernel)
-    unsigned long long *work;  // null, or [2] device totals the update kernel adds to: tets, count additions
+    unsigned long long *work;  // null, or [3] device totals the update kernel adds to: tets, count additions,
+                               // additions that are transfers across a face
 };
 constexpr int kMaxSegments = 1024;
 constexpr int kLenStride = 32;  // 128 bytes between segment lengths: no two share a line
@@ -146,11 +147,21 @@ inline void queue_shape(int64_t n_tiles, int32_t *nseg, int32_t *seg_cap)
 // scan_grid blocks stride over the tiles named in q.hdr (> 0 required).
 hipError_t launch_scan(const DevSim *sims, const Tile *tiles, int64_t iter, const QueueView &q, int32_t qsel,
                        int32_t scan_grid, hipStream_t st);
+// The update grid is grid_segments (1..kMaxSegments) x blocks_per_segment
+// blocks; block columns stride over the segments in use, so a grid with
+// fewer columns than segments is still complete.
 hipError_t launch_update(const DevSim *sims, const Tile *tiles, int64_t iter, int64_t partial, double tau_last,
-                         const QueueView &q, int32_t qsel, int32_t blocks_per_segment, hipStream_t st);
+                         const QueueView &q, int32_t qsel, int32_t blocks_per_segment, int32_t grid_segments,
+                         hipStream_t st);
 hipError_t launch_step(const DevSim *sims, const Tile *tiles, int64_t iter, int64_t partial, double tau_last,
                        const QueueView &q, int32_t qsel, int32_t scan_grid, int32_t blocks_per_segment,
-                       hipStream_t st);
+                       int32_t grid_segments, hipStream_t st);
+// Scan blocks needed to give every tile of a work list its own wavefront.
+inline int32_t scan_blocks_for(int64_t n_tiles)
+{
+    const int64_t b = (n_tiles + kBlock / 64 - 1) / (kBlock / 64);
+    return (int32_t)(b < 1 ? 1 : (b > (1 << 20) ? (1 << 20) : b));
+}
 hipError_t launch_advance(DevSim *sims, const WorkHeader *hdr, int64_t by, hipStream_t st);
 // Rebuilds the occupancy bytes of buf[parity] from the counts of every
 // realization and species and clears those of the other buffer (after

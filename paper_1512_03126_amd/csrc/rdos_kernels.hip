@@ -281,8 +281,10 @@ hipError_t launch_tau_select(const MeshRec *mesh, int32_t T, const double *D, in
 // ---------------------------------------------------------------------------
 // Per-lane working state lives in LDS slots with a stride of kBlock between
 // species, so species can be indexed at run time without private memory.
-// per-block tallies of the update kernel in the timing pass (its queue's `work` set)
-__shared__ uint32_t block_tets, block_adds;
+// per-block tallies of the update kernel in the timing pass (its queue's `work` set):
+// tets taken from the queue, count additions, and the additions that are
+// transfers across a face
+__shared__ uint32_t block_tets, block_adds, block_moves;
 
 struct LaneState {
     int32_t *N;     // counts during the period
@@ -480,7 +482,10 @@ __device__ __forceinline__ void update_tet(const DevSim &sm, int32_t t, int64_t 
                     if (out[f] > 0) {
                         atomicAdd(&nxt[(uint32_t)(s * Tp + nb[f])], (int32_t)out[f]);
                         mnxt[(uint32_t)(s * sm.mstride + (nb[f] >> 2))] = mark;
-                        if (tally) atomicAdd(&block_adds, 1u);
+                        if (tally) {
+                            atomicAdd(&block_adds, 1u);
+                            atomicAdd(&block_moves, 1u);
+                        }
                     }
                 ls.n(s) = Ns - (int32_t)n;
             }
@@ -495,8 +500,8 @@ __device__ __forceinline__ void update_tet(const DevSim &sm, int32_t t, int64_t 
 
 // Each period is two launches.
 //  scan:   one wavefront per tile of 1024 tets.  Each lane sweeps the
-//          occupancy bytes of 16 tets (four groups of four) and clears them;
-//          the tile's flagged groups are ranked over the wavefront and
+//          occupancy bytes of 16 tets (four groups of four) and compares
+//          them with the period's tag; the tile's flagged groups are ranked over the wavefront and
 //          listed in LDS, and the lanes then take the listed groups in turn:
 //          a lane reads its group's flagged count vectors (16 bytes per
 //          species), the group's tets that hold any molecule (all of them if
@@ -524,7 +529,7 @@ struct Queue {
     int32_t *counts;  // [rows][qcap]
     int32_t *len;     // [2][kMaxSegments] * kLenStride
     const WorkHeader *hdr;
-    unsigned long long *work;  // null, or [2] totals of the timing pass: tets updated, count additions
+    unsigned long long *work;  // null, or [3] totals of the timing pass: tets updated, count additions, face transfers
     int32_t rows;     // count rows allocated: at least the species of every simulation served
 };
 
@@ -717,7 +722,7 @@ __global__ __launch_bounds__(kBlock) void scan_kernel(const DevSim *__restrict__
 template <bool ANY_SCALED, int KS>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(KS <= 6 && !ANY_SCALED ? 4 : 3))) void
 update_kernel(const DevSim *__restrict__ sims, const Tile *__restrict__ tiles, Queue q, int32_t qsel, int64_t iter,
-              int64_t partial, double tau_last)
+              int64_t partial, double tau_last, int32_t grid_segments)
 {
     __shared__ double occ[KS * kBlock];
     __shared__ double last[KS * kBlock];
@@ -726,57 +731,66 @@ update_kernel(const DevSim *__restrict__ sims, const Tile *__restrict__ tiles, Q
     if (blockIdx.x == 0)
         for (int k = threadIdx.x; k < kMaxSegments; k += kBlock) q.len[((qsel ^ 1) * kMaxSegments + k) * kLenStride] = 0;
     const WorkHeader h = *q.hdr;
-    const int32_t seg = blockIdx.x % kMaxSegments;   // the grid is kMaxSegments * blocks-per-segment
-    const int32_t per_seg = max(1, (int32_t)(gridDim.x / kMaxSegments));
-    const int32_t part = blockIdx.x / kMaxSegments;
-    if (seg >= h.nseg || part >= per_seg) return;  // uniform over the block
+    // The grid is grid_segments x blocks-per-segment; block b works on
+    // segments b % grid_segments, + grid_segments, ... so any grid covers
+    // every segment in use (the host sizes it to the work list, one
+    // segment per block column when it can).
+    const int32_t per_seg = max(1, (int32_t)(gridDim.x / grid_segments));
+    const int32_t part = blockIdx.x / grid_segments;
+    if (part >= per_seg) return;  // uniform over the block
     const bool tally = q.work != nullptr;
     if (tally) {
-        if (threadIdx.x == 0) block_tets = block_adds = 0;
+        if (threadIdx.x == 0) block_tets = block_adds = block_moves = 0;
         __syncthreads();
     }
-    const int32_t n = min(q.len[(qsel * kMaxSegments + seg) * kLenStride], h.seg_cap);
-    const int32_t stride = per_seg * kBlock;
-    const int64_t seg0 = (int64_t)seg * h.seg_cap;
-    // each lane's next queue entry is read one tet ahead, so that it arrives
-    // with the loads of the tet before it instead of starting a round trip
-    int32_t next = part * kBlock + (int32_t)threadIdx.x < n ? q.tet[seg0 + part * kBlock + threadIdx.x] : 0;
-    for (int32_t i = part * kBlock + threadIdx.x; i < n; i += stride) {
-        if (tally) atomicAdd(&block_tets, 1u);
-        const int64_t idx = seg0 + i;
-        const int32_t entry = next;
-        // the entry's count rows are read with its tile and the next entry,
-        // not after the simulation is known.  Every load is issued (slots past
-        // the queue's rows repeat its last row), so none waits behind a
-        // branch; slots past a simulation's S hold values it never reads.
-        int32_t cn[KS];
+    for (int32_t seg = blockIdx.x % grid_segments; seg < h.nseg; seg += grid_segments) {
+        const int32_t n = min(q.len[(qsel * kMaxSegments + seg) * kLenStride], h.seg_cap);
+        const int32_t stride = per_seg * kBlock;
+        const int64_t seg0 = (int64_t)seg * h.seg_cap;
+        // each lane's next queue entry is read one tet ahead, so that it
+        // arrives with the loads of the tet before it instead of starting a
+        // round trip
+        int32_t next = part * kBlock + (int32_t)threadIdx.x < n ? q.tet[seg0 + part * kBlock + threadIdx.x] : 0;
+        for (int32_t i = part * kBlock + threadIdx.x; i < n; i += stride) {
+            if (tally) atomicAdd(&block_tets, 1u);
+            const int64_t idx = seg0 + i;
+            const int32_t entry = next;
+            // the entry's count rows are read with its tile and the next
+            // entry, not after the simulation is known.  Every load is
+            // issued (slots past the queue's rows repeat its last row), so
+            // none waits behind a branch; slots past a simulation's S hold
+            // values it never reads.
+            int32_t cn[KS];
 #pragma unroll
-        for (int s = 0; s < KS; ++s) cn[s] = q.counts[min(s, q.rows - 1) * h.qcap + idx];
-        const Tile tile = tiles[h.tile0 + entry / kTetsPerTile];
-        next = i + stride < n ? q.tet[idx + stride] : 0;
+            for (int s = 0; s < KS; ++s) cn[s] = q.counts[min(s, q.rows - 1) * h.qcap + idx];
+            const Tile tile = tiles[h.tile0 + entry / kTetsPerTile];
+            next = i + stride < n ? q.tet[idx + stride] : 0;
 #pragma unroll
-        for (int s = 0; s < KS; ++s) ls.n(s) = cn[s];
-        // lanes of one simulation run together with a wavefront-uniform
-        // descriptor (one round when the wavefront holds one simulation);
-        // descriptors do not change during a launch, so they are read as
-        // constant memory, which lets the uniform reads be scalar loads
-        using ConstSim = const __attribute__((address_space(4))) DevSim;
-        for (uint64_t todo = __ballot(1); todo;) {
-            const int32_t first = __builtin_amdgcn_readlane(tile.sim, (int32_t)__builtin_ctzll(todo));
-            // branch on the lane's ballot bit, not on the equality, so that the
-            // compiler cannot put the lane's own index in place of `first`
-            const uint64_t same = __ballot(tile.sim == first);
-            todo &= ~same;
-            if (!((same >> __lane_id()) & 1ull)) continue;
-            const DevSim &sm = *(const DevSim *)((ConstSim *)sims + first);
-            const int64_t period = sm.step0 + iter;
-            const double tau_k = period == partial ? tau_last : sm.tau;
-            const int64_t Tp = ((int64_t)sm.T + 3) & ~(int64_t)3;
-            const int64_t base = (int64_t)tile.realization * sm.S * Tp;
-            update_tet<ANY_SCALED>(sm, tile.tet0 + entry % kTetsPerTile, period, tau_k, sm.key1 ^ (uint32_t)tile.realization,
-                       sm.buf[(period + 1) & 1] + base, (int32_t)Tp,
-                       sm.mask[(period + 1) & 1] + (int64_t)tile.realization * sm.S * sm.mstride,
-                       occupancy_tag(period + 1), ls, tally);
+            for (int s = 0; s < KS; ++s) ls.n(s) = cn[s];
+            // lanes of one simulation run together with a wavefront-uniform
+            // descriptor (one round when the wavefront holds one simulation);
+            // descriptors do not change during a launch, so they are read as
+            // constant memory, which lets the uniform reads be scalar loads
+            using ConstSim = const __attribute__((address_space(4))) DevSim;
+            for (uint64_t todo = __ballot(1); todo;) {
+                const int32_t first = __builtin_amdgcn_readlane(tile.sim, (int32_t)__builtin_ctzll(todo));
+                // branch on the lane's ballot bit, not on the equality, so
+                // that the compiler cannot put the lane's own index in place
+                // of `first`
+                const uint64_t same = __ballot(tile.sim == first);
+                todo &= ~same;
+                if (!((same >> __lane_id()) & 1ull)) continue;
+                const DevSim &sm = *(const DevSim *)((ConstSim *)sims + first);
+                const int64_t period = sm.step0 + iter;
+                const double tau_k = period == partial ? tau_last : sm.tau;
+                const int64_t Tp = ((int64_t)sm.T + 3) & ~(int64_t)3;
+                const int64_t base = (int64_t)tile.realization * sm.S * Tp;
+                update_tet<ANY_SCALED>(sm, tile.tet0 + entry % kTetsPerTile, period, tau_k,
+                                       sm.key1 ^ (uint32_t)tile.realization, sm.buf[(period + 1) & 1] + base,
+                                       (int32_t)Tp,
+                                       sm.mask[(period + 1) & 1] + (int64_t)tile.realization * sm.S * sm.mstride,
+                                       occupancy_tag(period + 1), ls, tally);
+            }
         }
     }
     if (tally) {
@@ -784,6 +798,7 @@ update_kernel(const DevSim *__restrict__ sims, const Tile *__restrict__ tiles, Q
         if (threadIdx.x == 0) {
             atomicAdd(&q.work[0], (unsigned long long)block_tets);
             atomicAdd(&q.work[1], (unsigned long long)block_adds);
+            atomicAdd(&q.work[2], (unsigned long long)block_moves);
         }
     }
 }
@@ -808,38 +823,46 @@ hipError_t launch_scan(const DevSim *sims, const Tile *tiles, int64_t iter, cons
 }
 
 hipError_t launch_update(const DevSim *sims, const Tile *tiles, int64_t iter, int64_t partial, double tau_last,
-                         const QueueView &qv, int32_t qsel, int32_t blocks_per_segment, hipStream_t st)
+                         const QueueView &qv, int32_t qsel, int32_t blocks_per_segment, int32_t grid_segments,
+                         hipStream_t st)
 {
+    if (grid_segments < 1 || grid_segments > kMaxSegments) return hipErrorInvalidValue;
     const Queue q{qv.tet, qv.counts, qv.len, qv.hdr, qv.work, qv.species};
     const int32_t bps = blocks_per_segment > 0 ? blocks_per_segment : 1;
-    const dim3 grid(kMaxSegments * bps);
+    const dim3 grid(grid_segments * bps);
     // the queue's species rows bound the species of every simulation it serves
     if (qv.species <= 4) {
         if (qv.scaled)
-            update_kernel<true, 4><<<grid, kBlock, 0, st>>>(sims, tiles, q, qsel, iter, partial, tau_last);
+            update_kernel<true, 4><<<grid, kBlock, 0, st>>>(sims, tiles, q, qsel, iter, partial, tau_last,
+                                                                grid_segments);
         else
-            update_kernel<false, 4><<<grid, kBlock, 0, st>>>(sims, tiles, q, qsel, iter, partial, tau_last);
+            update_kernel<false, 4><<<grid, kBlock, 0, st>>>(sims, tiles, q, qsel, iter, partial, tau_last,
+                                                                grid_segments);
     } else if (qv.species <= 6) {
         if (qv.scaled)
-            update_kernel<true, 6><<<grid, kBlock, 0, st>>>(sims, tiles, q, qsel, iter, partial, tau_last);
+            update_kernel<true, 6><<<grid, kBlock, 0, st>>>(sims, tiles, q, qsel, iter, partial, tau_last,
+                                                                grid_segments);
         else
-            update_kernel<false, 6><<<grid, kBlock, 0, st>>>(sims, tiles, q, qsel, iter, partial, tau_last);
+            update_kernel<false, 6><<<grid, kBlock, 0, st>>>(sims, tiles, q, qsel, iter, partial, tau_last,
+                                                                grid_segments);
     } else {
         if (qv.scaled)
-            update_kernel<true, kMaxSpecies><<<grid, kBlock, 0, st>>>(sims, tiles, q, qsel, iter, partial, tau_last);
+            update_kernel<true, kMaxSpecies><<<grid, kBlock, 0, st>>>(sims, tiles, q, qsel, iter, partial, tau_last,
+                                                                grid_segments);
         else
-            update_kernel<false, kMaxSpecies><<<grid, kBlock, 0, st>>>(sims, tiles, q, qsel, iter, partial, tau_last);
+            update_kernel<false, kMaxSpecies><<<grid, kBlock, 0, st>>>(sims, tiles, q, qsel, iter, partial, tau_last,
+                                                                grid_segments);
     }
     return hipGetLastError();
 }
 
 hipError_t launch_step(const DevSim *sims, const Tile *tiles, int64_t iter, int64_t partial, double tau_last,
                        const QueueView &qv, int32_t qsel, int32_t scan_grid, int32_t blocks_per_segment,
-                       hipStream_t st)
+                       int32_t grid_segments, hipStream_t st)
 {
     hipError_t e = launch_scan(sims, tiles, iter, qv, qsel, scan_grid, st);
     if (e != hipSuccess) return e;
-    return launch_update(sims, tiles, iter, partial, tau_last, qv, qsel, blocks_per_segment, st);
+    return launch_update(sims, tiles, iter, partial, tau_last, qv, qsel, blocks_per_segment, grid_segments, st);
 }
 
 // Streaming copy used to measure the device's achievable HBM bandwidth (and

@@ -85,3 +85,88 @@ def test_split_threshold_tuner():
     assert one[n_max - 1] > 4 * one[3]    # one draw per molecule: cost grows with n
     with pytest.raises(P.RdosError):
         P.rdos_tune_split_threshold(0, 1)
+
+
+# Wider chemistries for the kernel instances sized for 5-6 and 7-8 species
+# (per-lane LDS and register budget depend on the species bound): A+B<->C,
+# a conversion chain, a pair that consumes and a homodimer that produces.
+WIDE_RX = {
+    6: [([0, 1], [2], 3e8), ([2], [0, 1], 400.0), ([3], [4], 60.0), ([4, 5], [3], 2e8), ([5, 5], [1], 1e8),
+        ([1], [5], 20.0)],
+    8: [([0, 1], [2], 3e8), ([2], [0, 1], 400.0), ([3], [4], 60.0), ([4, 5], [3], 2e8), ([5, 5], [1], 1e8),
+        ([6], [7], 30.0), ([7], [6], 25.0), ([6, 7], [], 1e8), ([1], [5], 20.0)],
+}
+
+
+@pytest.mark.parametrize("S,form,occ,thr", [(5, 1, True, 10), (6, 1, True, 3), (6, 0, True, 10),
+                                            (7, 1, False, 10), (8, 1, True, 40), (8, 0, True, 2)])
+def test_wide_chemistry_every_period(orc, S, form, occ, thr):
+    """Transfer form 1 (the closing alternative of Sec. II.B) and form 0 with
+    5-8 species: the update instances for the 6- and 8-species bounds and
+    the matching scan instances, bit for bit against the oracle after every
+    one of 32 periods (Algorithm 1, Steps 2-3)."""
+    import paper_1512_03126_amd as P
+
+    bound = 6 if S <= 6 else 8
+    rx = [r for r in WIDE_RX[bound] if max(r[0] + r[1] + [0]) < S]
+    Ds = [1e-12, 2e-12, 0.5e-12, 3e-12, 1.5e-12, 0.0, 4e-12, 1e-12][:S]
+    xyz, tets = W.tiny_lattice(3, 0.2e-6, jitter_frac=0.2, seed=11 + S)
+    T = tets.shape[0]
+    rng = np.random.default_rng(100 * S + thr)
+    init = rng.integers(0, 25, size=(2, S, T)).astype(np.int32)
+    init[:, 0, ::4] += 150           # the sequential-binomial branch
+    init[:, S - 1, 1::5] += 60
+    note(f"wide chemistry: {S} species, {len(rx)} reactions, transfer form {form}, occ={occ}, threshold {thr}")
+    g = P.Simulation(xyz, tets, Ds, rx, seed=21 + S, n_realizations=2, occupancy_correction=occ,
+                     split_threshold=thr, transfer_form=form)
+    os_ = []
+    for r in range(2):
+        o = orc.OracleSim(xyz, tets, Ds, rx, seed=21 + S, realization=r)
+        o.set_first_order(not occ)
+        o.set_split_threshold(thr)
+        o.set_transfer_form(form)
+        for q in range(S):
+            o.set_counts(q, init[r, q])
+            g.set_counts(q, init[r, q], realization=r)
+        os_.append(o)
+    assert g.tau == os_[0].tau
+    for period in range(32):
+        g.step(1)
+        for r, o in enumerate(os_):
+            o.step()
+            got, want = g.get_counts(None, realization=r), o.get_counts()
+            assert np.array_equal(got, want), (period, r, int((got != want).sum()))
+    g.close()
+
+
+def test_tags_wrap_without_a_zeroth_order_reaction(orc):
+    """The occupancy bytes hold a tag of the period they mark, repeating every
+    255 periods, and each map serves every other period, so a byte untouched
+    for a multiple of 510 periods matches again.  A+B<->C (no reaction without
+    reactants, so the map decides which tets run) for 1100 periods, compared
+    with the oracle at checkpoints on both sides of 510 and 1020."""
+    import paper_1512_03126_amd as P
+
+    xyz, tets = W.tiny_lattice(4, 0.2e-6, jitter_frac=0.2, seed=8)
+    T = tets.shape[0]
+    rx = [([0, 1], [2], 3e8), ([2], [0, 1], 400.0)]
+    Ds = [1e-12, 1e-12, 0.5e-12]
+    rng = np.random.default_rng(9)
+    init = np.zeros((3, T), np.int32)
+    for q in range(2):
+        np.add.at(init[q], rng.integers(0, T, 12), 1)   # sparse: most groups stay empty for long spells
+    note(f"tag wrap: {T} tets, 1100 periods")
+    g = P.Simulation(xyz, tets, Ds, rx, seed=4)
+    o = orc.OracleSim(xyz, tets, Ds, rx, seed=4)
+    for q in range(3):
+        g.set_counts(q, init[q])
+        o.set_counts(q, init[q])
+    done = 0
+    for stop in (250, 509, 510, 511, 765, 1019, 1020, 1021, 1100):
+        g.step(stop - done)
+        o.run_steps(stop - done)
+        done = stop
+        got, want = g.get_counts(), o.get_counts()
+        assert np.array_equal(got, want), (stop, int((got != want).sum()))
+    assert int(got.sum()) > 0
+    g.close()

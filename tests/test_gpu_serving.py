@@ -158,7 +158,52 @@ def test_timing_pass_counts_work(orc):
     got = s.get_counts()
     s.close()
     np.testing.assert_array_equal(o.get_counts(), got)
-    # whole chunks are launched; periods past a request's end update nothing
-    assert kt["update_launches"] == kt["scan_launches"] >= n
+    # a run's last periods, fewer than a chunk, are launched directly, as many
+    # as are left: one launch pair per period and none idle
+    assert kt["update_launches"] == kt["scan_launches"] == n
     assert work["tets"] == tets
     assert nnz_end <= work["additions"] <= 5 * m.n_species * tets
+    assert 0 < work["transfers"] <= work["additions"]
+    assert work["transfers"] <= 4 * m.n_species * tets
+
+
+def serving_size_request(i, species=6, t_lo=1e5, t_hi=2.5e5):
+    """A request of the serving mix's middle sizes (jittered lattice of
+    1e5-2.5e5 tets) with `species` species and at least two reactions: the
+    first seed of a fixed sequence that draws one."""
+    for j in range(1000):
+        m = W.serving_request(np.random.default_rng([91, i, j]), t_lo=t_lo, t_hi=t_hi, max_species=species)
+        if m.n_species == species and len(m.reactions) >= 2:
+            return m
+    raise AssertionError("no request of that shape in the first 1000 seeds")
+
+
+def test_serving_size_request_in_a_mix(orc):
+    """One request at the serving mix's sizes (>= 1e5 tets, 6 species, random
+    reactions) batched with small ones of 1-4 species in one engine: every
+    count of every request equals the oracle's after its periods."""
+    import paper_1512_03126_amd as P
+
+    big = serving_size_request(0)
+    assert big.n_tets >= 100000 and big.n_species == 6
+    reqs = [big] + [small_request(50 + i) for i in range(4)]
+    periods = [48, 30, 48, 62, 20]
+    note(f"serving-size mix: {big.n_tets} tets x 6 species + 4 small requests")
+    e = P.rdos_engine_create(0, 0)
+    tickets = []
+    for m, n in zip(reqs, periods):
+        s = P.Simulation(m.xyz, m.tets, m.D, m.reactions, seed=m.seed, tau_scale=None)
+        for q in range(m.n_species):
+            s.set_counts(q, m.init[0, q])
+        tickets.append((P.rdos_engine_submit(e, s.h, n, 1.0), s))
+    P.rdos_engine_drain(e)
+    mixed = []
+    for t, s in tickets:
+        P.rdos_engine_release(e, t)
+        mixed.append(s.get_counts())
+        s.close()
+    P.rdos_engine_destroy(e)
+    for k, (m, n, got) in enumerate(zip(reqs, periods, mixed)):
+        want = run_oracle(orc, m, n)
+        assert np.array_equal(want, got), (k, m.n_tets, m.n_species, int((want != got).sum()))
+    assert int(mixed[0].sum()) > 0
