@@ -276,7 +276,9 @@ enum {
                                 default, or the best candidate so far                    */
     RDOS_SHAPE_TUNED = 1,    /* tuned by this engine on live work of this size           */
     RDOS_SHAPE_CACHED = 2,   /* tuned earlier in this process (any engine) for this size */
-    RDOS_SHAPE_FIXED = 3     /* fixed by rdos_engine_set_shape                           */
+    RDOS_SHAPE_FIXED = 3,    /* fixed by rdos_engine_set_shape                           */
+    RDOS_SHAPE_SMALL_WORK = 4 /* work list of at most 1024 tiles: not tuned, 32-period
+                                 chunks (launch latency dominates there)                 */
 };
 
 /* The launch shape of the current work list: periods per graph replay, scan

@@ -305,7 +305,7 @@ def rdos_engine_stats(engine):
     return dict(launches=n.value, updates=u.value, busy_s=b.value)
 
 
-SHAPE_SOURCES = {0: "default", 1: "tuned", 2: "cached", 3: "fixed"}
+SHAPE_SOURCES = {0: "default", 1: "tuned", 2: "cached", 3: "fixed", 4: "small work"}
 
 
 def rdos_engine_launch_shape(engine):

@@ -11,6 +11,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <array>
 #include <chrono>
 #include <cmath>
 #include <condition_variable>
@@ -57,6 +58,11 @@ struct Shape {
         return chunk == o.chunk && scan_grid == o.scan_grid && update_bps == o.update_bps && chains == o.chains;
     }
 };
+
+// Work lists of up to this many tiles (size buckets below it) are not tuned:
+// all candidates clamp to about the same grids there.
+constexpr int32_t kSmallWorkTiles = 1024;
+constexpr Shape kSmallWorkShape{32, 2048, 1, 1};
 
 // Tuning results shared by every engine of the process, by work-list size
 // bucket: an engine that meets a bucket another engine has tuned starts
@@ -111,12 +117,14 @@ struct rdos_engine {
     int32_t n_tiles0 = 0;   // tiles of chain 0 when split: they come first in d_tiles
     int32_t hdr_chains = 0; // chain count the queue headers currently describe
     int32_t max_species = 1;
-    hipGraphExec_t graph = nullptr;
-    Shape graph_shape{0, 0, 0, 0};
-    int32_t graph_grid_tiles = 0;  // grid_tiles the captured graph was sized for
+    // instantiated chunk graphs by (shape, grid_tiles): a graph sized for a
+    // bucket serves every work list that fits it, so buckets that come back
+    // (serving) reuse their graphs
+    std::map<std::array<int32_t, 5>, hipGraphExec_t> graphs;
     int32_t grid_tiles = 1;        // launch grids serve work lists of up to this many tiles (size bucket)
+    double last_chunk_ms = 0.0;    // device time of the last full chunk
     int32_t qphase = 0;            // queue half (qsel) of the next period; graphs start at 0
-    bool graph_stale = true;  // a buffer the graph names was reallocated
+    bool graph_stale = true;  // a buffer the graphs name was reallocated
     bool rebuild = true;      // the slot set changed
 
     // tuner: each candidate runs two chunks per work-list size bucket (the
@@ -312,13 +320,28 @@ hipError_t enqueue_periods(rdos_engine *e, const Shape &sh, int32_t len, int32_t
     return err;
 }
 
-rdos_status capture(rdos_engine *e, const Shape &sh)
+void drop_graphs(rdos_engine *e)
+{
+    for (auto &kv : e->graphs) (void)hipGraphExecDestroy(kv.second);
+    e->graphs.clear();
+}
+
+// The graph of one chunk of shape `sh` at the current grid size, captured on
+// first use.
+rdos_status graph_for(rdos_engine *e, const Shape &sh, hipGraphExec_t *out)
 {
     std::lock_guard<std::mutex> lock(device_api_mutex());
-    if (e->graph) {
-        (void)hipGraphExecDestroy(e->graph);
-        e->graph = nullptr;
+    if (e->graph_stale) {
+        drop_graphs(e);
+        e->graph_stale = false;
     }
+    const std::array<int32_t, 5> key{sh.chunk, sh.scan_grid, sh.update_bps, sh.chains, e->grid_tiles};
+    auto it = e->graphs.find(key);
+    if (it != e->graphs.end()) {
+        *out = it->second;
+        return RDOS_OK;
+    }
+    if (e->graphs.size() >= 32) drop_graphs(e);
     hipGraph_t g = nullptr;
     ENGINE_HIP(e, hipStreamBeginCapture(e->stream, hipStreamCaptureModeThreadLocal), "begin capture");
     hipError_t err = enqueue_periods(e, sh, sh.chunk, 0, false);
@@ -327,12 +350,12 @@ rdos_status capture(rdos_engine *e, const Shape &sh)
         if (g) (void)hipGraphDestroy(g);
         return efail(e, RDOS_EDEVICE, "capture: %s", hipGetErrorString(err != hipSuccess ? err : err2));
     }
-    err = hipGraphInstantiate(&e->graph, g, nullptr, nullptr, 0);
+    hipGraphExec_t x = nullptr;
+    err = hipGraphInstantiate(&x, g, nullptr, nullptr, 0);
     (void)hipGraphDestroy(g);
     if (err != hipSuccess) return efail(e, RDOS_EDEVICE, "instantiate: %s", hipGetErrorString(err));
-    e->graph_shape = sh;
-    e->graph_grid_tiles = e->grid_tiles;
-    e->graph_stale = false;
+    e->graphs[key] = x;
+    *out = x;
     return RDOS_OK;
 }
 
@@ -448,7 +471,14 @@ void worker_main(rdos_engine *e)
             const std::pair<int, int> b{lg, species_bound(e->max_species)};
             // launch grids cover every work list of this size bucket
             e->grid_tiles = (int32_t)std::min<int64_t>(int64_t(1) << (lg + 1), int64_t(1) << 30);
-            if (b != e->bucket) {
+            if (b != e->bucket && !e->fixed_shape && e->grid_tiles <= kSmallWorkTiles) {
+                // small work lists: every candidate clamps to about the same
+                // grids and launch latency dominates; no tuning, long chunks
+                e->bucket = b;
+                e->best = kSmallWorkShape;
+                e->shape_source = RDOS_SHAPE_SMALL_WORK;
+                e->trial = 2 * e->candidates.size();
+            } else if (b != e->bucket) {
                 e->bucket = b;
                 auto hit = e->tuned.find(b);
                 bool found = hit != e->tuned.end();
@@ -514,13 +544,27 @@ void worker_main(rdos_engine *e)
                 fail_slots(e);
                 break;
             }
-        } else if (replay && (!e->graph || e->graph_stale || !(sh == e->graph_shape) ||
-                              e->graph_grid_tiles != e->grid_tiles)) {
-            if (capture(e, sh) != RDOS_OK) {
-                fail_slots(e);
-                break;
-            }
         }
+        hipGraphExec_t gx = nullptr;
+        if (replay && graph_for(e, sh, &gx) != RDOS_OK) {
+            fail_slots(e);
+            break;
+        }
+        // When no slot ends within them and no request waits to join, up to
+        // 8 chunks (about 2 ms of device time) are replayed back to back, so
+        // the host's turn between chunks does not leave the device idle.
+        int32_t reps = 1;
+        if (replay && !tuning && e->ready.empty() && e->waiting.empty() && e->admitting == 0) {
+            int64_t left_min = left_max;
+            for (uint64_t id : e->slots) {
+                const Ticket &tk = e->tickets[id];
+                left_min = std::min<int64_t>(left_min, tk.end_step - tk.sim->step);
+            }
+            int64_t r = left_min / sh.chunk;
+            if (e->last_chunk_ms > 0.0) r = std::min<int64_t>(r, (int64_t)(2.0 / e->last_chunk_ms));
+            reps = (int32_t)std::max<int64_t>(1, std::min<int64_t>(r, 8));
+        }
+        len *= reps;
         double work = 0.0;
         for (uint64_t id : e->slots) {
             Ticket &tk = e->tickets[id];
@@ -530,8 +574,12 @@ void worker_main(rdos_engine *e)
         const int32_t phase = e->qphase;
         lk.unlock();
         hipError_t err = hipEventRecord(e->ev0, e->stream);
-        if (err == hipSuccess)
-            err = replay ? hipGraphLaunch(e->graph, e->stream) : enqueue_periods(e, sh, len, phase, timed);
+        if (err == hipSuccess) {
+            if (replay)
+                for (int32_t k = 0; k < reps && err == hipSuccess; ++k) err = hipGraphLaunch(gx, e->stream);
+            else
+                err = enqueue_periods(e, sh, len, phase, timed);
+        }
         if (err == hipSuccess) err = hipEventRecord(e->ev1, e->stream);
         if (err == hipSuccess) err = hipEventSynchronize(e->ev1);
         float ms = 0.f;
@@ -556,6 +604,7 @@ void worker_main(rdos_engine *e)
             }
         }
         const double rate = ms > 0.f ? work / (double)ms : 0.0;
+        if (replay) e->last_chunk_ms = (double)ms / reps;
         if (tuning && replay) {  // only full graph-replayed chunks are scored
             if ((e->trial & 1) && rate > e->best_rate) {  // the candidate's second chunk
                 e->best_rate = rate;
@@ -912,7 +961,7 @@ void rdos_engine_destroy(rdos_engine *e)
         kv.second.sim->engine_owned = false;
         rdos_destroy(kv.second.sim);
     }
-    if (e->graph) (void)hipGraphExecDestroy(e->graph);
+    drop_graphs(e);
     void *p[] = {e->d_sims, e->d_tiles, e->d_work};
     for (void *q : p)
         if (q) (void)hipFree(q);

@@ -148,8 +148,9 @@ inline void queue_shape(int64_t n_tiles, int32_t *nseg, int32_t *seg_cap)
 hipError_t launch_scan(const DevSim *sims, const Tile *tiles, int64_t iter, const QueueView &q, int32_t qsel,
                        int32_t scan_grid, hipStream_t st);
 // The update grid is grid_segments (1..kMaxSegments) x blocks_per_segment
-// blocks; block columns stride over the segments in use, so a grid with
-// fewer columns than segments is still complete.
+// blocks, one block column per queue segment: grid_segments must be at least
+// the segments of the work list (else the kernel updates nothing and raises
+// bit 2 of the first simulation's flags).
 hipError_t launch_update(const DevSim *sims, const Tile *tiles, int64_t iter, int64_t partial, double tau_last,
                          const QueueView &q, int32_t qsel, int32_t blocks_per_segment, int32_t grid_segments,
                          hipStream_t st);

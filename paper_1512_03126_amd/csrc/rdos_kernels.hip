@@ -730,67 +730,75 @@ update_kernel(const DevSim *__restrict__ sims, const Tile *__restrict__ tiles, Q
     const LaneState ls{counts + threadIdx.x, occ + threadIdx.x, last + threadIdx.x};
     if (blockIdx.x == 0)
         for (int k = threadIdx.x; k < kMaxSegments; k += kBlock) q.len[((qsel ^ 1) * kMaxSegments + k) * kLenStride] = 0;
-    const WorkHeader h = *q.hdr;
-    // The grid is grid_segments x blocks-per-segment; block b works on
-    // segments b % grid_segments, + grid_segments, ... so any grid covers
-    // every segment in use (the host sizes it to the work list, one
-    // segment per block column when it can).
-    const int32_t per_seg = max(1, (int32_t)(gridDim.x / grid_segments));
-    const int32_t part = blockIdx.x / grid_segments;
-    if (part >= per_seg) return;  // uniform over the block
+    // the header's fields are uniform: held in scalar registers
+    WorkHeader h = *q.hdr;
+    h.n_tiles = __builtin_amdgcn_readfirstlane(h.n_tiles);
+    h.nseg = __builtin_amdgcn_readfirstlane(h.nseg);
+    h.seg_cap = __builtin_amdgcn_readfirstlane(h.seg_cap);
+    h.tile0 = __builtin_amdgcn_readfirstlane(h.tile0);
+    h.qcap = (int64_t)(((uint64_t)(uint32_t)__builtin_amdgcn_readfirstlane((int32_t)(uint32_t)h.qcap)) |
+                       ((uint64_t)(uint32_t)__builtin_amdgcn_readfirstlane((int32_t)((uint64_t)h.qcap >> 32)) << 32));
+    // The grid is grid_segments x blocks-per-segment; the host sizes
+    // grid_segments to cover every segment a launch may find in use.  A
+    // header with more segments than that is an internal error, reported
+    // through the flags of the work list's first simulation (never silent).
+    if (h.nseg > grid_segments) {
+        if (blockIdx.x == 0 && threadIdx.x == 0) atomicOr(sims[tiles[h.tile0].sim].flags, 4);
+        return;
+    }
+    // uniform over the block: kept in scalar registers
+    const int32_t seg = __builtin_amdgcn_readfirstlane((int32_t)(blockIdx.x % (uint32_t)grid_segments));
+    const int32_t per_seg = __builtin_amdgcn_readfirstlane(max(1, (int32_t)(gridDim.x / (uint32_t)grid_segments)));
+    const int32_t part = __builtin_amdgcn_readfirstlane((int32_t)(blockIdx.x / (uint32_t)grid_segments));
+    if (seg >= h.nseg || part >= per_seg) return;  // uniform over the block
     const bool tally = q.work != nullptr;
     if (tally) {
         if (threadIdx.x == 0) block_tets = block_adds = block_moves = 0;
         __syncthreads();
     }
-    for (int32_t seg = blockIdx.x % grid_segments; seg < h.nseg; seg += grid_segments) {
-        const int32_t n = min(q.len[(qsel * kMaxSegments + seg) * kLenStride], h.seg_cap);
-        const int32_t stride = per_seg * kBlock;
-        const int64_t seg0 = (int64_t)seg * h.seg_cap;
-        // each lane's next queue entry is read one tet ahead, so that it
-        // arrives with the loads of the tet before it instead of starting a
-        // round trip
-        int32_t next = part * kBlock + (int32_t)threadIdx.x < n ? q.tet[seg0 + part * kBlock + threadIdx.x] : 0;
-        for (int32_t i = part * kBlock + threadIdx.x; i < n; i += stride) {
-            if (tally) atomicAdd(&block_tets, 1u);
-            const int64_t idx = seg0 + i;
-            const int32_t entry = next;
-            // the entry's count rows are read with its tile and the next
-            // entry, not after the simulation is known.  Every load is
-            // issued (slots past the queue's rows repeat its last row), so
-            // none waits behind a branch; slots past a simulation's S hold
-            // values it never reads.
-            int32_t cn[KS];
+    const int32_t n = min(q.len[(qsel * kMaxSegments + seg) * kLenStride], h.seg_cap);
+    const int32_t stride = per_seg * kBlock;
+    const int64_t seg0 = (int64_t)seg * h.seg_cap;
+    // each lane's next queue entry is read one tet ahead, so that it arrives
+    // with the loads of the tet before it instead of starting a round trip
+    int32_t next = part * kBlock + (int32_t)threadIdx.x < n ? q.tet[seg0 + part * kBlock + threadIdx.x] : 0;
+    for (int32_t i = part * kBlock + threadIdx.x; i < n; i += stride) {
+        if (tally) atomicAdd(&block_tets, 1u);
+        const int64_t idx = seg0 + i;
+        const int32_t entry = next;
+        // the entry's count rows are read with its tile and the next entry,
+        // not after the simulation is known.  Every load is issued (slots past
+        // the queue's rows repeat its last row), so none waits behind a
+        // branch; slots past a simulation's S hold values it never reads.
+        int32_t cn[KS];
 #pragma unroll
-            for (int s = 0; s < KS; ++s) cn[s] = q.counts[min(s, q.rows - 1) * h.qcap + idx];
-            const Tile tile = tiles[h.tile0 + entry / kTetsPerTile];
-            next = i + stride < n ? q.tet[idx + stride] : 0;
+        for (int s = 0; s < KS; ++s) cn[s] = q.counts[min(s, q.rows - 1) * h.qcap + idx];
+        const Tile tile = tiles[h.tile0 + entry / kTetsPerTile];
+        next = i + stride < n ? q.tet[idx + stride] : 0;
 #pragma unroll
-            for (int s = 0; s < KS; ++s) ls.n(s) = cn[s];
-            // lanes of one simulation run together with a wavefront-uniform
-            // descriptor (one round when the wavefront holds one simulation);
-            // descriptors do not change during a launch, so they are read as
-            // constant memory, which lets the uniform reads be scalar loads
-            using ConstSim = const __attribute__((address_space(4))) DevSim;
-            for (uint64_t todo = __ballot(1); todo;) {
-                const int32_t first = __builtin_amdgcn_readlane(tile.sim, (int32_t)__builtin_ctzll(todo));
-                // branch on the lane's ballot bit, not on the equality, so
-                // that the compiler cannot put the lane's own index in place
-                // of `first`
-                const uint64_t same = __ballot(tile.sim == first);
-                todo &= ~same;
-                if (!((same >> __lane_id()) & 1ull)) continue;
-                const DevSim &sm = *(const DevSim *)((ConstSim *)sims + first);
-                const int64_t period = sm.step0 + iter;
-                const double tau_k = period == partial ? tau_last : sm.tau;
-                const int64_t Tp = ((int64_t)sm.T + 3) & ~(int64_t)3;
-                const int64_t base = (int64_t)tile.realization * sm.S * Tp;
-                update_tet<ANY_SCALED>(sm, tile.tet0 + entry % kTetsPerTile, period, tau_k,
-                                       sm.key1 ^ (uint32_t)tile.realization, sm.buf[(period + 1) & 1] + base,
-                                       (int32_t)Tp,
-                                       sm.mask[(period + 1) & 1] + (int64_t)tile.realization * sm.S * sm.mstride,
-                                       occupancy_tag(period + 1), ls, tally);
-            }
+        for (int s = 0; s < KS; ++s) ls.n(s) = cn[s];
+        // lanes of one simulation run together with a wavefront-uniform
+        // descriptor (one round when the wavefront holds one simulation);
+        // descriptors do not change during a launch, so they are read as
+        // constant memory, which lets the uniform reads be scalar loads
+        using ConstSim = const __attribute__((address_space(4))) DevSim;
+        for (uint64_t todo = __ballot(1); todo;) {
+            const int32_t first = __builtin_amdgcn_readlane(tile.sim, (int32_t)__builtin_ctzll(todo));
+            // branch on the lane's ballot bit, not on the equality, so that the
+            // compiler cannot put the lane's own index in place of `first`
+            const uint64_t same = __ballot(tile.sim == first);
+            todo &= ~same;
+            if (!((same >> __lane_id()) & 1ull)) continue;
+            const DevSim &sm = *(const DevSim *)((ConstSim *)sims + first);
+            const int64_t period = sm.step0 + iter;
+            const double tau_k = period == partial ? tau_last : sm.tau;
+            const int64_t Tp = ((int64_t)sm.T + 3) & ~(int64_t)3;
+            const int64_t base = (int64_t)tile.realization * sm.S * Tp;
+            update_tet<ANY_SCALED>(sm, tile.tet0 + entry % kTetsPerTile, period, tau_k,
+                                   sm.key1 ^ (uint32_t)tile.realization, sm.buf[(period + 1) & 1] + base,
+                                   (int32_t)Tp,
+                                   sm.mask[(period + 1) & 1] + (int64_t)tile.realization * sm.S * sm.mstride,
+                                   occupancy_tag(period + 1), ls, tally);
         }
     }
     if (tally) {
