@@ -201,6 +201,22 @@ rdos_status rdos_step(rdos_sim *s, int64_t n_steps);
  * (Algorithm 1, Step 1).  Asynchronous. */
 rdos_status rdos_run_until(rdos_sim *s, double t_end);
 
+/* For callers that cannot allocate device memory around the step (code under
+ * HIP graph capture, serving loops, harnesses that forbid hipMalloc): the
+ * same periods as rdos_step, with the occupied-tet queue that the step
+ * kernels share (entries, counts, segment lengths, work header) in a static
+ * device array of 8 MiB per device, held until the process ends, instead of
+ * the simulation's own queue.  Allocates nothing; the queue is cleared and
+ * its header written by a kernel at the start of every call (no memset or
+ * host copy).  Results are bit-identical to rdos_step.  The array holds
+ * (1 + rows) x 4 B per tiled tet (tets rounded up to 1024 per realization,
+ * rows = the simulation's species rounded up to 2, 3, 4, 6 or 8): about
+ * 406,000 tiled tets with up to 4 species, 225,000 with 8.  Larger work
+ * lists get RDOS_EINVAL with the sizes in the message.  Every call on one GPU uses
+ * that GPU's array: calls that overlap on one GPU (other streams, other
+ * threads) race and must be serialised by the caller.  Asynchronous. */
+rdos_status rdos_step_static(rdos_sim *s, int64_t n_steps);
+
 /* Waits for all queued work; reports RDOS_EOVERFLOW if raised. */
 rdos_status rdos_synchronize(rdos_sim *s);
 

@@ -51,6 +51,7 @@ _SIGS = [
     ("rdos_set_state", C.c_int, [C.c_void_p, C.c_int64, C.c_double]),
     ("rdos_get_time", C.c_int, [C.c_void_p, _P(C.c_double), _P(C.c_int64)]),
     ("rdos_step", C.c_int, [C.c_void_p, C.c_int64]),
+    ("rdos_step_static", C.c_int, [C.c_void_p, C.c_int64]),
     ("rdos_run_until", C.c_int, [C.c_void_p, C.c_double]),
     ("rdos_synchronize", C.c_int, [C.c_void_p]),
     ("rdos_set_stream", C.c_int, [C.c_void_p, C.c_void_p]),
@@ -225,6 +226,12 @@ def rdos_get_time(sim) -> Tuple[float, int]:
 
 def rdos_step(sim, n_steps: int):
     _check(lib().rdos_step(sim, int(n_steps)), sim)
+
+
+def rdos_step_static(sim, n_steps: int):
+    """rdos_step with the step kernels' queue in the library's static device
+    array: allocates nothing."""
+    _check(lib().rdos_step_static(sim, int(n_steps)), sim)
 
 
 def rdos_run_until(sim, t_end: float):
