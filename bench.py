@@ -258,6 +258,7 @@ def run_serving(P, args):
     e = P.rdos_engine_create(0, int(args.budget_gb * (1 << 30)))
     pending = {}  # ticket -> (sim, scheduled arrival, updates)
     lat, total_updates, tets = [], 0.0, []
+    parts, subm, submitted = [], [], {}
     t0 = time.perf_counter()
     last_done = t0
 
@@ -268,6 +269,8 @@ def run_serving(P, args):
             if done:
                 sim, sched, upd = pending.pop(tk)
                 now = time.perf_counter()
+                parts.append(P.rdos_engine_ticket_times(e, tk))
+                subm.append(submitted.pop(tk) - (t0 + sched))
                 P.rdos_engine_release(e, tk)
                 sim.close()
                 lat.append(now - (t0 + sched))
@@ -296,6 +299,7 @@ def run_serving(P, args):
         for q in range(m.n_species):
             sim.set_counts(q, m.init[0, q])
         tk = P.rdos_engine_submit(e, sim.h, args.request_steps, 1.0)
+        submitted[tk] = time.perf_counter()
         pending[tk] = (sim, sched, float(args.request_steps) * m.n_tets * m.n_species)
         tets.append(m.n_tets)
         if (i + 1) % 200 == 0:
@@ -312,12 +316,20 @@ def run_serving(P, args):
     st = P.rdos_engine_stats(e)
     P.rdos_engine_destroy(e)
     lat_ms = np.sort(np.array(lat) * 1e3)
+    br = {"host_before_submit": np.array(subm) * 1e3}
+    for k in ("wait_s", "setup_s", "join_s", "run_s"):
+        br[k.replace("_s", "")] = np.array([p_[k] for p_ in parts]) * 1e3
+    breakdown = {k: {"p50_ms": round(float(np.percentile(v, 50)), 3), "p99_ms": round(float(np.percentile(v, 99)), 3)}
+                 for k, v in br.items()}
     res = {"value": total_updates / wall, "wall_s": wall, "requests": len(lat),
            "p50_ms": float(np.percentile(lat_ms, 50)), "p99_ms": float(np.percentile(lat_ms, 99)),
+           "latency_parts": breakdown,
            "mean_tets": float(np.mean(tets)), "device_busy_s": st["busy_s"],
            "device_updates_per_busy_s": st["updates"] / max(st["busy_s"], 1e-9)}
     log(f"serving: {res['value']:.3e} upd/s aggregate, p50 {res['p50_ms']:.1f} ms, p99 {res['p99_ms']:.1f} ms, "
         f"{res['requests']} requests, mean {res['mean_tets']:.0f} tets")
+    log("serving latency parts (p50 / p99 ms): " + ", ".join(f"{k} {v['p50_ms']:.2f} / {v['p99_ms']:.2f}"
+                                                             for k, v in breakdown.items()))
     return res
 
 

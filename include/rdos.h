@@ -217,6 +217,17 @@ rdos_status rdos_run_until(rdos_sim *s, double t_end);
  * threads) race and must be serialised by the caller.  Asynchronous. */
 rdos_status rdos_step_static(rdos_sim *s, int64_t n_steps);
 
+/* How rdos_step and rdos_run_until launch the periods (results never depend
+ * on it).  0 (default): a work list of at most 8 tiles (1024 tets per
+ * realization and tile) runs all its periods in one cooperative launch, the
+ * scan and update phases of each period separated by grid-wide barriers;
+ * larger ones launch a scan and an update kernel per period.  1: always two
+ * launches per period.  2: always one cooperative launch.  The one-launch
+ * path exists for small meshes, where the gaps between launches dominate a
+ * period (the 1 um cube of Sec. II.A's Fig. 2 example: 750 tets).
+ * RDOS_EINVAL for other values. */
+rdos_status rdos_set_launch_mode(rdos_sim *s, int32_t mode);
+
 /* Waits for all queued work; reports RDOS_EOVERFLOW if raised. */
 rdos_status rdos_synchronize(rdos_sim *s);
 
@@ -257,6 +268,16 @@ rdos_status rdos_engine_submit(rdos_engine *e, rdos_sim *sim, int64_t n_steps, d
 /* Non-blocking: *done = 1 once the ticket's periods have all run;
  * *latency_s = seconds from submit to completion (valid when done). */
 rdos_status rdos_engine_poll(rdos_engine *e, uint64_t ticket, int *done, double *latency_s);
+
+/* Where a completed ticket's latency went (seconds): waiting for admission
+ * (the HBM budget, earlier requests in the FIFO), set-up on admission
+ * (finalize and the occupancy map), waiting to join the running work list
+ * (the next chunk boundary), and running its periods.  The four add up to
+ * the latency rdos_engine_poll reports.  RDOS_ESTATE for a ticket that has
+ * not completed (or failed, or asked for no periods).  Any pointer may be
+ * NULL. */
+rdos_status rdos_engine_ticket_times(rdos_engine *e, uint64_t ticket, double *wait_s, double *setup_s,
+                                     double *join_s, double *run_s);
 
 /* Blocks until every submitted ticket is done. */
 rdos_status rdos_engine_drain(rdos_engine *e);

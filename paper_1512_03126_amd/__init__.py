@@ -53,6 +53,7 @@ _SIGS = [
     ("rdos_step", C.c_int, [C.c_void_p, C.c_int64]),
     ("rdos_step_static", C.c_int, [C.c_void_p, C.c_int64]),
     ("rdos_run_until", C.c_int, [C.c_void_p, C.c_double]),
+    ("rdos_set_launch_mode", C.c_int, [C.c_void_p, C.c_int32]),
     ("rdos_synchronize", C.c_int, [C.c_void_p]),
     ("rdos_set_stream", C.c_int, [C.c_void_p, C.c_void_p]),
     ("rdos_get_geometry", C.c_int, [C.c_void_p, _P(C.c_int32), _P(C.c_double), _P(C.c_double), _P(C.c_double)]),
@@ -63,6 +64,8 @@ _SIGS = [
     ("rdos_engine_create", C.c_int, [_P(C.c_void_p), C.c_int, C.c_size_t]),
     ("rdos_engine_submit", C.c_int, [C.c_void_p, C.c_void_p, C.c_int64, C.c_double, _P(C.c_uint64)]),
     ("rdos_engine_poll", C.c_int, [C.c_void_p, C.c_uint64, _P(C.c_int), _P(C.c_double)]),
+    ("rdos_engine_ticket_times", C.c_int, [C.c_void_p, C.c_uint64, _P(C.c_double), _P(C.c_double), _P(C.c_double),
+                                           _P(C.c_double)]),
     ("rdos_engine_drain", C.c_int, [C.c_void_p]),
     ("rdos_engine_release", C.c_int, [C.c_void_p, C.c_uint64, _P(C.c_void_p)]),
     ("rdos_engine_stats", C.c_int, [C.c_void_p, _P(C.c_int64), _P(C.c_double), _P(C.c_double)]),
@@ -238,6 +241,12 @@ def rdos_run_until(sim, t_end: float):
     _check(lib().rdos_run_until(sim, float(t_end)), sim)
 
 
+def rdos_set_launch_mode(sim, mode: int):
+    """0: one cooperative launch for small work lists (default), 1: two
+    launches per period, 2: always one launch."""
+    _check(lib().rdos_set_launch_mode(sim, int(mode)), sim)
+
+
 def rdos_synchronize(sim):
     _check(lib().rdos_synchronize(sim), sim)
 
@@ -292,6 +301,14 @@ def rdos_engine_poll(engine, ticket: int):
     lat = C.c_double()
     _check(lib().rdos_engine_poll(engine, int(ticket), C.byref(done), C.byref(lat)), engine, True)
     return bool(done.value), lat.value
+
+
+def rdos_engine_ticket_times(engine, ticket: int):
+    """Latency breakdown of a completed ticket (seconds)."""
+    w, su, j, r = C.c_double(), C.c_double(), C.c_double(), C.c_double()
+    _check(lib().rdos_engine_ticket_times(engine, int(ticket), C.byref(w), C.byref(su), C.byref(j), C.byref(r)),
+           engine, True)
+    return dict(wait_s=w.value, setup_s=su.value, join_s=j.value, run_s=r.value)
 
 
 def rdos_engine_drain(engine):

@@ -47,12 +47,55 @@ rdos_status hip_fail(rdos_sim *s, hipError_t e, const char *what)
 
 int64_t padded_tets(int32_t T) { return ((int64_t)T + 3) & ~(int64_t)3; }
 
+// Device memory of simulations, their queues and their set-up comes from a
+// stream-ordered pool per device: allocation and release are ordered on the
+// simulation's stream and never synchronise the whole device (hipFree can,
+// which stalled admissions behind the engine's running chunks), and freed
+// memory stays in the pool for the next simulation.
+static hipMemPool_t pool_for(int device)
+{
+    static std::mutex mu;
+    static hipMemPool_t pools[64] = {};
+    if (device < 0 || device >= 64) return nullptr;
+    std::lock_guard<std::mutex> g(mu);
+    if (!pools[device]) {
+        hipMemPoolProps props{};
+        props.allocType = hipMemAllocationTypePinned;
+        props.handleTypes = hipMemHandleTypeNone;
+        props.location.type = hipMemLocationTypeDevice;
+        props.location.id = device;
+        hipMemPool_t pool = nullptr;
+        if (hipMemPoolCreate(&pool, &props) != hipSuccess) return nullptr;
+        uint64_t keep = ~0ull;  // never hand freed memory back to the driver
+        (void)hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &keep);
+        pools[device] = pool;
+    }
+    return pools[device];
+}
+
+hipError_t dev_alloc(void **p, size_t bytes, hipStream_t st)
+{
+    *p = nullptr;
+    int device = 0;
+    hipError_t e = hipGetDevice(&device);
+    if (e != hipSuccess) return e;
+    hipMemPool_t pool = pool_for(device);
+    if (!pool) return hipErrorOutOfMemory;
+    return hipMallocFromPoolAsync(p, bytes ? bytes : 16, pool, st);
+}
+
+void dev_free(void *p, hipStream_t st)
+{
+    if (p) (void)hipFreeAsync(p, st);
+}
+
 size_t queue_bytes(int64_t n_tiles, int32_t n_species)
 {
     int32_t nseg, seg_cap;
     queue_shape(n_tiles, &nseg, &seg_cap);
     return (size_t)nseg * seg_cap * (1 + (size_t)n_species) * sizeof(int32_t) +
-           2 * (size_t)kMaxSegments * kLenStride * sizeof(int32_t) + sizeof(WorkHeader);
+           2 * (size_t)kMaxSegments * kLenStride * sizeof(int32_t) + sizeof(WorkHeader) +
+           kPersistSyncWords * sizeof(uint32_t);
 }
 
 // Room for a work list of up to capacity_tiles tiles and n_species count rows.
@@ -62,11 +105,12 @@ hipError_t alloc_queue(QueueView *q, int64_t capacity_tiles, int32_t n_species, 
     queue_shape(capacity_tiles, &q->nseg, &q->seg_cap);
     q->qcap = (int64_t)q->nseg * q->seg_cap;
     q->species = std::max(n_species, 1);
-    hipError_t e = hipMalloc(&q->tet, (size_t)q->qcap * sizeof(int32_t));
-    if (e == hipSuccess) e = hipMalloc(&q->counts, (size_t)q->qcap * q->species * sizeof(int32_t));
+    hipError_t e = dev_alloc((void **)&q->tet, (size_t)q->qcap * sizeof(int32_t), st);
+    if (e == hipSuccess) e = dev_alloc((void **)&q->counts, (size_t)q->qcap * q->species * sizeof(int32_t), st);
     const size_t len_bytes = 2 * (size_t)kMaxSegments * kLenStride * sizeof(int32_t);
-    if (e == hipSuccess) e = hipMalloc(&q->len, len_bytes);
-    if (e == hipSuccess) e = hipMalloc(&q->hdr, sizeof(WorkHeader));
+    if (e == hipSuccess) e = dev_alloc((void **)&q->len, len_bytes, st);
+    if (e == hipSuccess) e = dev_alloc((void **)&q->hdr, sizeof(WorkHeader), st);
+    if (e == hipSuccess) e = dev_alloc((void **)&q->sync, kPersistSyncWords * sizeof(uint32_t), st);
     if (e == hipSuccess) e = hipMemsetAsync(q->len, 0, len_bytes, st);
     return e;
 }
@@ -92,12 +136,13 @@ hipError_t set_queue_work(QueueView *q, int64_t n_tiles, int32_t n_sims, hipStre
     return e;
 }
 
-void free_queue(QueueView *q)
+void free_queue(QueueView *q, hipStream_t st)
 {
-    if (q->tet) (void)hipFree(q->tet);
-    if (q->counts) (void)hipFree(q->counts);
-    if (q->len) (void)hipFree(q->len);
-    if (q->hdr) (void)hipFree(q->hdr);
+    dev_free(q->tet, st);
+    dev_free(q->counts, st);
+    dev_free(q->len, st);
+    dev_free(q->hdr, st);
+    dev_free(q->sync, st);
     *q = QueueView{};
 }
 
@@ -146,6 +191,48 @@ static uint64_t hash_tets(const std::vector<int32_t> &tv)
 
 rdos_status build_topology_uncached(rdos_sim *s, std::vector<int32_t> &nbr);
 
+// Face matching on the device (launch_face_match) for meshes of at least
+// 16384 cells whose vertex ids pack into a 64-bit key; false when it does not
+// apply or finds a bad face (the host matching then reports the first bad
+// face in key order).  The sort makes it O(T) where the host sort is
+// O(T log T): about a second on the host for a million tetrahedra.
+static bool device_topology(rdos_sim *s, std::vector<int32_t> &nbr)
+{
+    const int32_t cv = s->cell_verts, T = s->T;
+    int32_t bits = 1;
+    while (bits < 31 && ((int64_t)1 << bits) < (int64_t)s->n_verts) ++bits;
+    if (T < 16384 || (cv == 4 && bits > 21) || (int64_t)T * 4 > 0x7fffffff) return false;
+    if (hipSetDevice(s->device) != hipSuccess || !s->stream) return false;
+    const size_t cell_bytes = (size_t)T * cv * sizeof(int32_t), nbr_bytes = (size_t)T * 4 * sizeof(int32_t);
+    const size_t scratch_bytes = face_match_scratch_bytes(T, cv);
+    void *d_cells = nullptr, *d_nbr = nullptr, *d_err = nullptr, *scratch = nullptr;
+    bool ok;
+    {
+        std::lock_guard<std::mutex> g(device_api_mutex());
+        ok = dev_alloc(&d_cells, cell_bytes, s->stream) == hipSuccess &&
+             dev_alloc(&d_nbr, nbr_bytes, s->stream) == hipSuccess &&
+             dev_alloc(&d_err, sizeof(int32_t), s->stream) == hipSuccess &&
+             dev_alloc(&scratch, scratch_bytes, s->stream) == hipSuccess;
+    }
+    int32_t err = 1;
+    if (ok) {
+        nbr.assign((size_t)T * 4, -1);
+        ok = hipMemcpyAsync(d_cells, s->tet_verts.data(), cell_bytes, hipMemcpyHostToDevice, s->stream) == hipSuccess &&
+             hipMemsetAsync(d_nbr, 0xff, nbr_bytes, s->stream) == hipSuccess &&
+             hipMemsetAsync(d_err, 0, sizeof(int32_t), s->stream) == hipSuccess &&
+             launch_face_match((const int32_t *)d_cells, T, cv, bits, (int32_t *)d_nbr, scratch, (int32_t *)d_err,
+                               s->stream) == hipSuccess &&
+             hipMemcpyAsync(nbr.data(), d_nbr, nbr_bytes, hipMemcpyDeviceToHost, s->stream) == hipSuccess &&
+             hipMemcpyAsync(&err, d_err, sizeof(int32_t), hipMemcpyDeviceToHost, s->stream) == hipSuccess &&
+             hipStreamSynchronize(s->stream) == hipSuccess;
+    }
+    {
+        std::lock_guard<std::mutex> g(device_api_mutex());
+        for (void *p : {d_cells, d_nbr, d_err, scratch}) dev_free(p, s->stream);
+    }
+    return ok && err == 0;
+}
+
 rdos_status build_topology(rdos_sim *s, std::vector<int32_t> &nbr)
 {
     TopologyCache &c = topology_cache();
@@ -160,8 +247,10 @@ rdos_status build_topology(rdos_sim *s, std::vector<int32_t> &nbr)
                 return RDOS_OK;
             }
     }
-    rdos_status st = build_topology_uncached(s, nbr);
-    if (st != RDOS_OK) return st;
+    if (!device_topology(s, nbr)) {
+        rdos_status st = build_topology_uncached(s, nbr);
+        if (st != RDOS_OK) return st;
+    }
     std::lock_guard<std::mutex> g(c.mu);
     const size_t add = (s->tet_verts.size() + nbr.size()) * sizeof(int32_t);
     while (!c.entries.empty() && c.bytes + add > TopologyCache::kMaxBytes) {  // evict least recently used
@@ -315,6 +404,7 @@ rdos_status check_flags(rdos_sim *s)
     HIP_TRY(s, hipStreamSynchronize(s->stream), "synchronize");
     if (flags & 1) return fail(s, RDOS_EOVERFLOW, "a molecule count overflowed int32");
     if (flags & 4) return fail(s, RDOS_EDEVICE, "occupied-tet queue overflowed (internal error)");
+    if (flags & 8) return fail(s, RDOS_EDEVICE, "a grid barrier of the one-launch path timed out (internal error)");
     if (flags & 2)
         return fail(s, RDOS_EOVERFLOW, "a tet fired more than %u reactions in one period; shorten tau",
                     kMaxEventsPerPeriod);
@@ -332,6 +422,50 @@ rdos_status enqueue_period(rdos_sim *s, int64_t period, int64_t partial, double 
     return RDOS_OK;
 }
 
+// Grid of the one-launch path for this simulation, or 0 when it does not
+// apply (launch mode 0: work lists of at most kPersistTiles tiles; 1: never;
+// 2: always).  Blocks beyond what a cooperative launch may hold stride over
+// the tiles and queue segments.
+int32_t persist_grid(rdos_sim *s)
+{
+    if (s->launch_mode == 1 || (s->launch_mode == 0 && s->n_tiles > kPersistTiles)) return 0;
+    if (s->persist_limit < 0) s->persist_limit = persist_grid_limit(s->queue);
+    // four blocks per queue segment, so that a segment's tets are shared by
+    // 1024 lanes
+    const int32_t need = std::max(4 * s->queue.nseg, scan_blocks_for(s->n_tiles));
+    return s->persist_limit > 0 ? std::min(need, s->persist_limit) : 0;
+}
+
+// n periods from the current one; the last lasts tau_last when `partial`
+// (Algorithm 1, Step 1), all others tau.
+rdos_status enqueue_run(rdos_sim *s, int64_t n, bool partial, double tau_last)
+{
+    if (n <= 0) return RDOS_OK;
+    const int32_t grid = persist_grid(s);
+    if (grid <= 0) {
+        for (int64_t i = 0; i < n; ++i) {
+            const bool last = partial && i == n - 1;
+            rdos_status st = enqueue_period(s, s->step, last ? s->step : -1, last ? tau_last : 0.0);
+            if (st != RDOS_OK) return st;
+            s->step += 1;
+        }
+        return RDOS_OK;
+    }
+    rdos_status st = ensure_mask(s);
+    if (st != RDOS_OK) return st;
+    const int64_t partial_index = partial ? s->step + n - 1 : -1;
+    while (n > 0) {
+        const int32_t len = (int32_t)std::min<int64_t>(n, kPersistPeriods);
+        HIP_TRY(s, launch_persist(s->d_desc, s->d_tiles, s->step, len, (int32_t)(s->launches & 1), partial_index,
+                                  tau_last, s->queue, grid, s->queue.sync, s->stream),
+                "launch periods");
+        s->launches += len;
+        s->step += len;
+        n -= len;
+    }
+    return RDOS_OK;
+}
+
 double time_of(const rdos_sim *s, int64_t k)
 {
     return s->anchor_t + (double)(k - s->anchor_step) * s->tau;
@@ -344,9 +478,9 @@ void free_device(rdos_sim *s)
     std::lock_guard<std::mutex> g(device_api_mutex());
     void *ptrs[] = {s->d_mesh, s->d_buf[0], s->d_buf[1], s->d_mask[0], s->d_mask[1], s->d_flags, s->d_desc,
                     s->d_tiles, s->d_allowed};
-    for (void *p : ptrs)
-        if (p) (void)hipFree(p);
-    free_queue(&s->queue);
+    for (void *p : ptrs) dev_free(p, s->stream);
+    free_queue(&s->queue, s->stream);
+    if (s->stream) (void)hipStreamSynchronize(s->stream);
     s->d_mask[0] = s->d_mask[1] = nullptr;
     s->d_mesh = nullptr;
     s->d_allowed = nullptr;
@@ -518,15 +652,14 @@ rdos_status rdos_finalize(rdos_sim *s, double tau_scale, double *out_tau)
     // list, not only realizations x tets, must stay below 2^31
     if (tiles_of(s) * kTetsPerTile > 0x7fffffff)
         return fail(s, RDOS_EINVAL, "realizations x tiled tets exceed 2^31");
-    std::vector<int32_t> nbr;
-    rdos_status st = build_topology(s, nbr);
-    if (st != RDOS_OK) return st;
-
     HIP_TRY(s, hipSetDevice(s->device), "set device");
     if (!s->stream) {
         HIP_TRY(s, hipStreamCreateWithFlags(&s->stream, hipStreamNonBlocking), "create stream");
         s->own_stream = true;
     }
+    std::vector<int32_t> nbr;
+    rdos_status st = build_topology(s, nbr);
+    if (st != RDOS_OK) return st;
     const int32_t T = s->T;
     const int S = (int)s->D.size();
     const int64_t Tp = padded_tets(T);
@@ -543,8 +676,7 @@ rdos_status rdos_finalize(rdos_sim *s, double tau_scale, double *out_tau)
         std::unique_lock<std::mutex> g(device_api_mutex(), std::defer_lock);
         if (!alloc_lock.owns_lock()) g.lock();
         void *p[] = {d_xyz, d_vol, d_bc, d_area, d_D, d_tv, d_nbr, d_tau};
-        for (void *q : p)
-            if (q) (void)hipFree(q);
+        for (void *q : p) dev_free(q, s->stream);
     };
 #define SETUP_TRY(expr, what)                               \
     do {                                                    \
@@ -557,22 +689,22 @@ rdos_status rdos_finalize(rdos_sim *s, double tau_scale, double *out_tau)
         }                                                   \
     } while (0)
     alloc_lock.lock();
-    SETUP_TRY(hipMalloc(&s->d_mesh, (size_t)T * sizeof(MeshRec)), "allocate mesh tables");
-    SETUP_TRY(hipMalloc(&s->d_buf[0], count_bytes), "allocate counts");
-    SETUP_TRY(hipMalloc(&s->d_buf[1], count_bytes), "allocate counts");
-    SETUP_TRY(hipMalloc(&s->d_mask[0], mask_bytes), "allocate occupancy");
-    SETUP_TRY(hipMalloc(&s->d_mask[1], mask_bytes), "allocate occupancy");
-    SETUP_TRY(hipMalloc(&s->d_flags, 64), "allocate flags");
-    SETUP_TRY(hipMalloc(&s->d_desc, sizeof(DevSim)), "allocate descriptor");
+    SETUP_TRY(dev_alloc((void **)&s->d_mesh, (size_t)T * sizeof(MeshRec), s->stream), "allocate mesh tables");
+    SETUP_TRY(dev_alloc((void **)&s->d_buf[0], count_bytes, s->stream), "allocate counts");
+    SETUP_TRY(dev_alloc((void **)&s->d_buf[1], count_bytes, s->stream), "allocate counts");
+    SETUP_TRY(dev_alloc((void **)&s->d_mask[0], mask_bytes, s->stream), "allocate occupancy");
+    SETUP_TRY(dev_alloc((void **)&s->d_mask[1], mask_bytes, s->stream), "allocate occupancy");
+    SETUP_TRY(dev_alloc((void **)&s->d_flags, 64, s->stream), "allocate flags");
+    SETUP_TRY(dev_alloc((void **)&s->d_desc, sizeof(DevSim), s->stream), "allocate descriptor");
     SETUP_TRY(alloc_queue(&s->queue, tiles_of(s), S, s->stream), "allocate queue");
-    SETUP_TRY(hipMalloc(&d_xyz, s->xyz.size() * sizeof(double)), "allocate set-up");
-    SETUP_TRY(hipMalloc(&d_tv, s->tet_verts.size() * sizeof(int32_t)), "allocate set-up");
-    SETUP_TRY(hipMalloc(&d_nbr, nbr.size() * sizeof(int32_t)), "allocate set-up");
-    SETUP_TRY(hipMalloc(&d_vol, (size_t)T * sizeof(double)), "allocate set-up");
-    SETUP_TRY(hipMalloc(&d_bc, (size_t)T * 3 * sizeof(double)), "allocate set-up");
-    SETUP_TRY(hipMalloc(&d_area, (size_t)T * 4 * sizeof(double)), "allocate set-up");
-    SETUP_TRY(hipMalloc(&d_D, (size_t)S * sizeof(double)), "allocate set-up");
-    SETUP_TRY(hipMalloc(&d_tau, sizeof(unsigned long long) + 8), "allocate set-up");
+    SETUP_TRY(dev_alloc((void **)&d_xyz, s->xyz.size() * sizeof(double), s->stream), "allocate set-up");
+    SETUP_TRY(dev_alloc((void **)&d_tv, s->tet_verts.size() * sizeof(int32_t), s->stream), "allocate set-up");
+    SETUP_TRY(dev_alloc((void **)&d_nbr, nbr.size() * sizeof(int32_t), s->stream), "allocate set-up");
+    SETUP_TRY(dev_alloc((void **)&d_vol, (size_t)T * sizeof(double), s->stream), "allocate set-up");
+    SETUP_TRY(dev_alloc((void **)&d_bc, (size_t)T * 3 * sizeof(double), s->stream), "allocate set-up");
+    SETUP_TRY(dev_alloc((void **)&d_area, (size_t)T * 4 * sizeof(double), s->stream), "allocate set-up");
+    SETUP_TRY(dev_alloc((void **)&d_D, (size_t)S * sizeof(double), s->stream), "allocate set-up");
+    SETUP_TRY(dev_alloc((void **)&d_tau, sizeof(unsigned long long) + 8, s->stream), "allocate set-up");
     alloc_lock.unlock();
     SETUP_TRY(hipMemsetAsync(s->d_buf[0], 0, count_bytes, s->stream), "clear counts");
     SETUP_TRY(hipMemsetAsync(s->d_buf[1], 0, count_bytes, s->stream), "clear counts");
@@ -602,13 +734,13 @@ rdos_status rdos_finalize(rdos_sim *s, double tau_scale, double *out_tau)
         hipError_t e_sel;
         {
             std::lock_guard<std::mutex> g(device_api_mutex());
-            e_sel = hipMalloc(&scratch, tau_select_scratch_bytes(T, S));
+            e_sel = dev_alloc(&scratch, tau_select_scratch_bytes(T, S), s->stream);
         }
         if (e_sel == hipSuccess) {
             e_sel = launch_tau_select(s->d_mesh, T, d_D, S, s->tau_outliers, scratch, d_tau, s->stream);
             (void)hipStreamSynchronize(s->stream);
             std::lock_guard<std::mutex> g(device_api_mutex());
-            (void)hipFree(scratch);
+            dev_free(scratch, s->stream);
         }
         SETUP_TRY(e_sel, "tau selection");
     } else {
@@ -672,7 +804,7 @@ rdos_status rdos_finalize(rdos_sim *s, double tau_scale, double *out_tau)
         hipError_t e_al;
         {
             std::lock_guard<std::mutex> g(device_api_mutex());
-            e_al = hipMalloc(&s->d_allowed, allowed.size() * sizeof(uint32_t));
+            e_al = dev_alloc((void **)&s->d_allowed, allowed.size() * sizeof(uint32_t), s->stream);
         }
         if (e_al == hipSuccess)
             e_al = hipMemcpyAsync(s->d_allowed, allowed.data(), allowed.size() * sizeof(uint32_t),
@@ -709,7 +841,7 @@ rdos_status rdos_finalize(rdos_sim *s, double tau_scale, double *out_tau)
     hipError_t e;
     {
         std::lock_guard<std::mutex> g(device_api_mutex());
-        e = hipMalloc(&s->d_tiles, tiles.size() * sizeof(Tile));
+        e = dev_alloc((void **)&s->d_tiles, tiles.size() * sizeof(Tile), s->stream);
     }
     if (e != hipSuccess) {
         free_device(s);
@@ -835,12 +967,7 @@ rdos_status rdos_step(rdos_sim *s, int64_t n_steps)
     if (s->state != SimState::Ready) return fail(s, RDOS_ESTATE, "step before finalize");
     if (n_steps < 0) return fail(s, RDOS_EINVAL, "negative step count");
     HIP_TRY(s, hipSetDevice(s->device), "set device");
-    for (int64_t i = 0; i < n_steps; ++i) {
-        rdos_status st = enqueue_period(s, s->step, -1, 0.0);
-        if (st != RDOS_OK) return st;
-        s->step += 1;
-    }
-    return RDOS_OK;
+    return enqueue_run(s, n_steps, false, 0.0);
 }
 
 rdos_status rdos_run_until(rdos_sim *s, double t_end)
@@ -849,21 +976,27 @@ rdos_status rdos_run_until(rdos_sim *s, double t_end)
     if (s->state != SimState::Ready) return fail(s, RDOS_ESTATE, "run_until before finalize");
     if (!std::isfinite(t_end)) return fail(s, RDOS_EINVAL, "t_end must be finite");
     HIP_TRY(s, hipSetDevice(s->device), "set device");
-    for (;;) {
-        const double t = time_of(s, s->step);
-        if (t >= t_end) return RDOS_OK;
-        if (t + s->tau > t_end) {  // Step 1: the last period ends at t_end
-            rdos_status st = enqueue_period(s, s->step, s->step, t_end - t);
-            if (st != RDOS_OK) return st;
-            s->step += 1;
-            s->anchor_step = s->step;
-            s->anchor_t = t_end;
-            return RDOS_OK;
-        }
-        rdos_status st = enqueue_period(s, s->step, -1, 0.0);
-        if (st != RDOS_OK) return st;
-        s->step += 1;
+    // full periods while one more fits, then (Step 1) a last period shortened
+    // to end at t_end
+    int64_t k = s->step;
+    while (time_of(s, k) < t_end && !(time_of(s, k) + s->tau > t_end)) ++k;
+    const bool partial = time_of(s, k) < t_end;
+    const double tau_last = partial ? t_end - time_of(s, k) : 0.0;
+    rdos_status st = enqueue_run(s, k - s->step + (partial ? 1 : 0), partial, tau_last);
+    if (st != RDOS_OK) return st;
+    if (partial) {
+        s->anchor_step = s->step;
+        s->anchor_t = t_end;
     }
+    return RDOS_OK;
+}
+
+rdos_status rdos_set_launch_mode(rdos_sim *s, int32_t mode)
+{
+    CHECK_HANDLE(s);
+    if (mode < 0 || mode > 2) return fail(s, RDOS_EINVAL, "launch mode must be 0, 1 or 2");
+    s->launch_mode = mode;
+    return RDOS_OK;
 }
 
 rdos_status rdos_synchronize(rdos_sim *s)

@@ -38,6 +38,9 @@ struct Ticket {
     int64_t n_steps = 0;
     double tau_scale = 1.0;
     Clock::time_point submitted;
+    Clock::time_point admit_start;  // the admission thread took it (set-up begins)
+    Clock::time_point admit_end;    // set up and handed to the worker
+    Clock::time_point started;      // its first periods were launched
     Clock::time_point finished;
     bool admitted = false;
     bool done = false;
@@ -123,6 +126,9 @@ struct rdos_engine {
     std::map<std::array<int32_t, 5>, hipGraphExec_t> graphs;
     int32_t grid_tiles = 1;        // launch grids serve work lists of up to this many tiles (size bucket)
     double last_chunk_ms = 0.0;    // device time of the last full chunk
+    double last_period_ms = 0.0;   // device time per period of the last one-launch run
+    int32_t persist_limit = -1;    // blocks of a cooperative one-launch kernel (-1: not asked)
+    int32_t persist_key = -1;      // queue species bound and transfer form it was asked for
     int32_t qphase = 0;            // queue half (qsel) of the next period; graphs start at 0
     bool graph_stale = true;  // a buffer the graphs name was reallocated
     bool rebuild = true;      // the slot set changed
@@ -235,7 +241,7 @@ rdos_status build_work(rdos_engine *e)
         if ((int64_t)nseg * seg_cap > qs[c]->qcap || species_bound(max_species) > qs[c]->species) {
             ENGINE_HIP(e, hipStreamSynchronize(e->stream), "drain before reallocating the queue");
             std::lock_guard<std::mutex> g(device_api_mutex());
-            free_queue(qs[c]);
+            free_queue(qs[c], e->stream);
             ENGINE_HIP(e, alloc_queue(qs[c], need[c] + need[c] / 2, species_bound(max_species), e->stream),
                        "engine queue");
             e->graph_stale = true;
@@ -386,6 +392,7 @@ void admitter_main(rdos_engine *e)
             const bool fits = e->used + tk.bytes <= e->budget &&
                               (tiled <= 0x7fffffff || (e->slots.empty() && e->ready.empty()));
             if (fits) {
+                tk.admit_start = Clock::now();
                 e->waiting.pop_front();
                 e->used += tk.bytes;
                 ++e->admitting;
@@ -406,6 +413,7 @@ void admitter_main(rdos_engine *e)
                 lk.lock();
                 --e->admitting;
                 Ticket &t2 = e->tickets[id];
+                t2.admit_end = Clock::now();
                 if (st == RDOS_OK) {
                     t2.end_step = s->step + t2.n_steps;
                     t2.admitted = true;
@@ -453,7 +461,11 @@ void worker_main(rdos_engine *e)
     std::unique_lock<std::mutex> lk(e->mu);
     while (!e->stop) {
         if (!e->ready.empty()) {  // continuous batching: newly admitted simulations join here
-            for (uint64_t id : e->ready) e->slots.push_back(id);
+            const auto joined = Clock::now();
+            for (uint64_t id : e->ready) {
+                e->slots.push_back(id);
+                e->tickets[id].started = joined;
+            }
             e->ready.clear();
             e->rebuild = true;
         }
@@ -530,6 +542,32 @@ void worker_main(rdos_engine *e)
         bool replay = !timed && e->qphase == 0 && left_max >= sh.chunk;
         int32_t len = replay ? sh.chunk : (int32_t)std::min<int64_t>(left_max, sh.chunk);
         if (!replay && !timed && e->qphase == 1 && left_max >= sh.chunk) len = 1;
+        // Small work lists run their periods in one cooperative launch: as
+        // many as the slot nearest its end has left, or (when requests wait
+        // to join) at most a chunk, or about 2 ms of device time.
+        int32_t persist = 0;
+        if (!timed && e->shape_source == RDOS_SHAPE_SMALL_WORK && sh.chains == 1 && e->n_tiles <= kPersistTiles) {
+            const int32_t key = e->queue.species * 2 + e->queue.scaled;
+            if (key != e->persist_key) {
+                e->persist_limit = persist_grid_limit(e->queue);
+                e->persist_key = key;
+            }
+            if (e->persist_limit > 0)
+                persist = std::min(e->persist_limit, std::max(4 * e->queue.nseg, scan_blocks_for(e->n_tiles)));
+        }
+        if (persist > 0) {
+            replay = false;
+            const bool pending = !e->ready.empty() || !e->waiting.empty() || e->admitting > 0;
+            int64_t left_min = left_max;
+            for (uint64_t id : e->slots) {
+                const Ticket &tk = e->tickets[id];
+                left_min = std::min<int64_t>(left_min, tk.end_step - tk.sim->step);
+            }
+            int64_t cap = sh.chunk;
+            if (!pending && e->last_period_ms > 0.0)
+                cap = std::max<int64_t>(cap, (int64_t)(2.0 / e->last_period_ms));
+            len = (int32_t)std::max<int64_t>(1, std::min<int64_t>({left_min, cap, kPersistPeriods}));
+        }
         // the timing pass launches directly and tallies its work; captured graphs never do
         e->queue.work = e->queue2.work = timed ? e->d_work : nullptr;
         if (timed) {
@@ -575,10 +613,15 @@ void worker_main(rdos_engine *e)
         lk.unlock();
         hipError_t err = hipEventRecord(e->ev0, e->stream);
         if (err == hipSuccess) {
-            if (replay)
+            if (persist > 0) {
+                err = launch_persist(e->d_sims, e->d_tiles, 0, len, phase, -1, 0.0, e->queue, persist, e->queue.sync,
+                                     e->stream);
+                if (err == hipSuccess) err = launch_advance(e->d_sims, e->queue.hdr, len, e->stream);
+            } else if (replay) {
                 for (int32_t k = 0; k < reps && err == hipSuccess; ++k) err = hipGraphLaunch(gx, e->stream);
-            else
+            } else {
                 err = enqueue_periods(e, sh, len, phase, timed);
+            }
         }
         if (err == hipSuccess) err = hipEventRecord(e->ev1, e->stream);
         if (err == hipSuccess) err = hipEventSynchronize(e->ev1);
@@ -605,6 +648,7 @@ void worker_main(rdos_engine *e)
         }
         const double rate = ms > 0.f ? work / (double)ms : 0.0;
         if (replay) e->last_chunk_ms = (double)ms / reps;
+        if (persist > 0) e->last_period_ms = (double)ms / len;
         if (tuning && replay) {  // only full graph-replayed chunks are scored
             if ((e->trial & 1) && rate > e->best_rate) {  // the candidate's second chunk
                 e->best_rate = rate;
@@ -723,6 +767,24 @@ rdos_status rdos_engine_poll(rdos_engine *e, uint64_t ticket, int *done, double 
     if (latency_s)
         *latency_s = tk.done ? std::chrono::duration<double>(tk.finished - tk.submitted).count() : 0.0;
     if (tk.failed) return efail(e, RDOS_EDEVICE, "ticket failed: %s", tk.error.c_str());
+    return RDOS_OK;
+}
+
+rdos_status rdos_engine_ticket_times(rdos_engine *e, uint64_t ticket, double *wait_s, double *setup_s,
+                                     double *join_s, double *run_s)
+{
+    if (!e) return RDOS_EINVAL;
+    std::lock_guard<std::mutex> g(e->mu);
+    auto it = e->tickets.find(ticket);
+    if (it == e->tickets.end()) return efail(e, RDOS_EINVAL, "unknown ticket %llu", (unsigned long long)ticket);
+    const Ticket &tk = it->second;
+    if (!tk.done || tk.failed || tk.n_steps == 0)
+        return efail(e, RDOS_ESTATE, "ticket %llu has not run to completion", (unsigned long long)ticket);
+    auto sec = [](Clock::time_point a, Clock::time_point b) { return std::chrono::duration<double>(b - a).count(); };
+    if (wait_s) *wait_s = sec(tk.submitted, tk.admit_start);
+    if (setup_s) *setup_s = sec(tk.admit_start, tk.admit_end);
+    if (join_s) *join_s = sec(tk.admit_end, tk.started);
+    if (run_s) *run_s = sec(tk.started, tk.finished);
     return RDOS_OK;
 }
 
@@ -965,8 +1027,9 @@ void rdos_engine_destroy(rdos_engine *e)
     void *p[] = {e->d_sims, e->d_tiles, e->d_work};
     for (void *q : p)
         if (q) (void)hipFree(q);
-    free_queue(&e->queue);
-    free_queue(&e->queue2);
+    free_queue(&e->queue, e->stream);
+    free_queue(&e->queue2, e->stream);
+    (void)hipStreamSynchronize(e->stream);
     for (hipEvent_t ev : e->kev) (void)hipEventDestroy(ev);
     if (e->fork) (void)hipEventDestroy(e->fork);
     if (e->join) (void)hipEventDestroy(e->join);

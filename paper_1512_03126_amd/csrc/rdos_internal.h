@@ -94,6 +94,15 @@ hipError_t launch_geometry(const double *xyz, const int32_t *tet_verts, const in
 hipError_t launch_geometry_tri(const double *xyz, const int32_t *tri_verts, const int32_t *nbr, int32_t T,
                                double *scratch_area, double *scratch_bc, double *scratch_len, MeshRec *mesh,
                                int32_t *bad_area, hipStream_t st);
+// Face matching on the device for cells of cell_verts (4: tetrahedra, 3:
+// triangles) vertices with ids below 2^bits (bits <= 21 for tetrahedra, <= 31
+// for triangles): nbr[4 T] (filled with -1 by the caller) gets the cell
+// across each face; *err (zero on entry) becomes non-zero when a face lies on
+// more than two cells or twice on one.  scratch holds
+// face_match_scratch_bytes(T, cell_verts) bytes.
+size_t face_match_scratch_bytes(int32_t T, int32_t cell_verts);
+hipError_t launch_face_match(const int32_t *cells, int32_t T, int32_t cell_verts, int32_t bits, int32_t *nbr,
+                             void *scratch, int32_t *err, hipStream_t st);
 hipError_t launch_tau_min(const MeshRec *mesh, int32_t T, const double *D, int32_t S,
                           unsigned long long *out_bits, hipStream_t st);
 // Writes the k-th smallest (0-based, clamped to the last) of 1/(D_m g_t)
@@ -126,10 +135,12 @@ struct QueueView {
     int64_t qcap;       // allocated entries per count row
     int32_t species;    // allocated count rows
     int32_t scaled;     // some simulation of the work list uses transfer form 1 (picks the update kernel)
+    uint32_t *sync;     // [kPersistSyncWords] grid-barrier counters and failure word of the one-launch path
     unsigned long long *work;  // null, or [3] device totals the update kernel adds to: tets, count additions,
                                // additions that are transfers across a face
 };
 constexpr int kMaxSegments = 1024;
+constexpr int kPersistSyncWords = 64 * 32 + 32;  // 64 barrier counters on lines of their own, the failure word
 constexpr int kLenStride = 32;  // 128 bytes between segment lengths: no two share a line
 
 // Queue geometry for a work list of n_tiles tiles: tiles ti with
@@ -164,6 +175,16 @@ inline int32_t scan_blocks_for(int64_t n_tiles)
     return (int32_t)(b < 1 ? 1 : (b > (1 << 20) ? (1 << 20) : b));
 }
 hipError_t launch_advance(DevSim *sims, const WorkHeader *hdr, int64_t by, hipStream_t st);
+// Small work lists: n_periods periods in one cooperative launch of `grid`
+// blocks (at most persist_grid_limit(q), every block resident), grid-wide
+// barriers between the scan and update phases.  Period i uses queue half
+// (phase + i) & 1.  sync points at kPersistSyncWords words of device memory
+// (barrier counters, failure word) that no other launch uses meanwhile; a
+// barrier that times out raises bit 3 of every simulation's flags.
+int32_t persist_grid_limit(const QueueView &q);
+hipError_t launch_persist(const DevSim *sims, const Tile *tiles, int64_t iter0, int32_t n_periods, int32_t phase,
+                          int64_t partial, double tau_last, const QueueView &q, int32_t grid, uint32_t *sync,
+                          hipStream_t st);
 // Rebuilds the occupancy bytes of buf[parity] from the counts of every
 // realization and species and clears those of the other buffer (after
 // counts were set from the host).

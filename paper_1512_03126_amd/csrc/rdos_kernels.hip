@@ -174,6 +174,99 @@ hipError_t launch_geometry(const double *xyz, const int32_t *tet_verts, const in
     return hipGetLastError();
 }
 
+// ---------------------------------------------------------------------------
+// Face matching (the neighbours of Sec. II.A's subvolumes): each face of a
+// cell becomes a key, its vertex ids sorted and packed (bits per id), with
+// its slot 4 cell + face; after a radix sort the two cells of an interior
+// face sit side by side.  Triangles (surfaces) match edges the same way.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void face_keys_kernel(const int32_t *__restrict__ cells, int32_t T,
+                                                        int32_t cell_verts, int32_t bits,
+                                                        unsigned long long *__restrict__ keys,
+                                                        int32_t *__restrict__ slots)
+{
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= (int64_t)T * cell_verts) return;
+    const int32_t t = (int32_t)(i / cell_verts), f = (int32_t)(i % cell_verts);
+    uint32_t v[3];
+    int k = 0;
+    for (int j = 0; j < cell_verts; ++j)
+        if (j != f) v[k++] = (uint32_t)cells[(int64_t)t * cell_verts + j];
+    unsigned long long key;
+    if (cell_verts == 4) {  // sort three ids
+        uint32_t a = v[0], b = v[1], c = v[2], x;
+        if (a > b) { x = a; a = b; b = x; }
+        if (b > c) { x = b; b = c; c = x; }
+        if (a > b) { x = a; a = b; b = x; }
+        key = ((unsigned long long)a << (2 * bits)) | ((unsigned long long)b << bits) | (unsigned long long)c;
+    } else {
+        const uint32_t a = v[0] < v[1] ? v[0] : v[1], b = v[0] < v[1] ? v[1] : v[0];
+        key = ((unsigned long long)a << bits) | (unsigned long long)b;
+    }
+    keys[i] = key;
+    slots[i] = 4 * t + f;
+}
+
+// Thread i looks at the run of equal keys that starts at i: two slots are
+// neighbours across that face; more than two, or one cell twice, raises
+// *err (the caller then reports the first offending face in key order).
+__global__ __launch_bounds__(256) void face_pair_kernel(const unsigned long long *__restrict__ keys,
+                                                        const int32_t *__restrict__ slots, int64_t n,
+                                                        int32_t *__restrict__ nbr, int32_t *__restrict__ err)
+{
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= n || (i > 0 && keys[i - 1] == keys[i])) return;
+    if (i + 1 >= n || keys[i + 1] != keys[i]) return;  // a face on no other cell: boundary
+    if (i + 2 < n && keys[i + 2] == keys[i]) {
+        atomicOr(err, 1);
+        return;
+    }
+    const int32_t s0 = slots[i], s1 = slots[i + 1];
+    if (s0 / 4 == s1 / 4) {
+        atomicOr(err, 2);
+        return;
+    }
+    nbr[s0] = s1 / 4;
+    nbr[s1] = s0 / 4;
+}
+
+static size_t face_sort_temp_bytes(int64_t n)
+{
+    size_t bytes = 0;
+    (void)hipcub::DeviceRadixSort::SortPairs(nullptr, bytes, (const unsigned long long *)nullptr,
+                                             (unsigned long long *)nullptr, (const int32_t *)nullptr,
+                                             (int32_t *)nullptr, (int)n, 0, 64);
+    return bytes;
+}
+
+size_t face_match_scratch_bytes(int32_t T, int32_t cell_verts)
+{
+    const int64_t n = (int64_t)T * cell_verts;
+    return 2 * (size_t)n * (sizeof(unsigned long long) + sizeof(int32_t)) + 512 + face_sort_temp_bytes(n);
+}
+
+hipError_t launch_face_match(const int32_t *cells, int32_t T, int32_t cell_verts, int32_t bits, int32_t *nbr,
+                             void *scratch, int32_t *err, hipStream_t st)
+{
+    const int64_t n = (int64_t)T * cell_verts;
+    char *p = static_cast<char *>(scratch);
+    unsigned long long *k0 = reinterpret_cast<unsigned long long *>(p);
+    unsigned long long *k1 = k0 + n;
+    int32_t *s0 = reinterpret_cast<int32_t *>(k1 + n);
+    int32_t *s1 = s0 + n;
+    void *temp = reinterpret_cast<char *>(s1 + n) + 256;
+    size_t temp_bytes = face_sort_temp_bytes(n);
+    const unsigned grid = (unsigned)((n + 255) / 256);
+    face_keys_kernel<<<grid, 256, 0, st>>>(cells, T, cell_verts, bits, k0, s0);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    const int end_bit = (cell_verts == 4 ? 3 : 2) * bits;
+    e = hipcub::DeviceRadixSort::SortPairs(temp, temp_bytes, k0, k1, s0, s1, (int)n, 0, end_bit, st);
+    if (e != hipSuccess) return e;
+    face_pair_kernel<<<grid, 256, 0, st>>>(k1, s1, n, nbr, err);
+    return hipGetLastError();
+}
+
 // tau upper limit: min over tets and diffusing species of 1/(D g).  Positive
 // doubles order like their bit patterns, so an integer atomic min is exact.
 __global__ __launch_bounds__(256) void tau_min_kernel(const MeshRec *__restrict__ mesh, int32_t T,
@@ -540,30 +633,28 @@ struct Queue {
 constexpr int32_t kBufferWord3 = 0x00020000;
 constexpr int32_t kScanLoadPolicy = 16;
 
+constexpr int kScanWaves = kBlock / 64;
+constexpr int kTileGroups = kTetsPerTile / 4;    // 256 four-tet groups per tile
+
+// One period's scan by one wavefront over the tiles wave0, wave0 + n_waves,
+// ...  Per wavefront LDS: glist, the tile's flagged groups (group | species
+// mask << 8) in tet order, and stage, the queue entries of one chunk of 64
+// groups (at most 256 tets) staged at their ranks.
 template <int MAXS>
-__global__ __launch_bounds__(kBlock) void scan_kernel(const DevSim *__restrict__ sims,
-                                                      const Tile *__restrict__ tiles, int64_t iter, Queue q,
-                                                      int32_t qsel)
+__device__ __forceinline__ void scan_tiles(const DevSim *__restrict__ sims, const Tile *__restrict__ tiles,
+                                           int64_t iter, const Queue &q, int32_t qsel, int32_t wave0,
+                                           int32_t n_waves, int32_t *__restrict__ glist,
+                                           int32_t (*__restrict__ stage)[kTileGroups])
 {
-    constexpr int kWaves = kBlock / 64;
     constexpr int kLaneTets = kTetsPerTile / 64;   // 16 consecutive tets per lane in the map sweep
     constexpr int kGroups = kLaneTets / 4;           // its four-tet groups
-    constexpr int kTileGroups = kTetsPerTile / 4;    // 256 groups per tile
-    // Per wavefront: the tile's flagged groups (group | species mask << 8) in
-    // tet order, and the queue entries of one chunk of 64 groups (at most 256
-    // tets) staged at their ranks.
-    __shared__ int32_t glist[kWaves][kTileGroups];
-    __shared__ int32_t stage[kWaves][1 + MAXS][kTileGroups];
     const int lane = threadIdx.x & 63;
-    const int wv = threadIdx.x >> 6;
     const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
     const WorkHeader h = *q.hdr;
-    const int32_t n_waves = (int32_t)gridDim.x * kWaves;
     const gptr<int32_t> qtet = global(q.tet);
     const gptr<int32_t> qcnt = global(q.counts);
     // one wavefront per tile; the tile index is uniform over the wavefront
-    for (int32_t ti = __builtin_amdgcn_readfirstlane((int32_t)blockIdx.x * kWaves + (int32_t)(threadIdx.x >> 6));
-         ti < h.n_tiles; ti += n_waves) {
+    for (int32_t ti = __builtin_amdgcn_readfirstlane(wave0); ti < h.n_tiles; ti += n_waves) {
         const Tile tile = tiles[h.tile0 + ti];
         const DevSim &sm = sims[tile.sim];
         const int64_t period = sm.step0 + iter;
@@ -615,7 +706,7 @@ __global__ __launch_bounds__(kBlock) void scan_kernel(const DevSim *__restrict__
 #pragma unroll
             for (int k = 0; k < kGroups; ++k)
                 if (sp[k] != 0u) {
-                    glist[wv][r] = (lane * kGroups + k) | (int32_t)(sp[k] << 8);
+                    glist[r] = (lane * kGroups + k) | (int32_t)(sp[k] << 8);
                     ++r;
                 }
         }
@@ -637,7 +728,7 @@ __global__ __launch_bounds__(kBlock) void scan_kernel(const DevSim *__restrict__
         // coalesced store per row; the vectors read are then cleared.
         for (int32_t c0 = 0; c0 < F; c0 += 64) {
             const bool act = c0 + lane < F;
-            const int32_t gl = act ? glist[wv][c0 + lane] : 0;
+            const int32_t gl = act ? glist[c0 + lane] : 0;
             const int32_t gid = gl & 0xFF;
             const uint32_t gsp = act ? ((uint32_t)gl >> 8) : 0u;
             const int32_t tg = tile.tet0 + 4 * gid;  // the group's first tet
@@ -680,11 +771,11 @@ __global__ __launch_bounds__(kBlock) void scan_kernel(const DevSim *__restrict__
 #pragma unroll
             for (int b = 0; b < 4; ++b) {
                 if (!((bits >> b) & 1u)) continue;
-                stage[wv][0][k] = 4 * gid + b;
+                stage[0][k] = 4 * gid + b;
 #pragma unroll
                 for (int s = 0; s < MAXS; ++s) {
                     if (s >= S) break;
-                    stage[wv][1 + s][k] = b == 0 ? c[s].x : b == 1 ? c[s].y : b == 2 ? c[s].z : c[s].w;
+                    stage[1 + s][k] = b == 0 ? c[s].x : b == 1 ? c[s].y : b == 2 ? c[s].z : c[s].w;
                 }
                 ++k;
             }
@@ -693,10 +784,10 @@ __global__ __launch_bounds__(kBlock) void scan_kernel(const DevSim *__restrict__
             __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
             const int64_t base = (int64_t)seg * h.seg_cap + slot;
             for (int32_t e = lane; e < total; e += 64) {
-                qtet[base + e] = ti * kTetsPerTile + stage[wv][0][e];
+                qtet[base + e] = ti * kTetsPerTile + stage[0][e];
 #pragma unroll
                 for (int s = 0; s < MAXS; ++s)
-                    if (s < S) qcnt[s * h.qcap + base + e] = stage[wv][1 + s][e];
+                    if (s < S) qcnt[s * h.qcap + base + e] = stage[1 + s][e];
             }
             __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
             __builtin_amdgcn_wave_barrier();
@@ -715,47 +806,40 @@ __global__ __launch_bounds__(kBlock) void scan_kernel(const DevSim *__restrict__
     }
 }
 
-// Per-lane state for up to KS species in LDS (20 KS bytes per lane).  With
-// the default transfer form the kernel fits 128 VGPRs without spilling; for
-// KS <= 6 the LDS allows four blocks per CU too, so it runs four wavefronts
-// per SIMD.  The other instances keep the register budget of three.
-template <bool ANY_SCALED, int KS>
-__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(KS <= 6 && !ANY_SCALED ? 4 : 3))) void
-update_kernel(const DevSim *__restrict__ sims, const Tile *__restrict__ tiles, Queue q, int32_t qsel, int64_t iter,
-              int64_t partial, double tau_last, int32_t grid_segments)
+template <int MAXS>
+__global__ __launch_bounds__(kBlock) void scan_kernel(const DevSim *__restrict__ sims,
+                                                      const Tile *__restrict__ tiles, int64_t iter, Queue q,
+                                                      int32_t qsel)
 {
-    __shared__ double occ[KS * kBlock];
-    __shared__ double last[KS * kBlock];
-    __shared__ int32_t counts[KS * kBlock];
-    const LaneState ls{counts + threadIdx.x, occ + threadIdx.x, last + threadIdx.x};
-    if (blockIdx.x == 0)
-        for (int k = threadIdx.x; k < kMaxSegments; k += kBlock) q.len[((qsel ^ 1) * kMaxSegments + k) * kLenStride] = 0;
-    // the header's fields are uniform: held in scalar registers
-    WorkHeader h = *q.hdr;
+    __shared__ int32_t glist[kScanWaves][kTileGroups];
+    __shared__ int32_t stage[kScanWaves][1 + MAXS][kTileGroups];
+    const int wv = threadIdx.x >> 6;
+    scan_tiles<MAXS>(sims, tiles, iter, q, qsel, (int32_t)blockIdx.x * kScanWaves + wv,
+                     (int32_t)gridDim.x * kScanWaves, glist[wv], stage[wv]);
+}
+
+// The work header's fields, uniform over the grid: held in scalar registers.
+__device__ __forceinline__ WorkHeader read_header(const WorkHeader *p)
+{
+    WorkHeader h = *p;
     h.n_tiles = __builtin_amdgcn_readfirstlane(h.n_tiles);
     h.nseg = __builtin_amdgcn_readfirstlane(h.nseg);
     h.seg_cap = __builtin_amdgcn_readfirstlane(h.seg_cap);
     h.tile0 = __builtin_amdgcn_readfirstlane(h.tile0);
     h.qcap = (int64_t)(((uint64_t)(uint32_t)__builtin_amdgcn_readfirstlane((int32_t)(uint32_t)h.qcap)) |
                        ((uint64_t)(uint32_t)__builtin_amdgcn_readfirstlane((int32_t)((uint64_t)h.qcap >> 32)) << 32));
-    // The grid is grid_segments x blocks-per-segment; the host sizes
-    // grid_segments to cover every segment a launch may find in use.  A
-    // header with more segments than that is an internal error, reported
-    // through the flags of the work list's first simulation (never silent).
-    if (h.nseg > grid_segments) {
-        if (blockIdx.x == 0 && threadIdx.x == 0) atomicOr(sims[tiles[h.tile0].sim].flags, 4);
-        return;
-    }
-    // uniform over the block: kept in scalar registers
-    const int32_t seg = __builtin_amdgcn_readfirstlane((int32_t)(blockIdx.x % (uint32_t)grid_segments));
-    const int32_t per_seg = __builtin_amdgcn_readfirstlane(max(1, (int32_t)(gridDim.x / (uint32_t)grid_segments)));
-    const int32_t part = __builtin_amdgcn_readfirstlane((int32_t)(blockIdx.x / (uint32_t)grid_segments));
-    if (seg >= h.nseg || part >= per_seg) return;  // uniform over the block
-    const bool tally = q.work != nullptr;
-    if (tally) {
-        if (threadIdx.x == 0) block_tets = block_adds = block_moves = 0;
-        __syncthreads();
-    }
+    return h;
+}
+
+// One block's share (part of per_seg) of queue segment seg in one period:
+// Steps 2-3 of Algorithm 1 for each queued tet, with its additions into the
+// next buffer.
+template <bool ANY_SCALED, int KS>
+__device__ __forceinline__ void update_segment(const DevSim *__restrict__ sims, const Tile *__restrict__ tiles,
+                                               const Queue &q, int32_t qsel, int64_t iter, int64_t partial,
+                                               double tau_last, const WorkHeader &h, int32_t seg, int32_t part,
+                                               int32_t per_seg, const LaneState &ls, bool tally)
+{
     const int32_t n = min(q.len[(qsel * kMaxSegments + seg) * kLenStride], h.seg_cap);
     const int32_t stride = per_seg * kBlock;
     const int64_t seg0 = (int64_t)seg * h.seg_cap;
@@ -801,6 +885,43 @@ update_kernel(const DevSim *__restrict__ sims, const Tile *__restrict__ tiles, Q
                                    occupancy_tag(period + 1), ls, tally);
         }
     }
+}
+
+// Per-lane state for up to KS species in LDS (20 KS bytes per lane).  With
+// the default transfer form the kernel fits 128 VGPRs without spilling; for
+// KS <= 6 the LDS allows four blocks per CU too, so it runs four wavefronts
+// per SIMD.  The other instances keep the register budget of three.
+template <bool ANY_SCALED, int KS>
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(KS <= 6 && !ANY_SCALED ? 4 : 3))) void
+update_kernel(const DevSim *__restrict__ sims, const Tile *__restrict__ tiles, Queue q, int32_t qsel, int64_t iter,
+              int64_t partial, double tau_last, int32_t grid_segments)
+{
+    __shared__ double occ[KS * kBlock];
+    __shared__ double last[KS * kBlock];
+    __shared__ int32_t counts[KS * kBlock];
+    const LaneState ls{counts + threadIdx.x, occ + threadIdx.x, last + threadIdx.x};
+    if (blockIdx.x == 0)
+        for (int k = threadIdx.x; k < kMaxSegments; k += kBlock) q.len[((qsel ^ 1) * kMaxSegments + k) * kLenStride] = 0;
+    const WorkHeader h = read_header(q.hdr);
+    // The grid is grid_segments x blocks-per-segment; the host sizes
+    // grid_segments to cover every segment a launch may find in use.  A
+    // header with more segments than that is an internal error, reported
+    // through the flags of the work list's first simulation (never silent).
+    if (h.nseg > grid_segments) {
+        if (blockIdx.x == 0 && threadIdx.x == 0) atomicOr(sims[tiles[h.tile0].sim].flags, 4);
+        return;
+    }
+    // uniform over the block: kept in scalar registers
+    const int32_t seg = __builtin_amdgcn_readfirstlane((int32_t)(blockIdx.x % (uint32_t)grid_segments));
+    const int32_t per_seg = __builtin_amdgcn_readfirstlane(max(1, (int32_t)(gridDim.x / (uint32_t)grid_segments)));
+    const int32_t part = __builtin_amdgcn_readfirstlane((int32_t)(blockIdx.x / (uint32_t)grid_segments));
+    if (seg >= h.nseg || part >= per_seg) return;  // uniform over the block
+    const bool tally = q.work != nullptr;
+    if (tally) {
+        if (threadIdx.x == 0) block_tets = block_adds = block_moves = 0;
+        __syncthreads();
+    }
+    update_segment<ANY_SCALED, KS>(sims, tiles, q, qsel, iter, partial, tau_last, h, seg, part, per_seg, ls, tally);
     if (tally) {
         __syncthreads();
         if (threadIdx.x == 0) {
@@ -809,6 +930,150 @@ update_kernel(const DevSim *__restrict__ sims, const Tile *__restrict__ tiles, Q
             atomicAdd(&q.work[2], (unsigned long long)block_moves);
         }
     }
+}
+
+// ---------------------------------------------------------------------------
+// Small work lists: all periods of a run in one cooperative launch.  Each
+// period is the scan phase, a grid-wide barrier, the update phase and another
+// barrier, in place of two kernel launches whose gaps dominate when a period
+// holds little work (the 750-tet cube, served requests of a few hundred
+// tiles).
+// ---------------------------------------------------------------------------
+constexpr uint32_t kBarrierSpins = 1u << 22;  // about half a second of waiting per barrier
+
+// Grid-wide barrier of a cooperative launch (every block resident).  Block
+// b arrives on counter b % 64 (one per 128-byte line, so that the arrivals,
+// memory-side atomics, do not queue on one address) and the first
+// wavefront waits until the 64 counters sum to the arrivals of this epoch,
+// one counter per lane.  The agent-scope fences put each block's writes
+// (stores and atomics) before its arrival and the reads after the wait
+// behind every block's writes, as the boundary between two launches does.
+// A wait past its bound raises `fail` and stops waiting, and every later
+// barrier passes at once: a failure ends the kernel (with the simulations'
+// flags raised) instead of hanging it.
+constexpr int kBarrierLines = 64;
+constexpr int kBarrierStride = 32;  // uint32 per 128-byte line
+__device__ __forceinline__ void grid_barrier(uint32_t *bar, uint32_t nblocks, uint32_t &epoch, uint32_t *fail)
+{
+    __syncthreads();
+    if (threadIdx.x < 64) {
+        const uint32_t lane = threadIdx.x;
+        if (lane == 0) {
+            __threadfence();
+            atomicAdd(&bar[(blockIdx.x % kBarrierLines) * kBarrierStride], 1u);
+        }
+        const uint64_t target = (uint64_t)(epoch + 1) * nblocks;
+        uint32_t spins = 0;
+        for (;;) {
+            uint64_t sum = __hip_atomic_load(&bar[lane * kBarrierStride], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+#pragma unroll
+            for (int off = 32; off > 0; off >>= 1) sum += __shfl_xor(sum, off);
+            if (sum >= target) break;
+            if (__hip_atomic_load(fail, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u) break;
+            if (++spins > kBarrierSpins) {
+                if (lane == 0) atomicOr(fail, 1u);
+                break;
+            }
+            __builtin_amdgcn_s_sleep(2);
+        }
+        if (lane == 0) __threadfence();
+    }
+    ++epoch;
+    __syncthreads();
+}
+
+// n_periods periods of every tile: period i uses queue half (phase + i) & 1
+// and the iteration index iter0 + i (period = step0 + iteration, the period
+// equal to `partial` lasting tau_last).  Block b scans the tiles of its
+// wavefronts (grid-stride) and updates the queue segments b, b + grid, ...
+// sync holds the barrier counters (kBarrierLines lines, zero at launch) and,
+// after them, the failure word.  Each queue segment is shared by
+// max(1, grid / segments) blocks.
+template <bool ANY_SCALED, int KS>
+__global__ __launch_bounds__(kBlock) void persist_kernel(const DevSim *__restrict__ sims, const Tile *__restrict__ tiles,
+                                                         Queue q, int32_t phase, int64_t iter0, int32_t n_periods,
+                                                         int64_t partial, double tau_last, uint32_t *sync)
+{
+    __shared__ int32_t glist[kScanWaves][kTileGroups];
+    __shared__ int32_t stage[kScanWaves][1 + KS][kTileGroups];
+    __shared__ double occ[KS * kBlock];
+    __shared__ double last[KS * kBlock];
+    __shared__ int32_t counts[KS * kBlock];
+    const LaneState ls{counts + threadIdx.x, occ + threadIdx.x, last + threadIdx.x};
+    const int wv = threadIdx.x >> 6;
+    const uint32_t G = gridDim.x;
+    uint32_t epoch = 0;
+    const WorkHeader h = read_header(q.hdr);
+    uint32_t *fail = sync + kBarrierLines * kBarrierStride;
+    const int32_t per_seg = h.nseg > 0 ? max(1, (int32_t)G / h.nseg) : 1;
+    for (int32_t p = 0; p < n_periods; ++p) {
+        const int64_t iter = iter0 + p;
+        const int32_t qsel = (phase + p) & 1;
+        scan_tiles<KS>(sims, tiles, iter, q, qsel, (int32_t)blockIdx.x * kScanWaves + wv, (int32_t)G * kScanWaves,
+                       glist[wv], stage[wv]);
+        grid_barrier(sync, G, epoch, fail);
+        if (blockIdx.x == 0)  // the other half serves the next period's scan
+            for (int k = threadIdx.x; k < kMaxSegments; k += kBlock)
+                q.len[((qsel ^ 1) * kMaxSegments + k) * kLenStride] = 0;
+        if (per_seg > 1) {
+            if ((int32_t)blockIdx.x < h.nseg * per_seg)
+                update_segment<ANY_SCALED, KS>(sims, tiles, q, qsel, iter, partial, tau_last, h,
+                                               (int32_t)blockIdx.x % h.nseg, (int32_t)blockIdx.x / h.nseg, per_seg,
+                                               ls, false);
+        } else {
+            for (int32_t seg = __builtin_amdgcn_readfirstlane((int32_t)blockIdx.x); seg < h.nseg; seg += (int32_t)G)
+                update_segment<ANY_SCALED, KS>(sims, tiles, q, qsel, iter, partial, tau_last, h, seg, 0, 1, ls,
+                                               false);
+        }
+        grid_barrier(sync, G, epoch, fail);
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0 && __hip_atomic_load(fail, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u)
+        for (int32_t i = 0; i < h.n_sims; ++i) atomicOr(sims[i].flags, 8);
+}
+
+__global__ void sync_reset_kernel(uint32_t *sync)
+{
+    for (int i = threadIdx.x; i < kPersistSyncWords; i += blockDim.x) sync[i] = 0u;
+}
+
+namespace {
+template <bool ANY_SCALED, int KS>
+const void *persist_entry()
+{
+    return reinterpret_cast<const void *>(&persist_kernel<ANY_SCALED, KS>);
+}
+const void *persist_pick(int32_t species, int32_t scaled)
+{
+    if (species <= 4) return scaled ? persist_entry<true, 4>() : persist_entry<false, 4>();
+    if (species <= 6) return scaled ? persist_entry<true, 6>() : persist_entry<false, 6>();
+    return scaled ? persist_entry<true, kMaxSpecies>() : persist_entry<false, kMaxSpecies>();
+}
+}  // namespace
+
+int32_t persist_grid_limit(const QueueView &qv)
+{
+    int dev = 0, cus = 0, per_cu = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, persist_pick(qv.species, qv.scaled), kBlock, 0) !=
+        hipSuccess)
+        return 0;
+    return per_cu * cus;
+}
+
+hipError_t launch_persist(const DevSim *sims, const Tile *tiles, int64_t iter0, int32_t n_periods, int32_t phase,
+                          int64_t partial, double tau_last, const QueueView &qv, int32_t grid, uint32_t *sync,
+                          hipStream_t st)
+{
+    if (n_periods <= 0) return hipSuccess;
+    if (grid < 1 || !sync) return hipErrorInvalidValue;
+    sync_reset_kernel<<<1, 256, 0, st>>>(sync);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    Queue q{qv.tet, qv.counts, qv.len, qv.hdr, nullptr, qv.species};
+    void *args[] = {(void *)&sims, (void *)&tiles, (void *)&q, (void *)&phase, (void *)&iter0, (void *)&n_periods,
+                    (void *)&partial, (void *)&tau_last, (void *)&sync};
+    return hipLaunchCooperativeKernel(persist_pick(qv.species, qv.scaled), dim3(grid), dim3(kBlock), args, 0, st);
 }
 
 hipError_t launch_scan(const DevSim *sims, const Tile *tiles, int64_t iter, const QueueView &qv, int32_t qsel,

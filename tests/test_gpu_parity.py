@@ -493,3 +493,56 @@ def test_engine_budget_admits_in_turn(P, orc):
         np.testing.assert_array_equal(s.get_counts(0), o.get_counts(0))
         s.close()
     P.rdos_engine_destroy(e)
+
+
+@pytest.mark.parametrize("mode", [0, 1, 2])
+def test_launch_modes_every_period(P, orc, mode):
+    """The one-launch path (a cooperative kernel running every period, grid
+    barriers between the scan and update phases) and the two-launch path
+    give the oracle's counts after every period and after a run to a t_end
+    that shortens the last period (Algorithm 1, Step 1)."""
+    xyz, tets = W.tiny_lattice(4, 0.2e-6, jitter_frac=0.2, seed=12)
+    T = tets.shape[0]
+    rng = np.random.default_rng(30 + mode)
+    init = rng.integers(0, 20, size=(3, len(RICH_D), T)).astype(np.int32)
+    init[:, 0, ::5] += 150
+    note(f"launch mode {mode}: {T} tets x {len(RICH_D)} species x 3 realizations")
+    g, os_ = make_pair(P, orc, xyz, tets, RICH_D, RICH_REACTIONS, init, seed=7)
+    P.rdos_set_launch_mode(g.h, mode)
+    for k in range(6):
+        g.step(1 + k)
+        for o in os_:
+            o.run_steps(1 + k)
+        assert_same(g, os_, f"mode {mode}, after {k + 1} runs")
+    t_end = g.time()[0] + 17.5 * g.tau
+    g.run_until(t_end)
+    for o in os_:
+        o.run_until(t_end)
+    assert_same(g, os_, f"mode {mode}, run to t_end")
+    assert g.time()[0] == t_end
+    g.close()
+
+
+def test_one_launch_with_more_segments_than_blocks(P, orc):
+    """The one-launch path forced on a work list larger than one cooperative
+    grid can hold (three blocks per CU, 768 on 256 CUs): 48 realizations of a
+    16^3 x 6 lattice (24 tiles each, 1152 tiles in 1024 queue segments), so
+    blocks stride over the tiles and segments; counts equal to the oracle's
+    after 12 periods."""
+    xyz, tets = W.kuhn_lattice(16, 0.1e-6)
+    T = tets.shape[0]
+    rng = np.random.default_rng(5)
+    Rz = 48
+    init = np.zeros((Rz, 3, T), np.int32)
+    for r in range(Rz):
+        for q in range(2):
+            np.add.at(init[r, q], rng.integers(0, T, 400), 1)
+    note(f"one launch, strided: {T} tets x {Rz} realizations")
+    g, os_ = make_pair(P, orc, xyz, tets, [1e-12, 1e-12, 0.5e-12], [([0, 1], [2], 1e8), ([2], [0, 1], 10.0)], init,
+                       seed=9)
+    P.rdos_set_launch_mode(g.h, 2)
+    g.step(12)
+    for o in os_:
+        o.run_steps(12)
+    assert_same(g, os_, "one launch, strided")
+    g.close()
