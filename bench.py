@@ -147,7 +147,11 @@ def make_sims(P, models):
 
 
 def run_engine(P, e, sims, periods):
+    """All simulations start from the same chunk (held while they are
+    admitted), run `periods` periods, and are released."""
+    P.rdos_engine_hold(e, True)
     tks = [P.rdos_engine_submit(e, s.h, periods, 1.0) for s in sims]
+    P.rdos_engine_hold(e, False)
     P.rdos_engine_drain(e)
     for t in tks:
         P.rdos_engine_release(e, t)
@@ -404,6 +408,29 @@ def method_bytes(work, species, mesh_tets):
     return 8 * species * work["tets"] + 64 * mesh_tets + 8 * work["transfers"]
 
 
+def run_jittered(P, W, periods):
+    """The jittered 40^3 x 6 lattice (tet volumes spanning about 4x) with
+    A+B<->C and a fourth species D decaying at 1/s from 1 uM in one octant,
+    run plainly (one realization); tau = tau_scale x the smallest 1/(D g)
+    is about 1e-5 s here, so 0.05 s takes about 5000 periods: this runs the
+    first `periods` of them, timed after a warm-up."""
+    m = W.abcd_jittered()
+    sim = P.Simulation.from_model(m)
+    sim.step(8)
+    sim.synchronize()
+    t0 = time.perf_counter()
+    sim.step(periods)
+    sim.synchronize()
+    dt = time.perf_counter() - t0
+    tau = sim.tau
+    sim.close()
+    return {"workload": "jittered 40^3 x 6 Kuhn lattice (384000 tets, volumes spanning about 4x), A+B<->C plus D "
+                        "decaying at 1/s from 1 uM in one octant, 4 species, 1 realization, two launches per period",
+            "periods": periods, "tau_s": tau, "ms_per_period": round(dt / periods * 1e3, 5),
+            "updates_per_s": round(periods * m.n_tets * m.n_species / dt, 1),
+            "periods_to_0.05_s": int(round(0.05 / tau))}
+
+
 def run_small_mesh(P, W):
     """The 1 um diffusion cube (750 tets, one species, 1000 molecules at the
     centre) run plainly to 0.5 s: the last period is shortened to end there
@@ -446,7 +473,8 @@ def main():
     ap.add_argument("--seed", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-plain", action="store_true", help="skip the plain one-realization comparison")
-    ap.add_argument("--no-small", action="store_true", help="skip the small-mesh (750-tet cube) latency figure")
+    ap.add_argument("--no-small", action="store_true",
+                    help="skip the small-mesh (750-tet cube) and jittered-mesh (384k tets, 4 species) figures")
     ap.add_argument("--serving-seconds", type=float, default=12.0,
                     help="length of the serving leg of the default line (Poisson arrivals at --rate); 0 skips it")
     ap.add_argument("--cpu-periods", type=int, default=1014, help="oracle sample length (periods; 1014 = 0.3 s)")
@@ -460,9 +488,10 @@ def main():
         cmd = []
         for c, csv_path in zip(("FETCH_SIZE", "WRITE_SIZE"), args.traffic_from):
             out_dir, name = os.path.split(csv_path)
-            cmd.append(f"timeout -s KILL 300 rocprofv3 --pmc {c} --output-format csv -d {out_dir or '.'} "
+            cmd.append(f"timeout -s KILL 300 rocprofv3 --pmc {c} --kernel-include-regex "
+                       f"'scan_kernel|update_kernel|bandwidth_copy' --output-format csv -d {out_dir or '.'} "
                        f"-o {name.replace('_counter_collection.csv', '')} -- python3 bench.py --steps {args.steps} "
-                       f"--warmup {args.warmup} --no-cpu-baseline --no-plain"
+                       f"--warmup {args.warmup} --no-cpu-baseline --no-plain --no-small --serving-seconds 0"
                        + (f" --shape {args.shape}" if args.shape else ""))
         write_traffic(*args.traffic_from, args.steps, cmd)
         return
@@ -604,10 +633,12 @@ def main():
             config["plain_ms_per_step"] = round(plain["ms_per_step"], 4)
             config["batched_over_plain"] = round(value / plain["value"], 2)
 
-    small = None
+    small = jittered = None
     if not args.no_small:
         small = run_small_mesh(P, W)
         log(f"small mesh: {small['ms_per_period']:.4f} ms/period ({small['periods']} periods)")
+        jittered = run_jittered(P, W, 400)
+        log(f"jittered A+B<->C + D: {jittered['updates_per_s']:.3e} upd/s, {jittered['ms_per_period']:.4f} ms/period")
 
     served = None
     if args.serving_seconds > 0:
@@ -648,6 +679,8 @@ def main():
         out["serving"] = served
     if small:
         out["small_mesh"] = small
+    if jittered:
+        out["jittered_mesh"] = jittered
     print(json.dumps(out), flush=True)
 
 

@@ -279,6 +279,14 @@ rdos_status rdos_engine_poll(rdos_engine *e, uint64_t ticket, int *done, double 
 rdos_status rdos_engine_ticket_times(rdos_engine *e, uint64_t ticket, double *wait_s, double *setup_s,
                                      double *join_s, double *run_s);
 
+/* Starts a set of requests together.  on = 1: the engine starts no new chunk
+ * of periods (the running one finishes; admissions go on).  on = 0: waits
+ * until every queued request that fits the HBM budget has been admitted,
+ * then lets the engine run them all from the same chunk on.  Without it the
+ * first request admitted starts at once, and those admitted after it join
+ * at later chunks (continuous batching). */
+rdos_status rdos_engine_hold(rdos_engine *e, int32_t on);
+
 /* Blocks until every submitted ticket is done. */
 rdos_status rdos_engine_drain(rdos_engine *e);
 

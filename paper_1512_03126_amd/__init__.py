@@ -66,6 +66,7 @@ _SIGS = [
     ("rdos_engine_poll", C.c_int, [C.c_void_p, C.c_uint64, _P(C.c_int), _P(C.c_double)]),
     ("rdos_engine_ticket_times", C.c_int, [C.c_void_p, C.c_uint64, _P(C.c_double), _P(C.c_double), _P(C.c_double),
                                            _P(C.c_double)]),
+    ("rdos_engine_hold", C.c_int, [C.c_void_p, C.c_int32]),
     ("rdos_engine_drain", C.c_int, [C.c_void_p]),
     ("rdos_engine_release", C.c_int, [C.c_void_p, C.c_uint64, _P(C.c_void_p)]),
     ("rdos_engine_stats", C.c_int, [C.c_void_p, _P(C.c_int64), _P(C.c_double), _P(C.c_double)]),
@@ -309,6 +310,12 @@ def rdos_engine_ticket_times(engine, ticket: int):
     _check(lib().rdos_engine_ticket_times(engine, int(ticket), C.byref(w), C.byref(su), C.byref(j), C.byref(r)),
            engine, True)
     return dict(wait_s=w.value, setup_s=su.value, join_s=j.value, run_s=r.value)
+
+
+def rdos_engine_hold(engine, on: bool):
+    """on: start no new chunk; off: admit every queued request that fits, then
+    run them together."""
+    _check(lib().rdos_engine_hold(engine, 1 if on else 0), engine, True)
 
 
 def rdos_engine_drain(engine):

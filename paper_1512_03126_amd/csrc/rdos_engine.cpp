@@ -101,6 +101,8 @@ struct rdos_engine {
     bool stop = false;
     bool worker_dead = false;  // the worker left its loop after a device error
     bool stalled = false;      // nothing runs and the next request does not fit the budget
+    bool admit_blocked = false;  // the next waiting request does not fit the budget now
+    bool held = false;         // rdos_engine_hold: start no chunk
 
     uint64_t next_ticket = 1;
     std::map<uint64_t, Ticket> tickets;
@@ -438,7 +440,8 @@ void admitter_main(rdos_engine *e)
         // nothing runs or waits to join and the next request does not fit: only a release can help
         e->stalled = !progressed && !e->waiting.empty() && e->slots.empty() && e->ready.empty() &&
                      e->admitting == 0;
-        if (e->stalled) e->cv_done.notify_all();
+        e->admit_blocked = !progressed && !e->waiting.empty();
+        if (e->stalled || !progressed) e->cv_done.notify_all();
         if (!progressed) e->cv_admit.wait(lk);
     }
 }
@@ -460,6 +463,10 @@ void worker_main(rdos_engine *e)
     (void)hipSetDevice(e->device);
     std::unique_lock<std::mutex> lk(e->mu);
     while (!e->stop) {
+        if (e->held) {  // rdos_engine_hold: admissions go on, no chunk starts
+            e->cv_work.wait(lk);
+            continue;
+        }
         if (!e->ready.empty()) {  // continuous batching: newly admitted simulations join here
             const auto joined = Clock::now();
             for (uint64_t id : e->ready) {
@@ -751,6 +758,7 @@ rdos_status rdos_engine_submit(rdos_engine *e, rdos_sim *sim, int64_t n_steps, d
     tk.bytes = bytes;
     tk.submitted = Clock::now();
     e->waiting.push_back(id);
+    e->admit_blocked = false;  // the admission thread looks again
     if (ticket) *ticket = id;
     e->cv_admit.notify_all();
     return RDOS_OK;
@@ -788,6 +796,23 @@ rdos_status rdos_engine_ticket_times(rdos_engine *e, uint64_t ticket, double *wa
     return RDOS_OK;
 }
 
+rdos_status rdos_engine_hold(rdos_engine *e, int32_t on)
+{
+    if (!e) return RDOS_EINVAL;
+    std::unique_lock<std::mutex> lk(e->mu);
+    if (on) {
+        e->held = true;
+        return RDOS_OK;
+    }
+    // every queued request that fits is admitted before the worker goes on
+    e->cv_done.wait(lk, [&] {
+        return (e->admitting == 0 && (e->waiting.empty() || e->admit_blocked)) || e->worker_dead || e->stop;
+    });
+    e->held = false;
+    e->cv_work.notify_all();
+    return RDOS_OK;
+}
+
 rdos_status rdos_engine_drain(rdos_engine *e)
 {
     if (!e) return RDOS_EINVAL;
@@ -817,6 +842,7 @@ rdos_status rdos_engine_release(rdos_engine *e, uint64_t ticket, rdos_sim **sim)
     *sim = s;
     e->tickets.erase(it);
     e->stalled = false;  // budget was freed: the admission thread re-checks
+    e->admit_blocked = false;
     e->cv_admit.notify_all();
     return RDOS_OK;
 }

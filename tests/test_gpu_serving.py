@@ -67,6 +67,39 @@ def test_served_results_equal_alone(orc):
         np.testing.assert_array_equal(run_oracle(orc, m, n), got)
 
 
+def test_hold_starts_requests_together(orc):
+    """Requests submitted while the engine is held are all admitted before
+    it runs, then start from the same chunk: with the same number of
+    periods their run times (first launch to completion) are identical; every
+    result equals the oracle's, and the latency parts add up."""
+    import paper_1512_03126_amd as P
+
+    reqs = [small_request(60 + i) for i in range(3)]
+    note("serving: three requests started together by rdos_engine_hold")
+    e = P.rdos_engine_create(0, 0)
+    P.rdos_engine_hold(e, True)
+    tickets = []
+    for m in reqs:
+        s = P.Simulation(m.xyz, m.tets, m.D, m.reactions, seed=m.seed, tau_scale=None)
+        for q in range(m.n_species):
+            s.set_counts(q, m.init[0, q])
+        tickets.append((P.rdos_engine_submit(e, s.h, 40, 1.0), s))
+    time.sleep(0.05)
+    assert not any(P.rdos_engine_poll(e, t)[0] for t, _ in tickets)  # held: nothing has run
+    P.rdos_engine_hold(e, False)
+    P.rdos_engine_drain(e)
+    parts = [P.rdos_engine_ticket_times(e, t) for t, _ in tickets]
+    assert len({p_["run_s"] for p_ in parts}) == 1, parts
+    for (t, s), p_ in zip(tickets, parts):
+        lat = P.rdos_engine_poll(e, t)[1]
+        assert abs(sum(p_.values()) - lat) < 1e-6, (p_, lat)
+        P.rdos_engine_release(e, t)
+    for m, (t, s) in zip(reqs, tickets):
+        np.testing.assert_array_equal(run_oracle(orc, m, 40), s.get_counts())
+        s.close()
+    P.rdos_engine_destroy(e)
+
+
 def test_engine_stall_is_reported_not_hung():
     import paper_1512_03126_amd as P
 
