@@ -176,7 +176,7 @@ def settle_engine(P, e, sims, max_rounds=8):
 def variant_models(name):
     """Models and method options of the widened rows, each timed like the
     batched mix: the same 256 + 64 realizations with another method option,
-    a surface of the same size and occupancy, and six species."""
+    a surface of the same size and occupancy, six and ten species."""
     import numpy as np
 
     import workloads as W
@@ -193,6 +193,17 @@ def variant_models(name):
                                   axis=1)
             out.append(W.Model(m.name + "_six", m.xyz, m.tets, list(m.D) + [1e-12, 1e-12, 1e-12],
                                list(m.reactions) + [([3], [4], 1.0), ([4], [5], 1.0), ([5], [3], 1.0)],
+                               np.ascontiguousarray(init), m.t_end, m.seed))
+        return out, {}
+    if name == "ten_species":
+        # the chemistry of the 10-species stand-in for the model of Sec. III.C
+        # (4 reversible pairs, D of 10-100 um^2/s) on the batched meshes, each
+        # species as many molecules as A, placed elsewhere
+        chem = W.ten_species(seed=1)
+        out = []
+        for m in build_batched():
+            init = np.concatenate([np.roll(m.init[:, 0:1], 7919 * q, axis=2) for q in range(10)], axis=1)
+            out.append(W.Model(m.name + "_ten", m.xyz, m.tets, list(chem.D), list(chem.reactions),
                                np.ascontiguousarray(init), m.t_end, m.seed))
         return out, {}
     if name == "surface":
@@ -218,7 +229,8 @@ def run_variants(P, args):
     """Throughput of the widened rows on the engine (the default launch-shape
     tuning, warm-up, then --steps timed periods each)."""
     res = {}
-    for name in ("reference", "transfer_form_1", "first_order", "tau_outliers_10", "six_species", "surface"):
+    for name in ("reference", "transfer_form_1", "first_order", "tau_outliers_10", "six_species", "ten_species",
+                 "surface"):
         models, opts = variant_models(name)
         sims = []
         for m in models:
@@ -388,6 +400,52 @@ def write_traffic(fetch_csv, write_csv, launches, command, out_dir=None):
         log(f"{path}: {out['bytes_per_launch']:.4g} B per launch")
 
 
+def write_trace_summary(trace_csv, stats_csv, bench_json, launches, command, out_dir=None):
+    """Turns a rocprofv3 --kernel-trace --stats run of this script into
+    profiles/step_kernels_batched_trace.json: the average duration of the
+    timing pass's dispatches of both step kernels (the last `launches` of each
+    before the bandwidth probe's first copy), beside the averages the same run
+    measured with HIP events (its JSON line, `bench_json`), and the profiler's
+    per-kernel table for the whole run."""
+    import csv
+
+    rows = []
+    with open(trace_csv) as f:
+        for r in csv.DictReader(f):
+            rows.append((int(r["Start_Timestamp"]), int(r["End_Timestamp"]), r["Kernel_Name"]))
+    rows.sort()
+    copies = [s for s, _, n in rows if "bandwidth_copy_kernel" in n]
+    if not copies:
+        raise SystemExit(f"no bandwidth_copy_kernel dispatch in {trace_csv}")
+    with open(bench_json) as f:
+        line = json.loads([x for x in f if x.startswith("{")][-1])
+    kern = line["roofline"]["kernels"]
+    out = {"workload": "batched A+B<->C: 256 x 384000-tet + 64 x 48000-tet realizations, 3 species",
+           "kernel_sources": kernel_source_hash(), "command": command, "timing_pass": {},
+           "launch_shape": line["config"].get("launch_shape"), "ms_per_step": line["ms_per_step"]}
+    for k in ("scan_kernel", "update_kernel"):
+        ds = [(s, e, n) for s, e, n in rows if k in n and s < copies[0]][-launches:]
+        if len(ds) != launches:
+            raise SystemExit(f"{len(ds)} {k} dispatches before the copy probe, {launches} expected")
+        us = [(e - s) / 1e3 for s, e, _ in ds]
+        ev = kern[k]["avg_launch_ms"] * 1e3
+        avg = sum(us) / len(us)
+        out["timing_pass"][k] = {"instance": ds[-1][2], "launches": len(us), "trace_avg_us": round(avg, 1),
+                                 "trace_min_us": round(min(us), 1), "trace_max_us": round(max(us), 1),
+                                 "hip_events_avg_us": round(ev, 1), "events_over_trace": round(ev / avg, 3)}
+        log(f"{k}: trace {avg:.1f} us, HIP events {ev:.1f} us per launch over the timing pass")
+    with open(stats_csv) as f:
+        out["stats"] = [{"kernel": r["Name"][:120], "calls": int(r["Calls"]),
+                         "average_us": round(float(r["AverageNs"]) / 1e3, 1),
+                         "share_pct": round(float(r["Percentage"]), 2)}
+                        for r in list(csv.DictReader(f))[:12]]
+    path = os.path.join(out_dir or os.path.join(ROOT, "profiles"), "step_kernels_batched_trace.json")
+    with open(path, "w") as f:
+        json.dump(out, f, indent=1)
+        f.write("\n")
+    log(f"wrote {path}")
+
+
 def update_bytes(work, species):
     """Bytes the update kernel moves for the work it counted on the device,
     in this implementation's own units:
@@ -461,7 +519,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=5,
                     help="untimed periods first; the launch-shape tuner then settles in an untimed phase of its own")
     ap.add_argument("--workload", choices=["batched", "plain", "serving", "variants"], default="batched",
-                    help="variants: throughput of the method options, a surface and six species (not the "
+                    help="variants: throughput of the method options, a surface, six and ten species (not the "
                          "headline line)")
     ap.add_argument("--rate", type=float, default=20.0, help="serving: mean arrivals per second")
     ap.add_argument("--duration", type=float, default=60.0, help="serving: seconds of arrivals")
@@ -481,7 +539,19 @@ def main():
     ap.add_argument("--traffic-from", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
                     help="no run: write the kernels' HBM traffic files from two rocprofv3 --pmc runs of "
                          "`bench.py --steps K --no-cpu-baseline --no-plain` (K = --steps here)")
+    ap.add_argument("--trace-from", nargs=3, metavar=("TRACE_CSV", "STATS_CSV", "BENCH_JSON"),
+                    help="no run: write the step kernels' trace summary from a rocprofv3 --kernel-trace --stats "
+                         "run of `bench.py --steps K --warmup W` (K, W as here) and that run's JSON line")
+    ap.add_argument("--out-dir", default=None, help="with --traffic-from / --trace-from: where to write")
     args = ap.parse_args()
+
+    if args.trace_from:
+        out_dir, name = os.path.split(args.trace_from[0])
+        cmd = (f"cd /tmp && export TMPDIR=/tmp && rocprofv3 --kernel-trace --stats --output-format csv "
+               f"-d {out_dir or '.'} -o {name.replace('_kernel_trace.csv', '')} -- python3 $REPO/bench.py "
+               f"--gpus 1 --steps {args.steps} --warmup {args.warmup} > {args.trace_from[2]}")
+        write_trace_summary(*args.trace_from, args.steps, cmd, args.out_dir)
+        return
 
     if args.traffic_from:
         # the profiler commands that wrote the two files, reconstructed from their paths
@@ -493,7 +563,7 @@ def main():
                        f"-o {name.replace('_counter_collection.csv', '')} -- python3 bench.py --steps {args.steps} "
                        f"--warmup {args.warmup} --no-cpu-baseline --no-plain --no-small --serving-seconds 0"
                        + (f" --shape {args.shape}" if args.shape else ""))
-        write_traffic(*args.traffic_from, args.steps, cmd)
+        write_traffic(*args.traffic_from, args.steps, cmd, args.out_dir)
         return
 
     if args.gpus != 1:

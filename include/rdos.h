@@ -58,8 +58,8 @@ typedef enum {
 } rdos_status;
 
 /* Limits of one simulation. */
-#define RDOS_MAX_SPECIES 8
-#define RDOS_MAX_REACTIONS 16
+#define RDOS_MAX_SPECIES 16
+#define RDOS_MAX_REACTIONS 32
 
 /* New simulation on HIP device `device` with n_realizations independent
  * realizations (realization r uses Philox key (seed, r)).  Each realization is

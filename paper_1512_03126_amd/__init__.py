@@ -20,8 +20,8 @@ LIB_PATH = os.environ.get("RDOS_LIBRARY") or os.path.join(_HERE, "librdos.so")
 
 STATUS = {0: "RDOS_OK", -1: "RDOS_EINVAL", -2: "RDOS_ENOMEM", -3: "RDOS_EDEVICE", -4: "RDOS_ESTATE",
           -5: "RDOS_EOVERFLOW", -6: "RDOS_EBUSY"}
-MAX_SPECIES = 8
-MAX_REACTIONS = 16
+MAX_SPECIES = 16
+MAX_REACTIONS = 32
 
 
 class RdosError(RuntimeError):

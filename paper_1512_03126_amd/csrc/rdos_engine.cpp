@@ -200,7 +200,7 @@ rdos_status ensure(rdos_engine *e, T **buf, int64_t *cap, int64_t need, const ch
 }
 
 // Species rows of the queue, which also size the scan's register arrays.
-int species_bound(int s) { return s <= 2 ? 2 : (s == 3 ? 3 : (s <= 4 ? 4 : (s <= 6 ? 6 : kMaxSpecies))); }
+int species_bound(int s) { return s <= 2 ? 2 : (s == 3 ? 3 : (s <= 4 ? 4 : (s <= 6 ? 6 : (s <= 8 ? 8 : kMaxSpecies)))); }
 
 // Rewrites the device work list for the current slots (lock held).
 rdos_status build_work(rdos_engine *e)

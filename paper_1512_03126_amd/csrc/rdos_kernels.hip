@@ -379,6 +379,22 @@ hipError_t launch_tau_select(const MeshRec *mesh, int32_t T, const double *D, in
 // transfers across a face
 __shared__ uint32_t block_tets, block_adds, block_moves;
 
+// One count for tally `which` (0 tets, 1 additions, 2 face transfers) of the
+// timing pass, whose totals are work[0..2].  Instances of up to 8 species
+// count per block in LDS; the wider ones, whose per-lane state fills half the
+// LDS, add per wavefront straight to the totals (a ballot over the lanes that
+// count, one atomic by the first of them), so two blocks still fit a CU.
+template <int KS>
+__device__ __forceinline__ void tally_count(unsigned long long *work, int which)
+{
+    if constexpr (KS <= 8) {
+        atomicAdd(which == 0 ? &block_tets : (which == 1 ? &block_adds : &block_moves), 1u);
+    } else {
+        const uint64_t m = __ballot(1);
+        if (__lane_id() == (unsigned)__builtin_ctzll(m)) atomicAdd(&work[which], (unsigned long long)__popcll(m));
+    }
+}
+
 struct LaneState {
     int32_t *N;     // counts during the period
     double *occ;    // occupancy integral since the start of the period
@@ -419,12 +435,13 @@ __device__ __forceinline__ double propensity(const DevSim &sm, int q, const Lane
 // nxt and mnxt point at one realization's counts and occupancy rows; the
 // offsets into them are 32-bit (finalize keeps S Tp below 2^29), which keeps
 // the kernel within its register budget.
-template <bool ANY_SCALED>
+template <bool ANY_SCALED, int KS>
 __device__ __forceinline__ void update_tet(const DevSim &sm, int32_t t, int64_t period, double tau_k,
                                            uint32_t key1, int32_t *__restrict__ nxt, int32_t Tp,
                                            uint8_t *__restrict__ mnxt, uint8_t mark, const LaneState &ls,
-                                           bool tally)
+                                           unsigned long long *work)
 {
+    const bool tally = work != nullptr;
     const int S = sm.S;
     const int R = sm.R;
     const uint32_t period32 = (uint32_t)period;
@@ -539,7 +556,7 @@ __device__ __forceinline__ void update_tet(const DevSim &sm, int32_t t, int64_t 
             // selected per lane, instead of one vector load per species
             double Ds = 0.0;
 #pragma unroll
-            for (int k = 0; k < kMaxSpecies; ++k)
+            for (int k = 0; k < KS; ++k)
                 if (k < S) Ds = k == s ? sm.D[k] : Ds;
             double zeta = (tau_k * Ds) * g;
             if (zeta > 1.0) zeta = 1.0;
@@ -576,8 +593,8 @@ __device__ __forceinline__ void update_tet(const DevSim &sm, int32_t t, int64_t 
                         atomicAdd(&nxt[(uint32_t)(s * Tp + nb[f])], (int32_t)out[f]);
                         mnxt[(uint32_t)(s * sm.mstride + (nb[f] >> 2))] = mark;
                         if (tally) {
-                            atomicAdd(&block_adds, 1u);
-                            atomicAdd(&block_moves, 1u);
+                            tally_count<KS>(work, 1);
+                            tally_count<KS>(work, 2);
                         }
                     }
                 ls.n(s) = Ns - (int32_t)n;
@@ -586,7 +603,7 @@ __device__ __forceinline__ void update_tet(const DevSim &sm, int32_t t, int64_t 
         if (ls.n(s) > 0) {  // the molecules that stay
             atomicAdd(&nxt[(uint32_t)(s * Tp + t)], ls.n(s));
             mnxt[(uint32_t)(s * sm.mstride + (t >> 2))] = mark;
-            if (tally) atomicAdd(&block_adds, 1u);
+            if (tally) tally_count<KS>(work, 1);
         }
     }
 }
@@ -838,7 +855,7 @@ template <bool ANY_SCALED, int KS>
 __device__ __forceinline__ void update_segment(const DevSim *__restrict__ sims, const Tile *__restrict__ tiles,
                                                const Queue &q, int32_t qsel, int64_t iter, int64_t partial,
                                                double tau_last, const WorkHeader &h, int32_t seg, int32_t part,
-                                               int32_t per_seg, const LaneState &ls, bool tally)
+                                               int32_t per_seg, const LaneState &ls, unsigned long long *work)
 {
     const int32_t n = min(q.len[(qsel * kMaxSegments + seg) * kLenStride], h.seg_cap);
     const int32_t stride = per_seg * kBlock;
@@ -847,7 +864,7 @@ __device__ __forceinline__ void update_segment(const DevSim *__restrict__ sims, 
     // with the loads of the tet before it instead of starting a round trip
     int32_t next = part * kBlock + (int32_t)threadIdx.x < n ? q.tet[seg0 + part * kBlock + threadIdx.x] : 0;
     for (int32_t i = part * kBlock + threadIdx.x; i < n; i += stride) {
-        if (tally) atomicAdd(&block_tets, 1u);
+        if (work) tally_count<KS>(work, 0);
         const int64_t idx = seg0 + i;
         const int32_t entry = next;
         // the entry's count rows are read with its tile and the next entry,
@@ -878,11 +895,11 @@ __device__ __forceinline__ void update_segment(const DevSim *__restrict__ sims, 
             const double tau_k = period == partial ? tau_last : sm.tau;
             const int64_t Tp = ((int64_t)sm.T + 3) & ~(int64_t)3;
             const int64_t base = (int64_t)tile.realization * sm.S * Tp;
-            update_tet<ANY_SCALED>(sm, tile.tet0 + entry % kTetsPerTile, period, tau_k,
+            update_tet<ANY_SCALED, KS>(sm, tile.tet0 + entry % kTetsPerTile, period, tau_k,
                                    sm.key1 ^ (uint32_t)tile.realization, sm.buf[(period + 1) & 1] + base,
                                    (int32_t)Tp,
                                    sm.mask[(period + 1) & 1] + (int64_t)tile.realization * sm.S * sm.mstride,
-                                   occupancy_tag(period + 1), ls, tally);
+                                   occupancy_tag(period + 1), ls, work);
         }
     }
 }
@@ -890,9 +907,10 @@ __device__ __forceinline__ void update_segment(const DevSim *__restrict__ sims, 
 // Per-lane state for up to KS species in LDS (20 KS bytes per lane).  With
 // the default transfer form the kernel fits 128 VGPRs without spilling; for
 // KS <= 6 the LDS allows four blocks per CU too, so it runs four wavefronts
-// per SIMD.  The other instances keep the register budget of three.
+// per SIMD.  The other instances up to 8 species keep the register budget of
+// three; the 16-species one (80 KB of LDS per block) fits two blocks per CU.
 template <bool ANY_SCALED, int KS>
-__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(KS <= 6 && !ANY_SCALED ? 4 : 3))) void
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(KS <= 6 && !ANY_SCALED ? 4 : (KS <= 8 ? 3 : 2)))) void
 update_kernel(const DevSim *__restrict__ sims, const Tile *__restrict__ tiles, Queue q, int32_t qsel, int64_t iter,
               int64_t partial, double tau_last, int32_t grid_segments)
 {
@@ -916,18 +934,22 @@ update_kernel(const DevSim *__restrict__ sims, const Tile *__restrict__ tiles, Q
     const int32_t per_seg = __builtin_amdgcn_readfirstlane(max(1, (int32_t)(gridDim.x / (uint32_t)grid_segments)));
     const int32_t part = __builtin_amdgcn_readfirstlane((int32_t)(blockIdx.x / (uint32_t)grid_segments));
     if (seg >= h.nseg || part >= per_seg) return;  // uniform over the block
-    const bool tally = q.work != nullptr;
-    if (tally) {
-        if (threadIdx.x == 0) block_tets = block_adds = block_moves = 0;
-        __syncthreads();
+    const bool tally = KS <= 8 && q.work != nullptr;  // per-block tallies (see tally_count)
+    if constexpr (KS <= 8) {
+        if (tally) {
+            if (threadIdx.x == 0) block_tets = block_adds = block_moves = 0;
+            __syncthreads();
+        }
     }
-    update_segment<ANY_SCALED, KS>(sims, tiles, q, qsel, iter, partial, tau_last, h, seg, part, per_seg, ls, tally);
-    if (tally) {
-        __syncthreads();
-        if (threadIdx.x == 0) {
-            atomicAdd(&q.work[0], (unsigned long long)block_tets);
-            atomicAdd(&q.work[1], (unsigned long long)block_adds);
-            atomicAdd(&q.work[2], (unsigned long long)block_moves);
+    update_segment<ANY_SCALED, KS>(sims, tiles, q, qsel, iter, partial, tau_last, h, seg, part, per_seg, ls, q.work);
+    if constexpr (KS <= 8) {
+        if (tally) {
+            __syncthreads();
+            if (threadIdx.x == 0) {
+                atomicAdd(&q.work[0], (unsigned long long)block_tets);
+                atomicAdd(&q.work[1], (unsigned long long)block_adds);
+                atomicAdd(&q.work[2], (unsigned long long)block_moves);
+            }
         }
     }
 }
@@ -1019,11 +1041,11 @@ __global__ __launch_bounds__(kBlock) void persist_kernel(const DevSim *__restric
             if ((int32_t)blockIdx.x < h.nseg * per_seg)
                 update_segment<ANY_SCALED, KS>(sims, tiles, q, qsel, iter, partial, tau_last, h,
                                                (int32_t)blockIdx.x % h.nseg, (int32_t)blockIdx.x / h.nseg, per_seg,
-                                               ls, false);
+                                               ls, nullptr);
         } else {
             for (int32_t seg = __builtin_amdgcn_readfirstlane((int32_t)blockIdx.x); seg < h.nseg; seg += (int32_t)G)
                 update_segment<ANY_SCALED, KS>(sims, tiles, q, qsel, iter, partial, tau_last, h, seg, 0, 1, ls,
-                                               false);
+                                               nullptr);
         }
         grid_barrier(sync, G, epoch, fail);
     }
@@ -1046,6 +1068,7 @@ const void *persist_pick(int32_t species, int32_t scaled)
 {
     if (species <= 4) return scaled ? persist_entry<true, 4>() : persist_entry<false, 4>();
     if (species <= 6) return scaled ? persist_entry<true, 6>() : persist_entry<false, 6>();
+    if (species <= 8) return scaled ? persist_entry<true, 8>() : persist_entry<false, 8>();
     return scaled ? persist_entry<true, kMaxSpecies>() : persist_entry<false, kMaxSpecies>();
 }
 }  // namespace
@@ -1090,6 +1113,8 @@ hipError_t launch_scan(const DevSim *sims, const Tile *tiles, int64_t iter, cons
         scan_kernel<4><<<scan_grid, kBlock, 0, st>>>(sims, tiles, iter, q, qsel);
     else if (qv.species <= 6)
         scan_kernel<6><<<scan_grid, kBlock, 0, st>>>(sims, tiles, iter, q, qsel);
+    else if (qv.species <= 8)
+        scan_kernel<8><<<scan_grid, kBlock, 0, st>>>(sims, tiles, iter, q, qsel);
     else
         scan_kernel<kMaxSpecies><<<scan_grid, kBlock, 0, st>>>(sims, tiles, iter, q, qsel);
     return hipGetLastError();
@@ -1117,6 +1142,13 @@ hipError_t launch_update(const DevSim *sims, const Tile *tiles, int64_t iter, in
                                                                 grid_segments);
         else
             update_kernel<false, 6><<<grid, kBlock, 0, st>>>(sims, tiles, q, qsel, iter, partial, tau_last,
+                                                                grid_segments);
+    } else if (qv.species <= 8) {
+        if (qv.scaled)
+            update_kernel<true, 8><<<grid, kBlock, 0, st>>>(sims, tiles, q, qsel, iter, partial, tau_last,
+                                                                grid_segments);
+        else
+            update_kernel<false, 8><<<grid, kBlock, 0, st>>>(sims, tiles, q, qsel, iter, partial, tau_last,
                                                                 grid_segments);
     } else {
         if (qv.scaled)

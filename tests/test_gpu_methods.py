@@ -95,21 +95,28 @@ WIDE_RX = {
         ([1], [5], 20.0)],
     8: [([0, 1], [2], 3e8), ([2], [0, 1], 400.0), ([3], [4], 60.0), ([4, 5], [3], 2e8), ([5, 5], [1], 1e8),
         ([6], [7], 30.0), ([7], [6], 25.0), ([6, 7], [], 1e8), ([1], [5], 20.0)],
+    16: [([0, 1], [2], 3e8), ([2], [0, 1], 400.0), ([3], [4], 60.0), ([4, 5], [3], 2e8), ([5, 5], [1], 1e8),
+         ([6], [7], 30.0), ([7], [6], 25.0), ([6, 7], [], 1e8), ([1], [5], 20.0), ([8, 9], [10], 2e8),
+         ([10], [8, 9], 300.0), ([11], [12], 40.0), ([12, 12], [11], 1e8), ([13, 14], [15], 3e8),
+         ([15], [13, 14, 9], 50.0), ([9], [], 10.0)],
 }
 
 
 @pytest.mark.parametrize("S,form,occ,thr", [(5, 1, True, 10), (6, 1, True, 3), (6, 0, True, 10),
-                                            (7, 1, False, 10), (8, 1, True, 40), (8, 0, True, 2)])
+                                            (7, 1, False, 10), (8, 1, True, 40), (8, 0, True, 2),
+                                            (10, 1, True, 10), (12, 0, True, 10), (16, 1, True, 4),
+                                            (16, 0, False, 10)])
 def test_wide_chemistry_every_period(orc, S, form, occ, thr):
     """Transfer form 1 (the closing alternative of Sec. II.B) and form 0 with
-    5-8 species: the update instances for the 6- and 8-species bounds and
-    the matching scan instances, bit for bit against the oracle after every
-    one of 32 periods (Algorithm 1, Steps 2-3)."""
+    5-16 species: the update instances for the 6-, 8- and 16-species bounds
+    and the matching scan instances, bit for bit against the oracle after
+    every one of 32 periods (Algorithm 1, Steps 2-3)."""
     import paper_1512_03126_amd as P
 
-    bound = 6 if S <= 6 else 8
+    bound = 6 if S <= 6 else (8 if S <= 8 else 16)
     rx = [r for r in WIDE_RX[bound] if max(r[0] + r[1] + [0]) < S]
-    Ds = [1e-12, 2e-12, 0.5e-12, 3e-12, 1.5e-12, 0.0, 4e-12, 1e-12][:S]
+    Ds = [1e-12, 2e-12, 0.5e-12, 3e-12, 1.5e-12, 0.0, 4e-12, 1e-12,
+          2e-12, 0.7e-12, 1e-12, 0.0, 3e-12, 1.2e-12, 0.4e-12, 2.2e-12][:S]
     xyz, tets = W.tiny_lattice(3, 0.2e-6, jitter_frac=0.2, seed=11 + S)
     T = tets.shape[0]
     rng = np.random.default_rng(100 * S + thr)
@@ -169,4 +176,34 @@ def test_tags_wrap_without_a_zeroth_order_reaction(orc):
         got, want = g.get_counts(), o.get_counts()
         assert np.array_equal(got, want), (stop, int((got != want).sum()))
     assert int(got.sum()) > 0
+    g.close()
+
+
+def test_ten_species_model_every_period(orc):
+    """A model of the shape of Sec. III.C (10 species, 4 reversible
+    reactions, D of 10-100 um^2/s) in three realizations: the 16-species
+    kernel instances, bit for bit against the oracle after every one of 40
+    periods."""
+    import paper_1512_03126_amd as P
+
+    m = W.ten_species(n_realizations=3, seed=5)
+    note(f"ten species: {m.n_tets} tets, {len(m.reactions)} reactions, 3 realizations, 40 periods")
+    g = P.Simulation(m.xyz, m.tets, m.D, m.reactions, seed=m.seed, n_realizations=3)
+    os_ = []
+    for r in range(3):
+        o = orc.OracleSim(m.xyz, m.tets, m.D, m.reactions, seed=m.seed, realization=r)
+        for q in range(10):
+            o.set_counts(q, m.init[r, q])
+            g.set_counts(q, m.init[r, q], realization=r)
+        os_.append(o)
+    assert g.tau == os_[0].tau
+    fired = 0
+    for period in range(40):
+        g.step(1)
+        for r, o in enumerate(os_):
+            o.step()
+            got, want = g.get_counts(None, realization=r), o.get_counts()
+            assert np.array_equal(got, want), (period, r, int((got != want).sum()))
+        fired += int((got[2] + got[4] + got[7] + got[9]).sum() != (m.init[2, [2, 4, 7, 9]]).sum())
+    assert fired > 0   # the reactions ran
     g.close()

@@ -384,40 +384,59 @@ def test_tiled_work_list_bound(P):
         P.Simulation(xyz, tets, [1e-12], [], n_realizations=1_200_000)
 
 
-MAX_D = [1e-12, 2e-12, 0.5e-12, 0.0, 1.5e-12, 1e-12, 0.2e-12, 2e-12]   # 8 species, one not diffusing
-MAX_REACTIONS = [  # 16 reactions: every order, homodimers, up to three products
+EIGHT_D = [1e-12, 2e-12, 0.5e-12, 0.0, 1.5e-12, 1e-12, 0.2e-12, 2e-12]   # 8 species, one not diffusing
+SIXTEEN_RX = [  # 16 reactions: every order, homodimers, up to three products
     ([], [0], 2e-3), ([], [4], 1e-3), ([0], [1], 20.0), ([1], [0], 5.0),
     ([0, 1], [2], 2e3), ([2], [0, 1], 30.0), ([3], [5], 8.0), ([5, 5], [6], 5e3),
     ([6], [5, 5], 12.0), ([4], [], 3.0), ([7, 0], [7, 1], 1e3), ([2, 2], [3], 4e3),
     ([6], [4, 5, 7], 2.0), ([1, 4], [], 1e3), ([7], [7, 7], 1.0), ([7, 7], [7], 3e3),
 ]
+MAX_D = EIGHT_D + [0.8e-12, 3e-12, 0.0, 1.2e-12, 0.3e-12, 2.5e-12, 1e-12, 0.6e-12]   # 16 species, two immobile
+MAX_REACTIONS = SIXTEEN_RX + [  # 16 more over species 8-15, among them a three-product and a 0th-order one
+    ([], [8], 1e-3), ([8], [9], 15.0), ([9], [8], 6.0), ([8, 9], [10], 2e3),
+    ([10], [8, 9], 25.0), ([11, 11], [12], 4e3), ([12], [11, 11], 10.0), ([13], [], 2.0),
+    ([14, 2], [15], 1.5e3), ([15], [14, 2], 20.0), ([15], [13, 13, 14], 1.0), ([12, 13], [], 8e2),
+    ([10], [11], 5.0), ([14, 14], [14], 2e3), ([9, 15], [9, 8], 1e3), ([3], [13], 4.0),
+]
 
 
-def test_maximum_species_and_reactions(P, orc):
-    """The limits of one simulation, 8 species and 16 reactions, every
-    species present: the widest kernel instances, bit for bit; one more
-    species or reaction, or a third reactant, is refused."""
-    assert len(MAX_D) == 8 and len(MAX_REACTIONS) == 16
-    xyz, tets = W.tiny_lattice(6, 0.2e-6, jitter_frac=0.2, seed=21)   # 1296 tets: two tiles, ragged
-    rng = np.random.default_rng(21)
-    init = rng.integers(0, 12, size=(2, 8, tets.shape[0])).astype(np.int32)
-    note(f"maximum sizes: 8 species, 16 reactions, T={tets.shape[0]}, 2 realizations, 40 periods")
-    g, os_ = make_pair(P, orc, xyz, tets, MAX_D, MAX_REACTIONS, init, seed=21)
+def run_every_twenty(P, orc, D, reactions, seed, what):
+    xyz, tets = W.tiny_lattice(6, 0.2e-6, jitter_frac=0.2, seed=seed)   # 1296 tets: two tiles, ragged
+    rng = np.random.default_rng(seed)
+    init = rng.integers(0, 12, size=(2, len(D), tets.shape[0])).astype(np.int32)
+    note(f"{what}: {len(D)} species, {len(reactions)} reactions, T={tets.shape[0]}, 2 realizations, 40 periods")
+    g, os_ = make_pair(P, orc, xyz, tets, D, reactions, init, seed=seed)
     for _ in range(2):
         g.step(20)
         for o in os_:
             o.run_steps(20)
-        assert_same(g, os_, "maximum sizes")
+        assert_same(g, os_, what)
     g.close()
+    return xyz, tets
+
+
+def test_eight_species_sixteen_reactions(P, orc):
+    """8 species and 16 reactions, every species present: the 8-species
+    kernel instances, bit for bit."""
+    assert len(EIGHT_D) == 8 and len(SIXTEEN_RX) == 16
+    run_every_twenty(P, orc, EIGHT_D, SIXTEEN_RX, 21, "8 species")
+
+
+def test_maximum_species_and_reactions(P, orc):
+    """The limits of one simulation, 16 species and 32 reactions, every
+    species present: the widest kernel instances, bit for bit; one more
+    species or reaction, or a third reactant, is refused."""
+    assert len(MAX_D) == P.MAX_SPECIES == 16 and len(MAX_REACTIONS) == P.MAX_REACTIONS == 32
+    xyz, tets = run_every_twenty(P, orc, MAX_D, MAX_REACTIONS, 22, "maximum sizes")
     h = P.rdos_create(0, 1, 1)
     P.rdos_set_mesh(h, xyz, tets)
     for d in MAX_D:
         P.rdos_add_species(h, d)
-    with pytest.raises(P.RdosError, match="at most 8 species"):
+    with pytest.raises(P.RdosError, match="at most 16 species"):
         P.rdos_add_species(h, 1e-12)
     for r, p_, k in MAX_REACTIONS:
         P.rdos_add_reaction(h, r, p_, k)
-    with pytest.raises(P.RdosError, match="at most 16 reactions"):
+    with pytest.raises(P.RdosError, match="at most 32 reactions"):
         P.rdos_add_reaction(h, [0], [1], 1.0)
     with pytest.raises(P.RdosError, match="0..2 reactants"):
         P.rdos_add_reaction(h, [0, 1, 2], [], 1.0)

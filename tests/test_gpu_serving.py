@@ -200,6 +200,43 @@ def test_timing_pass_counts_work(orc):
     assert work["transfers"] <= 4 * m.n_species * tets
 
 
+def test_ten_species_in_the_engine(orc):
+    """A 10-species model of the shape of Sec. III.C served by the engine:
+    once in the timing pass (its wide instances tally work per wavefront:
+    the tets updated equal the tet-realizations holding molecules at the
+    start of every period) and once as small work (every period of the run
+    in one cooperative launch); both bit for bit against the oracle."""
+    import paper_1512_03126_amd as P
+
+    m = W.ten_species(seed=7)
+    n = 30
+    note(f"ten species in the engine: {m.n_tets} tets, {n} periods, timing pass then one launch")
+    o = orc.OracleSim(m.xyz, m.tets, m.D, m.reactions, seed=m.seed)
+    for q in range(10):
+        o.set_counts(q, m.init[0, q])
+    tets = 0
+    for _ in range(n):
+        tets += int((o.get_counts() != 0).any(axis=0).sum())
+        o.run_steps(1)
+    want = o.get_counts()
+    for profiling in (True, False):
+        e = P.rdos_engine_create(0, 0)
+        P.rdos_engine_set_profiling(e, profiling)
+        s = P.Simulation(m.xyz, m.tets, m.D, m.reactions, seed=m.seed, tau_scale=None)
+        for q in range(10):
+            s.set_counts(q, m.init[0, q])
+        t = P.rdos_engine_submit(e, s.h, n, 1.0)
+        P.rdos_engine_drain(e)
+        P.rdos_engine_release(e, t)
+        if profiling:
+            work = P.rdos_engine_work_counts(e)
+            assert work["tets"] == tets
+            assert 0 < work["transfers"] <= work["additions"]
+        P.rdos_engine_destroy(e)
+        np.testing.assert_array_equal(want, s.get_counts())
+        s.close()
+
+
 def serving_size_request(i, species=6, t_lo=1e5, t_hi=2.5e5):
     """A request of the serving mix's middle sizes (jittered lattice of
     1e5-2.5e5 tets) with `species` species and at least two reactions: the

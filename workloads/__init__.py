@@ -285,6 +285,36 @@ def production_annihilation(n: int = 5, a: float = 0.2e-6, D: float = 1e-11, k2:
                  seed, species_names=["A"])
 
 
+def ten_species(nx: int = 20, ny: int = 3, nz: int = 3, a: float = 0.1e-6, seed: int = 1,
+                n_realizations: int = 1, conc_lo: float = 0.1e-6, conc_hi: float = 1e-6) -> Model:
+    """A stand-in for the reaction-diffusion model of Sec. III.C and Fig. 10
+    (10 species, 8 reactions: 4 reversible pairs), whose exact species and
+    constants the paper gives only as ranges: D log-uniform in [10, 100]
+    um^2/s, the four bimolecular reactions log-uniform in [1, 1000] /(uM s),
+    the four first-order reverses in [1, 100] /s.  Species pair up as
+    S0 + S1 <-> S2, S2 + S3 <-> S4, S5 + S6 <-> S7, S7 + S8 <-> S9 in a bar of
+    nx x ny x nz Kuhn cells (the paper's cylinder stands in as a square
+    tube); each species starts log-uniform in [conc_lo, conc_hi] molar,
+    placed by volume, independently per realization."""
+    rng = np.random.default_rng([seed, 10])
+    xyz, tets = kuhn_box(nx, ny, nz, a)
+    D = [float(math.exp(rng.uniform(math.log(1e-11), math.log(1e-10)))) for _ in range(10)]
+    reactions = []
+    for x, y, z in ((0, 1, 2), (2, 3, 4), (5, 6, 7), (7, 8, 9)):
+        kf = float(math.exp(rng.uniform(math.log(1e6), math.log(1e9))))   # 1..1000 /(uM s) in /(M s)
+        kb = float(math.exp(rng.uniform(math.log(1.0), math.log(100.0))))
+        reactions += [([x, y], [z], kf), ([z], [x, y], kb)]
+    vol = _tet_volumes(xyz, tets)
+    vol_total = float(vol.sum())
+    conc = [math.exp(rng.uniform(math.log(conc_lo), math.log(conc_hi))) for _ in range(10)]
+    init = np.zeros((n_realizations, 10, tets.shape[0]), dtype=np.int32)
+    for r in range(n_realizations):
+        for s_ in range(10):
+            init[r, s_] = place_by_volume(xyz, tets, count_for(conc[s_], vol_total), rng, vol=vol)
+    return Model(f"ten_species_{nx}x{ny}x{nz}", xyz, tets, D, reactions, init, t_end=float("nan"), seed=seed,
+                 species_names=[f"S{i}" for i in range(10)])
+
+
 def triangle_lattice(nx: int, ny: int, a: float, jitter_frac: float = 0.0, seed: int = 1) -> Tuple[np.ndarray, np.ndarray]:
     """A planar surface (z = 0) of nx x ny square cells of edge a, each cut
     into two right triangles along a diagonal that alternates like a
