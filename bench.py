@@ -545,11 +545,16 @@ def main():
     ap.add_argument("--out-dir", default=None, help="with --traffic-from / --trace-from: where to write")
     args = ap.parse_args()
 
+    def in_repo(path):
+        # a path as the recorded commands name it: under $REPO, the repository root
+        rel = os.path.relpath(os.path.abspath(path or "."), ROOT)
+        return "$REPO" if rel == "." else ("$REPO/" + rel if not rel.startswith("..") else os.path.abspath(path))
+
     if args.trace_from:
         out_dir, name = os.path.split(args.trace_from[0])
         cmd = (f"cd /tmp && export TMPDIR=/tmp && rocprofv3 --kernel-trace --stats --output-format csv "
-               f"-d {out_dir or '.'} -o {name.replace('_kernel_trace.csv', '')} -- python3 $REPO/bench.py "
-               f"--gpus 1 --steps {args.steps} --warmup {args.warmup} > {args.trace_from[2]}")
+               f"-d {in_repo(out_dir)} -o {name.replace('_kernel_trace.csv', '')} -- python3 $REPO/bench.py "
+               f"--gpus 1 --steps {args.steps} --warmup {args.warmup} > {in_repo(args.trace_from[2])}")
         write_trace_summary(*args.trace_from, args.steps, cmd, args.out_dir)
         return
 
@@ -558,9 +563,10 @@ def main():
         cmd = []
         for c, csv_path in zip(("FETCH_SIZE", "WRITE_SIZE"), args.traffic_from):
             out_dir, name = os.path.split(csv_path)
-            cmd.append(f"timeout -s KILL 300 rocprofv3 --pmc {c} --kernel-include-regex "
-                       f"'scan_kernel|update_kernel|bandwidth_copy' --output-format csv -d {out_dir or '.'} "
-                       f"-o {name.replace('_counter_collection.csv', '')} -- python3 bench.py --steps {args.steps} "
+            cmd.append(f"cd /tmp && export TMPDIR=/tmp && timeout -s KILL 300 rocprofv3 --pmc {c} "
+                       f"--kernel-include-regex 'scan_kernel|update_kernel|bandwidth_copy' --output-format csv "
+                       f"-d {in_repo(out_dir)} -o {name.replace('_counter_collection.csv', '')} -- python3 "
+                       f"$REPO/bench.py --steps {args.steps} "
                        f"--warmup {args.warmup} --no-cpu-baseline --no-plain --no-small --serving-seconds 0"
                        + (f" --shape {args.shape}" if args.shape else ""))
         write_traffic(*args.traffic_from, args.steps, cmd, args.out_dir)

@@ -115,6 +115,8 @@ struct rdos_engine {
     int64_t cap_sims = 0;
     Tile *d_tiles = nullptr;
     int64_t cap_tiles = 0;
+    WorkUnit *d_units = nullptr;  // the work list's units, expanded into d_tiles on the device
+    int64_t cap_units = 0;
     QueueView queue{};   // chain 0 (all tiles when there is one chain)
     QueueView queue2{};  // chain 1
     int32_t n_tiles = 0;
@@ -207,9 +209,11 @@ rdos_status build_work(rdos_engine *e)
 {
     // Realizations never exchange molecules, so the (simulation, realization)
     // units split into two independent chains; units are dealt to the chain
-    // with fewer tiles so far, chain 0's tiles first in the list.
+    // with fewer tiles so far, chain 0's tiles first in the list.  The host
+    // lists the units; a kernel expands them into tiles.
     std::vector<DevSim> sims;
-    std::vector<Tile> part[2];
+    std::vector<WorkUnit> part[2];
+    int64_t part_tiles[2] = {0, 0};
     int32_t max_species = 1;
     int32_t any_scaled = 0;  // some slot uses transfer form 1: the update kernel instance that handles it
     for (size_t i = 0; i < e->slots.size(); ++i) {
@@ -219,23 +223,31 @@ rdos_status build_work(rdos_engine *e)
         d.step0 = s->step;
         d.step_end = tk.end_step;
         sims.push_back(d);
+        const int64_t per = (s->T + kTetsPerTile - 1) / kTetsPerTile;
         for (int32_t r = 0; r < s->Rz; ++r) {
-            std::vector<Tile> &dst = part[part[0].size() <= part[1].size() ? 0 : 1];
-            for (int32_t t0 = 0; t0 < s->T; t0 += kTetsPerTile)
-                dst.push_back({(int32_t)i, r, t0, std::min<int32_t>(kTetsPerTile, s->T - t0)});
+            const int c = part_tiles[0] <= part_tiles[1] ? 0 : 1;
+            part[c].push_back({(int32_t)i, r, s->T, 0});
+            part_tiles[c] += per;
         }
         max_species = std::max(max_species, (int32_t)s->D.size());
         if (s->desc.transfer_form == 1) any_scaled = 1;
     }
-    std::vector<Tile> tiles = part[0];
-    tiles.insert(tiles.end(), part[1].begin(), part[1].end());
-    e->n_tiles0 = (int32_t)part[0].size();
+    std::vector<WorkUnit> units = part[0];
+    units.insert(units.end(), part[1].begin(), part[1].end());
+    int64_t n_tiles = 0;
+    for (WorkUnit &u : units) {
+        u.first = (int32_t)n_tiles;
+        n_tiles += (u.T + kTetsPerTile - 1) / kTetsPerTile;
+    }
+    e->n_tiles0 = (int32_t)part_tiles[0];
     rdos_status st = ensure(e, &e->d_sims, &e->cap_sims, (int64_t)std::max<size_t>(sims.size(), 1), "engine slots");
     if (st != RDOS_OK) return st;
-    st = ensure(e, &e->d_tiles, &e->cap_tiles, (int64_t)std::max<size_t>(tiles.size(), 1), "engine tiles");
+    st = ensure(e, &e->d_tiles, &e->cap_tiles, std::max<int64_t>(n_tiles, 1), "engine tiles");
+    if (st != RDOS_OK) return st;
+    st = ensure(e, &e->d_units, &e->cap_units, (int64_t)std::max<size_t>(units.size(), 1), "engine work units");
     if (st != RDOS_OK) return st;
     // chain 0's queue can hold every tile (one chain); chain 1's the second half
-    const int64_t need[2] = {(int64_t)std::max<size_t>(tiles.size(), 1), (int64_t)std::max<size_t>(part[1].size(), 1)};
+    const int64_t need[2] = {std::max<int64_t>(n_tiles, 1), std::max<int64_t>(part_tiles[1], 1)};
     QueueView *qs[2] = {&e->queue, &e->queue2};
     for (int c = 0; c < 2; ++c) {
         int32_t nseg, seg_cap;
@@ -257,11 +269,14 @@ rdos_status build_work(rdos_engine *e)
         ENGINE_HIP(e, hipMemcpyAsync(e->d_sims, sims.data(), sims.size() * sizeof(DevSim), hipMemcpyHostToDevice,
                                      e->stream),
                    "upload slots");
-    if (!tiles.empty())
-        ENGINE_HIP(e, hipMemcpyAsync(e->d_tiles, tiles.data(), tiles.size() * sizeof(Tile), hipMemcpyHostToDevice,
-                                     e->stream),
-                   "upload tiles");
-    e->n_tiles = (int32_t)tiles.size();
+    if (!units.empty()) {
+        ENGINE_HIP(e, hipMemcpyAsync(e->d_units, units.data(), units.size() * sizeof(WorkUnit),
+                                     hipMemcpyHostToDevice, e->stream),
+                   "upload work units");
+        ENGINE_HIP(e, launch_expand_tiles(e->d_units, (int32_t)units.size(), (int32_t)n_tiles, e->d_tiles, e->stream),
+                   "expand tiles");
+    }
+    e->n_tiles = (int32_t)n_tiles;
     e->n_sims = (int32_t)sims.size();
     e->max_species = max_species;
     e->hdr_chains = 0;  // headers are written for the chain count of the next chunk
@@ -1050,7 +1065,7 @@ void rdos_engine_destroy(rdos_engine *e)
         rdos_destroy(kv.second.sim);
     }
     drop_graphs(e);
-    void *p[] = {e->d_sims, e->d_tiles, e->d_work};
+    void *p[] = {e->d_sims, e->d_tiles, e->d_units, e->d_work};
     for (void *q : p)
         if (q) (void)hipFree(q);
     free_queue(&e->queue, e->stream);

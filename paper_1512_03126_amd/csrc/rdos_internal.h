@@ -76,6 +76,15 @@ constexpr int kBlock = 256;        // threads per block (4 wavefronts)
 constexpr int kTetsPerLane = 4;    // one 16-byte load per species and lane
 constexpr int kTetsPerTile = kBlock * kTetsPerLane;
 
+// One realization of one simulation in a work list, for building the tile
+// list on the device: its tiles are tiles[first .. first + ceil(T / kTetsPerTile)).
+struct WorkUnit {
+    int32_t sim;
+    int32_t realization;
+    int32_t T;
+    int32_t first;
+};
+
 // Held while a graph is captured and around device allocations and frees
 // made by other threads, so neither can interfere with a capture.
 inline std::mutex &device_api_mutex()
@@ -175,6 +184,9 @@ inline int32_t scan_blocks_for(int64_t n_tiles)
     return (int32_t)(b < 1 ? 1 : (b > (1 << 20) ? (1 << 20) : b));
 }
 hipError_t launch_advance(DevSim *sims, const WorkHeader *hdr, int64_t by, hipStream_t st);
+// Writes tiles[0 .. n_tiles) from n_units work units whose `first` fields
+// ascend from 0 and leave no gaps (each unit has at least one tile).
+hipError_t launch_expand_tiles(const WorkUnit *units, int32_t n_units, int32_t n_tiles, Tile *tiles, hipStream_t st);
 // Small work lists: n_periods periods in one cooperative launch of `grid`
 // blocks (at most persist_grid_limit(q), every block resident), grid-wide
 // barriers between the scan and update phases.  Period i uses queue half

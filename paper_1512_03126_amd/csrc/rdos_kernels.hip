@@ -1099,6 +1099,33 @@ hipError_t launch_persist(const DevSim *sims, const Tile *tiles, int64_t iter0, 
     return hipLaunchCooperativeKernel(persist_pick(qv.species, qv.scaled), dim3(grid), dim3(kBlock), args, 0, st);
 }
 
+// Tile i belongs to the last unit whose first tile is at or before i.
+__global__ __launch_bounds__(256) void expand_tiles_kernel(const WorkUnit *__restrict__ units, int32_t n_units,
+                                                           int32_t n_tiles, Tile *__restrict__ tiles)
+{
+    const int32_t i = (int32_t)(blockIdx.x * blockDim.x + threadIdx.x);
+    if (i >= n_tiles) return;
+    int32_t lo = 0, hi = n_units - 1;
+    while (lo < hi) {
+        const int32_t mid = (lo + hi + 1) >> 1;
+        if (units[mid].first <= i)
+            lo = mid;
+        else
+            hi = mid - 1;
+    }
+    const WorkUnit u = units[lo];
+    const int32_t t0 = (i - u.first) * kTetsPerTile;
+    tiles[i] = Tile{u.sim, u.realization, t0, min(kTetsPerTile, u.T - t0)};
+}
+
+hipError_t launch_expand_tiles(const WorkUnit *units, int32_t n_units, int32_t n_tiles, Tile *tiles, hipStream_t st)
+{
+    if (n_tiles <= 0) return hipSuccess;
+    if (n_units <= 0) return hipErrorInvalidValue;
+    expand_tiles_kernel<<<(n_tiles + 255) / 256, 256, 0, st>>>(units, n_units, n_tiles, tiles);
+    return hipGetLastError();
+}
+
 hipError_t launch_scan(const DevSim *sims, const Tile *tiles, int64_t iter, const QueueView &qv, int32_t qsel,
                        int32_t scan_grid, hipStream_t st)
 {
