@@ -222,10 +222,12 @@ rdos_status rdos_step_static(rdos_sim *s, int64_t n_steps);
  * realization and tile) runs all its periods in one cooperative launch, the
  * scan and update phases of each period separated by grid-wide barriers;
  * larger ones launch a scan and an update kernel per period.  1: always two
- * launches per period.  2: always one cooperative launch.  The one-launch
- * path exists for small meshes, where the gaps between launches dominate a
- * period (the 1 um cube of Sec. II.A's Fig. 2 example: 750 tets).
- * RDOS_EINVAL for other values. */
+ * launches per period.  2: always one cooperative launch.  3: one fused
+ * launch per period (each wavefront scans its tiles and updates the tets it
+ * queued, no queue in device memory; simulations of more than 8 species
+ * launch two kernels instead).  The one-launch path exists for small meshes,
+ * where the gaps between launches dominate a period (the 1 um cube of
+ * Sec. II.A's Fig. 2 example: 750 tets).  RDOS_EINVAL for other values. */
 rdos_status rdos_set_launch_mode(rdos_sim *s, int32_t mode);
 
 /* Waits for all queued work; reports RDOS_EOVERFLOW if raised. */
@@ -327,7 +329,8 @@ enum {
 };
 
 /* The launch shape of the current work list: periods per graph replay, scan
- * blocks, update blocks per queue segment, 1 or 2 independent chains
+ * blocks, update blocks per queue segment (0: fused, see
+ * rdos_engine_set_shape), 1 or 2 independent chains
  * (halves of the realizations on two streams, so one half's update overlaps
  * the other's scan), and where it comes from (RDOS_SHAPE_*).  The tuner
  * scores each candidate on full graph-replayed chunks of live work, per
@@ -341,7 +344,10 @@ rdos_status rdos_engine_launch_shape(rdos_engine *e, int32_t *chunk, int32_t *sc
 
 /* Fixes the launch shape instead of tuning it: chunk (even, 2..1024)
  * periods per graph, scan_grid (1..2^20) blocks, update_bps (1..64) update
- * blocks per queue segment, chains 1 or 2.  chunk 0 returns to the tuner.
+ * blocks per queue segment or 0 for one fused launch per period (scan_grid
+ * blocks scan their tiles and update what they queued; work lists of more
+ * than 8 species rows launch two kernels with one update block per segment
+ * instead), chains 1 or 2.  chunk 0 returns to the tuner.
  * Results never depend on it; it exists for tests and for callers that
  * tune offline.  RDOS_EINVAL for values out of range. */
 rdos_status rdos_engine_set_shape(rdos_engine *e, int32_t chunk, int32_t scan_grid, int32_t update_bps,

@@ -244,7 +244,8 @@ def rdos_run_until(sim, t_end: float):
 
 def rdos_set_launch_mode(sim, mode: int):
     """0: one cooperative launch for small work lists (default), 1: two
-    launches per period, 2: always one launch."""
+    launches per period, 2: always one launch, 3: one fused launch per
+    period (up to 8 species)."""
     _check(lib().rdos_set_launch_mode(sim, int(mode)), sim)
 
 
@@ -344,11 +345,12 @@ def rdos_engine_launch_shape(engine):
     _check(lib().rdos_engine_launch_shape(engine, C.byref(a), C.byref(b), C.byref(c), C.byref(d), C.byref(src)),
            engine, True)
     return dict(chunk=a.value, scan_grid=b.value, update_blocks_per_segment=c.value, chains=d.value,
-                source=SHAPE_SOURCES.get(src.value, src.value))
+                fused=c.value == 0, source=SHAPE_SOURCES.get(src.value, src.value))
 
 
 def rdos_engine_set_shape(engine, chunk: int, scan_grid: int = 0, update_bps: int = 0, chains: int = 0):
-    """Fix the launch shape (no tuning); chunk 0 returns to the tuner."""
+    """Fix the launch shape (no tuning); chunk 0 returns to the tuner;
+    update_bps 0: one fused launch per period."""
     _check(lib().rdos_engine_set_shape(engine, int(chunk), int(scan_grid), int(update_bps), int(chains)), engine,
            True)
 

@@ -415,6 +415,14 @@ rdos_status enqueue_period(rdos_sim *s, int64_t period, int64_t partial, double 
 {
     rdos_status st = ensure_mask(s);
     if (st != RDOS_OK) return st;
+    if (s->launch_mode == 3 && s->queue.species <= kFusedSpecies) {
+        // one fused launch; the queue's length halves stay as they are, so
+        // the two-launch path that may follow keeps its parity
+        HIP_TRY(s, launch_fused(s->d_desc, s->d_tiles, period, partial, tau_last, s->queue,
+                                scan_blocks_for(s->n_tiles), s->stream),
+                "launch period");
+        return RDOS_OK;
+    }
     HIP_TRY(s, launch_step(s->d_desc, s->d_tiles, period, partial, tau_last, s->queue, (int32_t)(s->launches & 1),
                            scan_blocks_for(s->n_tiles), s->update_bps, s->queue.nseg, s->stream),
             "launch period");
@@ -423,12 +431,12 @@ rdos_status enqueue_period(rdos_sim *s, int64_t period, int64_t partial, double 
 }
 
 // Grid of the one-launch path for this simulation, or 0 when it does not
-// apply (launch mode 0: work lists of at most kPersistTiles tiles; 1: never;
-// 2: always).  Blocks beyond what a cooperative launch may hold stride over
+// apply (launch mode 0: work lists of at most kPersistTiles tiles; 1 and 3:
+// never; 2: always).  Blocks beyond what a cooperative launch may hold stride over
 // the tiles and queue segments.
 int32_t persist_grid(rdos_sim *s)
 {
-    if (s->launch_mode == 1 || (s->launch_mode == 0 && s->n_tiles > kPersistTiles)) return 0;
+    if (s->launch_mode == 1 || s->launch_mode == 3 || (s->launch_mode == 0 && s->n_tiles > kPersistTiles)) return 0;
     if (s->persist_limit < 0) s->persist_limit = persist_grid_limit(s->queue);
     // four blocks per queue segment, so that a segment's tets are shared by
     // 1024 lanes
@@ -994,7 +1002,7 @@ rdos_status rdos_run_until(rdos_sim *s, double t_end)
 rdos_status rdos_set_launch_mode(rdos_sim *s, int32_t mode)
 {
     CHECK_HANDLE(s);
-    if (mode < 0 || mode > 2) return fail(s, RDOS_EINVAL, "launch mode must be 0, 1 or 2");
+    if (mode < 0 || mode > 3) return fail(s, RDOS_EINVAL, "launch mode must be 0, 1, 2 or 3");
     s->launch_mode = mode;
     return RDOS_OK;
 }

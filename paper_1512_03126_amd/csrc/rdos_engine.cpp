@@ -54,7 +54,7 @@ struct Ticket {
 struct Shape {
     int32_t chunk;       // periods per graph replay (even: the queue length halves alternate)
     int32_t scan_grid;   // blocks of the scan launch (grid-stride over the tiles)
-    int32_t update_bps;  // update blocks per queue segment
+    int32_t update_bps;  // update blocks per queue segment; 0: one fused launch per period (no update kernel)
     int32_t chains;      // 1, or 2 independent halves of the realizations on two streams
     bool operator==(const Shape &o) const
     {
@@ -306,10 +306,11 @@ int32_t scan_grid_of(const rdos_engine *e, const Shape &sh)
 }
 int32_t update_segments_of(const rdos_engine *e) { return std::min<int32_t>(e->grid_tiles, kMaxSegments); }
 
-// The launches of `len` periods: a scan and an update launch per period, the
-// first on queue half `phase`, then one launch that moves every slot's
-// period index on by `len`.  With `timed`, events separate every launch
-// (direct launches only: event records are not captured into the graph).
+// The launches of `len` periods: a scan and an update launch per period (or
+// one fused launch, which leaves the queue halves alone), the first on
+// queue half `phase`, then one launch that moves every slot's period index
+// on by `len`.  With `timed`, events separate every launch (direct launches
+// only: event records are not captured into the graph).
 hipError_t enqueue_periods(rdos_engine *e, const Shape &sh, int32_t len, int32_t phase, bool timed)
 {
     hipError_t err = hipSuccess;
@@ -320,6 +321,11 @@ hipError_t enqueue_periods(rdos_engine *e, const Shape &sh, int32_t len, int32_t
         if (err == hipSuccess) err = hipStreamWaitEvent(e->stream2, e->fork, 0);
         for (int32_t i = 0; i < len && err == hipSuccess; ++i) {
             const int32_t qs = (phase + i) & 1;
+            if (sh.update_bps == 0) {
+                err = launch_fused(e->d_sims, e->d_tiles, i, -1, 0.0, e->queue, sg, e->stream);
+                if (err == hipSuccess) err = launch_fused(e->d_sims, e->d_tiles, i, -1, 0.0, e->queue2, sg, e->stream2);
+                continue;
+            }
             err = launch_step(e->d_sims, e->d_tiles, i, -1, 0.0, e->queue, qs, sg, sh.update_bps, gseg, e->stream);
             if (err == hipSuccess)
                 err = launch_step(e->d_sims, e->d_tiles, i, -1, 0.0, e->queue2, qs, sg, sh.update_bps, gseg,
@@ -333,6 +339,12 @@ hipError_t enqueue_periods(rdos_engine *e, const Shape &sh, int32_t len, int32_t
     if (timed) err = hipEventRecord(e->kev[0], e->stream);
     for (int32_t i = 0; i < len && err == hipSuccess; ++i) {
         const int32_t qs = (phase + i) & 1;
+        if (sh.update_bps == 0) {  // fused: timed as an update with an empty scan before it
+            if (timed) err = hipEventRecord(e->kev[2 * i + 1], e->stream);
+            if (err == hipSuccess) err = launch_fused(e->d_sims, e->d_tiles, i, -1, 0.0, e->queue, sg, e->stream);
+            if (err == hipSuccess && timed) err = hipEventRecord(e->kev[2 * i + 2], e->stream);
+            continue;
+        }
         err = launch_scan(e->d_sims, e->d_tiles, i, e->queue, qs, sg, e->stream);
         if (err == hipSuccess && timed) err = hipEventRecord(e->kev[2 * i + 1], e->stream);
         if (err == hipSuccess)
@@ -547,6 +559,9 @@ void worker_main(rdos_engine *e)
         Shape sh = tuning ? e->candidates[e->trial / 2] : e->best;
         const bool timed = e->profiling;
         if (timed || e->n_tiles0 == 0 || e->n_tiles0 == e->n_tiles) sh.chains = 1;  // nothing to split
+        if (sh.update_bps == 0 && e->queue.species > kFusedSpecies) sh.update_bps = 1;  // too wide to fuse
+        // fused periods leave the queue's length halves alone: any phase suits them
+        const bool fused = sh.update_bps == 0;
         if (set_chains(e, sh.chains) != RDOS_OK) {
             fail_slots(e);
             break;
@@ -561,9 +576,9 @@ void worker_main(rdos_engine *e)
             const Ticket &tk = e->tickets[id];
             left_max = std::max<int64_t>(left_max, tk.end_step - tk.sim->step);
         }
-        bool replay = !timed && e->qphase == 0 && left_max >= sh.chunk;
+        bool replay = !timed && (fused || e->qphase == 0) && left_max >= sh.chunk;
         int32_t len = replay ? sh.chunk : (int32_t)std::min<int64_t>(left_max, sh.chunk);
-        if (!replay && !timed && e->qphase == 1 && left_max >= sh.chunk) len = 1;
+        if (!replay && !timed && !fused && e->qphase == 1 && left_max >= sh.chunk) len = 1;
         // Small work lists run their periods in one cooperative launch: as
         // many as the slot nearest its end has left, or (when requests wait
         // to join) at most a chunk, or about 2 ms of device time.
@@ -655,7 +670,7 @@ void worker_main(rdos_engine *e)
             fail_slots(e);
             break;
         }
-        e->qphase = (phase + len) & 1;
+        if (!fused || persist > 0) e->qphase = (phase + len) & 1;
         if (timed) {
             for (int32_t i = 0; i < len; ++i) {
                 float a = 0.f, b = 0.f;
@@ -742,7 +757,9 @@ rdos_status rdos_engine_create(rdos_engine **out, int device, size_t hbm_budget_
         delete e;
         return RDOS_EDEVICE;
     }
-    e->candidates = {{16, 2048, 2, 1}, {16, 8192, 2, 1}, {16, 1024, 2, 2}, {16, 2048, 2, 2}, {16, 4096, 1, 2}};
+    // two-launch shapes, and one fused shape (one launch per period, no queue in device memory)
+    e->candidates = {{16, 2048, 2, 1}, {16, 8192, 2, 1}, {16, 1024, 2, 2}, {16, 2048, 2, 2}, {16, 4096, 1, 2},
+                     {16, 4096, 0, 2}};
     e->worker = std::thread(worker_main, e);
     e->admitter = std::thread(admitter_main, e);
     *out = e;
@@ -898,7 +915,7 @@ rdos_status rdos_engine_set_shape(rdos_engine *e, int32_t chunk, int32_t scan_gr
         e->shape_source = RDOS_SHAPE_DEFAULT;
         return RDOS_OK;
     }
-    if (chunk % 2 != 0 || chunk > 1024 || scan_grid < 1 || scan_grid > (1 << 20) || update_bps < 1 ||
+    if (chunk % 2 != 0 || chunk > 1024 || scan_grid < 1 || scan_grid > (1 << 20) || update_bps < 0 ||
         update_bps > 64 || (chains != 1 && chains != 2))
         return efail(e, RDOS_EINVAL, "launch shape out of range");
     e->best = Shape{chunk, scan_grid, update_bps, chains};

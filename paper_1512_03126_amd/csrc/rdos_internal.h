@@ -177,6 +177,13 @@ hipError_t launch_update(const DevSim *sims, const Tile *tiles, int64_t iter, in
 hipError_t launch_step(const DevSim *sims, const Tile *tiles, int64_t iter, int64_t partial, double tau_last,
                        const QueueView &q, int32_t qsel, int32_t scan_grid, int32_t blocks_per_segment,
                        int32_t grid_segments, hipStream_t st);
+// One launch per period (scan and update fused; no queue in device memory):
+// grid blocks of four wavefronts stride over the tiles named in q.hdr; the
+// queue supplies the header, the species bound and the work tallies only.
+// Queues of up to kFusedSpecies species rows (hipErrorInvalidValue beyond).
+constexpr int kFusedSpecies = 8;
+hipError_t launch_fused(const DevSim *sims, const Tile *tiles, int64_t iter, int64_t partial, double tau_last,
+                        const QueueView &q, int32_t grid, hipStream_t st);
 // Scan blocks needed to give every tile of a work list its own wavefront.
 inline int32_t scan_blocks_for(int64_t n_tiles)
 {

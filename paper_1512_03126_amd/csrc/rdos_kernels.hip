@@ -653,20 +653,154 @@ constexpr int32_t kScanLoadPolicy = 16;
 constexpr int kScanWaves = kBlock / 64;
 constexpr int kTileGroups = kTetsPerTile / 4;    // 256 four-tet groups per tile
 
+// The map sweep of one tile by one wavefront: the tile's flagged four-tet
+// groups, listed in glist (group | species mask << 8) in tet order.  Returns
+// how many, uniform over the wavefront.
+template <int MAXS>
+__device__ __forceinline__ int32_t list_groups(const DevSim &sm, const Tile &tile, int64_t period,
+                                               int32_t *__restrict__ glist)
+{
+    constexpr int kLaneTets = kTetsPerTile / 64;   // 16 consecutive tets per lane in the map sweep
+    constexpr int kGroups = kLaneTets / 4;           // its four-tet groups
+    const int lane = threadIdx.x & 63;
+    const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+    const int32_t off = lane * kLaneTets;
+    const int32_t valid = tile.ntet - off;  // tets of this lane inside the tile (may be <= 0)
+    const int64_t t0 = tile.tet0 + off;
+    const int S = sm.S;
+    // Per species, the four occupancy bytes of this lane's groups in one load
+    // (rows are padded to 16 bytes, t0 / 4 is a multiple of 4), all species
+    // together.  A byte flags its group when it holds this period's tag;
+    // nothing is cleared.
+    const gptr<const uint8_t> mrow =
+        global((const uint8_t *)sm.mask[period & 1]) + (int64_t)tile.realization * S * sm.mstride + (t0 >> 2);
+    const uint32_t tag = occupancy_tag(period);
+    uint32_t mb[MAXS];
+#pragma unroll
+    for (int s = 0; s < MAXS; ++s) {
+        mb[s] = 0u;
+        if (s < S && valid > 0) mb[s] = *(gptr<const uint32_t>)(mrow + (int64_t)s * sm.mstride);
+    }
+    // this lane's flagged groups and the species flagged in each (all of
+    // them in every group if a reaction has no reactants: every tet runs)
+    uint32_t sp[kGroups];
+    uint32_t fl = 0;
+#pragma unroll
+    for (int k = 0; k < kGroups; ++k) {
+        sp[k] = 0u;
+#pragma unroll
+        for (int s = 0; s < MAXS; ++s)
+            if (s < S && ((mb[s] >> (8 * k)) & 0xFFu) == tag) sp[k] |= 1u << s;
+        if (sm.zeroth) sp[k] = (1u << S) - 1u;
+        if (4 * k >= valid) sp[k] = 0u;
+        if (sp[k] != 0u) fl |= 1u << k;
+    }
+    // rank the flagged groups over the wavefront (lane order, then group
+    // order: tet order) and list them in LDS
+    const uint32_t fc = (uint32_t)__popc(fl);
+    int32_t fbefore = 0, F = 0;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        const uint64_t plane = __ballot((fc >> k) & 1u);
+        fbefore += __popcll(plane & below) << k;
+        F += __popcll(plane) << k;
+    }
+    if (F == 0) return 0;  // uniform over the wavefront
+    {
+        int32_t r = fbefore;
+#pragma unroll
+        for (int k = 0; k < kGroups; ++k)
+            if (sp[k] != 0u) {
+                glist[r] = (lane * kGroups + k) | (int32_t)(sp[k] << 8);
+                ++r;
+            }
+    }
+    // LDS operations of one wavefront complete in order; the fences keep
+    // the compiler from moving LDS reads and writes across each other
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    return F;
+}
+
+// One lane's group of a chunk of 64 listed groups: its flagged count
+// vectors (16 bytes per species, the others zero), which of its tets hold
+// molecules (all of them if a reaction has no reactant) and their rank over
+// the wavefront (before: tets of lower lanes; total: the chunk's).
+template <int MAXS>
+struct ChunkGroup {
+    v4i c[MAXS];
+    int32_t gid;
+    uint32_t bits;
+    int32_t before, total;
+};
+
+template <int MAXS>
+__device__ __forceinline__ void read_chunk(const DevSim &sm, const Tile &tile, const __amdgpu_buffer_rsrc_t &rs,
+                                           int64_t Tp, const int32_t *__restrict__ glist, int32_t c0, int32_t F,
+                                           ChunkGroup<MAXS> &g)
+{
+    const int lane = threadIdx.x & 63;
+    const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+    const bool act = c0 + lane < F;
+    const int32_t gl = act ? glist[c0 + lane] : 0;
+    g.gid = gl & 0xFF;
+    const uint32_t gsp = act ? ((uint32_t)gl >> 8) : 0u;
+    const int32_t tg = tile.tet0 + 4 * g.gid;  // the group's first tet
+    uint32_t bits = 0;
+#pragma unroll
+    for (int s = 0; s < MAXS; ++s) {
+        g.c[s] = v4i{0, 0, 0, 0};
+        if ((gsp >> s) & 1u)
+            g.c[s] = __builtin_bit_cast(v4i, __builtin_amdgcn_raw_buffer_load_b128(
+                                                 rs, (int32_t)((s * Tp + tg) * 4), 0, kScanLoadPolicy));
+        bits |= (uint32_t)(g.c[s].x != 0) | ((uint32_t)(g.c[s].y != 0) << 1) | ((uint32_t)(g.c[s].z != 0) << 2) |
+                ((uint32_t)(g.c[s].w != 0) << 3);
+    }
+    if (sm.zeroth && act) bits = 0xFu;  // a reaction without reactants: every tet runs
+    const int32_t in_group = tile.ntet - 4 * g.gid;
+    if (in_group < 4) bits &= in_group > 0 ? (1u << in_group) - 1u : 0u;
+    // a negative count was wrapped by an overflowing atomic add
+    int32_t sign = 0;
+#pragma unroll
+    for (int s = 0; s < MAXS; ++s) sign |= g.c[s].x | g.c[s].y | g.c[s].z | g.c[s].w;
+    if (sign < 0) atomicOr(sm.flags, 1);
+    g.bits = bits;
+    const uint32_t cnt = (uint32_t)__popc(bits);
+    int32_t before = 0, total = 0;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        const uint64_t plane = __ballot((cnt >> k) & 1u);
+        before += __popcll(plane & below) << k;
+        total += __popcll(plane) << k;
+    }
+    g.before = before;
+    g.total = total;
+}
+
+// The queued molecules now live in the queue: clear the vectors read so the
+// buffer is all zero when it is next filled.
+template <int MAXS>
+__device__ __forceinline__ void clear_chunk(int32_t *cur, const Tile &tile, int64_t Tp, const ChunkGroup<MAXS> &g)
+{
+    const int32_t tg = tile.tet0 + 4 * g.gid;
+#pragma unroll
+    for (int s = 0; s < MAXS; ++s)
+        if ((g.c[s].x | g.c[s].y | g.c[s].z | g.c[s].w) != 0)
+            *(gptr<v4i>)(global(cur) + s * Tp + tg) = v4i{0, 0, 0, 0};
+}
+
 // One period's scan by one wavefront over the tiles wave0, wave0 + n_waves,
-// ...  Per wavefront LDS: glist, the tile's flagged groups (group | species
-// mask << 8) in tet order, and stage, the queue entries of one chunk of 64
-// groups (at most 256 tets) staged at their ranks.
+// ...  Per wavefront LDS: glist, the tile's flagged groups, and stage, the
+// queue entries of one chunk of 64 groups (at most 256 tets) staged at their
+// ranks.
 template <int MAXS>
 __device__ __forceinline__ void scan_tiles(const DevSim *__restrict__ sims, const Tile *__restrict__ tiles,
                                            int64_t iter, const Queue &q, int32_t qsel, int32_t wave0,
                                            int32_t n_waves, int32_t *__restrict__ glist,
                                            int32_t (*__restrict__ stage)[kTileGroups])
 {
-    constexpr int kLaneTets = kTetsPerTile / 64;   // 16 consecutive tets per lane in the map sweep
-    constexpr int kGroups = kLaneTets / 4;           // its four-tet groups
     const int lane = threadIdx.x & 63;
-    const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
     const WorkHeader h = *q.hdr;
     const gptr<int32_t> qtet = global(q.tet);
     const gptr<int32_t> qcnt = global(q.counts);
@@ -676,62 +810,9 @@ __device__ __forceinline__ void scan_tiles(const DevSim *__restrict__ sims, cons
         const DevSim &sm = sims[tile.sim];
         const int64_t period = sm.step0 + iter;
         if (period >= sm.step_end) continue;  // uniform over the wavefront
-        const int32_t off = lane * kLaneTets;
-        const int32_t valid = tile.ntet - off;  // tets of this lane inside the tile (may be <= 0)
-        const int64_t t0 = tile.tet0 + off;
-        const int S = sm.S;
-        // Map sweep: per species, the four occupancy bytes of this lane's
-        // groups in one load (rows are padded to 16 bytes, t0 / 4 is a
-        // multiple of 4), all species together.  A byte flags its group when
-        // it holds this period's tag; nothing is cleared.
-        const gptr<const uint8_t> mrow =
-            global((const uint8_t *)sm.mask[period & 1]) + (int64_t)tile.realization * S * sm.mstride + (t0 >> 2);
-        const uint32_t tag = occupancy_tag(period);
-        uint32_t mb[MAXS];
-#pragma unroll
-        for (int s = 0; s < MAXS; ++s) {
-            mb[s] = 0u;
-            if (s < S && valid > 0) mb[s] = *(gptr<const uint32_t>)(mrow + (int64_t)s * sm.mstride);
-        }
-        // this lane's flagged groups and the species flagged in each (all of
-        // them in every group if a reaction has no reactants: every tet runs)
-        uint32_t sp[kGroups];
-        uint32_t fl = 0;
-#pragma unroll
-        for (int k = 0; k < kGroups; ++k) {
-            sp[k] = 0u;
-#pragma unroll
-            for (int s = 0; s < MAXS; ++s)
-                if (s < S && ((mb[s] >> (8 * k)) & 0xFFu) == tag) sp[k] |= 1u << s;
-            if (sm.zeroth) sp[k] = (1u << S) - 1u;
-            if (4 * k >= valid) sp[k] = 0u;
-            if (sp[k] != 0u) fl |= 1u << k;
-        }
-        // rank the flagged groups over the wavefront (lane order, then group
-        // order: tet order) and list them in LDS
-        const uint32_t fc = (uint32_t)__popc(fl);
-        int32_t fbefore = 0, F = 0;
-#pragma unroll
-        for (int k = 0; k < 3; ++k) {
-            const uint64_t plane = __ballot((fc >> k) & 1u);
-            fbefore += __popcll(plane & below) << k;
-            F += __popcll(plane) << k;
-        }
+        const int32_t F = list_groups<MAXS>(sm, tile, period, glist);
         if (F == 0) continue;  // uniform over the wavefront
-        {
-            int32_t r = fbefore;
-#pragma unroll
-            for (int k = 0; k < kGroups; ++k)
-                if (sp[k] != 0u) {
-                    glist[r] = (lane * kGroups + k) | (int32_t)(sp[k] << 8);
-                    ++r;
-                }
-        }
-        // LDS operations of one wavefront complete in order; the fences keep
-        // the compiler from moving LDS reads and writes across each other
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-        __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        const int S = sm.S;
         const int64_t Tp = ((int64_t)sm.T + 3) & ~(int64_t)3;
         int32_t *cur = sm.buf[period & 1] + (int64_t)tile.realization * S * Tp;
         // the realization's counts as a buffer resource (bounds-checked by
@@ -744,38 +825,9 @@ __device__ __forceinline__ void scan_tiles(const DevSim *__restrict__ sims, cons
         // wavefront, staged at their ranks and written to the queue with one
         // coalesced store per row; the vectors read are then cleared.
         for (int32_t c0 = 0; c0 < F; c0 += 64) {
-            const bool act = c0 + lane < F;
-            const int32_t gl = act ? glist[c0 + lane] : 0;
-            const int32_t gid = gl & 0xFF;
-            const uint32_t gsp = act ? ((uint32_t)gl >> 8) : 0u;
-            const int32_t tg = tile.tet0 + 4 * gid;  // the group's first tet
-            v4i c[MAXS];
-            uint32_t bits = 0;
-#pragma unroll
-            for (int s = 0; s < MAXS; ++s) {
-                c[s] = v4i{0, 0, 0, 0};
-                if ((gsp >> s) & 1u)
-                    c[s] = __builtin_bit_cast(v4i, __builtin_amdgcn_raw_buffer_load_b128(
-                                                       rs, (int32_t)((s * Tp + tg) * 4), 0, kScanLoadPolicy));
-                bits |= (uint32_t)(c[s].x != 0) | ((uint32_t)(c[s].y != 0) << 1) | ((uint32_t)(c[s].z != 0) << 2) |
-                        ((uint32_t)(c[s].w != 0) << 3);
-            }
-            if (sm.zeroth && act) bits = 0xFu;  // a reaction without reactants: every tet runs
-            const int32_t in_group = tile.ntet - 4 * gid;
-            if (in_group < 4) bits &= in_group > 0 ? (1u << in_group) - 1u : 0u;
-            // a negative count was wrapped by an overflowing atomic add
-            int32_t sign = 0;
-#pragma unroll
-            for (int s = 0; s < MAXS; ++s) sign |= c[s].x | c[s].y | c[s].z | c[s].w;
-            if (sign < 0) atomicOr(sm.flags, 1);
-            const uint32_t cnt = (uint32_t)__popc(bits);
-            int32_t before = 0, total = 0;
-#pragma unroll
-            for (int k = 0; k < 3; ++k) {
-                const uint64_t plane = __ballot((cnt >> k) & 1u);
-                before += __popcll(plane & below) << k;
-                total += __popcll(plane) << k;
-            }
+            ChunkGroup<MAXS> g;
+            read_chunk<MAXS>(sm, tile, rs, Tp, glist, c0, F, g);
+            const int32_t total = g.total;
             if (total == 0) continue;  // uniform; every vector read was zero
             int32_t slot = 0;
             if (lane == 0) slot = atomicAdd(&q.len[(qsel * kMaxSegments + seg) * kLenStride], total);
@@ -784,15 +836,15 @@ __device__ __forceinline__ void scan_tiles(const DevSim *__restrict__ sims, cons
                 if (lane == 0) atomicOr(sm.flags, 4);
                 continue;
             }
-            int32_t k = before;
+            int32_t k = g.before;
 #pragma unroll
             for (int b = 0; b < 4; ++b) {
-                if (!((bits >> b) & 1u)) continue;
-                stage[0][k] = 4 * gid + b;
+                if (!((g.bits >> b) & 1u)) continue;
+                stage[0][k] = 4 * g.gid + b;
 #pragma unroll
                 for (int s = 0; s < MAXS; ++s) {
                     if (s >= S) break;
-                    stage[1 + s][k] = b == 0 ? c[s].x : b == 1 ? c[s].y : b == 2 ? c[s].z : c[s].w;
+                    stage[1 + s][k] = b == 0 ? g.c[s].x : b == 1 ? g.c[s].y : b == 2 ? g.c[s].z : g.c[s].w;
                 }
                 ++k;
             }
@@ -809,12 +861,7 @@ __device__ __forceinline__ void scan_tiles(const DevSim *__restrict__ sims, cons
             __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
             __builtin_amdgcn_wave_barrier();
             __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-            // the queued molecules now live in the queue: clear the vectors
-            // read so this buffer is all zero when it is next filled
-#pragma unroll
-            for (int s = 0; s < MAXS; ++s)
-                if ((c[s].x | c[s].y | c[s].z | c[s].w) != 0)
-                    *(gptr<v4i>)(global(cur) + s * Tp + tg) = v4i{0, 0, 0, 0};
+            clear_chunk<MAXS>(cur, tile, Tp, g);
         }
         // the next tile's list must not overtake this tile's reads
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -848,6 +895,37 @@ __device__ __forceinline__ WorkHeader read_header(const WorkHeader *p)
     return h;
 }
 
+// Steps 2-3 for the queued tet `entry` (tile index * kTetsPerTile + offset)
+// of `tile`, its counts already in the lane's state.  Lanes of one
+// simulation run together with a wavefront-uniform descriptor (one round
+// when the wavefront holds one simulation); descriptors do not change during
+// a launch, so they are read as constant memory, which lets the uniform
+// reads be scalar loads.
+template <bool ANY_SCALED, int KS>
+__device__ __forceinline__ void update_entry(const DevSim *__restrict__ sims, const Tile &tile, int32_t entry,
+                                             int64_t iter, int64_t partial, double tau_last, const LaneState &ls,
+                                             unsigned long long *work)
+{
+    using ConstSim = const __attribute__((address_space(4))) DevSim;
+    for (uint64_t todo = __ballot(1); todo;) {
+        const int32_t first = __builtin_amdgcn_readlane(tile.sim, (int32_t)__builtin_ctzll(todo));
+        // branch on the lane's ballot bit, not on the equality, so that the
+        // compiler cannot put the lane's own index in place of `first`
+        const uint64_t same = __ballot(tile.sim == first);
+        todo &= ~same;
+        if (!((same >> __lane_id()) & 1ull)) continue;
+        const DevSim &sm = *(const DevSim *)((ConstSim *)sims + first);
+        const int64_t period = sm.step0 + iter;
+        const double tau_k = period == partial ? tau_last : sm.tau;
+        const int64_t Tp = ((int64_t)sm.T + 3) & ~(int64_t)3;
+        const int64_t base = (int64_t)tile.realization * sm.S * Tp;
+        update_tet<ANY_SCALED, KS>(sm, tile.tet0 + entry % kTetsPerTile, period, tau_k,
+                                   sm.key1 ^ (uint32_t)tile.realization, sm.buf[(period + 1) & 1] + base,
+                                   (int32_t)Tp, sm.mask[(period + 1) & 1] + (int64_t)tile.realization * sm.S * sm.mstride,
+                                   occupancy_tag(period + 1), ls, work);
+    }
+}
+
 // One block's share (part of per_seg) of queue segment seg in one period:
 // Steps 2-3 of Algorithm 1 for each queued tet, with its additions into the
 // next buffer.
@@ -878,29 +956,7 @@ __device__ __forceinline__ void update_segment(const DevSim *__restrict__ sims, 
         next = i + stride < n ? q.tet[idx + stride] : 0;
 #pragma unroll
         for (int s = 0; s < KS; ++s) ls.n(s) = cn[s];
-        // lanes of one simulation run together with a wavefront-uniform
-        // descriptor (one round when the wavefront holds one simulation);
-        // descriptors do not change during a launch, so they are read as
-        // constant memory, which lets the uniform reads be scalar loads
-        using ConstSim = const __attribute__((address_space(4))) DevSim;
-        for (uint64_t todo = __ballot(1); todo;) {
-            const int32_t first = __builtin_amdgcn_readlane(tile.sim, (int32_t)__builtin_ctzll(todo));
-            // branch on the lane's ballot bit, not on the equality, so that the
-            // compiler cannot put the lane's own index in place of `first`
-            const uint64_t same = __ballot(tile.sim == first);
-            todo &= ~same;
-            if (!((same >> __lane_id()) & 1ull)) continue;
-            const DevSim &sm = *(const DevSim *)((ConstSim *)sims + first);
-            const int64_t period = sm.step0 + iter;
-            const double tau_k = period == partial ? tau_last : sm.tau;
-            const int64_t Tp = ((int64_t)sm.T + 3) & ~(int64_t)3;
-            const int64_t base = (int64_t)tile.realization * sm.S * Tp;
-            update_tet<ANY_SCALED, KS>(sm, tile.tet0 + entry % kTetsPerTile, period, tau_k,
-                                   sm.key1 ^ (uint32_t)tile.realization, sm.buf[(period + 1) & 1] + base,
-                                   (int32_t)Tp,
-                                   sm.mask[(period + 1) & 1] + (int64_t)tile.realization * sm.S * sm.mstride,
-                                   occupancy_tag(period + 1), ls, work);
-        }
+        update_entry<ANY_SCALED, KS>(sims, tile, entry, iter, partial, tau_last, ls, work);
     }
 }
 
@@ -949,6 +1005,142 @@ update_kernel(const DevSim *__restrict__ sims, const Tile *__restrict__ tiles, Q
                 atomicAdd(&q.work[0], (unsigned long long)block_tets);
                 atomicAdd(&q.work[1], (unsigned long long)block_adds);
                 atomicAdd(&q.work[2], (unsigned long long)block_moves);
+            }
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Fused period: the scan and the update in one launch.  Within a period no
+// tile's update touches what another tile's scan reads or writes (the scan
+// reads and clears counts of buffer k and reads map k; updates add into
+// buffer k + 1 and mark map k + 1), so each wavefront scans its tiles into a
+// queue of its own in LDS, a ring, and updates the queued tets 64 at a time
+// as they accumulate.  Only consecutive periods need the launch boundary
+// between them.  No queue in device memory, one launch per period.
+// ---------------------------------------------------------------------------
+constexpr int kRing = 320;  // ring entries per wavefront: fewer than 64 waiting + one chunk's at most 256
+
+// Steps 2-3 for the n (1..64) queued tets from ring position head on, one
+// per lane.
+template <bool ANY_SCALED, int KS>
+__device__ __forceinline__ void ring_round(const DevSim *__restrict__ sims, const Tile *__restrict__ tiles,
+                                           int32_t tile0, int64_t iter, int64_t partial, double tau_last,
+                                           int32_t (*__restrict__ ring)[kRing], int32_t head, int32_t n,
+                                           const LaneState &ls, unsigned long long *work)
+{
+    const int lane = threadIdx.x & 63;
+    if (lane >= n) return;
+    int32_t pos = head + lane;
+    if (pos >= kRing) pos -= kRing;
+    const int32_t entry = ring[0][pos];
+    // rows past a simulation's S hold values it never reads
+#pragma unroll
+    for (int s = 0; s < KS; ++s) ls.n(s) = ring[1 + s][pos];
+    const Tile tile = tiles[tile0 + entry / kTetsPerTile];
+    if (work) tally_count<KS>(work, 0);
+    update_entry<ANY_SCALED, KS>(sims, tile, entry, iter, partial, tau_last, ls, work);
+}
+
+// One period of the tiles wave0, wave0 + n_waves, ... by one wavefront.  LDS
+// per wavefront: glist (the tile's flagged groups) and the ring, rows
+// [0] entry (tile index * kTetsPerTile + offset) and [1 + s] its count of
+// species s.
+template <bool ANY_SCALED, int KS>
+__device__ __forceinline__ void fused_tiles(const DevSim *__restrict__ sims, const Tile *__restrict__ tiles,
+                                            const WorkHeader &h, int64_t iter, int64_t partial, double tau_last,
+                                            int32_t wave0, int32_t n_waves, int32_t *__restrict__ glist,
+                                            int32_t (*__restrict__ ring)[kRing], const LaneState &ls,
+                                            unsigned long long *work)
+{
+    int32_t head = 0, pending = 0;  // uniform over the wavefront
+    for (int32_t ti = __builtin_amdgcn_readfirstlane(wave0); ti < h.n_tiles; ti += n_waves) {
+        const Tile tile = tiles[h.tile0 + ti];
+        const DevSim &sm = sims[tile.sim];
+        const int64_t period = sm.step0 + iter;
+        if (period >= sm.step_end) continue;  // uniform over the wavefront
+        const int32_t F = list_groups<KS>(sm, tile, period, glist);
+        if (F == 0) continue;  // uniform over the wavefront
+        const int S = sm.S;
+        const int64_t Tp = ((int64_t)sm.T + 3) & ~(int64_t)3;
+        int32_t *cur = sm.buf[period & 1] + (int64_t)tile.realization * S * Tp;
+        const __amdgpu_buffer_rsrc_t rs =
+            __builtin_amdgcn_make_buffer_rsrc(cur, (short)0, (int32_t)(S * Tp * 4), kBufferWord3);
+        for (int32_t c0 = 0; c0 < F; c0 += 64) {
+            ChunkGroup<KS> g;
+            read_chunk<KS>(sm, tile, rs, Tp, glist, c0, F, g);
+            if (g.total == 0) continue;  // uniform; every vector read was zero
+            // append the chunk's occupied tets at the ring's tail, in rank order
+            int32_t k = pending + g.before;
+#pragma unroll
+            for (int b = 0; b < 4; ++b) {
+                if (!((g.bits >> b) & 1u)) continue;
+                int32_t pos = head + k;
+                if (pos >= kRing) pos -= kRing;
+                ring[0][pos] = ti * kTetsPerTile + 4 * g.gid + b;
+#pragma unroll
+                for (int s = 0; s < KS; ++s) {
+                    if (s >= S) break;
+                    ring[1 + s][pos] = b == 0 ? g.c[s].x : b == 1 ? g.c[s].y : b == 2 ? g.c[s].z : g.c[s].w;
+                }
+                ++k;
+            }
+            pending += g.total;
+            clear_chunk<KS>(cur, tile, Tp, g);
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+            // whole rounds of 64 as soon as they are there
+            while (pending >= 64) {
+                ring_round<ANY_SCALED, KS>(sims, tiles, h.tile0, iter, partial, tau_last, ring, head, 64, ls, work);
+                head += 64;
+                if (head >= kRing) head -= kRing;
+                pending -= 64;
+                // the round's ring reads before the next chunk's writes
+                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+                __builtin_amdgcn_wave_barrier();
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+            }
+        }
+        // the next tile's list must not overtake this tile's reads
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    }
+    if (pending > 0)
+        ring_round<ANY_SCALED, KS>(sims, tiles, h.tile0, iter, partial, tau_last, ring, head, pending, ls, work);
+}
+
+template <bool ANY_SCALED, int KS>
+__global__ __launch_bounds__(kBlock) void fused_kernel(const DevSim *__restrict__ sims,
+                                                       const Tile *__restrict__ tiles, const WorkHeader *hdr,
+                                                       int64_t iter, int64_t partial, double tau_last,
+                                                       unsigned long long *work)
+{
+    __shared__ int32_t glist[kScanWaves][kTileGroups];
+    __shared__ int32_t ring[kScanWaves][1 + KS][kRing];
+    __shared__ double occ[KS * kBlock];
+    __shared__ double last[KS * kBlock];
+    __shared__ int32_t counts[KS * kBlock];
+    const LaneState ls{counts + threadIdx.x, occ + threadIdx.x, last + threadIdx.x};
+    const int wv = threadIdx.x >> 6;
+    const WorkHeader h = read_header(hdr);
+    const bool tally = KS <= 8 && work != nullptr;  // per-block tallies (see tally_count)
+    if constexpr (KS <= 8) {
+        if (tally) {
+            if (threadIdx.x == 0) block_tets = block_adds = block_moves = 0;
+            __syncthreads();
+        }
+    }
+    fused_tiles<ANY_SCALED, KS>(sims, tiles, h, iter, partial, tau_last, (int32_t)blockIdx.x * kScanWaves + wv,
+                                (int32_t)gridDim.x * kScanWaves, glist[wv], ring[wv], ls, work);
+    if constexpr (KS <= 8) {
+        if (tally) {
+            __syncthreads();
+            if (threadIdx.x == 0) {
+                atomicAdd(&work[0], (unsigned long long)block_tets);
+                atomicAdd(&work[1], (unsigned long long)block_adds);
+                atomicAdd(&work[2], (unsigned long long)block_moves);
             }
         }
     }
@@ -1184,6 +1376,32 @@ hipError_t launch_update(const DevSim *sims, const Tile *tiles, int64_t iter, in
         else
             update_kernel<false, kMaxSpecies><<<grid, kBlock, 0, st>>>(sims, tiles, q, qsel, iter, partial, tau_last,
                                                                 grid_segments);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_fused(const DevSim *sims, const Tile *tiles, int64_t iter, int64_t partial, double tau_last,
+                        const QueueView &qv, int32_t grid, hipStream_t st)
+{
+    if (grid <= 0) return hipErrorInvalidValue;
+    unsigned long long *work = qv.work;
+    if (qv.species <= 4) {
+        if (qv.scaled)
+            fused_kernel<true, 4><<<grid, kBlock, 0, st>>>(sims, tiles, qv.hdr, iter, partial, tau_last, work);
+        else
+            fused_kernel<false, 4><<<grid, kBlock, 0, st>>>(sims, tiles, qv.hdr, iter, partial, tau_last, work);
+    } else if (qv.species <= 6) {
+        if (qv.scaled)
+            fused_kernel<true, 6><<<grid, kBlock, 0, st>>>(sims, tiles, qv.hdr, iter, partial, tau_last, work);
+        else
+            fused_kernel<false, 6><<<grid, kBlock, 0, st>>>(sims, tiles, qv.hdr, iter, partial, tau_last, work);
+    } else if (qv.species <= 8) {
+        if (qv.scaled)
+            fused_kernel<true, 8><<<grid, kBlock, 0, st>>>(sims, tiles, qv.hdr, iter, partial, tau_last, work);
+        else
+            fused_kernel<false, 8><<<grid, kBlock, 0, st>>>(sims, tiles, qv.hdr, iter, partial, tau_last, work);
+    } else {
+        return hipErrorInvalidValue;  // the rings and lane state of 16 species exceed the LDS
     }
     return hipGetLastError();
 }

@@ -514,12 +514,13 @@ def test_engine_budget_admits_in_turn(P, orc):
     P.rdos_engine_destroy(e)
 
 
-@pytest.mark.parametrize("mode", [0, 1, 2])
+@pytest.mark.parametrize("mode", [0, 1, 2, 3])
 def test_launch_modes_every_period(P, orc, mode):
     """The one-launch path (a cooperative kernel running every period, grid
-    barriers between the scan and update phases) and the two-launch path
-    give the oracle's counts after every period and after a run to a t_end
-    that shortens the last period (Algorithm 1, Step 1)."""
+    barriers between the scan and update phases), the two-launch path and
+    the fused launch (scan and update of each period in one kernel) give the
+    oracle's counts after every period and after a run to a t_end that
+    shortens the last period (Algorithm 1, Step 1)."""
     xyz, tets = W.tiny_lattice(4, 0.2e-6, jitter_frac=0.2, seed=12)
     T = tets.shape[0]
     rng = np.random.default_rng(30 + mode)
@@ -539,6 +540,28 @@ def test_launch_modes_every_period(P, orc, mode):
         o.run_until(t_end)
     assert_same(g, os_, f"mode {mode}, run to t_end")
     assert g.time()[0] == t_end
+    g.close()
+
+
+def test_launch_modes_interleaved(P, orc):
+    """Runs that switch between the fused, two-launch and one-launch paths on
+    one simulation: the fused kernel leaves the queue's length halves alone,
+    so the two-launch periods before and after it keep their parity; counts
+    equal the oracle's after every run.  The fused runs cover a tile list of
+    several tiles per wavefront's ring (3 realizations x 3 tiles)."""
+    xyz, tets = W.tiny_lattice(6, 0.2e-6, jitter_frac=0.2, seed=14)   # 1296 tets: two tiles, ragged
+    T = tets.shape[0]
+    rng = np.random.default_rng(44)
+    init = rng.integers(0, 20, size=(3, len(RICH_D), T)).astype(np.int32)
+    init[:, 0, ::3] += 90   # A, not the autocatalytic B (B + F -> 2B + F would grow B several-fold per period)
+    note(f"interleaved launch modes: {T} tets x {len(RICH_D)} species x 3 realizations")
+    g, os_ = make_pair(P, orc, xyz, tets, RICH_D, RICH_REACTIONS, init, seed=9)
+    for k, mode in enumerate([1, 3, 3, 1, 2, 3, 1, 1, 3, 2, 1]):
+        P.rdos_set_launch_mode(g.h, mode)
+        g.step(1 + k % 3)
+        for o in os_:
+            o.run_steps(1 + k % 3)
+        assert_same(g, os_, f"run {k} (mode {mode})")
     g.close()
 
 

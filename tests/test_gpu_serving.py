@@ -125,17 +125,19 @@ def test_engine_stall_is_reported_not_hung():
     P.rdos_engine_destroy(e)
 
 
-def test_two_chains_survive_slot_changes(orc):
+@pytest.mark.parametrize("bps", [1, 0])
+def test_two_chains_survive_slot_changes(orc, bps):
     """Two chains with requests joining and leaving mid-run: the second
     chain's place in the work list moves with every change of the slot set
-    and must be read from the device header, not from the captured graph."""
+    and must be read from the device header, not from the captured graph.
+    With bps 0 every period is one fused launch per chain."""
     import paper_1512_03126_amd as P
 
     reqs = [small_request(20 + i) for i in range(10)]
     periods = [24 + 18 * (i % 4) for i in range(10)]
-    note("serving: fixed two-chain shape, staggered arrivals and departures")
+    note(f"serving: fixed two-chain shape (update blocks per segment {bps}), staggered arrivals and departures")
     e = P.rdos_engine_create(0, 0)
-    P.rdos_engine_set_shape(e, 8, 64, 1, 2)
+    P.rdos_engine_set_shape(e, 8, 64, bps, 2)
     tickets = []
     for i, (m, n) in enumerate(zip(reqs, periods)):
         s = P.Simulation(m.xyz, m.tets, m.D, m.reactions, seed=m.seed, tau_scale=None)
