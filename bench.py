@@ -349,6 +349,21 @@ def run_serving(P, args):
     return res
 
 
+def timing_pass_ids(ids, name_of, first_copy, launches, where):
+    """The dispatches of the timing pass in a profiled run of this script:
+    the last 2 x `launches` step-kernel dispatches before the bandwidth
+    probe's first copy, which must alternate scan_kernel, update_kernel (one
+    pair per period; anything else, such as a fused or two-chain shape, is
+    refused).  Returns {kernel: [ids]}."""
+    steps = [d for d in ids if d < first_copy and ("scan_kernel" in name_of(d) or "update_kernel" in name_of(d))]
+    last = steps[-2 * launches:]
+    want = ["scan_kernel", "update_kernel"] * launches
+    if len(last) != 2 * launches or any(k not in name_of(d) for k, d in zip(want, last)):
+        raise SystemExit(f"{where}: the last {2 * launches} step-kernel dispatches before the copy probe are not "
+                         f"{launches} scan/update pairs (was the launch shape fixed to a two-launch one?)")
+    return {"scan_kernel": last[0::2], "update_kernel": last[1::2]}
+
+
 def write_traffic(fetch_csv, write_csv, launches, command, out_dir=None):
     """Turns two rocprofv3 --pmc runs of this script (FETCH_SIZE, then
     WRITE_SIZE) into profiles/<kernel>_batched_traffic.json for both step
@@ -370,10 +385,13 @@ def write_traffic(fetch_csv, write_csv, launches, command, out_dir=None):
                 d = int(r["Dispatch_Id"])
                 disp[d] += float(r["Counter_Value"])
                 name[d] = r["Kernel_Name"]
+        copies = sorted(d for d in disp if "bandwidth_copy_kernel" in name[d])
+        if not copies:
+            raise SystemExit(f"no bandwidth_copy_kernel dispatch in {path}")
+        pass_ids = timing_pass_ids(sorted(disp), lambda d: name[d], copies[0], launches, path)
+
         def mean_kib(k, n):
-            ds = sorted(d for d in disp if k in name[d])[-n:]
-            if not ds:
-                raise SystemExit(f"no {k} dispatches in {path}")
+            ds = pass_ids[k] if k in pass_ids else copies[-n:]
             return sum(disp[d] for d in ds) / len(ds), len(ds)
         copy_kib, _ = mean_kib("bandwidth_copy_kernel", 5)
         scale = (1 << 30) / 1024 / copy_kib
@@ -414,19 +432,20 @@ def write_trace_summary(trace_csv, stats_csv, bench_json, launches, command, out
         for r in csv.DictReader(f):
             rows.append((int(r["Start_Timestamp"]), int(r["End_Timestamp"]), r["Kernel_Name"]))
     rows.sort()
-    copies = [s for s, _, n in rows if "bandwidth_copy_kernel" in n]
+    copies = [i for i, (_, _, n) in enumerate(rows) if "bandwidth_copy_kernel" in n]
     if not copies:
         raise SystemExit(f"no bandwidth_copy_kernel dispatch in {trace_csv}")
+    pass_ids = timing_pass_ids(list(range(len(rows))), lambda i: rows[i][2], copies[0], launches, trace_csv)
     with open(bench_json) as f:
         line = json.loads([x for x in f if x.startswith("{")][-1])
+    if line["config"].get("launch_shape", {}).get("fused"):
+        raise SystemExit(f"{bench_json}: a fused launch shape has no scan/update timing pass")
     kern = line["roofline"]["kernels"]
     out = {"workload": "batched A+B<->C: 256 x 384000-tet + 64 x 48000-tet realizations, 3 species",
            "kernel_sources": kernel_source_hash(), "command": command, "timing_pass": {},
            "launch_shape": line["config"].get("launch_shape"), "ms_per_step": line["ms_per_step"]}
     for k in ("scan_kernel", "update_kernel"):
-        ds = [(s, e, n) for s, e, n in rows if k in n and s < copies[0]][-launches:]
-        if len(ds) != launches:
-            raise SystemExit(f"{len(ds)} {k} dispatches before the copy probe, {launches} expected")
+        ds = [rows[i] for i in pass_ids[k]]
         us = [(e - s) / 1e3 for s, e, _ in ds]
         ev = kern[k]["avg_launch_ms"] * 1e3
         avg = sum(us) / len(us)
@@ -559,6 +578,10 @@ def main():
         return
 
     if args.traffic_from:
+        # The timing pass is the last run of scan/update pairs only when nothing after the warm-up tunes:
+        # the profiled runs fix a two-launch shape (under a profiler the tuner's choice can differ)
+        if not args.shape or int(args.shape.split(",")[2]) < 1:
+            raise SystemExit("--traffic-from needs the two-launch --shape the profiled runs fixed")
         # the profiler commands that wrote the two files, reconstructed from their paths
         cmd = []
         for c, csv_path in zip(("FETCH_SIZE", "WRITE_SIZE"), args.traffic_from):

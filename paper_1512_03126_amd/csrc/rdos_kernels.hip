@@ -675,22 +675,35 @@ __device__ __forceinline__ int32_t list_groups(const DevSim &sm, const Tile &til
     const gptr<const uint8_t> mrow =
         global((const uint8_t *)sm.mask[period & 1]) + (int64_t)tile.realization * S * sm.mstride + (t0 >> 2);
     const uint32_t tag = occupancy_tag(period);
-    uint32_t mb[MAXS];
-#pragma unroll
-    for (int s = 0; s < MAXS; ++s) {
-        mb[s] = 0u;
-        if (s < S && valid > 0) mb[s] = *(gptr<const uint32_t>)(mrow + (int64_t)s * sm.mstride);
-    }
     // this lane's flagged groups and the species flagged in each (all of
     // them in every group if a reaction has no reactants: every tet runs)
     uint32_t sp[kGroups];
+#pragma unroll
+    for (int k = 0; k < kGroups; ++k) sp[k] = 0u;
+    if constexpr (MAXS > 8) {
+        // one species row at a time (all rows at once take some 200 registers)
+        for (int s = 0; s < S; ++s) {
+            const uint32_t mb = valid > 0 ? *(gptr<const uint32_t>)(mrow + (int64_t)s * sm.mstride) : 0u;
+#pragma unroll
+            for (int k = 0; k < kGroups; ++k)
+                if (((mb >> (8 * k)) & 0xFFu) == tag) sp[k] |= 1u << s;
+        }
+    } else {
+        uint32_t mb[MAXS];
+#pragma unroll
+        for (int s = 0; s < MAXS; ++s) {
+            mb[s] = 0u;
+            if (s < S && valid > 0) mb[s] = *(gptr<const uint32_t>)(mrow + (int64_t)s * sm.mstride);
+        }
+#pragma unroll
+        for (int k = 0; k < kGroups; ++k)
+#pragma unroll
+            for (int s = 0; s < MAXS; ++s)
+                if (s < S && ((mb[s] >> (8 * k)) & 0xFFu) == tag) sp[k] |= 1u << s;
+    }
     uint32_t fl = 0;
 #pragma unroll
     for (int k = 0; k < kGroups; ++k) {
-        sp[k] = 0u;
-#pragma unroll
-        for (int s = 0; s < MAXS; ++s)
-            if (s < S && ((mb[s] >> (8 * k)) & 0xFFu) == tag) sp[k] |= 1u << s;
         if (sm.zeroth) sp[k] = (1u << S) - 1u;
         if (4 * k >= valid) sp[k] = 0u;
         if (sp[k] != 0u) fl |= 1u << k;
@@ -727,13 +740,25 @@ __device__ __forceinline__ int32_t list_groups(const DevSim &sm, const Tile &til
 // vectors (16 bytes per species, the others zero), which of its tets hold
 // molecules (all of them if a reaction has no reactant) and their rank over
 // the wavefront (before: tets of lower lanes; total: the chunk's).
+// Instances for more than 8 species keep no count vectors across the chunk
+// (16 of them are 64 registers): they note which were non-zero and read them
+// again, from L2, when they stage them.
 template <int MAXS>
 struct ChunkGroup {
-    v4i c[MAXS];
+    static constexpr bool kWide = MAXS > 8;
+    v4i c[kWide ? 1 : MAXS];
     int32_t gid;
+    uint32_t gsp;   // flagged species (their vectors were read)
+    uint32_t nz;    // species whose vector was non-zero
     uint32_t bits;
     int32_t before, total;
 };
+
+__device__ __forceinline__ v4i load_counts(const __amdgpu_buffer_rsrc_t &rs, int64_t Tp, int32_t tg, int s)
+{
+    return __builtin_bit_cast(v4i,
+                              __builtin_amdgcn_raw_buffer_load_b128(rs, (int32_t)((s * Tp + tg) * 4), 0, kScanLoadPolicy));
+}
 
 template <int MAXS>
 __device__ __forceinline__ void read_chunk(const DevSim &sm, const Tile &tile, const __amdgpu_buffer_rsrc_t &rs,
@@ -746,24 +771,36 @@ __device__ __forceinline__ void read_chunk(const DevSim &sm, const Tile &tile, c
     const int32_t gl = act ? glist[c0 + lane] : 0;
     g.gid = gl & 0xFF;
     const uint32_t gsp = act ? ((uint32_t)gl >> 8) : 0u;
+    g.gsp = gsp;
+    g.nz = 0u;
     const int32_t tg = tile.tet0 + 4 * g.gid;  // the group's first tet
     uint32_t bits = 0;
+    int32_t sign = 0;  // a negative count was wrapped by an overflowing atomic add
+    if constexpr (ChunkGroup<MAXS>::kWide) {
+        // the flagged species one at a time
+        for (uint32_t left = gsp; left; left &= left - 1u) {
+            const int s = __builtin_ctz(left);
+            const v4i c = load_counts(rs, Tp, tg, s);
+            const uint32_t b = (uint32_t)(c.x != 0) | ((uint32_t)(c.y != 0) << 1) | ((uint32_t)(c.z != 0) << 2) |
+                               ((uint32_t)(c.w != 0) << 3);
+            bits |= b;
+            if (b) g.nz |= 1u << s;
+            sign |= c.x | c.y | c.z | c.w;
+        }
+    } else {
 #pragma unroll
-    for (int s = 0; s < MAXS; ++s) {
-        g.c[s] = v4i{0, 0, 0, 0};
-        if ((gsp >> s) & 1u)
-            g.c[s] = __builtin_bit_cast(v4i, __builtin_amdgcn_raw_buffer_load_b128(
-                                                 rs, (int32_t)((s * Tp + tg) * 4), 0, kScanLoadPolicy));
-        bits |= (uint32_t)(g.c[s].x != 0) | ((uint32_t)(g.c[s].y != 0) << 1) | ((uint32_t)(g.c[s].z != 0) << 2) |
-                ((uint32_t)(g.c[s].w != 0) << 3);
+        for (int s = 0; s < MAXS; ++s) {
+            g.c[s] = v4i{0, 0, 0, 0};
+            if ((gsp >> s) & 1u) g.c[s] = load_counts(rs, Tp, tg, s);
+            bits |= (uint32_t)(g.c[s].x != 0) | ((uint32_t)(g.c[s].y != 0) << 1) |
+                    ((uint32_t)(g.c[s].z != 0) << 2) | ((uint32_t)(g.c[s].w != 0) << 3);
+        }
+#pragma unroll
+        for (int s = 0; s < MAXS; ++s) sign |= g.c[s].x | g.c[s].y | g.c[s].z | g.c[s].w;
     }
     if (sm.zeroth && act) bits = 0xFu;  // a reaction without reactants: every tet runs
     const int32_t in_group = tile.ntet - 4 * g.gid;
     if (in_group < 4) bits &= in_group > 0 ? (1u << in_group) - 1u : 0u;
-    // a negative count was wrapped by an overflowing atomic add
-    int32_t sign = 0;
-#pragma unroll
-    for (int s = 0; s < MAXS; ++s) sign |= g.c[s].x | g.c[s].y | g.c[s].z | g.c[s].w;
     if (sign < 0) atomicOr(sm.flags, 1);
     g.bits = bits;
     const uint32_t cnt = (uint32_t)__popc(bits);
@@ -785,9 +822,96 @@ __device__ __forceinline__ void clear_chunk(int32_t *cur, const Tile &tile, int6
 {
     const int32_t tg = tile.tet0 + 4 * g.gid;
 #pragma unroll
-    for (int s = 0; s < MAXS; ++s)
-        if ((g.c[s].x | g.c[s].y | g.c[s].z | g.c[s].w) != 0)
-            *(gptr<v4i>)(global(cur) + s * Tp + tg) = v4i{0, 0, 0, 0};
+    for (int s = 0; s < MAXS; ++s) {
+        bool nz;
+        if constexpr (ChunkGroup<MAXS>::kWide)
+            nz = (g.nz >> s) & 1u;
+        else
+            nz = (g.c[s].x | g.c[s].y | g.c[s].z | g.c[s].w) != 0;
+        if (nz) *(gptr<v4i>)(global(cur) + s * Tp + tg) = v4i{0, 0, 0, 0};
+    }
+}
+
+// Rows of a wavefront's staging area: the tet row and the species rows of
+// one pass.  Instances for more than 8 species stage four species at a time,
+// so that their LDS, and with it their occupancy, stays that of the others.
+template <int MAXS>
+constexpr int stage_rows()
+{
+    return ChunkGroup<MAXS>::kWide ? 1 + 4 : 1 + MAXS;
+}
+
+// Writes the chunk's occupied tets to the queue from `base` on, in rank
+// order: each row is staged in LDS at the tets' ranks, then stored with one
+// coalesced store per row (tet: tile index * kTetsPerTile + offset; then the
+// counts of species 0 .. S - 1).
+template <int MAXS>
+__device__ __forceinline__ void write_chunk(const __amdgpu_buffer_rsrc_t &rs, int64_t Tp, const Tile &tile, int32_t ti,
+                                            int S, const ChunkGroup<MAXS> &g, const Queue &q, const WorkHeader &h,
+                                            int64_t base, int32_t (*__restrict__ stage)[kTileGroups])
+{
+    const int lane = threadIdx.x & 63;
+    const gptr<int32_t> qtet = global(q.tet);
+    const gptr<int32_t> qcnt = global(q.counts);
+    const int32_t total = g.total;
+    if constexpr (ChunkGroup<MAXS>::kWide) {
+        const int32_t tg = tile.tet0 + 4 * g.gid;
+        int32_t k = g.before;
+#pragma unroll
+        for (int b = 0; b < 4; ++b)
+            if ((g.bits >> b) & 1u) stage[0][k++] = 4 * g.gid + b;
+        for (int s0 = 0; s0 < S; s0 += 4) {
+            // four species rows, each vector read again (from L2)
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                if (s0 + j >= S) break;
+                const int s = s0 + j;
+                const v4i c = ((g.gsp >> s) & 1u) ? load_counts(rs, Tp, tg, s) : v4i{0, 0, 0, 0};
+                k = g.before;
+#pragma unroll
+                for (int b = 0; b < 4; ++b)
+                    if ((g.bits >> b) & 1u) stage[1 + j][k++] = b == 0 ? c.x : b == 1 ? c.y : b == 2 ? c.z : c.w;
+            }
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+            for (int32_t e = lane; e < total; e += 64) {
+                if (s0 == 0) qtet[base + e] = ti * kTetsPerTile + stage[0][e];
+#pragma unroll
+                for (int j = 0; j < 4; ++j)
+                    if (s0 + j < S) qcnt[(s0 + j) * h.qcap + base + e] = stage[1 + j][e];
+            }
+            // the rows are read before the next pass writes them
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        }
+    } else {
+        int32_t k = g.before;
+#pragma unroll
+        for (int b = 0; b < 4; ++b) {
+            if (!((g.bits >> b) & 1u)) continue;
+            stage[0][k] = 4 * g.gid + b;
+#pragma unroll
+            for (int s = 0; s < MAXS; ++s) {
+                if (s >= S) break;
+                stage[1 + s][k] = b == 0 ? g.c[s].x : b == 1 ? g.c[s].y : b == 2 ? g.c[s].z : g.c[s].w;
+            }
+            ++k;
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        for (int32_t e = lane; e < total; e += 64) {
+            qtet[base + e] = ti * kTetsPerTile + stage[0][e];
+#pragma unroll
+            for (int s = 0; s < MAXS; ++s)
+                if (s < S) qcnt[s * h.qcap + base + e] = stage[1 + s][e];
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    }
 }
 
 // One period's scan by one wavefront over the tiles wave0, wave0 + n_waves,
@@ -802,8 +926,6 @@ __device__ __forceinline__ void scan_tiles(const DevSim *__restrict__ sims, cons
 {
     const int lane = threadIdx.x & 63;
     const WorkHeader h = *q.hdr;
-    const gptr<int32_t> qtet = global(q.tet);
-    const gptr<int32_t> qcnt = global(q.counts);
     // one wavefront per tile; the tile index is uniform over the wavefront
     for (int32_t ti = __builtin_amdgcn_readfirstlane(wave0); ti < h.n_tiles; ti += n_waves) {
         const Tile tile = tiles[h.tile0 + ti];
@@ -836,31 +958,7 @@ __device__ __forceinline__ void scan_tiles(const DevSim *__restrict__ sims, cons
                 if (lane == 0) atomicOr(sm.flags, 4);
                 continue;
             }
-            int32_t k = g.before;
-#pragma unroll
-            for (int b = 0; b < 4; ++b) {
-                if (!((g.bits >> b) & 1u)) continue;
-                stage[0][k] = 4 * g.gid + b;
-#pragma unroll
-                for (int s = 0; s < MAXS; ++s) {
-                    if (s >= S) break;
-                    stage[1 + s][k] = b == 0 ? g.c[s].x : b == 1 ? g.c[s].y : b == 2 ? g.c[s].z : g.c[s].w;
-                }
-                ++k;
-            }
-            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-            __builtin_amdgcn_wave_barrier();
-            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-            const int64_t base = (int64_t)seg * h.seg_cap + slot;
-            for (int32_t e = lane; e < total; e += 64) {
-                qtet[base + e] = ti * kTetsPerTile + stage[0][e];
-#pragma unroll
-                for (int s = 0; s < MAXS; ++s)
-                    if (s < S) qcnt[s * h.qcap + base + e] = stage[1 + s][e];
-            }
-            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-            __builtin_amdgcn_wave_barrier();
-            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+            write_chunk<MAXS>(rs, Tp, tile, ti, S, g, q, h, (int64_t)seg * h.seg_cap + slot, stage);
             clear_chunk<MAXS>(cur, tile, Tp, g);
         }
         // the next tile's list must not overtake this tile's reads
@@ -870,13 +968,16 @@ __device__ __forceinline__ void scan_tiles(const DevSim *__restrict__ sims, cons
     }
 }
 
+// The instances for more than 8 species get a register budget of four
+// wavefronts per SIMD; left free, the compiler spreads them over 250.
 template <int MAXS>
-__global__ __launch_bounds__(kBlock) void scan_kernel(const DevSim *__restrict__ sims,
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(MAXS > 8 ? 4 : 1))) void scan_kernel(
+    const DevSim *__restrict__ sims,
                                                       const Tile *__restrict__ tiles, int64_t iter, Queue q,
                                                       int32_t qsel)
 {
     __shared__ int32_t glist[kScanWaves][kTileGroups];
-    __shared__ int32_t stage[kScanWaves][1 + MAXS][kTileGroups];
+    __shared__ int32_t stage[kScanWaves][stage_rows<MAXS>()][kTileGroups];
     const int wv = threadIdx.x >> 6;
     scan_tiles<MAXS>(sims, tiles, iter, q, qsel, (int32_t)blockIdx.x * kScanWaves + wv,
                      (int32_t)gridDim.x * kScanWaves, glist[wv], stage[wv]);
@@ -1053,6 +1154,7 @@ __device__ __forceinline__ void fused_tiles(const DevSim *__restrict__ sims, con
                                             int32_t (*__restrict__ ring)[kRing], const LaneState &ls,
                                             unsigned long long *work)
 {
+    static_assert(KS <= kFusedSpecies, "the fused path keeps every count vector of a chunk in registers");
     int32_t head = 0, pending = 0;  // uniform over the wavefront
     for (int32_t ti = __builtin_amdgcn_readfirstlane(wave0); ti < h.n_tiles; ti += n_waves) {
         const Tile tile = tiles[h.tile0 + ti];
@@ -1209,7 +1311,7 @@ __global__ __launch_bounds__(kBlock) void persist_kernel(const DevSim *__restric
                                                          int64_t partial, double tau_last, uint32_t *sync)
 {
     __shared__ int32_t glist[kScanWaves][kTileGroups];
-    __shared__ int32_t stage[kScanWaves][1 + KS][kTileGroups];
+    __shared__ int32_t stage[kScanWaves][stage_rows<KS>()][kTileGroups];
     __shared__ double occ[KS * kBlock];
     __shared__ double last[KS * kBlock];
     __shared__ int32_t counts[KS * kBlock];
