@@ -300,10 +300,14 @@ rdos_status rdos_engine_release(rdos_engine *e, uint64_t ticket, rdos_sim **sim)
  * device was busy. */
 rdos_status rdos_engine_stats(rdos_engine *e, int64_t *launches, double *updates, double *busy_s);
 
-/* Per-kernel timing: when on, chunks are launched directly (not replayed
- * from the graph) with HIP events between every scan and update launch;
- * rdos_engine_kernel_times returns the summed milliseconds and launch counts
- * since profiling was switched on.  Results do not change. */
+/* Per-kernel timing.  on = 1 or 2: chunks are launched directly (not
+ * replayed from the graph) with HIP events between every scan and update
+ * launch; rdos_engine_kernel_times returns the summed milliseconds and launch
+ * counts since profiling was last switched.  With on = 1 the update kernel
+ * also tallies its work (rdos_engine_work_counts, cleared here); the tally
+ * adds about 8% to the update's time, so on = 2 times the kernel as graph
+ * replays run it and leaves the last tallies readable.  0 switches it off.
+ * Results do not change.  RDOS_EINVAL for other values. */
 rdos_status rdos_engine_set_profiling(rdos_engine *e, int on);
 rdos_status rdos_engine_kernel_times(rdos_engine *e, double *scan_ms, int64_t *scan_launches,
                                      double *update_ms, int64_t *update_launches);

@@ -355,8 +355,10 @@ def rdos_engine_set_shape(engine, chunk: int, scan_grid: int = 0, update_bps: in
            True)
 
 
-def rdos_engine_set_profiling(engine, on: bool):
-    _check(lib().rdos_engine_set_profiling(engine, 1 if on else 0), engine, True)
+def rdos_engine_set_profiling(engine, on: bool, tally: bool = True):
+    """on: time every launch with events (direct launches); tally: the update
+    kernel also counts its work (slower by about 8%)."""
+    _check(lib().rdos_engine_set_profiling(engine, (1 if tally else 2) if on else 0), engine, True)
 
 
 def rdos_engine_kernel_times(engine):

@@ -150,7 +150,7 @@ struct rdos_engine {
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
 
     // per-kernel timing: chunks launched directly with events between launches
-    bool profiling = false;
+    int profiling = 0;             // 0 off; 1 timed launches with work tallies; 2 timed launches only
     std::vector<hipEvent_t> kev;
     double scan_ms = 0.0, update_ms = 0.0;
     int64_t scan_n = 0, update_n = 0;
@@ -557,7 +557,7 @@ void worker_main(rdos_engine *e)
         // the tuner tries each candidate per size bucket, then keeps the best
         const bool tuning = !e->fixed_shape && e->trial < 2 * e->candidates.size();
         Shape sh = tuning ? e->candidates[e->trial / 2] : e->best;
-        const bool timed = e->profiling;
+        const bool timed = e->profiling != 0;
         if (timed || e->n_tiles0 == 0 || e->n_tiles0 == e->n_tiles) sh.chains = 1;  // nothing to split
         if (sh.update_bps == 0 && e->queue.species > kFusedSpecies) sh.update_bps = 1;  // too wide to fuse
         // fused periods leave the queue's length halves alone: any phase suits them
@@ -606,7 +606,7 @@ void worker_main(rdos_engine *e)
             len = (int32_t)std::max<int64_t>(1, std::min<int64_t>({left_min, cap, kPersistPeriods}));
         }
         // the timing pass launches directly and tallies its work; captured graphs never do
-        e->queue.work = e->queue2.work = timed ? e->d_work : nullptr;
+        e->queue.work = e->queue2.work = e->profiling == 1 ? e->d_work : nullptr;
         if (timed) {
             bool ok = true;
             while (ok && (int32_t)e->kev.size() < 2 * len + 1) {
@@ -927,8 +927,9 @@ rdos_status rdos_engine_set_shape(rdos_engine *e, int32_t chunk, int32_t scan_gr
 rdos_status rdos_engine_set_profiling(rdos_engine *e, int on)
 {
     if (!e) return RDOS_EINVAL;
+    if (on < 0 || on > 2) return efail(e, RDOS_EINVAL, "profiling mode must be 0, 1 or 2");
     std::lock_guard<std::mutex> g(e->mu);
-    if (on && !e->d_work) {
+    if (on == 1 && !e->d_work) {
         hipError_t err;
         {
             std::lock_guard<std::mutex> dg(device_api_mutex());
@@ -936,11 +937,11 @@ rdos_status rdos_engine_set_profiling(rdos_engine *e, int on)
         }
         if (err != hipSuccess) return efail(e, RDOS_ENOMEM, "work counters: %s", hipGetErrorString(err));
     }
-    if (on) {
+    if (on == 1) {
         ENGINE_HIP(e, hipMemsetAsync(e->d_work, 0, 3 * sizeof(unsigned long long), e->stream), "clear work counters");
         ENGINE_HIP(e, hipStreamSynchronize(e->stream), "clear work counters");
     }
-    e->profiling = on != 0;
+    e->profiling = on;
     e->scan_ms = e->update_ms = 0.0;
     e->scan_n = e->update_n = 0;
     return RDOS_OK;

@@ -49,13 +49,22 @@ def _csv(path, counter, rows):
             w.writerow({"Dispatch_Id": d, "Kernel_Name": name, "Counter_Name": counter, "Counter_Value": v})
 
 
+def _pairs(scan, update, n):
+    out = []
+    for i in range(n):
+        out += [("scan_kernel<3>(...)", scan(i)), ("update_kernel<false, 4>(...)", update(i))]
+    return out
+
+
 def test_write_traffic_scales_by_the_copy_kernel(tmp_path):
-    # the copy kernel moves 1 GiB each way; its counters read half (fetch) and all (write) of it
+    # the copy kernel moves 1 GiB each way; its counters read half (fetch) and all (write) of it.
+    # Earlier dispatches (tuning, replays) come first; the timing pass is the last 16 scan/update
+    # pairs before the copies.
     gib_kib = (1 << 30) / 1024
-    fetch = [("scan_kernel<3>(...)", 999.0)] * 3 + [("scan_kernel<3>(...)", 100.0 + i) for i in range(16)]
-    fetch += [("update_kernel<false, 4>(...)", 50.0)] * 16 + [("bandwidth_copy_kernel(...)", gib_kib / 2)] * 5
-    write = [("scan_kernel<3>(...)", 40.0)] * 19 + [("update_kernel<false, 4>(...)", 20.0 + i) for i in range(16)]
-    write += [("bandwidth_copy_kernel(...)", gib_kib)] * 5
+    fetch = [("update_kernel<false, 4>(...)", 999.0)] * 3 + _pairs(lambda i: 999.0, lambda i: 999.0, 4)
+    fetch += _pairs(lambda i: 100.0 + i, lambda i: 50.0, 16) + [("bandwidth_copy_kernel(...)", gib_kib / 2)] * 5
+    write = [("update_kernel<false, 4>(...)", 999.0)] * 3 + _pairs(lambda i: 999.0, lambda i: 999.0, 4)
+    write += _pairs(lambda i: 40.0, lambda i: 20.0 + i, 16) + [("bandwidth_copy_kernel(...)", gib_kib)] * 5
     _csv(tmp_path / "f.csv", "FETCH_SIZE", fetch)
     _csv(tmp_path / "w.csv", "WRITE_SIZE", write)
     bench.write_traffic(str(tmp_path / "f.csv"), str(tmp_path / "w.csv"), 16, ["cmd"], out_dir=str(tmp_path))
@@ -69,6 +78,22 @@ def test_write_traffic_scales_by_the_copy_kernel(tmp_path):
     assert upd["write_bytes_per_launch"] == round(27.5 * 1024)
     assert scan["kernel_sources"] == bench.kernel_source_hash() and scan["launches_averaged"] == 16
     assert not (tmp_path / "fused_kernel_batched_traffic.json").exists()
+
+
+def test_write_traffic_refuses_a_run_without_the_timing_pass(tmp_path):
+    # the last step dispatches before the copies are not scan/update pairs (e.g. a fused shape's
+    # timing pass, whose kernel the counter run does not collect, after two-chain replays that end
+    # on two updates): refused, no file written
+    gib_kib = (1 << 30) / 1024
+    rows = _pairs(lambda i: 100.0, lambda i: 50.0, 16) + [("update_kernel<false, 4>(...)", 50.0)]
+    rows += [("bandwidth_copy_kernel(...)", gib_kib)] * 5
+    _csv(tmp_path / "f.csv", "FETCH_SIZE", rows)
+    _csv(tmp_path / "w.csv", "WRITE_SIZE", rows)
+    import pytest
+
+    with pytest.raises(SystemExit, match="scan/update pairs"):
+        bench.write_traffic(str(tmp_path / "f.csv"), str(tmp_path / "w.csv"), 16, ["cmd"], out_dir=str(tmp_path))
+    assert not (tmp_path / "update_kernel_batched_traffic.json").exists()
 
 
 def test_source_hash_ignores_comments_and_layout(tmp_path, monkeypatch):

@@ -189,8 +189,21 @@ def test_timing_pass_counts_work(orc):
     P.rdos_engine_release(e, t)
     kt = P.rdos_engine_kernel_times(e)
     work = P.rdos_engine_work_counts(e)
-    P.rdos_engine_destroy(e)
     got = s.get_counts()
+    # timed without the tally: launches counted, the last tallies kept, results unchanged
+    P.rdos_engine_set_profiling(e, True, tally=False)
+    t = P.rdos_engine_submit(e, s.h, 6, 1.0)
+    P.rdos_engine_drain(e)
+    P.rdos_engine_release(e, t)
+    kt2 = P.rdos_engine_kernel_times(e)
+    assert kt2["update_launches"] == kt2["scan_launches"] == 6 and kt2["update_ms"] > 0
+    assert P.rdos_engine_work_counts(e) == work
+    o2 = orc.OracleSim(m.xyz, m.tets, m.D, m.reactions, seed=m.seed)
+    for q in range(m.n_species):
+        o2.set_counts(q, m.init[0, q])
+    o2.run_steps(n + 6)
+    np.testing.assert_array_equal(o2.get_counts(), s.get_counts())
+    P.rdos_engine_destroy(e)
     s.close()
     np.testing.assert_array_equal(o.get_counts(), got)
     # a run's last periods, fewer than a chunk, are launched directly, as many
