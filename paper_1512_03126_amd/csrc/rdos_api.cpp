@@ -705,6 +705,7 @@ rdos_status rdos_finalize(rdos_sim *s, double tau_scale, double *out_tau)
     SETUP_TRY(dev_alloc((void **)&s->d_flags, 64, s->stream), "allocate flags");
     SETUP_TRY(dev_alloc((void **)&s->d_desc, sizeof(DevSim), s->stream), "allocate descriptor");
     SETUP_TRY(alloc_queue(&s->queue, tiles_of(s), S, s->stream), "allocate queue");
+    s->queue.owned = tiles_of(s) <= kMaxSegments ? 1 : 0;  // a segment and a scan wavefront per tile
     SETUP_TRY(dev_alloc((void **)&d_xyz, s->xyz.size() * sizeof(double), s->stream), "allocate set-up");
     SETUP_TRY(dev_alloc((void **)&d_tv, s->tet_verts.size() * sizeof(int32_t), s->stream), "allocate set-up");
     SETUP_TRY(dev_alloc((void **)&d_nbr, nbr.size() * sizeof(int32_t), s->stream), "allocate set-up");

@@ -96,8 +96,12 @@ struct rdos_engine {
     std::condition_variable cv_admit;  // wakes the admission thread
     std::condition_variable cv_done;   // wakes drain()
     std::thread worker;
-    std::thread admitter;  // finalizes admitted simulations while the worker keeps launching
-    int admitting = 0;     // tickets being finalized right now
+    // admission threads: they finalize admitted simulations while the worker keeps launching, two so
+    // that a small request need not wait while a large one is set up
+    static constexpr int kAdmitters = 2;
+    std::thread admitters[kAdmitters];
+    int admitting = 0;            // tickets being finalized right now
+    int64_t admitting_tiled = 0;  // their tiled tets
     bool stop = false;
     bool worker_dead = false;  // the worker left its loop after a device error
     bool stalled = false;      // nothing runs and the next request does not fit the budget
@@ -401,10 +405,10 @@ int64_t tiled_tets(const rdos_sim *q)
     return (int64_t)q->Rz * ((q->T + kTetsPerTile - 1) / kTetsPerTile) * kTetsPerTile;
 }
 
-// Admission thread: takes waiting tickets in FIFO order while their device
-// memory fits the budget, finalizes those that are not finalized yet (with
-// the lock released, on the simulation's own stream) and hands them to the
-// worker, which adds them to the work list at its next chunk.
+// Admission threads: each takes the first waiting ticket while its device
+// memory fits the budget, finalizes it if it is not finalized yet (with the
+// lock released, on the simulation's own stream) and hands it to the
+// worker, which adds it to the work list at its next chunk.
 void admitter_main(rdos_engine *e)
 {
     (void)hipSetDevice(e->device);
@@ -415,16 +419,18 @@ void admitter_main(rdos_engine *e)
             const uint64_t id = e->waiting.front();
             Ticket &tk = e->tickets[id];
             // queue entries are int32 (tile * kTetsPerTile + offset): keep the work list below 2^31 tets
-            int64_t tiled = tiled_tets(tk.sim);
+            const int64_t own_tiled = tiled_tets(tk.sim);
+            int64_t tiled = own_tiled + e->admitting_tiled;
             for (uint64_t sid : e->slots) tiled += tiled_tets(e->tickets[sid].sim);
             for (uint64_t sid : e->ready) tiled += tiled_tets(e->tickets[sid].sim);
             const bool fits = e->used + tk.bytes <= e->budget &&
-                              (tiled <= 0x7fffffff || (e->slots.empty() && e->ready.empty()));
+                              (tiled <= 0x7fffffff || (e->slots.empty() && e->ready.empty() && e->admitting == 0));
             if (fits) {
                 tk.admit_start = Clock::now();
                 e->waiting.pop_front();
                 e->used += tk.bytes;
                 ++e->admitting;
+                e->admitting_tiled += own_tiled;
                 rdos_sim *s = tk.sim;
                 const double tau_scale = tk.tau_scale;
                 rdos_status st = RDOS_OK;
@@ -441,6 +447,7 @@ void admitter_main(rdos_engine *e)
                 if (st != RDOS_OK) err = s->error;
                 lk.lock();
                 --e->admitting;
+                e->admitting_tiled -= own_tiled;
                 Ticket &t2 = e->tickets[id];
                 t2.admit_end = Clock::now();
                 if (st == RDOS_OK) {
@@ -517,6 +524,9 @@ void worker_main(rdos_engine *e)
             const std::pair<int, int> b{lg, species_bound(e->max_species)};
             // launch grids cover every work list of this size bucket
             e->grid_tiles = (int32_t)std::min<int64_t>(int64_t(1) << (lg + 1), int64_t(1) << 30);
+            // every work list of a bucket this small has a segment per tile, and the scan grids
+            // give each tile a wavefront (the graphs of the bucket keep this scan instance)
+            e->queue.owned = e->queue2.owned = e->grid_tiles <= kMaxSegments ? 1 : 0;
             if (b != e->bucket && !e->fixed_shape && e->grid_tiles <= kSmallWorkTiles) {
                 // small work lists: every candidate clamps to about the same
                 // grids and launch latency dominates; no tuning, long chunks
@@ -761,7 +771,7 @@ rdos_status rdos_engine_create(rdos_engine **out, int device, size_t hbm_budget_
     // and under a profiler, which taxes each launch, it scored first; it stays available by set_shape.
     e->candidates = {{16, 2048, 2, 1}, {16, 8192, 2, 1}, {16, 1024, 2, 2}, {16, 2048, 2, 2}, {16, 4096, 1, 2}};
     e->worker = std::thread(worker_main, e);
-    e->admitter = std::thread(admitter_main, e);
+    for (std::thread &t : e->admitters) t = std::thread(admitter_main, e);
     *out = e;
     return RDOS_OK;
 }
@@ -1075,7 +1085,8 @@ void rdos_engine_destroy(rdos_engine *e)
     e->cv_work.notify_all();
     e->cv_admit.notify_all();
     if (e->worker.joinable()) e->worker.join();
-    if (e->admitter.joinable()) e->admitter.join();
+    for (std::thread &t : e->admitters)
+        if (t.joinable()) t.join();
     (void)hipSetDevice(e->device);
     (void)hipStreamSynchronize(e->stream);
     for (auto &kv : e->tickets) {  // simulations never released are destroyed with the engine

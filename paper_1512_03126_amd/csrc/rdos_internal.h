@@ -147,6 +147,9 @@ struct QueueView {
     uint32_t *sync;     // [kPersistSyncWords] grid-barrier counters and failure word of the one-launch path
     unsigned long long *work;  // null, or [3] device totals the update kernel adds to: tets, count additions,
                                // additions that are transfers across a face
+    int32_t owned;      // the work lists launched on it have a segment per tile and a scan wavefront per
+                        // tile (at most kMaxSegments tiles): the scan instance that fills segments by its
+                        // own count (checked again on the device)
 };
 constexpr int kMaxSegments = 1024;
 constexpr int kPersistSyncWords = 64 * 32 + 32;  // 64 barrier counters on lines of their own, the failure word

@@ -91,6 +91,7 @@ extern "C" rdos_status rdos_step_static(rdos_sim *s, int64_t n_steps)
     q.species = rows;
     q.scaled = s->queue.scaled;
     q.work = nullptr;
+    q.owned = s->n_tiles <= kMaxSegments ? 1 : 0;
     WorkHeader h{};
     h.n_tiles = s->n_tiles;
     h.n_sims = 1;
