@@ -674,6 +674,11 @@ def main():
         tuning_periods = settle_engine(P, e, sims)
         shape = P.rdos_engine_launch_shape(e)
         log(f"launch shape ({shape['source']}) after {tuning_periods} untimed tuning periods: {shape}")
+        tuner = [[c["chunk"], c["scan_grid"], c["update_blocks_per_segment"], c["chains"], round(c["ms_first"], 4),
+                  round(c["ms_second"], 4)] for c in P.rdos_engine_tuner_scores(e)]
+        if shape["source"] == "tuned":
+            log("tuner (chunk, scan grid, update blocks per segment, chains, ms per period in pass 1 and 2): "
+                + "; ".join(" ".join(str(v) for v in c) for c in tuner))
         st0 = P.rdos_engine_stats(e)
         t0 = time.perf_counter()
         run_engine(P, e, sims, K)
@@ -749,6 +754,8 @@ def main():
                   "realizations_per_s": round(320.0 / (ms_step * 1e-3 * 338), 3),
                   "engine_launches_timed": st1["launches"] - st0["launches"], "launch_shape": shape,
                   "launch_shape_source": shape["source"], "tuning_periods_untimed": tuning_periods}
+        if shape["source"] == "tuned":
+            config["tuner_ms_per_period"] = tuner  # [chunk, scan grid, update blocks/segment, chains, pass 1, 2]
         if plain:
             config["plain_updates_per_s"] = round(plain["value"], 1)
             config["plain_ms_per_step"] = round(plain["ms_per_step"], 4)

@@ -346,6 +346,19 @@ enum {
 rdos_status rdos_engine_launch_shape(rdos_engine *e, int32_t *chunk, int32_t *scan_grid,
                                      int32_t *update_bps, int32_t *chains, int32_t *source);
 
+/* What the tuner measured for the work list's current size bucket.  Per
+ * work-list size bucket it runs each candidate shape for two chunks of
+ * graph replays and scores the second (the first replays a freshly captured
+ * graph), then scores each once more in a second pass, and keeps the lowest
+ * mean time per period.  Writes the number of candidates to *n and, for the
+ * first min(cap, *n) of them in the order tried: shapes[4 c .. 4 c + 3] =
+ * chunk, scan_grid, update_bps, chains, and the device time per period (ms)
+ * of the scored chunk of each pass to ms_first[c] and ms_second[c] (0 where
+ * not measured: a bucket not tuned, taken from the cache, or still being
+ * tuned).  Any pointer may be NULL.  RDOS_EINVAL for a NULL engine or cap < 0. */
+rdos_status rdos_engine_tuner_scores(rdos_engine *e, int32_t cap, int32_t *n, int32_t *shapes, double *ms_first,
+                                     double *ms_second);
+
 /* Fixes the launch shape instead of tuning it: chunk (even, 2..1024)
  * periods per graph, scan_grid (1..2^20) blocks, update_bps (1..64) update
  * blocks per queue segment or 0 for one fused launch per period (scan_grid

@@ -72,6 +72,8 @@ _SIGS = [
     ("rdos_engine_stats", C.c_int, [C.c_void_p, _P(C.c_int64), _P(C.c_double), _P(C.c_double)]),
     ("rdos_engine_launch_shape", C.c_int, [C.c_void_p, _P(C.c_int32), _P(C.c_int32), _P(C.c_int32),
                                            _P(C.c_int32), _P(C.c_int32)]),
+    ("rdos_engine_tuner_scores", C.c_int, [C.c_void_p, C.c_int32, _P(C.c_int32), _P(C.c_int32), _P(C.c_double),
+                                           _P(C.c_double)]),
     ("rdos_engine_set_shape", C.c_int, [C.c_void_p, C.c_int32, C.c_int32, C.c_int32, C.c_int32]),
     ("rdos_engine_set_profiling", C.c_int, [C.c_void_p, C.c_int]),
     ("rdos_engine_work_counts", C.c_int, [C.c_void_p, _P(C.c_int64), _P(C.c_int64), _P(C.c_int64)]),
@@ -346,6 +348,20 @@ def rdos_engine_launch_shape(engine):
            engine, True)
     return dict(chunk=a.value, scan_grid=b.value, update_blocks_per_segment=c.value, chains=d.value,
                 fused=c.value == 0, source=SHAPE_SOURCES.get(src.value, src.value))
+
+
+def rdos_engine_tuner_scores(engine):
+    """The tuner's measurements for the current size bucket: one dict per
+    candidate shape, in the order tried, with the device ms per period of its
+    scored chunk in each of the two passes (0.0 where not measured)."""
+    n = C.c_int32()
+    _check(lib().rdos_engine_tuner_scores(engine, 0, C.byref(n), None, None, None), engine, True)
+    m = n.value
+    shapes = (C.c_int32 * (4 * max(m, 1)))()
+    first, second = (C.c_double * max(m, 1))(), (C.c_double * max(m, 1))()
+    _check(lib().rdos_engine_tuner_scores(engine, m, C.byref(n), shapes, first, second), engine, True)
+    return [dict(chunk=shapes[4 * c], scan_grid=shapes[4 * c + 1], update_blocks_per_segment=shapes[4 * c + 2],
+                 chains=shapes[4 * c + 3], ms_first=first[c], ms_second=second[c]) for c in range(m)]
 
 
 def rdos_engine_set_shape(engine, chunk: int, scan_grid: int = 0, update_bps: int = 0, chains: int = 0):

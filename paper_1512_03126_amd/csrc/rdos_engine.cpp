@@ -141,14 +141,16 @@ struct rdos_engine {
     bool graph_stale = true;  // a buffer the graphs name was reallocated
     bool rebuild = true;      // the slot set changed
 
-    // tuner: each candidate runs two chunks per work-list size bucket (the
-    // first replays a freshly captured graph and is not scored), best kept
+    // tuner, per work-list size bucket: a first pass runs each candidate for
+    // two chunks (the first replays a freshly captured graph and is not
+    // scored), a second pass scores each once more; the lowest mean time per
+    // period wins
     std::vector<Shape> candidates;
     bool fixed_shape = false;  // set_shape: no tuning, always `best`
     std::map<std::pair<int, int>, Shape> tuned;
     std::pair<int, int> bucket{-1, -1};
-    size_t trial = 0;  // chunks of tuning done in this bucket: candidate trial / 2
-    double best_rate = -1.0;
+    size_t trial = 0;  // chunks of tuning done in this bucket (tune_candidate maps them to candidates)
+    std::vector<double> trial_ms[2];  // ms per period of each candidate's scored chunk, by pass
     Shape best{16, 2048, 2, 1};
     int32_t shape_source = RDOS_SHAPE_DEFAULT;  // where `best` comes from
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
@@ -207,6 +209,15 @@ rdos_status ensure(rdos_engine *e, T **buf, int64_t *cap, int64_t need, const ch
 
 // Species rows of the queue, which also size the scan's register arrays.
 int species_bound(int s) { return s <= 2 ? 2 : (s == 3 ? 3 : (s <= 4 ? 4 : (s <= 6 ? 6 : (s <= 8 ? 8 : kMaxSpecies)))); }
+
+// Chunks of tuning per size bucket: two per candidate, then one more each.
+size_t tune_end(const rdos_engine *e) { return 3 * e->candidates.size(); }
+// The candidate that tuning chunk `trial` runs.
+size_t tune_candidate(const rdos_engine *e)
+{
+    const size_t m = e->candidates.size();
+    return e->trial < 2 * m ? e->trial / 2 : e->trial - 2 * m;
+}
 
 // Rewrites the device work list for the current slots (lock held).
 rdos_status build_work(rdos_engine *e)
@@ -533,7 +544,7 @@ void worker_main(rdos_engine *e)
                 e->bucket = b;
                 e->best = kSmallWorkShape;
                 e->shape_source = RDOS_SHAPE_SMALL_WORK;
-                e->trial = 2 * e->candidates.size();
+                e->trial = tune_end(e);
             } else if (b != e->bucket) {
                 e->bucket = b;
                 auto hit = e->tuned.find(b);
@@ -556,17 +567,17 @@ void worker_main(rdos_engine *e)
                         e->best = cached;
                         e->shape_source = RDOS_SHAPE_CACHED;
                     }
-                    e->trial = 2 * e->candidates.size();
+                    e->trial = tune_end(e);
                 } else {
                     e->trial = 0;
-                    e->best_rate = -1.0;
+                    for (auto &v : e->trial_ms) v.assign(e->candidates.size(), 0.0);
                     if (!e->fixed_shape) e->shape_source = RDOS_SHAPE_DEFAULT;
                 }
             }
         }
         // the tuner tries each candidate per size bucket, then keeps the best
-        const bool tuning = !e->fixed_shape && e->trial < 2 * e->candidates.size();
-        Shape sh = tuning ? e->candidates[e->trial / 2] : e->best;
+        const bool tuning = !e->fixed_shape && e->trial < tune_end(e);
+        Shape sh = tuning ? e->candidates[tune_candidate(e)] : e->best;
         const bool timed = e->profiling != 0;
         if (timed || e->n_tiles0 == 0 || e->n_tiles0 == e->n_tiles) sh.chains = 1;  // nothing to split
         if (sh.update_bps == 0 && e->queue.species > kFusedSpecies) sh.update_bps = 1;  // too wide to fuse
@@ -638,7 +649,10 @@ void worker_main(rdos_engine *e)
         // When no slot ends within them and no request waits to join, up to
         // 8 chunks (about 2 ms of device time) are replayed back to back, so
         // the host's turn between chunks does not leave the device idle.
-        int32_t reps = 1;
+        // When those replays take every slot to within a chunk of its end and
+        // all slots end together, the remaining periods are launched directly
+        // behind them, so the run ends without another turn of the host.
+        int32_t reps = 1, tail = 0;
         if (replay && !tuning && e->ready.empty() && e->waiting.empty() && e->admitting == 0) {
             int64_t left_min = left_max;
             for (uint64_t id : e->slots) {
@@ -648,8 +662,10 @@ void worker_main(rdos_engine *e)
             int64_t r = left_min / sh.chunk;
             if (e->last_chunk_ms > 0.0) r = std::min<int64_t>(r, (int64_t)(2.0 / e->last_chunk_ms));
             reps = (int32_t)std::max<int64_t>(1, std::min<int64_t>(r, 8));
+            if (left_min == left_max && (int64_t)reps * sh.chunk + sh.chunk > left_max)
+                tail = (int32_t)(left_max - (int64_t)reps * sh.chunk);
         }
-        len *= reps;
+        len = len * reps + tail;
         double work = 0.0;
         for (uint64_t id : e->slots) {
             Ticket &tk = e->tickets[id];
@@ -666,6 +682,8 @@ void worker_main(rdos_engine *e)
                 if (err == hipSuccess) err = launch_advance(e->d_sims, e->queue.hdr, len, e->stream);
             } else if (replay) {
                 for (int32_t k = 0; k < reps && err == hipSuccess; ++k) err = hipGraphLaunch(gx, e->stream);
+                if (err == hipSuccess && tail > 0)
+                    err = enqueue_periods(e, sh, tail, (phase + reps * sh.chunk) & 1, false);
             } else {
                 err = enqueue_periods(e, sh, len, phase, timed);
             }
@@ -693,16 +711,21 @@ void worker_main(rdos_engine *e)
                 }
             }
         }
-        const double rate = ms > 0.f ? work / (double)ms : 0.0;
-        if (replay) e->last_chunk_ms = (double)ms / reps;
+        if (replay && tail == 0) e->last_chunk_ms = (double)ms / reps;
         if (persist > 0) e->last_period_ms = (double)ms / len;
         if (tuning && replay) {  // only full graph-replayed chunks are scored
-            if ((e->trial & 1) && rate > e->best_rate) {  // the candidate's second chunk
-                e->best_rate = rate;
-                e->best = sh;
-            }
+            const size_t m = e->candidates.size();
+            if (e->trial >= 2 * m || (e->trial & 1)) e->trial_ms[e->trial >= 2 * m][tune_candidate(e)] = ms / len;
             ++e->trial;
-            if (e->trial == 2 * e->candidates.size()) {
+            if (e->trial == tune_end(e)) {
+                double best_ms = 0.0;
+                for (size_t c = 0; c < m; ++c) {
+                    const double t = 0.5 * (e->trial_ms[0][c] + e->trial_ms[1][c]);
+                    if (c == 0 || t < best_ms) {
+                        best_ms = t;
+                        e->best = e->candidates[c];
+                    }
+                }
                 e->tuned[e->bucket] = e->best;
                 e->shape_source = RDOS_SHAPE_TUNED;
                 TuneCache &tc = tune_cache();
@@ -769,7 +792,8 @@ rdos_status rdos_engine_create(rdos_engine **out, int device, size_t hbm_budget_
     }
     // Two-launch shapes only: the fused shape (update_bps 0) lost to them on every tuned size measured,
     // and under a profiler, which taxes each launch, it scored first; it stays available by set_shape.
-    e->candidates = {{16, 2048, 2, 1}, {16, 8192, 2, 1}, {16, 1024, 2, 2}, {16, 2048, 2, 2}, {16, 4096, 1, 2}};
+    // One 32-period shape: fewer graph launches per period, at the cost of a longer wait to join.
+    e->candidates = {{16, 2048, 2, 1}, {16, 1024, 2, 2}, {16, 2048, 2, 2}, {16, 4096, 1, 2}, {32, 4096, 1, 2}};
     e->worker = std::thread(worker_main, e);
     for (std::thread &t : e->admitters) t = std::thread(admitter_main, e);
     *out = e;
@@ -909,6 +933,28 @@ rdos_status rdos_engine_launch_shape(rdos_engine *e, int32_t *chunk, int32_t *sc
     if (update_bps) *update_bps = e->best.update_bps;
     if (chains) *chains = e->best.chains;
     if (source) *source = e->shape_source;
+    return RDOS_OK;
+}
+
+rdos_status rdos_engine_tuner_scores(rdos_engine *e, int32_t cap, int32_t *n, int32_t *shapes, double *ms_first,
+                                     double *ms_second)
+{
+    if (!e || cap < 0) return RDOS_EINVAL;
+    std::lock_guard<std::mutex> g(e->mu);
+    const int32_t m = (int32_t)e->candidates.size();
+    if (n) *n = m;
+    for (int32_t c = 0; c < std::min(cap, m); ++c) {
+        const Shape &sh = e->candidates[c];
+        if (shapes) {
+            shapes[4 * c] = sh.chunk;
+            shapes[4 * c + 1] = sh.scan_grid;
+            shapes[4 * c + 2] = sh.update_bps;
+            shapes[4 * c + 3] = sh.chains;
+        }
+        const bool have = e->trial_ms[0].size() == (size_t)m;
+        if (ms_first) ms_first[c] = have ? e->trial_ms[0][c] : 0.0;
+        if (ms_second) ms_second[c] = have ? e->trial_ms[1][c] : 0.0;
+    }
     return RDOS_OK;
 }
 

@@ -292,3 +292,49 @@ def test_serving_size_request_in_a_mix(orc):
         want = run_oracle(orc, m, n)
         assert np.array_equal(want, got), (k, m.n_tets, m.n_species, int((want != got).sum()))
     assert int(mixed[0].sum()) > 0
+
+
+def test_tuner_scores_and_shape_independence(orc):
+    """A work list large enough to be tuned (48 realizations x 48,000 tets,
+    2256 tiles): every candidate shape is scored in both passes, the kept
+    shape has the lowest mean time per period, and the counts equal a run
+    with a fixed shape and, for one realization, the oracle."""
+    import paper_1512_03126_amd as P
+
+    m = W.abc_lattice(n=20, a=0.1e-6, seed=3, n_realizations=48)
+    n = 320
+    note(f"tuner: {m.n_realizations} x {m.n_tets} tets, {n} periods, tuned against a fixed shape")
+    out = []
+    for fixed in (None, (16, 1024, 1, 1)):
+        e = P.rdos_engine_create(0, 0)
+        if fixed:
+            P.rdos_engine_set_shape(e, *fixed)
+        s = P.Simulation(m.xyz, m.tets, m.D, m.reactions, seed=m.seed, n_realizations=m.n_realizations)
+        for r in range(m.n_realizations):
+            for q in range(m.n_species):
+                s.set_counts(q, m.init[r, q], realization=r)
+        t = P.rdos_engine_submit(e, s.h, n, 1.0)
+        P.rdos_engine_drain(e)
+        P.rdos_engine_release(e, t)
+        shape = P.rdos_engine_launch_shape(e)
+        scores = P.rdos_engine_tuner_scores(e)
+        P.rdos_engine_destroy(e)
+        out.append([s.get_counts(None, realization=r) for r in range(m.n_realizations)])
+        s.close()
+        if fixed:
+            assert shape["source"] == "fixed"
+            continue
+        assert shape["source"] == "tuned", shape
+        assert len(scores) >= 2
+        assert all(c["ms_first"] > 0 and c["ms_second"] > 0 for c in scores), scores
+        mean = [0.5 * (c["ms_first"] + c["ms_second"]) for c in scores]
+        best = scores[int(np.argmin(mean))]
+        assert (best["scan_grid"], best["update_blocks_per_segment"], best["chains"]) == \
+            (shape["scan_grid"], shape["update_blocks_per_segment"], shape["chains"]), (shape, scores)
+    for r in range(m.n_realizations):
+        np.testing.assert_array_equal(out[0][r], out[1][r])
+    o = orc.OracleSim(m.xyz, m.tets, m.D, m.reactions, seed=m.seed, realization=7)
+    for q in range(m.n_species):
+        o.set_counts(q, m.init[7, q])
+    o.run_steps(n)
+    np.testing.assert_array_equal(o.get_counts(), out[0][7])
