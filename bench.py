@@ -744,6 +744,19 @@ def main():
             roof["copy_probe_GBps"] = round(P.rdos_bandwidth_probe(0, 1 << 30, 20), 1)
         except Exception as ex:  # informational only
             log(f"bandwidth probe failed: {ex}")
+        # The update's count additions are random atomics into the next count
+        # buffer: their rate against the device's rate for random atomics
+        # alone (the same number per launch, into a buffer of the same size)
+        try:
+            n_add = int(up["additions_per_launch"])
+            probe = P.rdos_atomic_probe(0, 4 * upd_per_period, max(n_add, 1), 10)
+            up["additions_per_s"] = round(n_add / (upd_ms * 1e-3), 1)
+            up["atomic_probe_per_s"] = round(probe, 1)
+            up["additions_frac_of_atomic_probe"] = round(up["additions_per_s"] / probe, 4)
+            log(f"update_kernel: {up['additions_per_s']:.3e} additions/s; random atomics alone "
+                f"{probe:.3e}/s ({up['additions_frac_of_atomic_probe']:.2f})")
+        except Exception as ex:  # informational only
+            log(f"atomic probe failed: {ex}")
         P.rdos_engine_destroy(e)
         for x in sims:
             x.close()

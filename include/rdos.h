@@ -386,6 +386,15 @@ rdos_status rdos_tune_split_threshold(int device, int32_t n_max, int32_t *thresh
  * times.  The same kernel calibrates hardware byte counters. */
 rdos_status rdos_bandwidth_probe(int device, size_t bytes, int reps, double *gbps);
 
+/* Measures the device's rate of random integer atomics (additions per
+ * second): 262,144 lanes each add 1 at ceil(n_atomics / 262,144) slots of an
+ * int32 buffer of `bytes` (fewer than 2^32 slots) chosen by a counter-based
+ * hash, with no result returned to the lane, `reps` timed launches after one
+ * untimed.  The update step's count additions are such atomics, so this rate
+ * bounds them as the copy kernel's bandwidth bounds a streaming kernel.
+ * RDOS_EINVAL for bad sizes, RDOS_ENOMEM if the buffer cannot be allocated. */
+rdos_status rdos_atomic_probe(int device, size_t bytes, int64_t n_atomics, int reps, double *per_s);
+
 const char *rdos_engine_last_error(const rdos_engine *e);
 void rdos_engine_destroy(rdos_engine *e);
 

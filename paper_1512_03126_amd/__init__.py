@@ -80,6 +80,7 @@ _SIGS = [
     ("rdos_engine_kernel_times", C.c_int, [C.c_void_p, _P(C.c_double), _P(C.c_int64), _P(C.c_double),
                                            _P(C.c_int64)]),
     ("rdos_bandwidth_probe", C.c_int, [C.c_int, C.c_size_t, C.c_int, _P(C.c_double)]),
+    ("rdos_atomic_probe", C.c_int, [C.c_int, C.c_size_t, C.c_int64, C.c_int, _P(C.c_double)]),
     ("rdos_tune_split_threshold", C.c_int, [C.c_int, C.c_int32, _P(C.c_int32), _P(C.c_double), _P(C.c_double)]),
     ("rdos_engine_last_error", C.c_char_p, [C.c_void_p]),
     ("rdos_engine_destroy", None, [C.c_void_p]),
@@ -405,6 +406,13 @@ def rdos_bandwidth_probe(device: int = 0, nbytes: int = 1 << 30, reps: int = 20)
     g = C.c_double()
     _check(lib().rdos_bandwidth_probe(int(device), int(nbytes), int(reps), C.byref(g)))
     return g.value
+
+
+def rdos_atomic_probe(device: int = 0, nbytes: int = 1 << 30, n_atomics: int = 1 << 22, reps: int = 10) -> float:
+    """Random int32 atomic additions per second into a buffer of nbytes."""
+    r = C.c_double()
+    _check(lib().rdos_atomic_probe(int(device), int(nbytes), int(n_atomics), int(reps), C.byref(r)))
+    return r.value
 
 
 def rdos_engine_destroy(engine):

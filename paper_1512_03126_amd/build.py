@@ -12,7 +12,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "librdos.so")
-SOURCES = ["rdos_kernels.hip", "rdos_api.cpp", "rdos_engine.cpp", "rdos_static.hip"]
+SOURCES = ["rdos_kernels.hip", "rdos_api.cpp", "rdos_engine.cpp", "rdos_static.hip", "rdos_probes.hip"]
 ARCH = os.environ.get("RDOS_OFFLOAD_ARCH", "gfx950")
 
 

@@ -62,3 +62,16 @@ def test_kernels_are_built_for_gfx950_without_fast_math():
     flags = open(os.path.join(ROOT, "paper_1512_03126_amd", "build.py")).read()
     assert "-ffp-contract=off" in flags and "gfx950" in flags and "-packed-fp32-ops" in flags
     assert "ffast-math" not in flags.replace("-fno-fast-math", "")
+
+
+def test_atomic_probe_rejects_bad_sizes_before_touching_a_device():
+    import paper_1512_03126_amd as P
+
+    L = P.lib()
+    r = ctypes.c_double(-1.0)
+    assert L.rdos_atomic_probe(0, 1 << 20, 0, 1, ctypes.byref(r)) == -1        # no atomics
+    assert L.rdos_atomic_probe(0, 1 << 20, 1000, 0, ctypes.byref(r)) == -1     # no timed launch
+    assert L.rdos_atomic_probe(0, 2, 1000, 1, ctypes.byref(r)) == -1           # no int32 slot
+    assert L.rdos_atomic_probe(0, 16 << 30, 1000, 1, ctypes.byref(r)) == -1    # 2^32 slots
+    assert L.rdos_atomic_probe(0, 1 << 20, 1000, 1, None) == -1
+    assert r.value == -1.0

@@ -207,3 +207,19 @@ def test_ten_species_model_every_period(orc):
         fired += int((got[2] + got[4] + got[7] + got[9]).sum() != (m.init[2, [2, 4, 7, 9]]).sum())
     assert fired > 0   # the reactions ran
     g.close()
+
+
+def test_atomic_probe_rate():
+    """The random-atomic probe that prices the update's count additions: a
+    positive, plausible rate, and the same order of magnitude for a buffer
+    16 times smaller."""
+    import paper_1512_03126_amd as P
+
+    note("random-atomic probe: 2^22 additions into 1 GiB and into 64 MiB")
+    big = P.rdos_atomic_probe(0, 1 << 30, 1 << 22, 3)
+    small = P.rdos_atomic_probe(0, 64 << 20, 1 << 22, 3)
+    note(f"random atomics: {big:.3e}/s into 1 GiB, {small:.3e}/s into 64 MiB")
+    assert 1e9 < big < 1e13 and 1e9 < small < 1e13
+    assert small > 0.5 * big
+    with pytest.raises(P.RdosError):
+        P.rdos_atomic_probe(0, 1 << 20, 0, 1)
