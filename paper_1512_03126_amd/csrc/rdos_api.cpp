@@ -159,17 +159,19 @@ size_t state_bytes(const rdos_sim *s)
            masks + occupancy + sizeof(DevSim) + 64;
 }
 
-// Face-matching results are cached by mesh connectivity (the tet_verts
-// array): requests that share a lattice but move its vertices reuse them.
+// Face-matching results are cached by mesh connectivity (the cell array):
+// requests that share a lattice but move its vertices reuse them.  An entry
+// shares the cell array of the simulation that made it and its neighbour
+// table ([T][4] ints) with the simulations set up from it; nothing is copied.
 struct TopologyCache {
     struct Entry {
         int32_t cell_verts = 4;
-        std::vector<int32_t> tet_verts;
-        std::shared_ptr<const std::vector<int32_t>> nbr;
+        std::shared_ptr<const std::vector<int32_t>> cells;
+        std::shared_ptr<const int32_t> nbr;
         uint64_t last_use = 0;
     };
     std::mutex mu;
-    std::multimap<uint64_t, Entry> entries;  // by hash of tet_verts
+    std::multimap<uint64_t, Entry> entries;  // by hash of the cell array
     size_t bytes = 0;
     uint64_t clock = 0;
     static constexpr size_t kMaxBytes = size_t(1) << 30;
@@ -208,90 +210,68 @@ static uint64_t hash_tets(const std::vector<int32_t> &tv)
     return r;
 }
 
-rdos_status build_topology_uncached(rdos_sim *s, std::vector<int32_t> &nbr);
-
-// Face matching on the device (launch_face_match) for meshes of at least
-// 16384 cells whose vertex ids pack into a 64-bit key; false when it does not
-// apply or finds a bad face (the host matching then reports the first bad
-// face in key order).  The sort makes it O(T) where the host sort is
-// O(T log T): about a second on the host for a million tetrahedra.
-static bool device_topology(rdos_sim *s, std::vector<int32_t> &nbr)
+// A neighbour table of n ints, left uninitialized for its producer to fill.
+static std::shared_ptr<int32_t> new_table(size_t n)
 {
-    const int32_t cv = s->cell_verts, T = s->T;
-    int32_t bits = 1;
-    while (bits < 31 && ((int64_t)1 << bits) < (int64_t)s->n_verts) ++bits;
-    if (T < 16384 || (cv == 4 && bits > 21) || (int64_t)T * 4 > 0x7fffffff) return false;
-    if (hipSetDevice(s->device) != hipSuccess || !s->stream) return false;
-    const size_t cell_bytes = (size_t)T * cv * sizeof(int32_t), nbr_bytes = (size_t)T * 4 * sizeof(int32_t);
-    const size_t scratch_bytes = face_match_scratch_bytes(T, cv);
-    void *d_cells = nullptr, *d_nbr = nullptr, *d_err = nullptr, *scratch = nullptr;
-    bool ok;
-    {
-        std::lock_guard<std::mutex> g(device_api_mutex());
-        ok = dev_alloc(&d_cells, cell_bytes, s->stream) == hipSuccess &&
-             dev_alloc(&d_nbr, nbr_bytes, s->stream) == hipSuccess &&
-             dev_alloc(&d_err, sizeof(int32_t), s->stream) == hipSuccess &&
-             dev_alloc(&scratch, scratch_bytes, s->stream) == hipSuccess;
-    }
-    int32_t err = 1;
-    if (ok) {
-        nbr.assign((size_t)T * 4, -1);
-        ok = hipMemcpyAsync(d_cells, s->tet_verts.data(), cell_bytes, hipMemcpyHostToDevice, s->stream) == hipSuccess &&
-             hipMemsetAsync(d_nbr, 0xff, nbr_bytes, s->stream) == hipSuccess &&
-             hipMemsetAsync(d_err, 0, sizeof(int32_t), s->stream) == hipSuccess &&
-             launch_face_match((const int32_t *)d_cells, T, cv, bits, (int32_t *)d_nbr, scratch, (int32_t *)d_err,
-                               s->stream) == hipSuccess &&
-             hipMemcpyAsync(nbr.data(), d_nbr, nbr_bytes, hipMemcpyDeviceToHost, s->stream) == hipSuccess &&
-             hipMemcpyAsync(&err, d_err, sizeof(int32_t), hipMemcpyDeviceToHost, s->stream) == hipSuccess &&
-             hipStreamSynchronize(s->stream) == hipSuccess;
-    }
-    {
-        std::lock_guard<std::mutex> g(device_api_mutex());
-        for (void *p : {d_cells, d_nbr, d_err, scratch}) dev_free(p, s->stream);
-    }
-    return ok && err == 0;
+    return std::shared_ptr<int32_t>(new int32_t[n], std::default_delete<int32_t[]>());
 }
 
-rdos_status build_topology(rdos_sim *s, std::shared_ptr<const std::vector<int32_t>> &out)
+// The cached neighbour table of this simulation's connectivity, or null;
+// *hash receives the key for topology_insert.
+static std::shared_ptr<const int32_t> topology_lookup(rdos_sim *s, uint64_t *hash)
 {
     TopologyCache &c = topology_cache();
-    const uint64_t h = hash_tets(s->tet_verts) ^ (uint64_t)s->cell_verts;
-    {
-        std::lock_guard<std::mutex> g(c.mu);
-        auto range = c.entries.equal_range(h);
-        for (auto it = range.first; it != range.second; ++it)
-            if (it->second.cell_verts == s->cell_verts && it->second.tet_verts == s->tet_verts) {
-                it->second.last_use = ++c.clock;
-                out = it->second.nbr;  // shared, not copied
-                return RDOS_OK;
-            }
-    }
-    std::vector<int32_t> nbr;
-    if (!device_topology(s, nbr)) {
-        rdos_status st = build_topology_uncached(s, nbr);
-        if (st != RDOS_OK) return st;
-    }
-    out = std::make_shared<const std::vector<int32_t>>(std::move(nbr));
+    const uint64_t h = hash_tets(*s->tet_verts) ^ (uint64_t)s->cell_verts;
+    *hash = h;
     std::lock_guard<std::mutex> g(c.mu);
-    const size_t add = (s->tet_verts.size() + out->size()) * sizeof(int32_t);
-    while (!c.entries.empty() && c.bytes + add > TopologyCache::kMaxBytes) {  // evict least recently used
+    auto range = c.entries.equal_range(h);
+    for (auto it = range.first; it != range.second; ++it)
+        if (it->second.cell_verts == s->cell_verts &&
+            (it->second.cells == s->tet_verts || *it->second.cells == *s->tet_verts)) {
+            it->second.last_use = ++c.clock;
+            return it->second.nbr;
+        }
+    return nullptr;
+}
+
+// Adds a table made for this simulation's connectivity (least recently used
+// entries make room).
+static void topology_insert(rdos_sim *s, uint64_t h, std::shared_ptr<const int32_t> nbr)
+{
+    TopologyCache &c = topology_cache();
+    std::lock_guard<std::mutex> g(c.mu);
+    const size_t add = (s->tet_verts->size() + 4 * (size_t)s->T) * sizeof(int32_t);
+    while (!c.entries.empty() && c.bytes + add > TopologyCache::kMaxBytes) {
         auto old = c.entries.begin();
         for (auto it = c.entries.begin(); it != c.entries.end(); ++it)
             if (it->second.last_use < old->second.last_use) old = it;
-        c.bytes -= (old->second.tet_verts.size() + old->second.nbr->size()) * sizeof(int32_t);
+        c.bytes -= (old->second.cells->size() + 4 * (old->second.cells->size() / old->second.cell_verts)) *
+                   sizeof(int32_t);
         c.entries.erase(old);
     }
-    if (add <= TopologyCache::kMaxBytes) {
-        TopologyCache::Entry en;
-        en.cell_verts = s->cell_verts;
-        en.tet_verts = s->tet_verts;
-        en.nbr = out;
-        en.last_use = ++c.clock;
-        c.entries.emplace(h, std::move(en));
-        c.bytes += add;
-    }
-    return RDOS_OK;
+    if (add > TopologyCache::kMaxBytes) return;
+    TopologyCache::Entry en;
+    en.cell_verts = s->cell_verts;
+    en.cells = s->tet_verts;
+    en.nbr = std::move(nbr);
+    en.last_use = ++c.clock;
+    c.entries.emplace(h, std::move(en));
+    c.bytes += add;
 }
+
+// Face matching runs on the device (launch_face_match) for meshes of at least
+// 16384 cells whose vertex ids pack into a 64-bit key (*bits: bits per vertex
+// id).  The sort makes it O(T) where the host sort is O(T log T): about a
+// second on the host for a million tetrahedra.
+static bool device_match_applies(const rdos_sim *s, int32_t *bits)
+{
+    int32_t b = 1;
+    while (b < 31 && ((int64_t)1 << b) < (int64_t)s->n_verts) ++b;
+    *bits = b;
+    return s->T >= 16384 && !(s->cell_verts == 4 && b > 21) && (int64_t)s->T * 4 <= 0x7fffffff;
+}
+
+rdos_status build_topology_uncached(rdos_sim *s, std::vector<int32_t> &nbr);
 
 // Edge matching for a surface of triangles: each edge (opposite local vertex
 // e) keyed by its sorted vertex pair; slot 3 of every triangle is a boundary.
@@ -304,7 +284,7 @@ static rdos_status build_edges(rdos_sim *s, std::vector<int32_t> &nbr)
     const int32_t T = s->T;
     std::vector<EdgeKey> keys((size_t)T * 3);
     for (int32_t t = 0; t < T; ++t) {
-        const int32_t *v = &s->tet_verts[3 * (size_t)t];
+        const int32_t *v = &(*s->tet_verts)[3 * (size_t)t];
         for (int e = 0; e < 3; ++e) {
             const int32_t p = v[e == 0 ? 1 : 0], q = v[e <= 1 ? 2 : 1];
             keys[3 * (size_t)t + e] = {std::min(p, q), std::max(p, q), 4 * t + e};
@@ -344,7 +324,7 @@ rdos_status build_topology_uncached(rdos_sim *s, std::vector<int32_t> &nbr)
     const int32_t T = s->T;
     std::vector<FaceKey> keys((size_t)T * 4);
     for (int32_t t = 0; t < T; ++t) {
-        const int32_t *v = &s->tet_verts[4 * (size_t)t];
+        const int32_t *v = &(*s->tet_verts)[4 * (size_t)t];
         for (int f = 0; f < 4; ++f) {
             std::array<int32_t, 3> tri;
             int q = 0;
@@ -562,7 +542,7 @@ rdos_status rdos_set_mesh(rdos_sim *s, int32_t n_verts, const double *xyz, int32
         if (tet_verts[i] < 0 || tet_verts[i] >= n_verts)
             return fail(s, RDOS_EINVAL, "vertex id %d out of range at %lld", tet_verts[i], (long long)i);
     s->xyz.assign(xyz, xyz + 3 * (size_t)n_verts);
-    s->tet_verts.assign(tet_verts, tet_verts + 4 * (size_t)n_tets);
+    s->tet_verts = std::make_shared<const std::vector<int32_t>>(tet_verts, tet_verts + 4 * (size_t)n_tets);
     s->n_verts = n_verts;
     s->T = n_tets;
     s->state = SimState::Meshed;
@@ -582,7 +562,7 @@ rdos_status rdos_set_surface_mesh(rdos_sim *s, int32_t n_verts, const double *xy
         if (tri_verts[i] < 0 || tri_verts[i] >= n_verts)
             return fail(s, RDOS_EINVAL, "vertex id %d out of range at %lld", tri_verts[i], (long long)i);
     s->xyz.assign(xyz, xyz + 3 * (size_t)n_verts);
-    s->tet_verts.assign(tri_verts, tri_verts + 3 * (size_t)n_tris);
+    s->tet_verts = std::make_shared<const std::vector<int32_t>>(tri_verts, tri_verts + 3 * (size_t)n_tris);
     s->cell_verts = 3;
     s->n_verts = n_verts;
     s->T = n_tris;
@@ -686,11 +666,24 @@ rdos_status rdos_finalize(rdos_sim *s, double tau_scale, double *out_tau)
         HIP_TRY(s, hipStreamCreateWithFlags(&s->stream, hipStreamNonBlocking), "create stream");
         s->own_stream = true;
     }
-    std::shared_ptr<const std::vector<int32_t>> nbr_table;
-    rdos_status st = build_topology(s, nbr_table);
-    if (st != RDOS_OK) return st;
-    const std::vector<int32_t> &nbr = *nbr_table;
+    // Face matching (step a0): the cached table of this connectivity, else
+    // matching on the device in the set-up buffers below, else on the host.
     const int32_t T = s->T;
+    const size_t nbr_n = 4 * (size_t)T;
+    uint64_t topo_hash = 0;
+    std::shared_ptr<const int32_t> nbr_table = topology_lookup(s, &topo_hash);
+    const bool fresh = !nbr_table;
+    int32_t bits = 0;
+    bool on_device = fresh && device_match_applies(s, &bits);
+    rdos_status st = RDOS_OK;
+    if (fresh && !on_device) {
+        std::vector<int32_t> host;
+        st = build_topology_uncached(s, host);
+        if (st != RDOS_OK) return st;
+        std::shared_ptr<int32_t> t = new_table(nbr_n);
+        std::memcpy(t.get(), host.data(), nbr_n * sizeof(int32_t));
+        nbr_table = t;
+    }
     const int S = (int)s->D.size();
     const int64_t Tp = padded_tets(T);
     const size_t count_bytes = (size_t)s->Rz * S * (size_t)Tp * sizeof(int32_t);
@@ -698,14 +691,15 @@ rdos_status rdos_finalize(rdos_sim *s, double tau_scale, double *out_tau)
 
     // temporary set-up buffers
     double *d_xyz = nullptr, *d_vol = nullptr, *d_bc = nullptr, *d_area = nullptr, *d_D = nullptr;
-    int32_t *d_tv = nullptr, *d_nbr = nullptr;
+    int32_t *d_tv = nullptr, *d_nbr = nullptr, *d_match_err = nullptr;
+    void *d_match = nullptr;
     unsigned long long *d_tau = nullptr;
     std::unique_lock<std::mutex> alloc_lock(device_api_mutex(), std::defer_lock);
     auto cleanup = [&]() {
         if (s->stream) (void)hipStreamSynchronize(s->stream);
         std::unique_lock<std::mutex> g(device_api_mutex(), std::defer_lock);
         if (!alloc_lock.owns_lock()) g.lock();
-        void *p[] = {d_xyz, d_vol, d_bc, d_area, d_D, d_tv, d_nbr, d_tau};
+        void *p[] = {d_xyz, d_vol, d_bc, d_area, d_D, d_tv, d_nbr, d_tau, d_match_err, d_match};
         for (void *q : p) dev_free(q, s->stream);
     };
 #define SETUP_TRY(expr, what)                               \
@@ -729,8 +723,12 @@ rdos_status rdos_finalize(rdos_sim *s, double tau_scale, double *out_tau)
     SETUP_TRY(alloc_queue(&s->queue, tiles_of(s), S, s->stream), "allocate queue");
     s->queue.owned = tiles_of(s) <= kMaxSegments ? 1 : 0;  // a segment and a scan wavefront per tile
     SETUP_TRY(dev_alloc((void **)&d_xyz, s->xyz.size() * sizeof(double), s->stream), "allocate set-up");
-    SETUP_TRY(dev_alloc((void **)&d_tv, s->tet_verts.size() * sizeof(int32_t), s->stream), "allocate set-up");
-    SETUP_TRY(dev_alloc((void **)&d_nbr, nbr.size() * sizeof(int32_t), s->stream), "allocate set-up");
+    SETUP_TRY(dev_alloc((void **)&d_tv, s->tet_verts->size() * sizeof(int32_t), s->stream), "allocate set-up");
+    SETUP_TRY(dev_alloc((void **)&d_nbr, nbr_n * sizeof(int32_t), s->stream), "allocate set-up");
+    if (on_device) {
+        SETUP_TRY(dev_alloc((void **)&d_match_err, 64, s->stream), "allocate face matching");
+        SETUP_TRY(dev_alloc(&d_match, face_match_scratch_bytes(T, s->cell_verts), s->stream), "allocate face matching");
+    }
     SETUP_TRY(dev_alloc((void **)&d_vol, (size_t)T * sizeof(double), s->stream), "allocate set-up");
     SETUP_TRY(dev_alloc((void **)&d_bc, (size_t)T * 3 * sizeof(double), s->stream), "allocate set-up");
     SETUP_TRY(dev_alloc((void **)&d_area, (size_t)T * 4 * sizeof(double), s->stream), "allocate set-up");
@@ -745,11 +743,43 @@ rdos_status rdos_finalize(rdos_sim *s, double tau_scale, double *out_tau)
     SETUP_TRY(hipMemsetAsync(d_tau, 0xff, sizeof(unsigned long long), s->stream), "clear tau");
     SETUP_TRY(hipMemcpyAsync(d_xyz, s->xyz.data(), s->xyz.size() * sizeof(double), hipMemcpyHostToDevice, s->stream),
               "upload vertices");
-    SETUP_TRY(hipMemcpyAsync(d_tv, s->tet_verts.data(), s->tet_verts.size() * sizeof(int32_t), hipMemcpyHostToDevice,
-                             s->stream),
+    SETUP_TRY(hipMemcpyAsync(d_tv, s->tet_verts->data(), s->tet_verts->size() * sizeof(int32_t),
+                             hipMemcpyHostToDevice, s->stream),
               "upload tetrahedra");
-    SETUP_TRY(hipMemcpyAsync(d_nbr, nbr.data(), nbr.size() * sizeof(int32_t), hipMemcpyHostToDevice, s->stream),
-              "upload neighbours");
+    if (on_device) {
+        // keys of each face's sorted vertex ids, a radix sort, pairs of equal keys
+        int32_t match_err = 1;
+        SETUP_TRY(hipMemsetAsync(d_nbr, 0xff, nbr_n * sizeof(int32_t), s->stream), "face matching");
+        SETUP_TRY(hipMemsetAsync(d_match_err, 0, sizeof(int32_t), s->stream), "face matching");
+        SETUP_TRY(launch_face_match(d_tv, T, s->cell_verts, bits, d_nbr, d_match, d_match_err, s->stream),
+                  "face matching");
+        SETUP_TRY(hipMemcpyAsync(&match_err, d_match_err, sizeof(int32_t), hipMemcpyDeviceToHost, s->stream),
+                  "face matching");
+        SETUP_TRY(hipStreamSynchronize(s->stream), "face matching");
+        if (match_err == 0) {
+            // the table stays on the device for the geometry pass; a host copy goes to the cache
+            std::shared_ptr<int32_t> t = new_table(nbr_n);
+            SETUP_TRY(hipMemcpyAsync(t.get(), d_nbr, nbr_n * sizeof(int32_t), hipMemcpyDeviceToHost, s->stream),
+                      "read neighbours");
+            nbr_table = t;
+        } else {
+            // a bad face: the host matching names the first one in key order
+            std::vector<int32_t> host;
+            st = build_topology_uncached(s, host);
+            if (st != RDOS_OK) {
+                cleanup();
+                free_device(s);
+                return st;
+            }
+            std::shared_ptr<int32_t> t = new_table(nbr_n);
+            std::memcpy(t.get(), host.data(), nbr_n * sizeof(int32_t));
+            nbr_table = t;
+            on_device = false;
+        }
+    }
+    if (!on_device)
+        SETUP_TRY(hipMemcpyAsync(d_nbr, nbr_table.get(), nbr_n * sizeof(int32_t), hipMemcpyHostToDevice, s->stream),
+                  "upload neighbours");
     SETUP_TRY(hipMemcpyAsync(d_D, s->D.data(), (size_t)S * sizeof(double), hipMemcpyHostToDevice, s->stream),
               "upload D");
     if (s->cell_verts == 3)
@@ -893,6 +923,7 @@ rdos_status rdos_finalize(rdos_sim *s, double tau_scale, double *out_tau)
         free_device(s);
         return st;
     }
+    if (fresh) topology_insert(s, topo_hash, std::move(nbr_table));  // the read-back was waited for above
     s->state = SimState::Ready;
     s->step = 0;
     s->anchor_step = 0;

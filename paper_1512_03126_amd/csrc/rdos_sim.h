@@ -5,6 +5,7 @@
 
 #include <cstdint>
 #include <map>
+#include <memory>
 #include <string>
 #include <vector>
 
@@ -34,7 +35,8 @@ struct rdos_sim {
     // model (host copy)
     int32_t n_verts = 0, T = 0;
     std::vector<double> xyz;
-    std::vector<int32_t> tet_verts;  // cells: [T][4] tetrahedra, or [T][3] triangles of a surface
+    std::shared_ptr<const std::vector<int32_t>> tet_verts;  // cells: [T][4] tetrahedra, or [T][3] triangles of a
+                                                            // surface (shared with the topology cache)
     int32_t cell_verts = 4;
     std::vector<double> D;
     std::vector<rdos::Reaction> rx;
