@@ -92,6 +92,34 @@ def test_geometry_and_tau_bit_exact(P, orc):
             g.close()
 
 
+def test_large_mesh_face_matching_paths(P, orc):
+    """Meshes of at least 16,384 cells are matched on the device, in the
+    set-up buffers.  A bad face there falls back to the host matching, which
+    names it, and nothing is cached.  A fresh lattice matched on the device,
+    the same lattice again from the cache, and the oracle agree on every
+    neighbour, weight, g and N_A V, bit for bit."""
+    n = 17   # 29,478 tets: a lattice no other test uses, so its first set-up is uncached
+    xyz0, tets = W.kuhn_lattice(n, 0.1e-6)
+    xyz = W.jitter(xyz0, n, 0.1e-6, 0.2, 5)
+    note(f"face matching on the device: T={tets.shape[0]}, bad faces, then fresh and cached set-ups")
+    bad = tets.copy()
+    bad[100, 3] = bad[100, 2]
+    with pytest.raises(P.RdosError, match="repeats a face"):
+        P.Simulation(xyz, bad, [1e-12], [])
+    with pytest.raises(P.RdosError, match="shared"):
+        P.Simulation(xyz, np.concatenate([tets, tets[:1]]), [1e-12], [])
+    o = orc.OracleSim(xyz, tets, [1e-12, 0.4e-12], [])
+    og = o.geometry()
+    for _ in range(2):   # matched on the device, then taken from the cache
+        g = P.Simulation(xyz, tets, [1e-12, 0.4e-12], [])
+        assert g.tau == o.tau
+        gg = g.geometry()
+        np.testing.assert_array_equal(gg["nbr"], og["nbr"])
+        for key in ("w", "g", "nav"):
+            assert np.array_equal(gg[key].view(np.uint64), og[key].view(np.uint64)), key
+        g.close()
+
+
 @pytest.mark.parametrize("n,jit,Rz,seed", [(1, 0.0, 3, 1), (2, 0.2, 2, 7), (3, 0.2, 1, 11)])
 def test_rich_chemistry_every_period(P, orc, n, jit, Rz, seed):
     xyz, tets = W.tiny_lattice(n, 0.2e-6, jitter_frac=jit, seed=seed)
