@@ -545,6 +545,7 @@ void worker_main(rdos_engine *e)
                 e->best = kSmallWorkShape;
                 e->shape_source = RDOS_SHAPE_SMALL_WORK;
                 e->trial = tune_end(e);
+                for (auto &v : e->trial_ms) v.assign(e->candidates.size(), 0.0);  // nothing measured here
             } else if (b != e->bucket) {
                 e->bucket = b;
                 auto hit = e->tuned.find(b);
@@ -568,6 +569,7 @@ void worker_main(rdos_engine *e)
                         e->shape_source = RDOS_SHAPE_CACHED;
                     }
                     e->trial = tune_end(e);
+                    for (auto &v : e->trial_ms) v.assign(e->candidates.size(), 0.0);  // measured elsewhere
                 } else {
                     e->trial = 0;
                     for (auto &v : e->trial_ms) v.assign(e->candidates.size(), 0.0);

@@ -298,16 +298,17 @@ def test_tuner_scores_and_shape_independence(orc):
     """A work list large enough to be tuned (48 realizations x 48,000 tets,
     2256 tiles): every candidate shape is scored in both passes, the kept
     shape has the lowest mean time per period, and the counts equal a run
-    with a fixed shape and, for one realization, the oracle."""
+    with a fixed shape, a run from the cached shape (no scores of its own)
+    and, for one realization, the oracle."""
     import paper_1512_03126_amd as P
 
     m = W.abc_lattice(n=20, a=0.1e-6, seed=3, n_realizations=48)
     n = 320
     note(f"tuner: {m.n_realizations} x {m.n_tets} tets, {n} periods, tuned against a fixed shape")
     out = []
-    for fixed in (None, (16, 1024, 1, 1)):
+    for fixed in (None, (16, 1024, 1, 1), "cached"):
         e = P.rdos_engine_create(0, 0)
-        if fixed:
+        if isinstance(fixed, tuple):
             P.rdos_engine_set_shape(e, *fixed)
         s = P.Simulation(m.xyz, m.tets, m.D, m.reactions, seed=m.seed, n_realizations=m.n_realizations)
         for r in range(m.n_realizations):
@@ -321,6 +322,10 @@ def test_tuner_scores_and_shape_independence(orc):
         P.rdos_engine_destroy(e)
         out.append([s.get_counts(None, realization=r) for r in range(m.n_realizations)])
         s.close()
+        if fixed == "cached":   # a second engine on the same size bucket starts from the tuned shape
+            assert shape["source"] == "cached", shape
+            assert all(c["ms_first"] == 0 and c["ms_second"] == 0 for c in scores), scores
+            continue
         if fixed:
             assert shape["source"] == "fixed"
             continue
@@ -333,6 +338,7 @@ def test_tuner_scores_and_shape_independence(orc):
             (shape["scan_grid"], shape["update_blocks_per_segment"], shape["chains"]), (shape, scores)
     for r in range(m.n_realizations):
         np.testing.assert_array_equal(out[0][r], out[1][r])
+        np.testing.assert_array_equal(out[0][r], out[2][r])
     o = orc.OracleSim(m.xyz, m.tets, m.D, m.reactions, seed=m.seed, realization=7)
     for q in range(m.n_species):
         o.set_counts(q, m.init[7, q])
