@@ -344,3 +344,53 @@ def test_tuner_scores_and_shape_independence(orc):
         o.set_counts(q, m.init[7, q])
     o.run_steps(n)
     np.testing.assert_array_equal(o.get_counts(), out[0][7])
+
+
+@pytest.mark.parametrize("shape", [None, (8, 64, 1, 2), (8, 64, 0, 2)])
+def test_zeroth_order_reaction_in_the_engine(orc, shape):
+    """A reaction without reactants (0 -> A, Sec. III.A's production) makes
+    every tet of its simulation run each period, whatever the occupancy map
+    holds.  Two such simulations (one production everywhere, one restricted
+    to a region) batched with one without, through the one-launch path for
+    small work lists, two chains of two launches, and two fused chains:
+    every count of every realization against the oracle."""
+    import paper_1512_03126_amd as P
+
+    xyz, tets = W.tiny_lattice(4, 0.2e-6, jitter_frac=0.2, seed=12)
+    T = tets.shape[0]
+    D = [1e-12, 0.6e-12, 0.3e-12]
+    base = [([0, 1], [2], 3e8), ([2], [0, 1], 400.0)]
+    models = [(base + [([], [0], 3e-5)], None, 2, 31), (base + [([], [1], 8e-5)], {2: np.arange(0, T, 7)}, 2, 32),
+              (base, None, 3, 33)]
+    periods = 60
+    note(f"zeroth-order production in the engine: {T} tets, shape {shape}")
+    e = P.rdos_engine_create(0, 0)
+    if shape is not None:
+        P.rdos_engine_set_shape(e, *shape)
+    rng = np.random.default_rng(5)
+    runs = []
+    P.rdos_engine_hold(e, True)
+    for rx, regions, rz, seed in models:
+        init = rng.integers(0, 4, size=(rz, 3, T)).astype(np.int32)
+        init[:, :, rng.random(T) < 0.7] = 0   # sparse: the map, not the production, decides most tets
+        s = P.Simulation(xyz, tets, D, rx, seed=seed, n_realizations=rz, tau_scale=None, regions=regions)
+        for r in range(rz):
+            for q in range(3):
+                s.set_counts(q, init[r, q], realization=r)
+        runs.append((s, rx, regions, rz, seed, init, P.rdos_engine_submit(e, s.h, periods, 1.0)))
+    P.rdos_engine_hold(e, False)
+    P.rdos_engine_drain(e)
+    if shape is not None:
+        assert P.rdos_engine_launch_shape(e)["chains"] == 2
+    for s, rx, regions, rz, seed, init, t in runs:
+        P.rdos_engine_release(e, t)
+        for r in range(rz):
+            o = orc.OracleSim(xyz, tets, D, rx, seed=seed, realization=r)
+            for rid, tl in (regions or {}).items():
+                o.set_reaction_region(rid, tl)
+            for q in range(3):
+                o.set_counts(q, init[r, q])
+            o.run_steps(periods)
+            np.testing.assert_array_equal(o.get_counts(), s.get_counts(None, realization=r))
+        s.close()
+    P.rdos_engine_destroy(e)
