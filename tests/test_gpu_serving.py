@@ -394,3 +394,55 @@ def test_zeroth_order_reaction_in_the_engine(orc, shape):
             np.testing.assert_array_equal(o.get_counts(), s.get_counts(None, realization=r))
         s.close()
     P.rdos_engine_destroy(e)
+
+
+@pytest.mark.parametrize("shape", [None, (8, 64, 1, 2), (8, 64, 0, 2)])
+def test_method_options_mixed_in_the_engine(orc, shape):
+    """Simulations with different method options in one work list: transfer
+    form 1 (the closing alternative of Sec. II.B) beside form 0 makes the
+    whole list run the scaled update instance, in which each simulation must
+    still follow its own form; first-order splitting, a split threshold of 2
+    and outlier relaxation ride along.  Through the one-launch path, two
+    chains of two launches and two fused chains, every count of every
+    realization against the oracle."""
+    import paper_1512_03126_amd as P
+
+    xyz, tets = W.tiny_lattice(4, 0.2e-6, jitter_frac=0.2, seed=13)
+    T = tets.shape[0]
+    D = [1e-12, 0.6e-12, 0.3e-12]
+    rx = [([0, 1], [2], 3e8), ([2], [0, 1], 400.0), ([0], [], 20.0)]
+    opts = [dict(transfer_form=1), dict(), dict(occupancy_correction=False, split_threshold=2),
+            dict(tau_outliers=5, transfer_form=1)]
+    periods = 50
+    note(f"method options mixed in the engine: {T} tets, shape {shape}")
+    e = P.rdos_engine_create(0, 0)
+    if shape is not None:
+        P.rdos_engine_set_shape(e, *shape)
+    rng = np.random.default_rng(8)
+    runs = []
+    P.rdos_engine_hold(e, True)
+    for k, o in enumerate(opts):
+        rz = 2
+        init = rng.integers(0, 40, size=(rz, 3, T)).astype(np.int32)
+        init[:, 0, ::5] += 60   # some tets with many molecules: the sequential-binomial branch
+        s = P.Simulation(xyz, tets, D, rx, seed=40 + k, n_realizations=rz, tau_scale=None, **o)
+        for r in range(rz):
+            for q in range(3):
+                s.set_counts(q, init[r, q], realization=r)
+        runs.append((s, o, rz, 40 + k, init, P.rdos_engine_submit(e, s.h, periods, 1.0)))
+    P.rdos_engine_hold(e, False)
+    P.rdos_engine_drain(e)
+    for s, o, rz, seed, init, t in runs:
+        P.rdos_engine_release(e, t)
+        for r in range(rz):
+            orc_sim = orc.OracleSim(xyz, tets, D, rx, seed=seed, realization=r)
+            orc_sim.set_first_order(not o.get("occupancy_correction", True))
+            orc_sim.set_split_threshold(o.get("split_threshold", 10))
+            orc_sim.set_transfer_form(o.get("transfer_form", 0))
+            orc_sim.set_tau_outliers(o.get("tau_outliers", 0))
+            for q in range(3):
+                orc_sim.set_counts(q, init[r, q])
+            orc_sim.run_steps(periods)
+            np.testing.assert_array_equal(orc_sim.get_counts(), s.get_counts(None, realization=r), str(o))
+        s.close()
+    P.rdos_engine_destroy(e)
