@@ -208,7 +208,10 @@ rdos_status ensure(rdos_engine *e, T **buf, int64_t *cap, int64_t need, const ch
 }
 
 // Species rows of the queue, which also size the scan's register arrays.
-int species_bound(int s) { return s <= 2 ? 2 : (s == 3 ? 3 : (s <= 4 ? 4 : (s <= 6 ? 6 : (s <= 8 ? 8 : kMaxSpecies)))); }
+int species_bound(int s)
+{
+    return s <= 2 ? 2 : (s == 3 ? 3 : (s <= 4 ? 4 : (s <= 6 ? 6 : (s <= 8 ? 8 : (s <= 10 ? 10 : kMaxSpecies)))));
+}
 
 // Chunks of tuning per size bucket: two per candidate, then one more each.
 size_t tune_end(const rdos_engine *e) { return 3 * e->candidates.size(); }

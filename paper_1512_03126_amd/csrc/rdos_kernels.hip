@@ -1076,10 +1076,12 @@ __device__ __forceinline__ void update_segment(const DevSim *__restrict__ sims, 
 // Per-lane state for up to KS species in LDS (20 KS bytes per lane).  With
 // the default transfer form the kernel fits 128 VGPRs without spilling; for
 // KS <= 6 the LDS allows four blocks per CU too, so it runs four wavefronts
-// per SIMD.  The other instances up to 8 species keep the register budget of
-// three; the 16-species one (80 KB of LDS per block) fits two blocks per CU.
+// per SIMD.  The other instances up to 10 species keep the register budget
+// of three (the 10-species one, 50 KB of LDS per block, fits three blocks per
+// CU: the paper's 10-species models run it); the 16-species one (80 KB) fits
+// two blocks per CU.
 template <bool ANY_SCALED, int KS>
-__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(KS <= 6 && !ANY_SCALED ? 4 : (KS <= 8 ? 3 : 2)))) void
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(KS <= 6 && !ANY_SCALED ? 4 : (KS <= 10 ? 3 : 2)))) void
 update_kernel(const DevSim *__restrict__ sims, const Tile *__restrict__ tiles, Queue q, int32_t qsel, int64_t iter,
               int64_t partial, double tau_last, int32_t grid_segments)
 {
@@ -1493,6 +1495,13 @@ hipError_t launch_update(const DevSim *sims, const Tile *tiles, int64_t iter, in
         else
             update_kernel<false, 8><<<grid, kBlock, 0, st>>>(sims, tiles, q, qsel, iter, partial, tau_last,
                                                                 grid_segments);
+    } else if (qv.species <= 10) {
+        if (qv.scaled)
+            update_kernel<true, 10><<<grid, kBlock, 0, st>>>(sims, tiles, q, qsel, iter, partial, tau_last,
+                                                                 grid_segments);
+        else
+            update_kernel<false, 10><<<grid, kBlock, 0, st>>>(sims, tiles, q, qsel, iter, partial, tau_last,
+                                                                  grid_segments);
     } else {
         if (qv.scaled)
             update_kernel<true, kMaxSpecies><<<grid, kBlock, 0, st>>>(sims, tiles, q, qsel, iter, partial, tau_last,

@@ -108,7 +108,7 @@ WIDE_RX = {
                                             (16, 0, False, 10)])
 def test_wide_chemistry_every_period(orc, S, form, occ, thr):
     """Transfer form 1 (the closing alternative of Sec. II.B) and form 0 with
-    5-16 species: the update instances for the 6-, 8- and 16-species bounds
+    5-16 species: the update instances for the 6-, 8-, 10- and 16-species bounds
     and the matching scan instances, bit for bit against the oracle after
     every one of 32 periods (Algorithm 1, Steps 2-3)."""
     import paper_1512_03126_amd as P
