@@ -380,14 +380,20 @@ hipError_t launch_tau_select(const MeshRec *mesh, int32_t T, const double *D, in
 __shared__ uint32_t block_tets, block_adds, block_moves;
 
 // One count for tally `which` (0 tets, 1 additions, 2 face transfers) of the
-// timing pass, whose totals are work[0..2].  Instances of up to 8 species
-// count per block in LDS; the wider ones, whose per-lane state fills half the
-// LDS, add per wavefront straight to the totals (a ballot over the lanes that
-// count, one atomic by the first of them), so two blocks still fit a CU.
+// timing pass, whose totals are work[0..2].  Instances of up to 6 species
+// count per block in LDS; from 8 species on, where the per-lane state sets
+// how many blocks fit a CU (the 8-species one fills a quarter of the LDS to
+// the byte), they add per wavefront straight to the totals (a ballot over the
+// lanes that count, one atomic by the first of them).
+template <int KS>
+constexpr bool block_tallies()
+{
+    return KS <= 6;
+}
 template <int KS>
 __device__ __forceinline__ void tally_count(unsigned long long *work, int which)
 {
-    if constexpr (KS <= 8) {
+    if constexpr (block_tallies<KS>()) {
         atomicAdd(which == 0 ? &block_tets : (which == 1 ? &block_adds : &block_moves), 1u);
     } else {
         const uint64_t m = __ballot(1);
@@ -833,12 +839,13 @@ __device__ __forceinline__ void clear_chunk(int32_t *cur, const Tile &tile, int6
 }
 
 // Rows of a wavefront's staging area: the tet row and the species rows of
-// one pass.  Instances for more than 8 species stage four species at a time,
-// so that their LDS, and with it their occupancy, stays that of the others.
+// one pass.  Instances for more than 4 species stage four species at a time,
+// so that their LDS (24 KB per block), and with it their occupancy, stays
+// that of the 4-species one.
 template <int MAXS>
 constexpr int stage_rows()
 {
-    return ChunkGroup<MAXS>::kWide ? 1 + 4 : 1 + MAXS;
+    return MAXS > 4 ? 1 + 4 : 1 + MAXS;
 }
 
 // Writes the chunk's occupied tets to the queue from `base` on, in rank
@@ -880,6 +887,38 @@ __device__ __forceinline__ void write_chunk(const __amdgpu_buffer_rsrc_t &rs, in
 #pragma unroll
                 for (int j = 0; j < 4; ++j)
                     if (s0 + j < S) qcnt[(s0 + j) * h.qcap + base + e] = stage[1 + j][e];
+            }
+            // the rows are read before the next pass writes them
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        }
+    } else if constexpr (MAXS > 4) {
+        // species rows four at a time, from the vectors held in registers
+#pragma unroll
+        for (int s0 = 0; s0 < MAXS; s0 += 4) {
+            if (s0 >= S) break;
+            int32_t k = g.before;
+#pragma unroll
+            for (int b = 0; b < 4; ++b) {
+                if (!((g.bits >> b) & 1u)) continue;
+                if (s0 == 0) stage[0][k] = 4 * g.gid + b;
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    if (s0 + j >= MAXS || s0 + j >= S) break;
+                    const v4i &c = g.c[s0 + j];
+                    stage[1 + j][k] = b == 0 ? c.x : b == 1 ? c.y : b == 2 ? c.z : c.w;
+                }
+                ++k;
+            }
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+            for (int32_t e = lane; e < total; e += 64) {
+                if (s0 == 0) qtet[base + e] = ti * kTetsPerTile + stage[0][e];
+#pragma unroll
+                for (int j = 0; j < 4; ++j)
+                    if (s0 + j < MAXS && s0 + j < S) qcnt[(s0 + j) * h.qcap + base + e] = stage[1 + j][e];
             }
             // the rows are read before the next pass writes them
             __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -1075,13 +1114,14 @@ __device__ __forceinline__ void update_segment(const DevSim *__restrict__ sims, 
 
 // Per-lane state for up to KS species in LDS (20 KS bytes per lane).  With
 // the default transfer form the kernel fits 128 VGPRs without spilling; for
-// KS <= 6 the LDS allows four blocks per CU too, so it runs four wavefronts
-// per SIMD.  The other instances up to 10 species keep the register budget
-// of three (the 10-species one, 50 KB of LDS per block, fits three blocks per
-// CU: the paper's 10-species models run it); the 16-species one (80 KB) fits
-// two blocks per CU.
+// KS <= 8 the LDS allows four blocks per CU too (the 8-species instance fills
+// a quarter of it to the byte, so it keeps no tallies there), so it runs four
+// wavefronts per SIMD.  The transfer-form-1 instances and the 10-species one
+// keep the register budget of three (the 10-species one, 50 KB of LDS per
+// block, fits three blocks per CU: the paper's 10-species models run it); the
+// 16-species one (80 KB) fits two blocks per CU.
 template <bool ANY_SCALED, int KS>
-__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(KS <= 6 && !ANY_SCALED ? 4 : (KS <= 10 ? 3 : 2)))) void
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(KS <= 8 && !ANY_SCALED ? 4 : (KS <= 10 ? 3 : 2)))) void
 update_kernel(const DevSim *__restrict__ sims, const Tile *__restrict__ tiles, Queue q, int32_t qsel, int64_t iter,
               int64_t partial, double tau_last, int32_t grid_segments)
 {
@@ -1105,15 +1145,15 @@ update_kernel(const DevSim *__restrict__ sims, const Tile *__restrict__ tiles, Q
     const int32_t per_seg = __builtin_amdgcn_readfirstlane(max(1, (int32_t)(gridDim.x / (uint32_t)grid_segments)));
     const int32_t part = __builtin_amdgcn_readfirstlane((int32_t)(blockIdx.x / (uint32_t)grid_segments));
     if (seg >= h.nseg || part >= per_seg) return;  // uniform over the block
-    const bool tally = KS <= 8 && q.work != nullptr;  // per-block tallies (see tally_count)
-    if constexpr (KS <= 8) {
+    const bool tally = block_tallies<KS>() && q.work != nullptr;  // per-block tallies (see tally_count)
+    if constexpr (block_tallies<KS>()) {
         if (tally) {
             if (threadIdx.x == 0) block_tets = block_adds = block_moves = 0;
             __syncthreads();
         }
     }
     update_segment<ANY_SCALED, KS>(sims, tiles, q, qsel, iter, partial, tau_last, h, seg, part, per_seg, ls, q.work);
-    if constexpr (KS <= 8) {
+    if constexpr (block_tallies<KS>()) {
         if (tally) {
             __syncthreads();
             if (threadIdx.x == 0) {
@@ -1241,8 +1281,8 @@ __global__ __launch_bounds__(kBlock) void fused_kernel(const DevSim *__restrict_
     const LaneState ls{counts + threadIdx.x, occ + threadIdx.x, last + threadIdx.x};
     const int wv = threadIdx.x >> 6;
     const WorkHeader h = read_header(hdr);
-    const bool tally = KS <= 8 && work != nullptr;  // per-block tallies (see tally_count)
-    if constexpr (KS <= 8) {
+    const bool tally = block_tallies<KS>() && work != nullptr;  // per-block tallies (see tally_count)
+    if constexpr (block_tallies<KS>()) {
         if (tally) {
             if (threadIdx.x == 0) block_tets = block_adds = block_moves = 0;
             __syncthreads();
@@ -1250,7 +1290,7 @@ __global__ __launch_bounds__(kBlock) void fused_kernel(const DevSim *__restrict_
     }
     fused_tiles<ANY_SCALED, KS>(sims, tiles, h, iter, partial, tau_last, (int32_t)blockIdx.x * kScanWaves + wv,
                                 (int32_t)gridDim.x * kScanWaves, glist[wv], ring[wv], ls, work);
-    if constexpr (KS <= 8) {
+    if constexpr (block_tallies<KS>()) {
         if (tally) {
             __syncthreads();
             if (threadIdx.x == 0) {
